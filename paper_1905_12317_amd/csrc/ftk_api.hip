@@ -1,0 +1,613 @@
+// C-ABI of the FTK library: plans, shift tables, transform and alignment.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/ftk.h"
+#include "kernels.h"
+#include "planner.h"
+
+namespace {
+
+constexpr double kPi = 3.14159265358979323846264338327950288;
+constexpr int kNufftWidth = 8;
+constexpr size_t kLdsLimit = 160 * 1024;
+
+thread_local std::string g_last_error;
+
+int fail(int code, const std::string& msg) {
+  g_last_error = msg;
+  return code;
+}
+
+int hip_fail(hipError_t e, const char* where) {
+  return fail(FTK_EDEVICE, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+int round_up(int x, int m) { return (x + m - 1) / m * m; }
+
+size_t env_bytes(const char* name, size_t dflt) {
+  const char* v = std::getenv(name);
+  if (!v || !*v) return dflt;
+  char* end = nullptr;
+  unsigned long long mb = std::strtoull(v, &end, 10);
+  if (end == v || mb == 0) return dflt;
+  return static_cast<size_t>(mb) << 20;
+}
+
+struct DevBuf {
+  void* ptr = nullptr;
+  size_t bytes = 0;
+  void release() {
+    if (ptr) (void)hipFree(ptr);
+    ptr = nullptr;
+    bytes = 0;
+  }
+  hipError_t ensure(size_t want) {
+    if (want <= bytes) return hipSuccess;
+    release();
+    hipError_t e = hipMalloc(&ptr, want);
+    if (e != hipSuccess) {
+      ptr = nullptr;
+      return e;
+    }
+    bytes = want;
+    return hipSuccess;
+  }
+  template <class T>
+  T* as() const {
+    return static_cast<T*>(ptr);
+  }
+};
+
+// Per-mode factor tables, FP64 (Section 4.5).
+struct HostTables {
+  int H = 0, L = 0;
+  double sigma_next = 0;
+  std::vector<int> ell, eta;
+  std::vector<double> sigma;
+  std::vector<double> k, w;  // radial rule
+  std::vector<double> G;     // [H][M] Sigma v(k_m / kmax), sign (-1)^l for l < 0
+  ftkplan::Truncation tr;
+};
+
+int build_tables(int n, int M, double W, double eps, HostTables& t) {
+  const double kmax = 0.5 * kPi * n;
+  ftkplan::radial_rule(M, kmax, t.k, t.w);
+  t.tr = ftkplan::truncate(kPi * W, eps);
+  t.L = t.tr.L;
+  t.sigma_next = t.tr.sigma_next;
+  t.H = static_cast<int>(t.tr.terms.size());
+  for (const auto& term : t.tr.terms) {
+    t.ell.push_back(term.ell);
+    t.eta.push_back(term.eta);
+    t.sigma.push_back(term.sigma);
+  }
+  // G[zeta][m] = Sigma v(y_m) = sum_i sqrt(xw_i) J_l(x_i y_m) U[i][eta]
+  t.G.assign(static_cast<size_t>(t.H) * M, 0.0);
+  const ftkplan::ModalSVD& s0 = t.tr.svds[0];
+  const int P = s0.P;
+  std::vector<double> J(static_cast<size_t>(t.L + 1) * P);
+  std::vector<double> tmp(t.L + 1);
+  for (int m = 0; m < M; ++m) {
+    const double y = t.k[m] / kmax;
+    for (int i = 0; i < P; ++i) {
+      ftkplan::bessel_orders(t.L, s0.xn[i] * y, tmp.data());
+      for (int l = 0; l <= t.L; ++l) J[static_cast<size_t>(l) * P + i] = tmp[l];
+    }
+    for (int z = 0; z < t.H; ++z) {
+      const int la = std::abs(t.ell[z]);
+      const ftkplan::ModalSVD& s = t.tr.svds[la];
+      double acc = 0.0;
+      for (int i = 0; i < P; ++i) acc += std::sqrt(s.xw[i]) * J[static_cast<size_t>(la) * P + i] * s.U[i * P + t.eta[z]];
+      if (t.ell[z] < 0 && (la & 1)) acc = -acc;
+      t.G[static_cast<size_t>(z) * M + m] = acc;
+    }
+  }
+  return FTK_OK;
+}
+
+// Y[delta][zeta] = u_zeta(pi |d|) exp(-i l (omega + pi/2)), d in pixels.
+int build_Y(const HostTables& t, const double* shifts, int N, double W, std::vector<std::complex<double>>& Y) {
+  const ftkplan::ModalSVD& s0 = t.tr.svds[0];
+  const int P = s0.P;
+  Y.assign(static_cast<size_t>(N) * t.H, 0.0);
+  std::vector<double> J(static_cast<size_t>(t.L + 1) * P), tmp(t.L + 1);
+  for (int d = 0; d < N; ++d) {
+    const double dx = shifts[2 * d], dy = shifts[2 * d + 1];
+    if (!std::isfinite(dx) || !std::isfinite(dy)) return fail(FTK_EINVAL, "ftk_set_shifts: non-finite shift");
+    const double rad = std::hypot(dx, dy);
+    if (rad > W * (1.0 + 1e-9)) return fail(FTK_ERANGE, "ftk_set_shifts: shift outside the planned disk");
+    const double om = std::atan2(dy, dx);
+    const double x = kPi * rad;
+    for (int j = 0; j < P; ++j) {
+      ftkplan::bessel_orders(t.L, x * s0.yn[j], tmp.data());
+      for (int l = 0; l <= t.L; ++l) J[static_cast<size_t>(l) * P + j] = tmp[l];
+    }
+    for (int z = 0; z < t.H; ++z) {
+      const int la = std::abs(t.ell[z]);
+      const ftkplan::ModalSVD& s = t.tr.svds[la];
+      double acc = 0.0;
+      for (int j = 0; j < P; ++j) acc += std::sqrt(s.yw[j]) * J[static_cast<size_t>(la) * P + j] * s.V[j * P + t.eta[z]];
+      const double u = acc / s.sigma[t.eta[z]];
+      const double ph = -t.ell[z] * (om + 0.5 * kPi);
+      Y[static_cast<size_t>(d) * t.H + z] = std::complex<double>(u * std::cos(ph), u * std::sin(ph));
+    }
+  }
+  return FTK_OK;
+}
+
+}  // namespace
+
+// Events around kernel launches, per stage (see ftk_plan_profile).
+struct StageTimer {
+  static constexpr int kStages = 4;
+  bool on = false;
+  struct Rec {
+    hipEvent_t a, b;
+    int stage;
+  };
+  std::vector<Rec> recs;
+  std::vector<hipEvent_t> pool;
+  hipEvent_t get() {
+    if (!pool.empty()) {
+      hipEvent_t e = pool.back();
+      pool.pop_back();
+      return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+  }
+  hipEvent_t begin(hipStream_t s) {
+    if (!on) return nullptr;
+    hipEvent_t e = get();
+    if (e) (void)hipEventRecord(e, s);
+    return e;
+  }
+  void end(hipEvent_t a, hipStream_t s, int stage) {
+    if (!on || !a) return;
+    hipEvent_t b = get();
+    if (!b) return;
+    (void)hipEventRecord(b, s);
+    recs.push_back({a, b, stage});
+  }
+  void clear() {
+    for (auto& r : recs) {
+      pool.push_back(r.a);
+      pool.push_back(r.b);
+    }
+    recs.clear();
+  }
+  void destroy() {
+    clear();
+    for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+    pool.clear();
+  }
+};
+
+struct ftk_plan {
+  StageTimer timer;
+  int n = 0, M = 0, Qa = 0, precision = 0;
+  double W = 0, eps = 0, kmax = 0;
+  HostTables t;
+  int H_pad = 0, N = 0, N_pad = 0;
+  ftkplan::SpreadKernel sk;
+  // plan-owned device tables
+  DevBuf cz, ell, yt, tw_nf, tw_qa, deapod, ptbase, ptker;
+  // workspace
+  DevBuf ws_tr_h, ws_tr_g, ws_coef_a, ws_coef_b, ws_stage, ws_keys;
+  size_t device_bytes() const {
+    return cz.bytes + ell.bytes + yt.bytes + tw_nf.bytes + tw_qa.bytes + deapod.bytes + ptbase.bytes +
+           ptker.bytes + ws_tr_h.bytes + ws_tr_g.bytes + ws_coef_a.bytes + ws_coef_b.bytes + ws_stage.bytes +
+           ws_keys.bytes;
+  }
+  void release_all() {
+    for (DevBuf* b : {&cz, &ell, &yt, &tw_nf, &tw_qa, &deapod, &ptbase, &ptker, &ws_tr_h, &ws_tr_g, &ws_coef_a,
+                      &ws_coef_b, &ws_stage, &ws_keys})
+      b->release();
+  }
+};
+
+namespace {
+
+template <class T>
+hipError_t upload(DevBuf& b, const std::vector<T>& v) {
+  hipError_t e = b.ensure(v.size() * sizeof(T));
+  if (e != hipSuccess) return e;
+  return hipMemcpy(b.ptr, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice);
+}
+
+std::vector<float> twiddles(int L) {
+  std::vector<float> t(2 * L);
+  for (int k = 0; k < L; ++k) {
+    const double a = -2.0 * kPi * k / L;
+    t[2 * k] = static_cast<float>(std::cos(a));
+    t[2 * k + 1] = static_cast<float>(std::sin(a));
+  }
+  return t;
+}
+
+int upload_plan_tables(ftk_plan* p) {
+  const int M = p->M, H = p->t.H, Hp = p->H_pad;
+  std::vector<float> cz(static_cast<size_t>(Hp) * M, 0.f);
+  std::vector<int> ell(Hp, 0);
+  for (int z = 0; z < H; ++z) {
+    ell[z] = p->t.ell[z];
+    for (int m = 0; m < M; ++m)
+      cz[static_cast<size_t>(z) * M + m] = static_cast<float>(2.0 * kPi * p->t.w[m] * p->t.G[static_cast<size_t>(z) * M + m]);
+  }
+  // NUFFT: deapodisation with all scale factors, and per-point kernel weights
+  const int n = p->n, nf = p->sk.nf, w = p->sk.w, Qa = p->Qa, half = Qa / 2;
+  const double dx = 2.0 / n;
+  std::vector<float> dea(n);
+  const double scale = dx * p->sk.h / std::sqrt(static_cast<double>(Qa));
+  for (int i = 0; i < n; ++i) dea[i] = static_cast<float>(scale / p->sk.ft(i - n / 2));
+  std::vector<int> pb(static_cast<size_t>(M) * half * 2);
+  std::vector<float> pk(static_cast<size_t>(M) * half * 2 * w);
+  for (int m = 0; m < M; ++m)
+    for (int q = 0; q < half; ++q) {
+      const double psi = 2.0 * kPi * q / Qa;
+      const double t[2] = {p->t.k[m] * std::cos(psi) * dx, p->t.k[m] * std::sin(psi) * dx};
+      const size_t pt = static_cast<size_t>(m) * half + q;
+      for (int d = 0; d < 2; ++d) {
+        const double u = t[d] / p->sk.h;
+        const long base = static_cast<long>(std::floor(u)) - w / 2 + 1;
+        long bm = base % nf;
+        if (bm < 0) bm += nf;
+        pb[2 * pt + d] = static_cast<int>(bm);
+        for (int a = 0; a < w; ++a) {
+          const double z = (u - static_cast<double>(base + a)) / (0.5 * w);
+          double v = 0.0;
+          if (std::fabs(z) < 1.0) v = std::exp(p->sk.beta * (std::sqrt(1.0 - z * z) - 1.0));
+          pk[(pt * 2 + d) * w + a] = static_cast<float>(v);
+        }
+      }
+    }
+  hipError_t e;
+  if ((e = upload(p->cz, cz)) != hipSuccess) return hip_fail(e, "upload cz");
+  if ((e = upload(p->ell, ell)) != hipSuccess) return hip_fail(e, "upload ell");
+  if ((e = upload(p->tw_nf, twiddles(nf))) != hipSuccess) return hip_fail(e, "upload tw_nf");
+  if ((e = upload(p->tw_qa, twiddles(Qa))) != hipSuccess) return hip_fail(e, "upload tw_qa");
+  if ((e = upload(p->deapod, dea)) != hipSuccess) return hip_fail(e, "upload deapod");
+  if ((e = upload(p->ptbase, pb)) != hipSuccess) return hip_fail(e, "upload ptbase");
+  if ((e = upload(p->ptker, pk)) != hipSuccess) return hip_fail(e, "upload ptker");
+  return FTK_OK;
+}
+
+int check_plan_args(int n, int K, int Q, double W, double eps, int precision) {
+  if (n < 4 || n > 1024 || (n & 1)) return fail(FTK_EINVAL, "n must be even and in [4, 1024]");
+  if (K < 1 || K > 512) return fail(FTK_EINVAL, "K (radial nodes) must be in [1, 512]");
+  if (Q < 8 || Q > 4096 || (Q & 1)) return fail(FTK_EINVAL, "Q must be even and in [8, 4096]");
+  if (!(W > 0.0) || W > n / 4.0) return fail(FTK_EINVAL, "W (shift radius, px) must be in (0, n/4]");
+  if (!(eps > 0.0) || !(eps < 1.0)) return fail(FTK_EINVAL, "eps must be in (0, 1)");
+  if (precision != FTK_FP32 && precision != FTK_BF16X3) return fail(FTK_EINVAL, "unknown precision");
+  if (precision == FTK_BF16X3) return fail(FTK_EUNSUPPORTED, "bf16x3 kernels are not built yet");
+  if (!ftkplan::fft_supported(Q) || Q % 64 != 0 || Q > 384)
+    return fail(FTK_EUNSUPPORTED, "Q must be a multiple of 64 of the form 2^a 3^b, at most 384");
+  if (ftkplan::fft_size(2 * n) > 4096) return fail(FTK_EUNSUPPORTED, "image too large for the transform");
+  return FTK_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* ftk_strerror(int status) {
+  switch (status) {
+    case FTK_OK: return "FTK_OK";
+    case FTK_EINVAL: return "FTK_EINVAL: invalid argument";
+    case FTK_ENOMEM: return "FTK_ENOMEM: out of memory";
+    case FTK_EDEVICE: return "FTK_EDEVICE: HIP runtime error";
+    case FTK_ERANGE: return "FTK_ERANGE: shift outside the planned disk";
+    case FTK_ESTATE: return "FTK_ESTATE: call order violated";
+    case FTK_EUNSUPPORTED: return "FTK_EUNSUPPORTED: size not supported";
+    default: return "unknown ftk status";
+  }
+}
+
+const char* ftk_last_error_message(void) { return g_last_error.c_str(); }
+
+int ftk_plan_tables(int n, int K, double W, double eps, const double* shifts_px, int N, int* H_out, int32_t* ell,
+                    double* sigma, double* G, double* k, double* w, double* Y, double* sigma_next) {
+  if (n < 4 || K < 1 || K > 512 || !(W > 0) || !(eps > 0) || !(eps < 1) || N < 0 || (N > 0 && !shifts_px))
+    return fail(FTK_EINVAL, "ftk_plan_tables: invalid argument");
+  try {
+    HostTables t;
+    build_tables(n, K, W, eps, t);
+    if (H_out) *H_out = t.H;
+    if (sigma_next) *sigma_next = t.sigma_next;
+    for (int z = 0; z < t.H; ++z) {
+      if (ell) ell[z] = t.ell[z];
+      if (sigma) sigma[z] = t.sigma[z];
+    }
+    if (G) std::memcpy(G, t.G.data(), t.G.size() * sizeof(double));
+    if (k) std::memcpy(k, t.k.data(), K * sizeof(double));
+    if (w) std::memcpy(w, t.w.data(), K * sizeof(double));
+    if (Y && N > 0) {
+      std::vector<std::complex<double>> Yc;
+      int rc = build_Y(t, shifts_px, N, W, Yc);
+      if (rc != FTK_OK) return rc;
+      std::memcpy(Y, Yc.data(), Yc.size() * sizeof(std::complex<double>));
+    }
+  } catch (const std::bad_alloc&) {
+    return fail(FTK_ENOMEM, "ftk_plan_tables: host allocation failed");
+  } catch (const std::exception& ex) {
+    return fail(FTK_EINVAL, std::string("ftk_plan_tables: ") + ex.what());
+  }
+  return FTK_OK;
+}
+
+int ftk_plan_create(ftk_plan** out, int n, int K, int Q, double W, double eps, int precision) {
+  if (!out) return fail(FTK_EINVAL, "ftk_plan_create: out is NULL");
+  *out = nullptr;
+  int rc = check_plan_args(n, K, Q, W, eps, precision);
+  if (rc != FTK_OK) return rc;
+  ftk_plan* p = nullptr;
+  try {
+    p = new ftk_plan();
+    p->n = n;
+    p->M = K;
+    p->Qa = Q;
+    p->W = W;
+    p->eps = eps;
+    p->precision = precision;
+    p->kmax = 0.5 * kPi * n;
+    build_tables(n, K, W, eps, p->t);
+    p->H_pad = round_up(std::max(p->t.H, 1), 64);
+    p->sk = ftkplan::spread_kernel(n, kNufftWidth);
+  } catch (const std::bad_alloc&) {
+    delete p;
+    return fail(FTK_ENOMEM, "ftk_plan_create: host allocation failed");
+  } catch (const std::exception& ex) {
+    delete p;
+    return fail(FTK_EINVAL, std::string("ftk_plan_create: ") + ex.what());
+  }
+  rc = upload_plan_tables(p);
+  if (rc != FTK_OK) {
+    p->release_all();
+    delete p;
+    return rc;
+  }
+  *out = p;
+  return FTK_OK;
+}
+
+void ftk_plan_destroy(ftk_plan* p) {
+  if (!p) return;
+  p->timer.destroy();
+  p->release_all();
+  delete p;
+}
+
+int ftk_plan_info(const ftk_plan* p, ftk_plan_info_t* o) {
+  if (!p || !o) return fail(FTK_EINVAL, "ftk_plan_info: NULL argument");
+  o->n = p->n;
+  o->M = p->M;
+  o->Qa = p->Qa;
+  o->H = p->t.H;
+  o->L = p->t.L;
+  o->N = p->N;
+  o->precision = p->precision;
+  o->nufft_width = p->sk.w;
+  o->nufft_grid = p->sk.nf;
+  o->shift_radius_px = p->W;
+  o->eps = p->eps;
+  o->sigma_next = p->t.sigma_next;
+  o->kmax = p->kmax;
+  o->coeff_bytes_per_image = static_cast<size_t>(8) * p->M * p->Qa;
+  o->device_bytes = p->device_bytes();
+  return FTK_OK;
+}
+
+int ftk_set_shifts(ftk_plan* p, const double* shifts_px, int N) {
+  if (!p || !shifts_px) return fail(FTK_EINVAL, "ftk_set_shifts: NULL argument");
+  if (N < 1 || N > 65536) return fail(FTK_EINVAL, "ftk_set_shifts: N must be in [1, 65536]");
+  std::vector<std::complex<double>> Y;
+  try {
+    int rc = build_Y(p->t, shifts_px, N, p->W, Y);
+    if (rc != FTK_OK) return rc;
+  } catch (const std::bad_alloc&) {
+    return fail(FTK_ENOMEM, "ftk_set_shifts: host allocation failed");
+  }
+  const int H = p->t.H, Hp = p->H_pad;
+  const int Np = round_up(N, 16);
+  // real embedding of Y, transposed: yt[2 zeta + c'][2 delta + c]
+  std::vector<float> yt(static_cast<size_t>(2 * Hp) * 2 * Np, 0.f);
+  const size_t rs = static_cast<size_t>(2 * Np);
+  for (int d = 0; d < N; ++d)
+    for (int z = 0; z < H; ++z) {
+      const std::complex<double> y = Y[static_cast<size_t>(d) * H + z];
+      const float yr = static_cast<float>(y.real()), yi = static_cast<float>(y.imag());
+      yt[(2 * z + 0) * rs + 2 * d + 0] = yr;
+      yt[(2 * z + 1) * rs + 2 * d + 0] = -yi;
+      yt[(2 * z + 0) * rs + 2 * d + 1] = yi;
+      yt[(2 * z + 1) * rs + 2 * d + 1] = yr;
+    }
+  hipError_t e = upload(p->yt, yt);
+  if (e != hipSuccess) return hip_fail(e, "ftk_set_shifts: upload");
+  p->N = N;
+  p->N_pad = Np;
+  return FTK_OK;
+}
+
+int ftk_transform(ftk_plan* p, const float* imgs, int cnt, void* coeffs, void* stream) {
+  if (!p) return fail(FTK_EINVAL, "ftk_transform: NULL plan");
+  if (cnt < 0) return fail(FTK_EINVAL, "ftk_transform: cnt < 0");
+  if (cnt == 0) return FTK_OK;
+  if (!imgs || !coeffs) return fail(FTK_EINVAL, "ftk_transform: NULL buffer");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int n = p->n, nf = p->sk.nf;
+  const size_t per_img = (static_cast<size_t>(n) * nf + static_cast<size_t>(nf) * nf) * sizeof(float2);
+  const size_t budget = env_bytes("FTK_TRANSFORM_SCRATCH_MB", size_t(512) << 20);
+  int chunk = static_cast<int>(std::max<size_t>(1, budget / per_img));
+  chunk = std::min(chunk, cnt);
+  hipError_t e;
+  if ((e = p->ws_tr_h.ensure(static_cast<size_t>(chunk) * n * nf * sizeof(float2))) != hipSuccess)
+    return fail(FTK_ENOMEM, "ftk_transform: scratch");
+  if ((e = p->ws_tr_g.ensure(static_cast<size_t>(chunk) * nf * nf * sizeof(float2))) != hipSuccess)
+    return fail(FTK_ENOMEM, "ftk_transform: scratch");
+  if (transform_lds_bytes(nf, p->Qa, 4) > kLdsLimit) return fail(FTK_EUNSUPPORTED, "ftk_transform: LDS");
+  for (int c0 = 0; c0 < cnt; c0 += chunk) {
+    const int c = std::min(chunk, cnt - c0);
+    TransformArgs a;
+    a.imgs = imgs + static_cast<size_t>(c0) * n * n;
+    a.coeffs = static_cast<float2*>(coeffs) + static_cast<size_t>(c0) * p->Qa * p->M;
+    a.scratchH = p->ws_tr_h.as<float2>();
+    a.scratchG = p->ws_tr_g.as<float2>();
+    a.deapod = p->deapod.as<float>();
+    a.tw_nf = p->tw_nf.as<float2>();
+    a.tw_qa = p->tw_qa.as<float2>();
+    a.pt_base = p->ptbase.as<int>();
+    a.pt_ker = p->ptker.as<float>();
+    a.n = n;
+    a.nf = nf;
+    a.M = p->M;
+    a.Qa = p->Qa;
+    a.w = p->sk.w;
+    hipEvent_t ev = p->timer.begin(s);
+    if ((e = launch_transform(a, c, s)) != hipSuccess) return hip_fail(e, "ftk_transform: launch");
+    p->timer.end(ev, s, 0);
+  }
+  return FTK_OK;
+}
+
+int ftk_align_coeffs(ftk_plan* p, const void* img_coeffs, int nA, const void* tmpl_coeffs, int nB, float* X,
+                     ftk_pose* best, void* stream) {
+  if (!p) return fail(FTK_EINVAL, "ftk_align_coeffs: NULL plan");
+  if (nA < 0 || nB < 0) return fail(FTK_EINVAL, "ftk_align_coeffs: negative count");
+  if (p->N <= 0) return fail(FTK_ESTATE, "ftk_align_coeffs: call ftk_set_shifts first");
+  if (nA == 0 || nB == 0) return FTK_OK;
+  if (!X && !best) return fail(FTK_EINVAL, "ftk_align_coeffs: X and best are both NULL");
+  if (!img_coeffs || !tmpl_coeffs) return fail(FTK_EINVAL, "ftk_align_coeffs: NULL coefficients");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int QH = p->Qa / 2;
+  const size_t pairs = static_cast<size_t>(nA) * nB;
+  const size_t per_pair = static_cast<size_t>(QH) * 2 * p->H_pad * sizeof(float);
+  const size_t budget = env_bytes("FTK_STAGE_MB", size_t(512) << 20);
+  int chunkA = static_cast<int>(std::max<size_t>(1, budget / (per_pair * nB)));
+  chunkA = std::min(chunkA, nA);
+  hipError_t e;
+  if ((e = p->ws_stage.ensure(static_cast<size_t>(chunkA) * nB * per_pair)) != hipSuccess)
+    return fail(FTK_ENOMEM, "ftk_align: staging buffer");
+  if ((e = p->ws_keys.ensure(pairs * sizeof(unsigned long long))) != hipSuccess)
+    return fail(FTK_ENOMEM, "ftk_align: key buffer");
+  unsigned long long* keys = p->ws_keys.as<unsigned long long>();
+  hipEvent_t ev = p->timer.begin(s);
+  if ((e = launch_keys_init(keys, pairs, s)) != hipSuccess) return hip_fail(e, "ftk_align: keys init");
+  p->timer.end(ev, s, 3);
+
+  Step1Args a1{};
+  a1.cz = p->cz.as<float>();
+  a1.ell = p->ell.as<int>();
+  a1.zs = p->ws_stage.as<float>();
+  a1.b = static_cast<const float2*>(tmpl_coeffs);
+  a1.nB = nB;
+  a1.M = p->M;
+  a1.Qa = p->Qa;
+  a1.H_pad = p->H_pad;
+  a1.L = p->t.L;
+  a1.zblk = (p->H_pad % 128 == 0) ? 128 : 64;
+  a1.tb = (nB >= 48) ? 64 : 32;
+  a1.qblk = 8;
+  if (step1_lds_bytes(a1) > kLdsLimit) {
+    a1.zblk = 64;
+    if (step1_lds_bytes(a1) > kLdsLimit) a1.tb = 32;
+    if (step1_lds_bytes(a1) > kLdsLimit) return fail(FTK_EUNSUPPORTED, "ftk_align: step 1 tiles exceed LDS");
+  }
+  Step3Args a3{};
+  a3.yt = p->yt.as<float>();
+  a3.tw_qa = p->tw_qa.as<float2>();
+  a3.Qa = p->Qa;
+  a3.H_pad = p->H_pad;
+  a3.N = p->N;
+  a3.N_pad = p->N_pad;
+  {
+    const int units = (p->N + 15) / 16;
+    int maxw = (p->Qa / 64 > 4) ? 8 : 16;
+    while (maxw > 1 && step3_lds_bytes(p->Qa, maxw) > kLdsLimit) --maxw;
+    const int nblk = (units + maxw - 1) / maxw;
+    a3.nwaves = (units + nblk - 1) / nblk;
+  }
+  for (int A0 = 0; A0 < nA; A0 += chunkA) {
+    const int na = std::min(chunkA, nA - A0);
+    a1.a = static_cast<const float2*>(img_coeffs) + static_cast<size_t>(A0) * p->Qa * p->M;
+    a1.nA = na;
+    ev = p->timer.begin(s);
+    if ((e = launch_step1(a1, p->precision, s)) != hipSuccess) return hip_fail(e, "ftk_align: step 1");
+    p->timer.end(ev, s, 1);
+    a3.zs = p->ws_stage.as<float>();
+    a3.pairs = na * nB;
+    a3.keys = keys + static_cast<size_t>(A0) * nB;
+    a3.X = X ? X + static_cast<size_t>(A0) * nB * p->N * p->Qa : nullptr;
+    ev = p->timer.begin(s);
+    if ((e = launch_step3(a3, p->precision, s)) != hipSuccess) return hip_fail(e, "ftk_align: step 3");
+    p->timer.end(ev, s, 2);
+  }
+  if (best) {
+    ev = p->timer.begin(s);
+    if ((e = launch_keys_to_poses(keys, best, pairs, p->Qa, s)) != hipSuccess)
+      return hip_fail(e, "ftk_align: poses");
+    p->timer.end(ev, s, 3);
+  }
+  return FTK_OK;
+}
+
+int ftk_align(ftk_plan* p, const float* images, int nA, const float* templates, int nB, float* X, ftk_pose* best,
+              void* stream) {
+  if (!p) return fail(FTK_EINVAL, "ftk_align: NULL plan");
+  if (nA < 0 || nB < 0) return fail(FTK_EINVAL, "ftk_align: negative count");
+  if (p->N <= 0) return fail(FTK_ESTATE, "ftk_align: call ftk_set_shifts first");
+  if (nA == 0 || nB == 0) return FTK_OK;
+  if (!X && !best) return fail(FTK_EINVAL, "ftk_align: X and best are both NULL");
+  if (!images || !templates) return fail(FTK_EINVAL, "ftk_align: NULL images");
+  const size_t cb = static_cast<size_t>(8) * p->M * p->Qa;
+  hipError_t e;
+  if ((e = p->ws_coef_a.ensure(cb * nA)) != hipSuccess) return fail(FTK_ENOMEM, "ftk_align: coefficients");
+  if ((e = p->ws_coef_b.ensure(cb * nB)) != hipSuccess) return fail(FTK_ENOMEM, "ftk_align: coefficients");
+  int rc = ftk_transform(p, images, nA, p->ws_coef_a.ptr, stream);
+  if (rc != FTK_OK) return rc;
+  rc = ftk_transform(p, templates, nB, p->ws_coef_b.ptr, stream);
+  if (rc != FTK_OK) return rc;
+  return ftk_align_coeffs(p, p->ws_coef_a.ptr, nA, p->ws_coef_b.ptr, nB, X, best, stream);
+}
+
+int ftk_plan_profile(ftk_plan* p, int enable) {
+  if (!p) return fail(FTK_EINVAL, "ftk_plan_profile: NULL plan");
+  p->timer.clear();
+  p->timer.on = enable != 0;
+  return FTK_OK;
+}
+
+int ftk_plan_stage_times(ftk_plan* p, double* ms, int64_t* launches, int nstages) {
+  if (!p || nstages < 0) return fail(FTK_EINVAL, "ftk_plan_stage_times: invalid argument");
+  for (int i = 0; i < nstages; ++i) {
+    if (ms) ms[i] = 0.0;
+    if (launches) launches[i] = 0;
+  }
+  int rc = FTK_OK;
+  for (const auto& r : p->timer.recs) {
+    hipError_t e = hipEventSynchronize(r.b);
+    float t = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&t, r.a, r.b);
+    if (e != hipSuccess) {
+      rc = hip_fail(e, "ftk_plan_stage_times");
+      break;
+    }
+    if (r.stage < nstages) {
+      if (ms) ms[r.stage] += t;
+      if (launches) launches[r.stage] += 1;
+    }
+  }
+  p->timer.clear();
+  return rc;
+}
+
+}  // extern "C"

@@ -1,0 +1,393 @@
+// The pair-wise FTK contractions on MFMA (gfx950), FP32 form.
+//
+// Step 1 (eq. fbk3): for one image A and a block of templates B at a fixed
+// mode q,
+//     Zhat[B][zeta] = sum_m conj b_B(k_m; q) * P[zeta][m],
+//     P[zeta][m]    = 2 pi w_m G_zeta(k_m) a_A(k_m; q - l_zeta mod Qa),
+// written as a real GEMM with K = 2M (re/im of b) and 2 H columns
+// (re/im of Zhat): rows = templates, columns = (zeta, re|im).  The image
+// operand P is built on the fly in registers from an LDS window of the
+// image's mode rows q - l, l = -L..L, and the LDS table of 2 pi w G.
+// Only q = 0..Qa/2 is needed (Hermitian symmetry of a real inner
+// product); the Nyquist mode is packed into q = 0 as Zhat(0) + i Zhat(Qa/2).
+// The result is staged in HBM as [pair][q][zeta] (complex interleaved).
+//
+// Step 3 + Step 2: per pair,
+//     Xhat[delta][q] = sum_zeta Y[delta][zeta] Zhat[zeta][q]
+// as a real GEMM (rows = (delta, re|im), K = (zeta, re|im), columns = q)
+// with the shift panel read from L2 and Zhat staged in LDS; then for every
+// shift the real rotation sum X[delta][r] = sum_q Xhat e^{-2 pi i q r / Qa}
+// as a half-length complex FFT (real-output packing), and the argmax over
+// (delta, r) reduced with wave shuffles and a 64-bit atomicMax per pair.
+#include "device_common.h"
+#include "kernels.h"
+
+using namespace ftkdev;
+
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+namespace {
+
+__device__ __forceinline__ f32x16 zero16() {
+  f32x16 z;
+#pragma unroll
+  for (int i = 0; i < 16; ++i) z[i] = 0.f;
+  return z;
+}
+
+// ---------------------------------------------------------------- Step 1
+
+template <int RT, int CPW>
+__global__ void __launch_bounds__(256) step1_fp32(Step1Args p) {
+  extern __shared__ float smem[];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  constexpr int TB = 32 * RT;
+  const int M = p.M, Qa = p.Qa, L = p.L, QH = Qa / 2;
+  const int nzb = p.H_pad / p.zblk;
+  const int bblk = blockIdx.x / nzb;
+  const int zb = blockIdx.x - bblk * nzb;
+  const int b0 = bblk * TB;
+  const int z0 = zb * p.zblk;
+  const int A = blockIdx.z;
+  const int RS = TB + 1;
+  float* Rt = smem;                                   // [2M][RS]
+  float* czs = Rt + 2 * M * RS;                       // [zblk][M]
+  int* ellz = reinterpret_cast<int*>(czs + p.zblk * M);  // [zblk]
+  float2* win = reinterpret_cast<float2*>(ellz + ((p.zblk + 1) & ~1));  // [2L+1][M]
+
+  for (int i = tid; i < p.zblk * M; i += 256) czs[i] = p.cz[static_cast<size_t>(z0) * M + i];
+  for (int i = tid; i < p.zblk; i += 256) ellz[i] = p.ell[z0 + i];
+
+  const int r = lane >> 5;
+  const int c32 = lane & 31;
+  int zl[CPW], cc[CPW];
+#pragma unroll
+  for (int ct = 0; ct < CPW; ++ct) {
+    const int j = (wave * CPW + ct) * 32 + c32;
+    zl[ct] = j >> 1;
+    cc[ct] = j & 1;
+  }
+  const float2* abase = p.a + static_cast<size_t>(A) * Qa * M;
+  const int nwin = 2 * L + 1;
+
+  f32x16 acc[RT][CPW];
+
+  auto gemm_q = [&](int q) {
+    __syncthreads();
+    for (int i = tid; i < TB * M; i += 256) {
+      const int B = i / M;
+      const int m = i - B * M;
+      float2 v = make_float2(0.f, 0.f);
+      if (b0 + B < p.nB) v = p.b[(static_cast<size_t>(b0 + B) * Qa + q) * M + m];
+      Rt[(2 * m) * RS + B] = v.x;
+      Rt[(2 * m + 1) * RS + B] = v.y;
+    }
+    for (int i = tid; i < nwin * M; i += 256) {
+      const int li = i / M;
+      const int m = i - li * M;
+      int row = q - (li - L);
+      row %= Qa;
+      row += (row < 0) ? Qa : 0;
+      win[i] = abase[static_cast<size_t>(row) * M + m];
+    }
+    __syncthreads();
+    const float2* wrow[CPW];
+    const float* crow[CPW];
+#pragma unroll
+    for (int ct = 0; ct < CPW; ++ct) {
+      wrow[ct] = win + (ellz[zl[ct]] + L) * M;
+      crow[ct] = czs + zl[ct] * M;
+    }
+    for (int m = 0; m < M; ++m) {
+      float av[RT], bv[CPW];
+#pragma unroll
+      for (int rt = 0; rt < RT; ++rt) av[rt] = Rt[(2 * m + r) * RS + rt * 32 + c32];
+#pragma unroll
+      for (int ct = 0; ct < CPW; ++ct) {
+        const float2 wv = wrow[ct][m];
+        const float cm = crow[ct][m];
+        const float pr = cm * wv.x, pi = cm * wv.y;
+        bv[ct] = (r == cc[ct]) ? (r ? -pr : pr) : pi;
+      }
+#pragma unroll
+      for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+        for (int ct = 0; ct < CPW; ++ct)
+          acc[rt][ct] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[rt], bv[ct], acc[rt][ct], 0, 0, 0);
+    }
+  };
+
+  const int twoH = 2 * p.H_pad;
+  float* zbase = p.zs + static_cast<size_t>(A) * p.nB * QH * twoH;
+  const int q_begin = blockIdx.y * p.qblk;
+  const int q_end = min(QH, q_begin + p.qblk);
+  for (int qq = q_begin; qq < q_end; ++qq) {
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+      for (int ct = 0; ct < CPW; ++ct) acc[rt][ct] = zero16();
+    if (qq == 0) {
+      // Nyquist mode first; fold it into the accumulator as i * Zhat(Qa/2)
+      gemm_q(QH);
+#pragma unroll
+      for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+        for (int ct = 0; ct < CPW; ++ct)
+#pragma unroll
+          for (int i = 0; i < 16; ++i) {
+            const float other = __shfl_xor(acc[rt][ct][i], 1);
+            acc[rt][ct][i] = cc[ct] ? other : -other;
+          }
+    }
+    gemm_q(qq);
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+      for (int ct = 0; ct < CPW; ++ct) {
+        const int col = 2 * z0 + (wave * CPW + ct) * 32 + c32;
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+          const int row = 8 * (i >> 2) + 4 * r + (i & 3);
+          const int B = b0 + rt * 32 + row;
+          if (B < p.nB) zbase[(static_cast<size_t>(B) * QH + qq) * twoH + col] = acc[rt][ct][i];
+        }
+      }
+  }
+}
+
+// ---------------------------------------------------------------- Step 3
+
+__device__ __forceinline__ void better(float& bv, uint32_t& bi, float v, uint32_t i) {
+  if (v > bv || (v == bv && i < bi)) {
+    bv = v;
+    bi = i;
+  }
+}
+
+template <int CTQ>
+__device__ __forceinline__ void step3_epilogue(const Step3Args& p, f32x16 (&acc)[CTQ], int pair, int d0,
+                                               float2* fb, int lane) {
+  constexpr int QH = 32 * CTQ;
+  const int Qa = 2 * QH;
+  const int r = lane >> 5;
+  const int c32 = lane & 31;
+  float2* fb2 = fb + 4 * QH;
+  float bv = -__builtin_inff();
+  uint32_t bi = 0xffffffffu;
+  float* Xp = p.X ? p.X + static_cast<size_t>(pair) * p.N * Qa : nullptr;
+#pragma unroll
+  for (int g = 0; g < 4; ++g) {
+#pragma unroll
+    for (int ct = 0; ct < CTQ; ++ct)
+#pragma unroll
+      for (int d = 0; d < 2; ++d)
+        fb[(2 * r + d) * QH + ct * 32 + c32] = make_float2(acc[ct][4 * g + 2 * d], acc[ct][4 * g + 2 * d + 1]);
+    wave_sync();
+    for (int t = lane; t < 4 * QH; t += 64) {
+      const int row = t / QH;
+      const int k = t - row * QH;
+      const float2 P = fb[t];
+      float2 Z;
+      if (k == 0) {
+        Z = make_float2(P.x + P.y, P.x - P.y);
+      } else {
+        const float2 Qc = cconj(fb[row * QH + QH - k]);
+        const float2 s = cadd(P, Qc);
+        const float2 u = cmul(csub(P, Qc), p.tw_qa[k]);
+        Z = make_float2(s.x - u.y, s.y + u.x);
+      }
+      fb2[t] = Z;
+    }
+    wave_sync();
+    float2* res = fft_batched<false>(fb2, fb, QH, 4, p.tw_qa, 2, lane, 64, WaveSync());
+    for (int t = lane; t < 4 * QH; t += 64) {
+      const int row = t / QH;
+      const int s = t - row * QH;
+      const int delta = d0 + 4 * g + row;
+      if (delta < p.N) {
+        const float2 z = res[t];
+        const uint32_t idx = static_cast<uint32_t>(delta) * Qa + 2 * s;
+        better(bv, bi, z.x, idx);
+        better(bv, bi, z.y, idx + 1);
+        if (Xp) reinterpret_cast<float2*>(Xp + static_cast<size_t>(delta) * Qa)[s] = z;
+      }
+    }
+    wave_sync();
+  }
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+    const float ov = __shfl_xor(bv, off);
+    const uint32_t oi = static_cast<uint32_t>(__shfl_xor(static_cast<int>(bi), off));
+    better(bv, bi, ov, oi);
+  }
+  if (lane == 0 && bi != 0xffffffffu) atomicMax(p.keys + pair, pose_key(bv, bi));
+}
+
+template <int CTQ, int MAXT>
+__global__ void __launch_bounds__(MAXT) step3_fp32(Step3Args p) {
+  extern __shared__ float smem[];
+  constexpr int QH = 32 * CTQ;
+  constexpr int ZS = (QH % 64 == 0) ? QH + 32 : QH;  // row stride: ZS % 64 == 32
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int pair = blockIdx.x;
+  const int d0 = (blockIdx.y * p.nwaves + wave) * 16;
+  const int r = lane >> 5;
+  const int c32 = lane & 31;
+  const int nk = 2 * p.H_pad;
+  const int ystride = 2 * p.N_pad;
+  const float* zsp = p.zs + static_cast<size_t>(pair) * QH * nk;
+  float* zt = smem;  // [32][ZS]
+  f32x16 acc[CTQ];
+#pragma unroll
+  for (int ct = 0; ct < CTQ; ++ct) acc[ct] = zero16();
+  const bool active = d0 < p.N;
+  for (int kc = 0; kc < nk; kc += 32) {
+    __syncthreads();
+    for (int t = tid; t < QH * 8; t += blockDim.x) {
+      const int qq = t >> 3;
+      const int k4 = (t & 7) * 4;
+      const float4 v = *reinterpret_cast<const float4*>(zsp + static_cast<size_t>(qq) * nk + kc + k4);
+      zt[(k4 + 0) * ZS + qq] = v.x;
+      zt[(k4 + 1) * ZS + qq] = v.y;
+      zt[(k4 + 2) * ZS + qq] = v.z;
+      zt[(k4 + 3) * ZS + qq] = v.w;
+    }
+    __syncthreads();
+    if (active) {
+      float av[16];
+#pragma unroll
+      for (int z = 0; z < 16; ++z)
+        av[z] = p.yt[static_cast<size_t>(kc + 2 * z + r) * ystride + 2 * d0 + c32];
+#pragma unroll
+      for (int z = 0; z < 16; ++z)
+#pragma unroll
+        for (int ct = 0; ct < CTQ; ++ct) {
+          const float b = zt[(2 * z + r) * ZS + ct * 32 + c32];
+          acc[ct] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[z], b, acc[ct], 0, 0, 0);
+        }
+    }
+  }
+  __syncthreads();
+  if (!active) return;
+  float2* fb = reinterpret_cast<float2*>(smem) + wave * 8 * QH;
+  step3_epilogue<CTQ>(p, acc, pair, d0, fb, lane);
+}
+
+__global__ void keys_init_kernel(unsigned long long* keys, size_t count) {
+  size_t i = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < count) keys[i] = 0ull;
+}
+
+struct PoseOut {
+  float value;
+  int32_t shift;
+  int32_t rot;
+};
+
+__global__ void keys_to_poses_kernel(const unsigned long long* keys, PoseOut* poses, size_t count, int Qa) {
+  size_t i = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  const unsigned long long k = keys[i];
+  PoseOut o;
+  if (k == 0ull) {
+    o.value = __builtin_nanf("");
+    o.shift = -1;
+    o.rot = -1;
+  } else {
+    const uint32_t idx = key_index(k);
+    o.value = key_value(k);
+    o.shift = static_cast<int32_t>(idx / Qa);
+    o.rot = static_cast<int32_t>(idx % Qa);
+  }
+  poses[i] = o;
+}
+
+}  // namespace
+
+size_t step1_lds_bytes(const Step1Args& a) {
+  const int RS = a.tb + 1;
+  size_t bytes = sizeof(float) * (2 * a.M * RS + a.zblk * a.M) + sizeof(int) * ((a.zblk + 1) & ~1) +
+                 sizeof(float2) * (2 * a.L + 1) * a.M;
+  return bytes;
+}
+
+size_t step3_lds_bytes(int Qa, int nwaves) {
+  const int QH = Qa / 2;
+  const int ZS = (QH % 64 == 0) ? QH + 32 : QH;
+  size_t k = sizeof(float) * 32 * ZS;
+  size_t e = sizeof(float2) * static_cast<size_t>(nwaves) * 8 * QH;
+  return k > e ? k : e;
+}
+
+template <int RT, int CPW>
+static hipError_t launch_step1_t(const Step1Args& a, hipStream_t s) {
+  const int nzb = a.H_pad / a.zblk;
+  const int nbb = (a.nB + 32 * RT - 1) / (32 * RT);
+  const int QH = a.Qa / 2;
+  dim3 grid(nbb * nzb, (QH + a.qblk - 1) / a.qblk, a.nA);
+  size_t lds = step1_lds_bytes(a);
+  auto kern = step1_fp32<RT, CPW>;
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(kern, grid, dim3(256), lds, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_step1(const Step1Args& a, int precision, hipStream_t s) {
+  (void)precision;
+  if (a.nA <= 0 || a.nB <= 0) return hipSuccess;
+  const int cpw = a.zblk / 64;  // 2*zblk columns over 4 waves of 32-wide tiles
+  if (a.tb == 64) {
+    if (cpw == 1) return launch_step1_t<2, 1>(a, s);
+    if (cpw == 2) return launch_step1_t<2, 2>(a, s);
+  } else {
+    if (cpw == 1) return launch_step1_t<1, 1>(a, s);
+    if (cpw == 2) return launch_step1_t<1, 2>(a, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+template <int CTQ, int MAXT>
+static hipError_t launch_step3_t(const Step3Args& a, hipStream_t s) {
+  const int per_blk = 16 * a.nwaves;
+  dim3 grid(a.pairs, (a.N + per_blk - 1) / per_blk, 1);
+  size_t lds = step3_lds_bytes(a.Qa, a.nwaves);
+  auto kern = step3_fp32<CTQ, MAXT>;
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(kern, grid, dim3(64 * a.nwaves), lds, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_step3(const Step3Args& a, int precision, hipStream_t s) {
+  (void)precision;
+  if (a.pairs <= 0) return hipSuccess;
+  switch (a.Qa / 64) {
+    case 1: return launch_step3_t<1, 1024>(a, s);
+    case 2: return launch_step3_t<2, 1024>(a, s);
+    case 3: return launch_step3_t<3, 1024>(a, s);
+    case 4: return launch_step3_t<4, 1024>(a, s);
+    case 6: return launch_step3_t<6, 512>(a, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_keys_init(unsigned long long* keys, size_t count, hipStream_t s) {
+  if (count == 0) return hipSuccess;
+  hipLaunchKernelGGL(keys_init_kernel, dim3((count + 255) / 256), dim3(256), 0, s, keys, count);
+  return hipGetLastError();
+}
+
+hipError_t launch_keys_to_poses(const unsigned long long* keys, void* poses, size_t count, int Qa,
+                                hipStream_t s) {
+  if (count == 0) return hipSuccess;
+  hipLaunchKernelGGL(keys_to_poses_kernel, dim3((count + 255) / 256), dim3(256), 0, s, keys,
+                     static_cast<PoseOut*>(poses), count, Qa);
+  return hipGetLastError();
+}

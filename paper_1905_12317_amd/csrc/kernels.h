@@ -1,0 +1,60 @@
+// Internal interface between the C-ABI layer and the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+struct TransformArgs {
+  const float* imgs;     // [cnt][n][n]
+  float2* coeffs;        // [cnt][Qa][M]
+  float2* scratchH;      // [cnt][n][nf]
+  float2* scratchG;      // [cnt][nf][nf] (transposed: [l2][l1])
+  const float* deapod;   // [n] per-dimension deconvolution and scale
+  const float2* tw_nf;   // [nf] exp(-2 pi i k / nf)
+  const float2* tw_qa;   // [Qa] exp(-2 pi i k / Qa)
+  const int* pt_base;    // [M * Qa/2][2] first fine-grid index (mod nf) per dimension
+  const float* pt_ker;   // [M * Qa/2][2][w] spreading-kernel weights per dimension
+  int n, nf, M, Qa, w;
+};
+
+size_t transform_lds_bytes(int nf, int Qa, int nwaves);
+hipError_t launch_transform(const TransformArgs& args, int cnt, hipStream_t stream);
+
+// Step 1 (eq. fbk3): Zhat[pair][qq][zeta] for qq in [0, Qa/2), with the
+// Nyquist mode packed into qq = 0 as Zhat(0) + i Zhat(Qa/2).
+struct Step1Args {
+  const float2* a;       // image coefficients [nA][Qa][M] (chunk base)
+  const float2* b;       // template coefficients [nB][Qa][M]
+  const float* cz;       // [H_pad][M]: 2 pi w_m Sigma v(k_m), 0 on padding
+  const int* ell;        // [H_pad]: l_zeta, 0 on padding
+  float* zs;             // [nA][nB][Qa/2][2 H_pad] complex interleaved
+  // split-precision operands (bf16 hi/lo); unused by the FP32 kernel
+  const uint16_t* b_hi;  // [nB][Qa][2M] bf16 of (re, im) interleaved
+  const uint16_t* b_lo;
+  int nA, nB, M, Qa, H_pad, L;
+  int zblk;              // zeta per workgroup (multiple of 64)
+  int tb;                // templates per workgroup (32 or 64)
+  int qblk;              // q values per workgroup
+};
+
+// Step 3 + rotation FFT + argmax.
+struct Step3Args {
+  const float* zs;       // [pairs][Qa/2][2 H_pad]
+  const float* yt;       // [2 H_pad][2 N_pad] real embedding of Y, transposed
+  const uint16_t* yt_hi; // split-precision copies (bf16), same layout
+  const uint16_t* yt_lo;
+  float* X;              // [pairs][N][Qa] or nullptr
+  unsigned long long* keys;  // [pairs]
+  const float2* tw_qa;   // [Qa]
+  int pairs, Qa, H_pad, N, N_pad;
+  int nwaves;            // waves per workgroup; each wave owns 16 shifts
+};
+
+size_t step1_lds_bytes(const Step1Args& a);
+size_t step3_lds_bytes(int Qa, int nwaves);
+hipError_t launch_step1(const Step1Args& args, int precision, hipStream_t stream);
+hipError_t launch_step3(const Step3Args& args, int precision, hipStream_t stream);
+hipError_t launch_keys_init(unsigned long long* keys, size_t count, hipStream_t stream);
+hipError_t launch_keys_to_poses(const unsigned long long* keys, void* poses, size_t count, int Qa,
+                                hipStream_t stream);

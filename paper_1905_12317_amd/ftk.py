@@ -1,0 +1,226 @@
+"""Thin Python binding of libftk.so (argument marshalling only).
+
+Every computation runs in the HIP library; this module only converts
+Python/torch arguments to the C-ABI's plain pointers, sizes and streams.
+Device buffers are torch CUDA (HIP) tensors; streams default to torch's
+current stream.  If the library is not built, importing the binding's
+functions raises: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libftk.so")
+
+FTK_OK = 0
+FTK_FP32 = 0
+FTK_BF16X3 = 1
+PRECISIONS = {"fp32": FTK_FP32, "bf16x3": FTK_BF16X3}
+
+
+class FTKError(RuntimeError):
+    def __init__(self, code: int, where: str, detail: str):
+        super().__init__(f"{where}: {detail} (status {code})")
+        self.code = code
+
+
+class PlanInfo(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int), ("M", ctypes.c_int), ("Qa", ctypes.c_int), ("H", ctypes.c_int),
+                ("L", ctypes.c_int), ("N", ctypes.c_int), ("precision", ctypes.c_int),
+                ("nufft_width", ctypes.c_int), ("nufft_grid", ctypes.c_int),
+                ("shift_radius_px", ctypes.c_double), ("eps", ctypes.c_double),
+                ("sigma_next", ctypes.c_double), ("kmax", ctypes.c_double),
+                ("coeff_bytes_per_image", ctypes.c_size_t), ("device_bytes", ctypes.c_size_t)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+POSE_DTYPE = np.dtype([("value", np.float32), ("shift", np.int32), ("rot", np.int32)])
+
+#: every symbol include/ftk.h declares
+EXPORTS = ["ftk_plan_create", "ftk_plan_destroy", "ftk_plan_info", "ftk_set_shifts", "ftk_transform",
+           "ftk_align_coeffs", "ftk_align", "ftk_plan_tables", "ftk_plan_profile", "ftk_plan_stage_times",
+           "ftk_strerror", "ftk_last_error_message"]
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load libftk.so once; raise if it is not built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run paper_1905_12317_amd.build.build()")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i, d = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
+    L.ftk_plan_create.argtypes = [ctypes.POINTER(vp), i, i, i, d, d, i]
+    L.ftk_plan_destroy.argtypes = [vp]
+    L.ftk_plan_destroy.restype = None
+    L.ftk_plan_info.argtypes = [vp, ctypes.POINTER(PlanInfo)]
+    L.ftk_set_shifts.argtypes = [vp, vp, i]
+    L.ftk_transform.argtypes = [vp, vp, i, vp, vp]
+    L.ftk_align_coeffs.argtypes = [vp, vp, i, vp, i, vp, vp, vp]
+    L.ftk_align.argtypes = [vp, vp, i, vp, i, vp, vp, vp]
+    L.ftk_plan_tables.argtypes = [i, i, d, d, vp, i, ctypes.POINTER(i), vp, vp, vp, vp, vp, vp,
+                                  ctypes.POINTER(d)]
+    L.ftk_plan_profile.argtypes = [vp, i]
+    L.ftk_plan_stage_times.argtypes = [vp, vp, vp, i]
+    L.ftk_strerror.restype = ctypes.c_char_p
+    L.ftk_strerror.argtypes = [i]
+    L.ftk_last_error_message.restype = ctypes.c_char_p
+    L.ftk_last_error_message.argtypes = []
+    _lib = L
+    return L
+
+
+def _check(rc: int, where: str):
+    if rc != FTK_OK:
+        L = lib()
+        raise FTKError(rc, where, L.ftk_last_error_message().decode() or L.ftk_strerror(rc).decode())
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return ctypes.c_void_p(stream)
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _require_cuda(t, dtype, name):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
+def ftk_plan_tables(n: int, K: int, W: float, eps: float, shifts_px=None):
+    """Host-only FP64 tables of the planner (no device work)."""
+    L = lib()
+    H = ctypes.c_int(0)
+    sn = ctypes.c_double(0)
+    _check(L.ftk_plan_tables(n, K, W, eps, None, 0, ctypes.byref(H), None, None, None, None, None, None,
+                             ctypes.byref(sn)), "ftk_plan_tables")
+    H = H.value
+    ell = np.zeros(H, np.int32)
+    sig = np.zeros(H)
+    G = np.zeros((H, K))
+    k = np.zeros(K)
+    w = np.zeros(K)
+    N = 0
+    Y = None
+    sh = None
+    if shifts_px is not None:
+        sh = np.ascontiguousarray(shifts_px, dtype=np.float64).reshape(-1, 2)
+        N = sh.shape[0]
+        Y = np.zeros((N, H), np.complex128)
+    Hc = ctypes.c_int(0)
+    _check(L.ftk_plan_tables(n, K, W, eps, sh.ctypes.data if sh is not None else None, N, ctypes.byref(Hc),
+                             ell.ctypes.data, sig.ctypes.data, G.ctypes.data, k.ctypes.data, w.ctypes.data,
+                             Y.ctypes.data if Y is not None else None, ctypes.byref(sn)), "ftk_plan_tables")
+    return dict(H=H, ell=ell, sigma=sig, G=G, k=k, w=w, Y=Y, sigma_next=sn.value)
+
+
+class Plan:
+    """Owns an ftk_plan (ftk_plan_create / ftk_plan_destroy)."""
+
+    def __init__(self, n: int, K: int, Q: int, W: float, eps: float, precision="fp32"):
+        L = lib()
+        prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+        h = ctypes.c_void_p()
+        _check(L.ftk_plan_create(ctypes.byref(h), n, K, Q, W, eps, prec), "ftk_plan_create")
+        self._h = h
+        self.n, self.M, self.Qa = n, K, Q
+        self.N = 0
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().ftk_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def info(self) -> dict:
+        inf = PlanInfo()
+        _check(lib().ftk_plan_info(self._h, ctypes.byref(inf)), "ftk_plan_info")
+        return inf.as_dict()
+
+    STAGES = ("transform", "step1", "step3", "bookkeeping")
+
+    def profile(self, enable: bool = True):
+        _check(lib().ftk_plan_profile(self._h, 1 if enable else 0), "ftk_plan_profile")
+
+    def stage_times(self) -> dict:
+        """Per-stage (milliseconds, launches) since profile() or the last read."""
+        ms = np.zeros(len(self.STAGES))
+        cnt = np.zeros(len(self.STAGES), np.int64)
+        _check(lib().ftk_plan_stage_times(self._h, ms.ctypes.data, cnt.ctypes.data, len(self.STAGES)),
+               "ftk_plan_stage_times")
+        return {name: (float(ms[i]), int(cnt[i])) for i, name in enumerate(self.STAGES)}
+
+    def set_shifts(self, shifts_px):
+        sh = np.ascontiguousarray(shifts_px, dtype=np.float64).reshape(-1, 2)
+        _check(lib().ftk_set_shifts(self._h, sh.ctypes.data, sh.shape[0]), "ftk_set_shifts")
+        self.N = sh.shape[0]
+
+    def transform(self, imgs, coeffs=None, stream=None):
+        import torch
+        _require_cuda(imgs, torch.float32, "imgs")
+        cnt = imgs.shape[0]
+        if coeffs is None:
+            coeffs = torch.empty((cnt, self.Qa, self.M), dtype=torch.complex64, device=imgs.device)
+        _require_cuda(coeffs, torch.complex64, "coeffs")
+        _check(lib().ftk_transform(self._h, _ptr(imgs), cnt, _ptr(coeffs), _stream(stream)), "ftk_transform")
+        return coeffs
+
+    def _outputs(self, nA, nB, want_X, device, X, best):
+        import torch
+        if want_X and X is None:
+            X = torch.empty((nA, nB, self.N, self.Qa), dtype=torch.float32, device=device)
+        if best is None:
+            best = torch.empty((nA, nB, 3), dtype=torch.int32, device=device)
+        return X, best
+
+    def align_coeffs(self, a, b, want_X=False, X=None, best=None, stream=None):
+        import torch
+        _require_cuda(a, torch.complex64, "img_coeffs")
+        _require_cuda(b, torch.complex64, "tmpl_coeffs")
+        X, best = self._outputs(a.shape[0], b.shape[0], want_X, a.device, X, best)
+        _check(lib().ftk_align_coeffs(self._h, _ptr(a), a.shape[0], _ptr(b), b.shape[0], _ptr(X), _ptr(best),
+                                      _stream(stream)), "ftk_align_coeffs")
+        return X, best
+
+    def align(self, images, templates, want_X=False, X=None, best=None, stream=None):
+        import torch
+        _require_cuda(images, torch.float32, "images")
+        _require_cuda(templates, torch.float32, "templates")
+        X, best = self._outputs(images.shape[0], templates.shape[0], want_X, images.device, X, best)
+        _check(lib().ftk_align(self._h, _ptr(images), images.shape[0], _ptr(templates), templates.shape[0],
+                               _ptr(X), _ptr(best), _stream(stream)), "ftk_align")
+        return X, best
+
+
+def poses_numpy(best) -> np.ndarray:
+    """Device ftk_pose tensor [..., 3] (int32 view) -> structured numpy array."""
+    raw = best.detach().cpu().numpy().astype(np.int32, copy=False)
+    return raw.view(POSE_DTYPE).reshape(raw.shape[:-1])
