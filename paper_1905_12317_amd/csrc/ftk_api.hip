@@ -516,7 +516,7 @@ int ftk_align_coeffs(ftk_plan* p, const void* img_coeffs, int nA, const void* tm
   a1.L = p->t.L;
   a1.zblk = (p->H_pad % 128 == 0) ? 128 : 64;
   a1.tb = (nB >= 48) ? 64 : 32;
-  a1.qblk = 8;
+  a1.qblk = 16;
   if (step1_lds_bytes(a1) > kLdsLimit) {
     a1.zblk = 64;
     if (step1_lds_bytes(a1) > kLdsLimit) a1.tb = 32;

@@ -40,6 +40,7 @@ __device__ __forceinline__ f32x16 zero16() {
 template <int RT, int CPW>
 __global__ void __launch_bounds__(256) step1_fp32(Step1Args p) {
   extern __shared__ float smem[];
+  constexpr int MAXKR = 24;  // template-tile prefetch registers per thread
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
@@ -51,13 +52,55 @@ __global__ void __launch_bounds__(256) step1_fp32(Step1Args p) {
   const int b0 = bblk * TB;
   const int z0 = zb * p.zblk;
   const int A = blockIdx.z;
-  const int RS = TB + 1;
-  float* Rt = smem;                                   // [2M][RS]
-  float* czs = Rt + 2 * M * RS;                       // [zblk][M]
-  int* ellz = reinterpret_cast<int*>(czs + p.zblk * M);  // [zblk]
-  float2* win = reinterpret_cast<float2*>(ellz + ((p.zblk + 1) & ~1));  // [2L+1][M]
+  // LDS: two template tiles [2M][RS], 2 pi w G rows [zblk][MS], l per zeta,
+  // and a ring of image mode rows [WR][MS] (complex).  Row strides are odd
+  // so that the 16 distinct zeta rows a half-wave reads hit distinct banks.
+  const int RS = TB + 1, MS = M + 1, WR = 2 * L + 2;
+  float* czs = smem + 4 * M * RS;
+  int* ellz = reinterpret_cast<int*>(czs + p.zblk * MS);
+  float2* ring = reinterpret_cast<float2*>(ellz + ((p.zblk + 1) & ~1));
 
-  for (int i = tid; i < p.zblk * M; i += 256) czs[i] = p.cz[static_cast<size_t>(z0) * M + i];
+  const int nR = TB * M;
+  const int kr = (nR + 255) / 256;
+  const bool pref = kr <= MAXKR;
+  const float2* abase = p.a + static_cast<size_t>(A) * Qa * M;
+
+  auto r_elem = [&](int q, int i) -> float2 {
+    const int B = i / M;
+    const int m = i - B * M;
+    if (b0 + B < p.nB) return p.b[(static_cast<size_t>(b0 + B) * Qa + q) * M + m];
+    return make_float2(0.f, 0.f);
+  };
+  auto r_store = [&](int buf, int i, float2 v) {
+    const int B = i / M;
+    const int m = i - B * M;
+    float* R = smem + buf * (2 * M * RS);
+    R[(2 * m) * RS + B] = v.x;
+    R[(2 * m + 1) * RS + B] = v.y;
+  };
+  auto grow = [&](int r) -> const float2* {
+    r %= Qa;
+    r += (r < 0) ? Qa : 0;
+    return abase + static_cast<size_t>(r) * M;
+  };
+  auto slot = [&](int r) {
+    int sl = r % WR;
+    return sl + ((sl < 0) ? WR : 0);
+  };
+  auto load_window = [&](int q) {  // rows q-L .. q+L, between barriers
+    for (int i = tid; i < (2 * L + 1) * M; i += 256) {
+      const int li = i / M;
+      const int m = i - li * M;
+      const int r = q + L - li;
+      ring[slot(r) * MS + m] = grow(r)[m];
+    }
+  };
+
+  for (int i = tid; i < p.zblk * M; i += 256) {
+    const int z = i / M;
+    const int m = i - z * M;
+    czs[z * MS + m] = p.cz[static_cast<size_t>(z0 + z) * M + m];
+  }
   for (int i = tid; i < p.zblk; i += 256) ellz[i] = p.ell[z0 + i];
 
   const int r = lane >> 5;
@@ -69,68 +112,89 @@ __global__ void __launch_bounds__(256) step1_fp32(Step1Args p) {
     zl[ct] = j >> 1;
     cc[ct] = j & 1;
   }
-  const float2* abase = p.a + static_cast<size_t>(A) * Qa * M;
-  const int nwin = 2 * L + 1;
 
+  // the q values of this block; the block holding q = 0 first does the
+  // Nyquist mode Qa/2, which is folded into q = 0 as i * Zhat(Qa/2)
+  const int qb0 = blockIdx.y * p.qblk;
+  const int qb1 = min(QH, qb0 + p.qblk);
+  const bool with_nyq = (qb0 == 0);
+  const int nlist = (qb1 - qb0) + (with_nyq ? 1 : 0);
+  auto qat = [&](int t) { return with_nyq ? (t == 0 ? QH : t - 1) : qb0 + t; };
+
+  {
+    const int q = qat(0);
+    for (int i = tid; i < nR; i += 256) r_store(0, i, r_elem(q, i));
+    load_window(q);
+  }
+  __syncthreads();
+
+  const int twoH = 2 * p.H_pad;
+  float* zbase = p.zs + static_cast<size_t>(A) * p.nB * QH * twoH;
   f32x16 acc[RT][CPW];
+#pragma unroll
+  for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+    for (int ct = 0; ct < CPW; ++ct) acc[rt][ct] = zero16();
 
-  auto gemm_q = [&](int q) {
-    __syncthreads();
-    for (int i = tid; i < TB * M; i += 256) {
-      const int B = i / M;
-      const int m = i - B * M;
-      float2 v = make_float2(0.f, 0.f);
-      if (b0 + B < p.nB) v = p.b[(static_cast<size_t>(b0 + B) * Qa + q) * M + m];
-      Rt[(2 * m) * RS + B] = v.x;
-      Rt[(2 * m + 1) * RS + B] = v.y;
+  int cur = 0;
+  for (int t = 0; t < nlist; ++t) {
+    const int q = qat(t);
+    const int qn = (t + 1 < nlist) ? qat(t + 1) : -1;
+    const bool contig = (qn == q + 1);
+    float2 rreg[MAXKR];
+    float2 wreg[2];
+    if (qn >= 0 && pref) {
+#pragma unroll
+      for (int k = 0; k < MAXKR; ++k) {
+        const int i = tid + 256 * k;
+        if (k < kr && i < nR) rreg[k] = r_elem(qn, i);
+      }
     }
-    for (int i = tid; i < nwin * M; i += 256) {
-      const int li = i / M;
-      const int m = i - li * M;
-      int row = q - (li - L);
-      row %= Qa;
-      row += (row < 0) ? Qa : 0;
-      win[i] = abase[static_cast<size_t>(row) * M + m];
+    if (qn >= 0 && contig) {
+      const float2* g = grow(qn + L);
+#pragma unroll
+      for (int k = 0; k < 2; ++k) {
+        const int i = tid + 256 * k;
+        if (i < M) wreg[k] = g[i];
+      }
     }
-    __syncthreads();
-    const float2* wrow[CPW];
+    // LDS addresses are formed from the shared base (never through a pointer
+    // table) so that the compiler keeps them in the LDS address space
+    const float* R = smem + (cur ? 2 * M * RS : 0) + r * RS + c32;
+    // column (zeta, c) of lane half r takes Re P (r == c, negated when r = 1)
+    // or Im P (r != c): one component of the ring row times 2 pi w G
+    const float* wcomp[CPW];
     const float* crow[CPW];
+    float sgn[CPW];
 #pragma unroll
     for (int ct = 0; ct < CPW; ++ct) {
-      wrow[ct] = win + (ellz[zl[ct]] + L) * M;
-      crow[ct] = czs + zl[ct] * M;
+      const int comp = (r != cc[ct]) ? 1 : 0;
+      wcomp[ct] = reinterpret_cast<const float*>(ring + slot(q - ellz[zl[ct]]) * MS) + comp;
+      crow[ct] = czs + zl[ct] * MS;
+      sgn[ct] = (r == 1 && cc[ct] == 1) ? -1.f : 1.f;
     }
-    for (int m = 0; m < M; ++m) {
+    auto mstep = [&](int m) {
       float av[RT], bv[CPW];
 #pragma unroll
-      for (int rt = 0; rt < RT; ++rt) av[rt] = Rt[(2 * m + r) * RS + rt * 32 + c32];
+      for (int rt = 0; rt < RT; ++rt) av[rt] = R[2 * m * RS + rt * 32];
 #pragma unroll
-      for (int ct = 0; ct < CPW; ++ct) {
-        const float2 wv = wrow[ct][m];
-        const float cm = crow[ct][m];
-        const float pr = cm * wv.x, pi = cm * wv.y;
-        bv[ct] = (r == cc[ct]) ? (r ? -pr : pr) : pi;
-      }
+      for (int ct = 0; ct < CPW; ++ct) bv[ct] = (sgn[ct] * crow[ct][m]) * wcomp[ct][2 * m];
 #pragma unroll
       for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
         for (int ct = 0; ct < CPW; ++ct)
           acc[rt][ct] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[rt], bv[ct], acc[rt][ct], 0, 0, 0);
+    };
+    const int M4 = M & ~3;
+    for (int m = 0; m < M4; m += 4) {
+      mstep(m);
+      mstep(m + 1);
+      mstep(m + 2);
+      mstep(m + 3);
     }
-  };
-
-  const int twoH = 2 * p.H_pad;
-  float* zbase = p.zs + static_cast<size_t>(A) * p.nB * QH * twoH;
-  const int q_begin = blockIdx.y * p.qblk;
-  const int q_end = min(QH, q_begin + p.qblk);
-  for (int qq = q_begin; qq < q_end; ++qq) {
-#pragma unroll
-    for (int rt = 0; rt < RT; ++rt)
-#pragma unroll
-      for (int ct = 0; ct < CPW; ++ct) acc[rt][ct] = zero16();
-    if (qq == 0) {
-      // Nyquist mode first; fold it into the accumulator as i * Zhat(Qa/2)
-      gemm_q(QH);
+    for (int m = M4; m < M; ++m) mstep(m);
+    if (q == QH) {
+      // fold: the q = 0 result accumulates onto i * Zhat(Qa/2)
 #pragma unroll
       for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
@@ -140,20 +204,48 @@ __global__ void __launch_bounds__(256) step1_fp32(Step1Args p) {
             const float other = __shfl_xor(acc[rt][ct][i], 1);
             acc[rt][ct][i] = cc[ct] ? other : -other;
           }
+    } else {
+#pragma unroll
+      for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+        for (int ct = 0; ct < CPW; ++ct) {
+          const int col = 2 * z0 + (wave * CPW + ct) * 32 + c32;
+#pragma unroll
+          for (int i = 0; i < 16; ++i) {
+            const int row = 8 * (i >> 2) + 4 * r + (i & 3);
+            const int B = b0 + rt * 32 + row;
+            if (B < p.nB) zbase[(static_cast<size_t>(B) * QH + q) * twoH + col] = acc[rt][ct][i];
+          }
+          acc[rt][ct] = zero16();
+        }
     }
-    gemm_q(qq);
+    if (qn >= 0) {
+      // hand-over: the next template tile goes to the idle buffer and the
+      // next window row to ring slot (q+1+L) mod WR, which q does not read
+      if (pref) {
 #pragma unroll
-    for (int rt = 0; rt < RT; ++rt)
-#pragma unroll
-      for (int ct = 0; ct < CPW; ++ct) {
-        const int col = 2 * z0 + (wave * CPW + ct) * 32 + c32;
-#pragma unroll
-        for (int i = 0; i < 16; ++i) {
-          const int row = 8 * (i >> 2) + 4 * r + (i & 3);
-          const int B = b0 + rt * 32 + row;
-          if (B < p.nB) zbase[(static_cast<size_t>(B) * QH + qq) * twoH + col] = acc[rt][ct][i];
+        for (int k = 0; k < MAXKR; ++k) {
+          const int i = tid + 256 * k;
+          if (k < kr && i < nR) r_store(cur ^ 1, i, rreg[k]);
         }
       }
+      if (contig) {
+        float2* dst = ring + slot(qn + L) * MS;
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+          const int i = tid + 256 * k;
+          if (i < M) dst[i] = wreg[k];
+        }
+      }
+      __syncthreads();
+      if (!pref || !contig) {
+        if (!pref)
+          for (int i = tid; i < nR; i += 256) r_store(cur ^ 1, i, r_elem(qn, i));
+        if (!contig) load_window(qn);
+        __syncthreads();
+      }
+      cur ^= 1;
+    }
   }
 }
 
@@ -168,7 +260,7 @@ __device__ __forceinline__ void better(float& bv, uint32_t& bi, float v, uint32_
 
 template <int CTQ>
 __device__ __forceinline__ void step3_epilogue(const Step3Args& p, f32x16 (&acc)[CTQ], int pair, int d0,
-                                               float2* fb, int lane) {
+                                               float2* fb, const float2* tw, int lane) {
   constexpr int QH = 32 * CTQ;
   const int Qa = 2 * QH;
   const int r = lane >> 5;
@@ -195,13 +287,13 @@ __device__ __forceinline__ void step3_epilogue(const Step3Args& p, f32x16 (&acc)
       } else {
         const float2 Qc = cconj(fb[row * QH + QH - k]);
         const float2 s = cadd(P, Qc);
-        const float2 u = cmul(csub(P, Qc), p.tw_qa[k]);
+        const float2 u = cmul(csub(P, Qc), tw[k]);
         Z = make_float2(s.x - u.y, s.y + u.x);
       }
       fb2[t] = Z;
     }
     wave_sync();
-    float2* res = fft_batched<false>(fb2, fb, QH, 4, p.tw_qa, 2, lane, 64, WaveSync());
+    float2* res = fft_batched<false>(fb2, fb, QH, 4, tw, 2, lane, 64, WaveSync());
     for (int t = lane; t < 4 * QH; t += 64) {
       const int row = t / QH;
       const int s = t - row * QH;
@@ -240,41 +332,82 @@ __global__ void __launch_bounds__(MAXT) step3_fp32(Step3Args p) {
   const int nk = 2 * p.H_pad;
   const int ystride = 2 * p.N_pad;
   const float* zsp = p.zs + static_cast<size_t>(pair) * QH * nk;
-  float* zt = smem;  // [32][ZS]
+  // LDS: twiddles [Qa] (complex), then two staging buffers [32][ZS] for the
+  // K-chunks of Zhat, reused by the FFT epilogue once the K loop is done
+  float2* twl = reinterpret_cast<float2*>(smem);
+  float* region = smem + 2 * (2 * QH);
+  // staging buffer b is region + b * 32 * ZS (formed from the shared base)
+  const int nthr = blockDim.x;
+  for (int i = tid; i < 2 * QH; i += nthr) twl[i] = p.tw_qa[i];
+  constexpr int MAXF4 = 2;
+  const int nf4 = QH * 8;  // float4 per K-chunk
+  const int per = (nf4 + nthr - 1) / nthr;
+  const bool pref = per <= MAXF4;
+  auto fetch = [&](int kc, int t) {
+    const int qq = t >> 3;
+    const int k4 = (t & 7) * 4;
+    return *reinterpret_cast<const float4*>(zsp + static_cast<size_t>(qq) * nk + kc + k4);
+  };
+  auto put = [&](float* dst, int t, float4 v) {
+    const int qq = t >> 3;
+    const int k4 = (t & 7) * 4;
+    dst[(k4 + 0) * ZS + qq] = v.x;
+    dst[(k4 + 1) * ZS + qq] = v.y;
+    dst[(k4 + 2) * ZS + qq] = v.z;
+    dst[(k4 + 3) * ZS + qq] = v.w;
+  };
+  for (int t = tid; t < nf4; t += nthr) put(region, t, fetch(0, t));
+  __syncthreads();
   f32x16 acc[CTQ];
 #pragma unroll
   for (int ct = 0; ct < CTQ; ++ct) acc[ct] = zero16();
   const bool active = d0 < p.N;
+  int cur = 0;
   for (int kc = 0; kc < nk; kc += 32) {
-    __syncthreads();
-    for (int t = tid; t < QH * 8; t += blockDim.x) {
-      const int qq = t >> 3;
-      const int k4 = (t & 7) * 4;
-      const float4 v = *reinterpret_cast<const float4*>(zsp + static_cast<size_t>(qq) * nk + kc + k4);
-      zt[(k4 + 0) * ZS + qq] = v.x;
-      zt[(k4 + 1) * ZS + qq] = v.y;
-      zt[(k4 + 2) * ZS + qq] = v.z;
-      zt[(k4 + 3) * ZS + qq] = v.w;
+    const bool more = kc + 32 < nk;
+    float4 nreg[MAXF4];
+    if (more && pref) {
+#pragma unroll
+      for (int k = 0; k < MAXF4; ++k) {
+        const int t = tid + k * nthr;
+        if (k < per && t < nf4) nreg[k] = fetch(kc + 32, t);
+      }
     }
-    __syncthreads();
     if (active) {
-      float av[16];
+      const float* Z = region + cur * (32 * ZS) + r * ZS + c32;
 #pragma unroll
-      for (int z = 0; z < 16; ++z)
-        av[z] = p.yt[static_cast<size_t>(kc + 2 * z + r) * ystride + 2 * d0 + c32];
+      for (int half = 0; half < 2; ++half) {
+        float av[8];
 #pragma unroll
-      for (int z = 0; z < 16; ++z)
+        for (int z = 0; z < 8; ++z)
+          av[z] = p.yt[static_cast<size_t>(kc + 16 * half + 2 * z + r) * ystride + 2 * d0 + c32];
 #pragma unroll
-        for (int ct = 0; ct < CTQ; ++ct) {
-          const float b = zt[(2 * z + r) * ZS + ct * 32 + c32];
-          acc[ct] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[z], b, acc[ct], 0, 0, 0);
+        for (int z = 0; z < 8; ++z)
+#pragma unroll
+          for (int ct = 0; ct < CTQ; ++ct) {
+            const float b = Z[(16 * half + 2 * z) * ZS + ct * 32];
+            acc[ct] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[z], b, acc[ct], 0, 0, 0);
+          }
+      }
+    }
+    if (more) {
+      if (pref) {
+#pragma unroll
+        for (int k = 0; k < MAXF4; ++k) {
+          const int t = tid + k * nthr;
+          if (k < per && t < nf4) put(region + (cur ^ 1) * (32 * ZS), t, nreg[k]);
         }
+      } else {
+        for (int t = tid; t < nf4; t += nthr) put(region + (cur ^ 1) * (32 * ZS), t, fetch(kc + 32, t));
+      }
+      __syncthreads();
+      cur ^= 1;
     }
   }
   __syncthreads();
   if (!active) return;
-  float2* fb = reinterpret_cast<float2*>(smem) + wave * 8 * QH;
-  step3_epilogue<CTQ>(p, acc, pair, d0, fb, lane);
+  float2* fb = reinterpret_cast<float2*>(region) + wave * 8 * QH;
+  step3_epilogue<CTQ>(p, acc, pair, d0, fb, twl, lane);
 }
 
 __global__ void keys_init_kernel(unsigned long long* keys, size_t count) {
@@ -309,18 +442,17 @@ __global__ void keys_to_poses_kernel(const unsigned long long* keys, PoseOut* po
 }  // namespace
 
 size_t step1_lds_bytes(const Step1Args& a) {
-  const int RS = a.tb + 1;
-  size_t bytes = sizeof(float) * (2 * a.M * RS + a.zblk * a.M) + sizeof(int) * ((a.zblk + 1) & ~1) +
-                 sizeof(float2) * (2 * a.L + 1) * a.M;
-  return bytes;
+  const size_t RS = a.tb + 1, MS = a.M + 1, WR = 2 * a.L + 2;
+  return sizeof(float) * (4 * a.M * RS + a.zblk * MS) + sizeof(int) * ((a.zblk + 1) & ~1) +
+         sizeof(float2) * WR * MS;
 }
 
 size_t step3_lds_bytes(int Qa, int nwaves) {
   const int QH = Qa / 2;
   const int ZS = (QH % 64 == 0) ? QH + 32 : QH;
-  size_t k = sizeof(float) * 32 * ZS;
+  size_t k = sizeof(float) * 2 * 32 * ZS;
   size_t e = sizeof(float2) * static_cast<size_t>(nwaves) * 8 * QH;
-  return k > e ? k : e;
+  return sizeof(float2) * Qa + (k > e ? k : e);
 }
 
 template <int RT, int CPW>
