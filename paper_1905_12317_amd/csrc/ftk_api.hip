@@ -33,6 +33,22 @@ int hip_fail(hipError_t e, const char* where) {
 
 int round_up(int x, int m) { return (x + m - 1) / m * m; }
 
+// bf16 bits of a float, round to nearest even (NaN kept quiet)
+uint16_t bf16_rne(float f) {
+  uint32_t u;
+  std::memcpy(&u, &f, 4);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return 0x7fc0;
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return static_cast<uint16_t>(u >> 16);
+}
+
+double bf16_value(uint16_t h) {
+  const uint32_t u = static_cast<uint32_t>(h) << 16;
+  float f;
+  std::memcpy(&f, &u, 4);
+  return f;
+}
+
 size_t env_bytes(const char* name, size_t dflt) {
   const char* v = std::getenv(name);
   if (!v || !*v) return dflt;
@@ -201,17 +217,17 @@ struct ftk_plan {
   int H_pad = 0, N = 0, N_pad = 0;
   ftkplan::SpreadKernel sk;
   // plan-owned device tables
-  DevBuf cz, ell, yt, tw_nf, tw_qa, deapod, ptbase, ptker;
+  DevBuf cz, ell, yt, yt_hi, yt_lo, tw_nf, tw_qa, deapod, ptbase, ptker;
   // workspace
   DevBuf ws_tr_h, ws_tr_g, ws_coef_a, ws_coef_b, ws_stage, ws_keys;
   size_t device_bytes() const {
-    return cz.bytes + ell.bytes + yt.bytes + tw_nf.bytes + tw_qa.bytes + deapod.bytes + ptbase.bytes +
-           ptker.bytes + ws_tr_h.bytes + ws_tr_g.bytes + ws_coef_a.bytes + ws_coef_b.bytes + ws_stage.bytes +
-           ws_keys.bytes;
+    return cz.bytes + ell.bytes + yt.bytes + yt_hi.bytes + yt_lo.bytes + tw_nf.bytes + tw_qa.bytes +
+           deapod.bytes + ptbase.bytes + ptker.bytes + ws_tr_h.bytes + ws_tr_g.bytes + ws_coef_a.bytes +
+           ws_coef_b.bytes + ws_stage.bytes + ws_keys.bytes;
   }
   void release_all() {
-    for (DevBuf* b : {&cz, &ell, &yt, &tw_nf, &tw_qa, &deapod, &ptbase, &ptker, &ws_tr_h, &ws_tr_g, &ws_coef_a,
-                      &ws_coef_b, &ws_stage, &ws_keys})
+    for (DevBuf* b : {&cz, &ell, &yt, &yt_hi, &yt_lo, &tw_nf, &tw_qa, &deapod, &ptbase, &ptker, &ws_tr_h,
+                      &ws_tr_g, &ws_coef_a, &ws_coef_b, &ws_stage, &ws_keys})
       b->release();
   }
 };
@@ -289,7 +305,8 @@ int check_plan_args(int n, int K, int Q, double W, double eps, int precision) {
   if (!(W > 0.0) || W > n / 4.0) return fail(FTK_EINVAL, "W (shift radius, px) must be in (0, n/4]");
   if (!(eps > 0.0) || !(eps < 1.0)) return fail(FTK_EINVAL, "eps must be in (0, 1)");
   if (precision != FTK_FP32 && precision != FTK_BF16X3) return fail(FTK_EINVAL, "unknown precision");
-  if (precision == FTK_BF16X3) return fail(FTK_EUNSUPPORTED, "bf16x3 kernels are not built yet");
+  if (precision == FTK_BF16X3 && K % 8 != 0)
+    return fail(FTK_EUNSUPPORTED, "the bf16x3 form needs K (radial nodes) to be a multiple of 8");
   if (!ftkplan::fft_supported(Q) || Q % 64 != 0 || Q > 384)
     return fail(FTK_EUNSUPPORTED, "Q must be a multiple of 64 of the form 2^a 3^b, at most 384");
   if (ftkplan::fft_size(2 * n) > 4096) return fail(FTK_EUNSUPPORTED, "image too large for the transform");
@@ -433,6 +450,33 @@ int ftk_set_shifts(ftk_plan* p, const double* shifts_px, int N) {
     }
   hipError_t e = upload(p->yt, yt);
   if (e != hipSuccess) return hip_fail(e, "ftk_set_shifts: upload");
+  if (p->precision == FTK_BF16X3) {
+    // split hi/lo bf16 copies in MFMA lane order: [row tile][K step][lane][8],
+    // row tile = 32 embedded rows (16 shifts), K step = 16 embedded terms;
+    // lane l holds row l % 32 and k = 8 (l / 32) .. +7 of the step
+    const int nrt = 2 * Np / 32, nks = 2 * Hp / 16;
+    std::vector<uint16_t> hi(static_cast<size_t>(nrt) * nks * 512), lo(hi.size());
+    for (int rt = 0; rt < nrt; ++rt)
+      for (int ks = 0; ks < nks; ++ks)
+        for (int l = 0; l < 64; ++l)
+          for (int e8 = 0; e8 < 8; ++e8) {
+            const int row = rt * 32 + (l & 31);
+            const int k = ks * 16 + 8 * (l >> 5) + e8;
+            // the FP64 value of the embedded entry
+            double v = 0.0;
+            const int d = row >> 1, z = k >> 1;
+            if (d < N && z < H) {
+              const std::complex<double> y = Y[static_cast<size_t>(d) * H + z];
+              const int c = row & 1, cp = k & 1;
+              v = (c == cp) ? y.real() : (c == 0 ? -y.imag() : y.imag());
+            }
+            const size_t at = ((static_cast<size_t>(rt) * nks + ks) * 64 + l) * 8 + e8;
+            hi[at] = bf16_rne(static_cast<float>(v));
+            lo[at] = bf16_rne(static_cast<float>(v - bf16_value(hi[at])));
+          }
+    if ((e = upload(p->yt_hi, hi)) != hipSuccess) return hip_fail(e, "ftk_set_shifts: upload");
+    if ((e = upload(p->yt_lo, lo)) != hipSuccess) return hip_fail(e, "ftk_set_shifts: upload");
+  }
   p->N = N;
   p->N_pad = Np;
   return FTK_OK;
@@ -517,13 +561,17 @@ int ftk_align_coeffs(ftk_plan* p, const void* img_coeffs, int nA, const void* tm
   a1.zblk = (p->H_pad % 128 == 0) ? 128 : 64;
   a1.tb = (nB >= 48) ? 64 : 32;
   a1.qblk = 16;
-  if (step1_lds_bytes(a1) > kLdsLimit) {
+  const bool split = p->precision == FTK_BF16X3;
+  auto lds1 = [&]() { return split ? step1_bf16_lds_bytes(a1) : step1_lds_bytes(a1); };
+  if (lds1() > kLdsLimit) {
     a1.zblk = 64;
-    if (step1_lds_bytes(a1) > kLdsLimit) a1.tb = 32;
-    if (step1_lds_bytes(a1) > kLdsLimit) return fail(FTK_EUNSUPPORTED, "ftk_align: step 1 tiles exceed LDS");
+    if (lds1() > kLdsLimit) a1.tb = 32;
+    if (lds1() > kLdsLimit) return fail(FTK_EUNSUPPORTED, "ftk_align: step 1 tiles exceed LDS");
   }
   Step3Args a3{};
   a3.yt = p->yt.as<float>();
+  a3.yt_hi = p->yt_hi.as<uint16_t>();
+  a3.yt_lo = p->yt_lo.as<uint16_t>();
   a3.tw_qa = p->tw_qa.as<float2>();
   a3.Qa = p->Qa;
   a3.H_pad = p->H_pad;
@@ -532,7 +580,8 @@ int ftk_align_coeffs(ftk_plan* p, const void* img_coeffs, int nA, const void* tm
   {
     const int units = (p->N + 15) / 16;
     int maxw = (p->Qa / 64 > 4) ? 8 : 16;
-    while (maxw > 1 && step3_lds_bytes(p->Qa, maxw) > kLdsLimit) --maxw;
+    auto lds3 = [&](int w) { return split ? step3_bf16_lds_bytes(p->Qa, w) : step3_lds_bytes(p->Qa, w); };
+    while (maxw > 1 && lds3(maxw) > kLdsLimit) --maxw;
     const int nblk = (units + maxw - 1) / maxw;
     a3.nwaves = (units + nblk - 1) / nblk;
   }
@@ -541,14 +590,16 @@ int ftk_align_coeffs(ftk_plan* p, const void* img_coeffs, int nA, const void* tm
     a1.a = static_cast<const float2*>(img_coeffs) + static_cast<size_t>(A0) * p->Qa * p->M;
     a1.nA = na;
     ev = p->timer.begin(s);
-    if ((e = launch_step1(a1, p->precision, s)) != hipSuccess) return hip_fail(e, "ftk_align: step 1");
+    e = split ? launch_step1_bf16(a1, s) : launch_step1(a1, p->precision, s);
+    if (e != hipSuccess) return hip_fail(e, "ftk_align: step 1");
     p->timer.end(ev, s, 1);
     a3.zs = p->ws_stage.as<float>();
     a3.pairs = na * nB;
     a3.keys = keys + static_cast<size_t>(A0) * nB;
     a3.X = X ? X + static_cast<size_t>(A0) * nB * p->N * p->Qa : nullptr;
     ev = p->timer.begin(s);
-    if ((e = launch_step3(a3, p->precision, s)) != hipSuccess) return hip_fail(e, "ftk_align: step 3");
+    e = split ? launch_step3_bf16(a3, s) : launch_step3(a3, p->precision, s);
+    if (e != hipSuccess) return hip_fail(e, "ftk_align: step 3");
     p->timer.end(ev, s, 2);
   }
   if (best) {

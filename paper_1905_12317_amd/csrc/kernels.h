@@ -55,6 +55,12 @@ size_t step1_lds_bytes(const Step1Args& a);
 size_t step3_lds_bytes(int Qa, int nwaves);
 hipError_t launch_step1(const Step1Args& args, int precision, hipStream_t stream);
 hipError_t launch_step3(const Step3Args& args, int precision, hipStream_t stream);
+// split-bf16 forms of the two contractions (kern_align_bf16.hip)
+size_t step1_bf16_lds_bytes(const Step1Args& a);
+size_t step3_bf16_lds_bytes(int Qa, int nwaves);
+hipError_t launch_step1_bf16(const Step1Args& args, hipStream_t stream);
+hipError_t launch_step3_bf16(const Step3Args& args, hipStream_t stream);
+
 hipError_t launch_keys_init(unsigned long long* keys, size_t count, hipStream_t stream);
 hipError_t launch_keys_to_poses(const unsigned long long* keys, void* poses, size_t count, int Qa,
                                 hipStream_t stream);
