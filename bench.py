@@ -130,7 +130,20 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--form", default="all", choices=["fp32", "bf16x3", "all"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--calibrate-copy-mib", type=int, default=0,
+                    help="only run a plain device-to-device copy of this many MiB (3 times) and exit; "
+                         "used to scale the FETCH_SIZE / WRITE_SIZE counters")
     args = ap.parse_args()
+    if args.calibrate_copy_mib > 0:
+        import torch
+        n = args.calibrate_copy_mib * (1 << 20) // 4
+        x = torch.ones(n, dtype=torch.float32, device="cuda:0")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_mib": args.calibrate_copy_mib, "bytes_read": n * 4, "bytes_written": n * 4}))
+        return
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
               "(the path would shard templates across GPUs, see the design notes)", file=sys.stderr)

@@ -128,6 +128,58 @@ __device__ float2* fft_batched(float2* a, float2* b, int L, int batch, const flo
   return src;
 }
 
+// The same Stockham FFT with the length, batch, thread count and twiddle
+// stride known at compile time: every index division becomes a shift or a
+// multiply and every pass unrolls.  Radix order as above.
+template <int L, int R, int NS, int BATCH, bool INV, int NTH, int TWS>
+__device__ __forceinline__ void ct_pass(const float2* __restrict__ src, float2* __restrict__ dst,
+                                        const float2* __restrict__ tw, int tid) {
+  constexpr int LR = L / R;
+  constexpr int STRIDE = L / (NS * R);
+  constexpr int TOTAL = LR * BATCH;
+#pragma unroll
+  for (int t0 = 0; t0 < TOTAL; t0 += NTH) {
+    const int t = t0 + tid;
+    if ((TOTAL % NTH) == 0 || t < TOTAL) {
+      const int b = t / LR;
+      const int j = t - b * LR;
+      const int k = j % NS;
+      const float2* s = src + b * L;
+      float2* d = dst + b * L;
+      float2 v[R];
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        float2 x = s[j + r * LR];
+        if (r > 0) {
+          float2 w = tw[(k * r * STRIDE) * TWS];
+          if (INV) w.y = -w.y;
+          x = cmul(x, w);
+        }
+        v[r] = x;
+      }
+      if (R == 2) dft2<INV>(v);
+      if (R == 3) dft3<INV>(v);
+      if (R == 4) dft4<INV>(v);
+      const int base = (j / NS) * NS * R + k;
+#pragma unroll
+      for (int r = 0; r < R; ++r) d[base + r * NS] = v[r];
+    }
+  }
+}
+
+template <int L, int NS, int BATCH, bool INV, int NTH, int TWS, class Sync>
+__device__ __forceinline__ float2* ct_fft(float2* a, float2* b, const float2* __restrict__ tw, int tid, Sync sync) {
+  if constexpr (NS >= L) {
+    return a;
+  } else {
+    constexpr int REM = L / NS;
+    constexpr int R = (REM % 4 == 0) ? 4 : ((REM % 2 == 0) ? 2 : 3);
+    ct_pass<L, R, NS, BATCH, INV, NTH, TWS>(a, b, tw, tid);
+    sync();
+    return ct_fft<L, NS * R, BATCH, INV, NTH, TWS>(b, a, tw, tid, sync);
+  }
+}
+
 // Order-preserving key of (value, index): a larger key is a larger value,
 // and for equal values the smaller index.  Used with 64-bit atomicMax.
 __device__ __forceinline__ unsigned long long pose_key(float v, uint32_t idx) {

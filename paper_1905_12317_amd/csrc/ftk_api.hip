@@ -10,7 +10,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/ftk.h"
+#include "ftk.h"
 #include "kernels.h"
 #include "planner.h"
 
@@ -219,15 +219,15 @@ struct ftk_plan {
   // plan-owned device tables
   DevBuf cz, ell, yt, yt_hi, yt_lo, tw_nf, tw_qa, deapod, ptbase, ptker;
   // workspace
-  DevBuf ws_tr_h, ws_tr_g, ws_coef_a, ws_coef_b, ws_stage, ws_keys;
+  DevBuf ws_tr_h, ws_tr_g, ws_coef_a, ws_coef_b, ws_stage, ws_keys, ws_tmpl;
   size_t device_bytes() const {
     return cz.bytes + ell.bytes + yt.bytes + yt_hi.bytes + yt_lo.bytes + tw_nf.bytes + tw_qa.bytes +
            deapod.bytes + ptbase.bytes + ptker.bytes + ws_tr_h.bytes + ws_tr_g.bytes + ws_coef_a.bytes +
-           ws_coef_b.bytes + ws_stage.bytes + ws_keys.bytes;
+           ws_coef_b.bytes + ws_stage.bytes + ws_keys.bytes + ws_tmpl.bytes;
   }
   void release_all() {
     for (DevBuf* b : {&cz, &ell, &yt, &yt_hi, &yt_lo, &tw_nf, &tw_qa, &deapod, &ptbase, &ptker, &ws_tr_h,
-                      &ws_tr_g, &ws_coef_a, &ws_coef_b, &ws_stage, &ws_keys})
+                      &ws_tr_g, &ws_coef_a, &ws_coef_b, &ws_stage, &ws_keys, &ws_tmpl})
       b->release();
   }
 };
@@ -436,17 +436,18 @@ int ftk_set_shifts(ftk_plan* p, const double* shifts_px, int N) {
   }
   const int H = p->t.H, Hp = p->H_pad;
   const int Np = round_up(N, 16);
-  // real embedding of Y, transposed: yt[2 zeta + c'][2 delta + c]
+  // real embedding of Y, transposed: yt[k'][2 delta + c] with the K index
+  // k' = c' H_pad + zeta matching the staged Zhat rows [q][c'][zeta]
   std::vector<float> yt(static_cast<size_t>(2 * Hp) * 2 * Np, 0.f);
   const size_t rs = static_cast<size_t>(2 * Np);
   for (int d = 0; d < N; ++d)
     for (int z = 0; z < H; ++z) {
       const std::complex<double> y = Y[static_cast<size_t>(d) * H + z];
       const float yr = static_cast<float>(y.real()), yi = static_cast<float>(y.imag());
-      yt[(2 * z + 0) * rs + 2 * d + 0] = yr;
-      yt[(2 * z + 1) * rs + 2 * d + 0] = -yi;
-      yt[(2 * z + 0) * rs + 2 * d + 1] = yi;
-      yt[(2 * z + 1) * rs + 2 * d + 1] = yr;
+      yt[static_cast<size_t>(z) * rs + 2 * d + 0] = yr;
+      yt[static_cast<size_t>(Hp + z) * rs + 2 * d + 0] = -yi;
+      yt[static_cast<size_t>(z) * rs + 2 * d + 1] = yi;
+      yt[static_cast<size_t>(Hp + z) * rs + 2 * d + 1] = yr;
     }
   hipError_t e = upload(p->yt, yt);
   if (e != hipSuccess) return hip_fail(e, "ftk_set_shifts: upload");
@@ -464,10 +465,10 @@ int ftk_set_shifts(ftk_plan* p, const double* shifts_px, int N) {
             const int k = ks * 16 + 8 * (l >> 5) + e8;
             // the FP64 value of the embedded entry
             double v = 0.0;
-            const int d = row >> 1, z = k >> 1;
+            const int d = row >> 1, z = k % Hp;
             if (d < N && z < H) {
               const std::complex<double> y = Y[static_cast<size_t>(d) * H + z];
-              const int c = row & 1, cp = k & 1;
+              const int c = row & 1, cp = k / Hp;
               v = (c == cp) ? y.real() : (c == 0 ? -y.imag() : y.imag());
             }
             const size_t at = ((static_cast<size_t>(rt) * nks + ks) * 64 + l) * 8 + e8;
@@ -534,8 +535,9 @@ int ftk_align_coeffs(ftk_plan* p, const void* img_coeffs, int nA, const void* tm
   hipStream_t s = static_cast<hipStream_t>(stream);
   const int QH = p->Qa / 2;
   const size_t pairs = static_cast<size_t>(nA) * nB;
-  const size_t per_pair = static_cast<size_t>(QH) * 2 * p->H_pad * sizeof(float);
-  const size_t budget = env_bytes("FTK_STAGE_MB", size_t(512) << 20);
+  const size_t per_pair = static_cast<size_t>(QH + 1) * 2 * p->H_pad * sizeof(float);
+  const size_t budget = env_bytes("FTK_STAGE_MB", size_t(2048) << 20);
+  const bool split = p->precision == FTK_BF16X3;
   int chunkA = static_cast<int>(std::max<size_t>(1, budget / (per_pair * nB)));
   chunkA = std::min(chunkA, nA);
   hipError_t e;
@@ -547,27 +549,32 @@ int ftk_align_coeffs(ftk_plan* p, const void* img_coeffs, int nA, const void* tm
   hipEvent_t ev = p->timer.begin(s);
   if ((e = launch_keys_init(keys, pairs, s)) != hipSuccess) return hip_fail(e, "ftk_align: keys init");
   p->timer.end(ev, s, 3);
+  // template operand of Step 1: embedded (and split) once per call
+  const int prec = split ? 1 : 0;
+  if ((e = p->ws_tmpl.ensure(tmpl_prep_bytes(nB, p->M, p->Qa, prec))) != hipSuccess)
+    return fail(FTK_ENOMEM, "ftk_align: template operand buffer");
+  ev = p->timer.begin(s);
+  if ((e = launch_tmpl_prep(static_cast<const float2*>(tmpl_coeffs), p->ws_tmpl.ptr, nB, p->M, p->Qa, prec, s)) !=
+      hipSuccess)
+    return hip_fail(e, "ftk_align: template operand");
+  p->timer.end(ev, s, 1);
 
   Step1Args a1{};
   a1.cz = p->cz.as<float>();
   a1.ell = p->ell.as<int>();
   a1.zs = p->ws_stage.as<float>();
   a1.b = static_cast<const float2*>(tmpl_coeffs);
+  a1.r32 = p->ws_tmpl.as<float>();
+  a1.r16 = p->ws_tmpl.ptr;
   a1.nB = nB;
   a1.M = p->M;
   a1.Qa = p->Qa;
   a1.H_pad = p->H_pad;
   a1.L = p->t.L;
   a1.zblk = (p->H_pad % 128 == 0) ? 128 : 64;
-  a1.tb = (nB >= 48) ? 64 : 32;
-  a1.qblk = 16;
-  const bool split = p->precision == FTK_BF16X3;
-  auto lds1 = [&]() { return split ? step1_bf16_lds_bytes(a1) : step1_lds_bytes(a1); };
-  if (lds1() > kLdsLimit) {
-    a1.zblk = 64;
-    if (lds1() > kLdsLimit) a1.tb = 32;
-    if (lds1() > kLdsLimit) return fail(FTK_EUNSUPPORTED, "ftk_align: step 1 tiles exceed LDS");
-  }
+  if (step1_v2_lds_bytes(p->M, a1.zblk, prec) > kLdsLimit) a1.zblk = 64;
+  if (step1_v2_lds_bytes(p->M, a1.zblk, prec) > kLdsLimit)
+    return fail(FTK_EUNSUPPORTED, "ftk_align: step 1 tiles exceed LDS");
   Step3Args a3{};
   a3.yt = p->yt.as<float>();
   a3.yt_hi = p->yt_hi.as<uint16_t>();
@@ -579,7 +586,10 @@ int ftk_align_coeffs(ftk_plan* p, const void* img_coeffs, int nA, const void* tm
   a3.N_pad = p->N_pad;
   {
     const int units = (p->N + 15) / 16;
-    int maxw = (p->Qa / 64 > 4) ? 8 : 16;
+    // waves per workgroup: at most 8 lets two workgroups share a CU, so one
+    // workgroup's FFT epilogue overlaps the other's MFMA loop
+    int maxw = static_cast<int>(env_bytes("FTK_STEP3_MAXW", size_t(8) << 20) >> 20);
+    maxw = std::max(1, std::min(maxw, (p->Qa / 64 > 4) ? 8 : 16));
     auto lds3 = [&](int w) { return split ? step3_bf16_lds_bytes(p->Qa, w) : step3_lds_bytes(p->Qa, w); };
     while (maxw > 1 && lds3(maxw) > kLdsLimit) --maxw;
     const int nblk = (units + maxw - 1) / maxw;
@@ -589,8 +599,14 @@ int ftk_align_coeffs(ftk_plan* p, const void* img_coeffs, int nA, const void* tm
     const int na = std::min(chunkA, nA - A0);
     a1.a = static_cast<const float2*>(img_coeffs) + static_cast<size_t>(A0) * p->Qa * p->M;
     a1.nA = na;
+    {
+      // split the template sweep until the grid holds about 4 workgroups per CU
+      const int base = na * (QH + 1) * (p->H_pad / a1.zblk);
+      const int max_parts = std::max(1, ((nB + 15) / 16 + 7) / 8);
+      a1.tparts = std::min(max_parts, std::max(1, (1024 + base - 1) / base));
+    }
     ev = p->timer.begin(s);
-    e = split ? launch_step1_bf16(a1, s) : launch_step1(a1, p->precision, s);
+    e = launch_step1_v2(a1, prec, s);
     if (e != hipSuccess) return hip_fail(e, "ftk_align: step 1");
     p->timer.end(ev, s, 1);
     a3.zs = p->ws_stage.as<float>();

@@ -317,7 +317,7 @@ __device__ __forceinline__ void epilogue(const Step3Args& p, f32x16 (&acc)[CTQ],
       fb2[t] = Z;
     }
     wave_sync();
-    float2* res = fft_batched<false>(fb2, fb, QH, 4, tw, 2, lane, 64, WaveSync());
+    float2* res = ct_fft<QH, 1, 4, false, 64, 2>(fb2, fb, tw, lane, WaveSync());
     for (int t = lane; t < 4 * QH; t += 64) {
       const int row = t / QH;
       const int s = t - row * QH;
@@ -356,7 +356,7 @@ __global__ void __launch_bounds__(MAXT) step3_bf16x3(Step3Args p) {
   const int c32 = lane & 31;
   const int nk = 2 * p.H_pad;
   const int nks = nk / 16;
-  const float* zsp = p.zs + static_cast<size_t>(pair) * QH * nk;
+  const float* zsp = p.zs + static_cast<size_t>(pair) * (QH + 1) * nk;
   float2* twl = reinterpret_cast<float2*>(smem);
   float* region = smem + 4 * QH;
   const int buf_words = QH * ROWW;
@@ -366,10 +366,22 @@ __global__ void __launch_bounds__(MAXT) step3_bf16x3(Step3Args p) {
   const int nf4 = QH * (KC / 4);
   const int per = (nf4 + nthr - 1) / nthr;
   const bool pref = per <= MAXF4;
+  // Zhat rows are [q][c][zeta]; row Qa/2 is folded into row 0 (see the FP32 form)
   auto fetch = [&](int kc, int t) {
     const int qq = t >> 3;
-    const int k4 = (t & 7) * 4;
-    return *reinterpret_cast<const float4*>(zsp + static_cast<size_t>(qq) * nk + kc + k4);
+    const int k = kc + (t & 7) * 4;
+    float4 v = *reinterpret_cast<const float4*>(zsp + static_cast<size_t>(qq) * nk + k);
+    if (qq == 0) {
+      const float* ny = zsp + static_cast<size_t>(QH) * nk;
+      if (k < p.H_pad) {
+        const float4 w = *reinterpret_cast<const float4*>(ny + k + p.H_pad);
+        v.x -= w.x; v.y -= w.y; v.z -= w.z; v.w -= w.w;
+      } else {
+        const float4 w = *reinterpret_cast<const float4*>(ny + k - p.H_pad);
+        v.x += w.x; v.y += w.y; v.z += w.z; v.w += w.w;
+      }
+    }
+    return v;
   };
   auto put = [&](int buf, int t, float4 v) {
     const int qq = t >> 3;

@@ -1,0 +1,362 @@
+// Step 1 of the FTK (eq. fbk3) on gfx950 MFMA, FP32 and split-bf16 forms.
+//
+//     Zhat_B[zeta](q) = sum_m conj b_B(k_m; q) P_zeta(m; q),
+//     P_zeta(m; q)   = 2 pi w_m G_zeta(k_m) a(k_m; q - l_zeta mod Qa),
+//
+// for one image, one mode q and every template B, written as a real GEMM:
+//   rows    (B, c)      c = 0 real part, c = 1 imaginary part of Zhat
+//   K       (m, c')     c' = 0 real part, c' = 1 imaginary part of P
+//   columns zeta
+// with the template operand R'[(B,c)][(m,c')] = [[br, bi], [-bi, br]] and the
+// image operand P[(m,c')][zeta] = (Re P, Im P).  The template operand is
+// embedded once per call by tmpl_prep_* in MFMA lane order (and, for the
+// split form, split into bf16 hi + lo); a workgroup owns one image, one q
+// and a block of zeta, forms P for that q once in LDS, and its waves sweep
+// all template blocks.  Modes q = 0 .. Qa/2 are computed (Hermitian
+// symmetry of a real inner product); the result is staged as
+// zs[pair][q][c][zeta] with Qa/2 + 1 rows of q.
+#include "device_common.h"
+#include "kernels.h"
+
+using namespace ftkdev;
+
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+
+namespace {
+
+__device__ __forceinline__ f32x16 zero16() {
+  f32x16 z;
+#pragma unroll
+  for (int i = 0; i < 16; ++i) z[i] = 0.f;
+  return z;
+}
+
+// R'[(B,c)][(m,c')] from the template's complex coefficient b = (br, bi)
+__device__ __forceinline__ float embed(float2 b, int c, int cp) {
+  return c == 0 ? (cp == 0 ? b.x : b.y) : (cp == 0 ? -b.y : b.x);
+}
+
+// ---- template operand preparation -------------------------------------
+
+// FP32 form, 32x32x2 MFMA: one K step is one m (k' = 2m + c').
+// Layout [q][row tile][m][lane] floats; lane l: row l % 32 -> (B, c), c' = l / 32.
+__global__ void tmpl_prep_fp32(const float2* __restrict__ b, float* __restrict__ out, int nB, int nRT, int M,
+                               int Qa, int NQ) {
+  const size_t total = static_cast<size_t>(NQ) * nRT * M * 64;
+  for (size_t t = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x; t < total;
+       t += static_cast<size_t>(gridDim.x) * blockDim.x) {
+    const int lane = static_cast<int>(t & 63);
+    size_t u = t >> 6;
+    const int m = static_cast<int>(u % M);
+    u /= M;
+    const int rt = static_cast<int>(u % nRT);
+    const int q = static_cast<int>(u / nRT);
+    const int row = lane & 31;
+    const int B = rt * 16 + (row >> 1);
+    float v = 0.f;
+    if (B < nB) v = embed(b[(static_cast<size_t>(B) * Qa + q) * M + m], row & 1, lane >> 5);
+    out[t] = v;
+  }
+}
+
+// Split form, 32x32x16 MFMA: one K step is 8 m (k' = 16 ks + 8 (l/32) + e).
+// Layout [q][row tile][ks][lane][8 hi, 8 lo] bf16.
+__global__ void tmpl_prep_bf16(const float2* __restrict__ b, __bf16* __restrict__ out, int nB, int nRT, int M,
+                               int Qa, int NQ) {
+  const int nks = M / 8;
+  const size_t total = static_cast<size_t>(NQ) * nRT * nks * 64;
+  for (size_t t = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x; t < total;
+       t += static_cast<size_t>(gridDim.x) * blockDim.x) {
+    const int lane = static_cast<int>(t & 63);
+    size_t u = t >> 6;
+    const int ks = static_cast<int>(u % nks);
+    u /= nks;
+    const int rt = static_cast<int>(u % nRT);
+    const int q = static_cast<int>(u / nRT);
+    const int row = lane & 31;
+    const int B = rt * 16 + (row >> 1);
+    const int c = row & 1;
+    bf16x8 hi, lo;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int kp = ks * 16 + 8 * (lane >> 5) + e;
+      float v = 0.f;
+      if (B < nB) v = embed(b[(static_cast<size_t>(B) * Qa + q) * M + (kp >> 1)], c, kp & 1);
+      const __bf16 h = static_cast<__bf16>(v);
+      hi[e] = h;
+      lo[e] = static_cast<__bf16>(v - static_cast<float>(h));
+    }
+    bf16x8* o = reinterpret_cast<bf16x8*>(out) + t * 2;
+    o[0] = hi;
+    o[1] = lo;
+  }
+}
+
+// ---- Step 1, FP32 form --------------------------------------------------
+
+// Grid: x = image in chunk, y = q in [0, Qa/2], z = zeta block.
+// LDS: image operand P[k'][zeta] (k' = 2m + c', zeta contiguous, stride PS).
+template <int RT, int CT>
+__global__ void __launch_bounds__(256) step1_fp32_v2(Step1Args p) {
+  extern __shared__ float smem[];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int M = p.M, Qa = p.Qa, QH = Qa / 2;
+  const int A = blockIdx.x;
+  const int q = blockIdx.y;
+  const int z0 = (blockIdx.z / p.tparts) * (32 * CT);
+  const int part = blockIdx.z % p.tparts;  // this workgroup's share of the template row tiles
+  constexpr int ZB = 32 * CT;
+  constexpr int PS = (ZB % 64 == 0) ? ZB + 32 : ZB;  // row stride == 32 mod 64 words
+  const float2* arow = p.a + static_cast<size_t>(A) * Qa * M;
+  for (int i = tid; i < ZB * M; i += 256) {
+    const int z = i / M;
+    const int m = i - z * M;
+    int row = q - p.ell[z0 + z];
+    row %= Qa;
+    row += (row < 0) ? Qa : 0;
+    const float2 av = arow[static_cast<size_t>(row) * M + m];
+    const float cm = p.cz[static_cast<size_t>(z0 + z) * M + m];
+    smem[(2 * m) * PS + z] = cm * av.x;
+    smem[(2 * m + 1) * PS + z] = cm * av.y;
+  }
+  __syncthreads();
+  const int r = lane >> 5;
+  const int c32 = lane & 31;
+  const int NQ = QH + 1;
+  const int nRT = (p.nB + 15) / 16;
+  const int twoH = 2 * p.H_pad;
+  const float* Pb = smem + r * PS + c32;
+  float* zbase = p.zs + static_cast<size_t>(A) * p.nB * NQ * twoH + static_cast<size_t>(q) * twoH;
+  const float* rq = p.r32 + static_cast<size_t>(q) * nRT * M * 64 + lane;
+  for (int rt0 = (part * 4 + wave) * RT; rt0 < nRT; rt0 += 4 * RT * p.tparts) {
+    f32x16 acc[RT][CT];
+#pragma unroll
+    for (int i = 0; i < RT; ++i)
+#pragma unroll
+      for (int j = 0; j < CT; ++j) acc[i][j] = zero16();
+    const float* ra[RT];
+#pragma unroll
+    for (int i = 0; i < RT; ++i) ra[i] = rq + static_cast<size_t>(min(rt0 + i, nRT - 1)) * M * 64;
+    float an[RT];
+#pragma unroll
+    for (int i = 0; i < RT; ++i) an[i] = ra[i][0];
+    for (int m = 0; m < M; ++m) {
+      float av[RT];
+#pragma unroll
+      for (int i = 0; i < RT; ++i) av[i] = an[i];
+      if (m + 1 < M) {
+#pragma unroll
+        for (int i = 0; i < RT; ++i) an[i] = ra[i][(m + 1) * 64];
+      }
+#pragma unroll
+      for (int j = 0; j < CT; ++j) {
+        const float bv = Pb[(2 * m) * PS + j * 32];
+#pragma unroll
+        for (int i = 0; i < RT; ++i)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[i], bv, acc[i][j], 0, 0, 0);
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < RT; ++i) {
+      if (rt0 + i >= nRT) continue;
+#pragma unroll
+      for (int j = 0; j < CT; ++j)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+          const int row = 8 * (v >> 2) + 4 * r + (v & 3);
+          const int B = (rt0 + i) * 16 + (row >> 1);
+          if (B < p.nB)
+            zbase[static_cast<size_t>(B) * NQ * twoH + (row & 1) * p.H_pad + z0 + j * 32 + c32] = acc[i][j][v];
+        }
+    }
+  }
+}
+
+// ---- Step 1, split-bf16 form -------------------------------------------
+
+__device__ __forceinline__ f32x16 mfma3(bf16x8 ahi, bf16x8 alo, bf16x8 bhi, bf16x8 blo, f32x16 c) {
+  c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ahi, bhi, c, 0, 0, 0);
+  c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ahi, blo, c, 0, 0, 0);
+  c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(alo, bhi, c, 0, 0, 0);
+  return c;
+}
+
+// LDS: image operand per zeta row: [2M bf16 hi][2M bf16 lo] + 4 words pad.
+template <int RT, int CT>
+__global__ void __launch_bounds__(256) step1_bf16_v2(Step1Args p) {
+  extern __shared__ float smem[];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int M = p.M, Qa = p.Qa, QH = Qa / 2;
+  const int A = blockIdx.x;
+  const int q = blockIdx.y;
+  constexpr int ZB = 32 * CT;
+  const int z0 = (blockIdx.z / p.tparts) * ZB;
+  const int part = blockIdx.z % p.tparts;
+  const int RW = 2 * M + 4;  // words per zeta row
+  const float2* arow = p.a + static_cast<size_t>(A) * Qa * M;
+  // two m per item: (Pr, Pi) of m and m+1 -> 4 consecutive k'
+  for (int i = tid; i < ZB * (M / 2); i += 256) {
+    const int z = i / (M / 2);
+    const int m2 = i - z * (M / 2);
+    int row = q - p.ell[z0 + z];
+    row %= Qa;
+    row += (row < 0) ? Qa : 0;
+    const float4 av = reinterpret_cast<const float4*>(arow + static_cast<size_t>(row) * M)[m2];
+    const float2 cm = reinterpret_cast<const float2*>(p.cz + static_cast<size_t>(z0 + z) * M)[m2];
+    const float4 pv = make_float4(cm.x * av.x, cm.x * av.y, cm.y * av.z, cm.y * av.w);
+    const float x[4] = {pv.x, pv.y, pv.z, pv.w};
+    bf16x4 hi, lo;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const __bf16 h = static_cast<__bf16>(x[e]);
+      hi[e] = h;
+      lo[e] = static_cast<__bf16>(x[e] - static_cast<float>(h));
+    }
+    float* dst = smem + z * RW + 2 * m2;
+    *reinterpret_cast<bf16x4*>(dst) = hi;
+    *reinterpret_cast<bf16x4*>(dst + M) = lo;
+  }
+  __syncthreads();
+  const int r = lane >> 5;
+  const int c32 = lane & 31;
+  const int NQ = QH + 1;
+  const int nRT = (p.nB + 15) / 16;
+  const int nks = M / 8;
+  const int twoH = 2 * p.H_pad;
+  const float* Pb = smem + c32 * RW + 4 * r;
+  float* zbase = p.zs + static_cast<size_t>(A) * p.nB * NQ * twoH + static_cast<size_t>(q) * twoH;
+  const bf16x8* rq = reinterpret_cast<const bf16x8*>(p.r16) + (static_cast<size_t>(q) * nRT * nks * 64 + lane) * 2;
+  for (int rt0 = (part * 4 + wave) * RT; rt0 < nRT; rt0 += 4 * RT * p.tparts) {
+    f32x16 acc[RT][CT];
+#pragma unroll
+    for (int i = 0; i < RT; ++i)
+#pragma unroll
+      for (int j = 0; j < CT; ++j) acc[i][j] = zero16();
+    const bf16x8* ra[RT];
+#pragma unroll
+    for (int i = 0; i < RT; ++i) ra[i] = rq + static_cast<size_t>(min(rt0 + i, nRT - 1)) * nks * 128;
+    bf16x8 nhi[RT], nlo[RT];
+#pragma unroll
+    for (int i = 0; i < RT; ++i) {
+      nhi[i] = ra[i][0];
+      nlo[i] = ra[i][1];
+    }
+    for (int ks = 0; ks < nks; ++ks) {
+      bf16x8 ahi[RT], alo[RT];
+#pragma unroll
+      for (int i = 0; i < RT; ++i) {
+        ahi[i] = nhi[i];
+        alo[i] = nlo[i];
+      }
+      if (ks + 1 < nks) {
+#pragma unroll
+        for (int i = 0; i < RT; ++i) {
+          nhi[i] = ra[i][(ks + 1) * 128];
+          nlo[i] = ra[i][(ks + 1) * 128 + 1];
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < CT; ++j) {
+        const float* prow = Pb + j * 32 * RW + 8 * ks;
+        const bf16x8 bhi = *reinterpret_cast<const bf16x8*>(prow);
+        const bf16x8 blo = *reinterpret_cast<const bf16x8*>(prow + M);
+#pragma unroll
+        for (int i = 0; i < RT; ++i) acc[i][j] = mfma3(ahi[i], alo[i], bhi, blo, acc[i][j]);
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < RT; ++i) {
+      if (rt0 + i >= nRT) continue;
+#pragma unroll
+      for (int j = 0; j < CT; ++j)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+          const int row = 8 * (v >> 2) + 4 * r + (v & 3);
+          const int B = (rt0 + i) * 16 + (row >> 1);
+          if (B < p.nB)
+            zbase[static_cast<size_t>(B) * NQ * twoH + (row & 1) * p.H_pad + z0 + j * 32 + c32] = acc[i][j][v];
+        }
+    }
+  }
+}
+
+template <class K>
+hipError_t set_lds(K kern, size_t lds) {
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
+                             static_cast<int>(lds));
+}
+
+}  // namespace
+
+size_t tmpl_prep_bytes(int nB, int M, int Qa, int precision) {
+  const size_t nRT = (nB + 15) / 16, NQ = Qa / 2 + 1;
+  if (precision == 0) return NQ * nRT * M * 64 * sizeof(float);
+  return NQ * nRT * (M / 8) * 64 * 32;
+}
+
+hipError_t launch_tmpl_prep(const float2* b, void* out, int nB, int M, int Qa, int precision, hipStream_t s) {
+  if (nB <= 0) return hipSuccess;
+  const int nRT = (nB + 15) / 16, NQ = Qa / 2 + 1;
+  const size_t total = static_cast<size_t>(NQ) * nRT * (precision == 0 ? M : M / 8) * 64;
+  const int blocks = static_cast<int>(std::min<size_t>((total + 255) / 256, 65536));
+  if (precision == 0)
+    hipLaunchKernelGGL(tmpl_prep_fp32, dim3(blocks), dim3(256), 0, s, b, static_cast<float*>(out), nB, nRT, M, Qa,
+                       NQ);
+  else
+    hipLaunchKernelGGL(tmpl_prep_bf16, dim3(blocks), dim3(256), 0, s, b, static_cast<__bf16*>(out), nB, nRT, M,
+                       Qa, NQ);
+  return hipGetLastError();
+}
+
+size_t step1_v2_lds_bytes(int M, int zb, int precision) {
+  if (precision == 0) {
+    const int PS = (zb % 64 == 0) ? zb + 32 : zb;
+    return sizeof(float) * 2 * M * PS;
+  }
+  return sizeof(float) * zb * (2 * M + 4);
+}
+
+hipError_t launch_step1_v2(const Step1Args& a, int precision, hipStream_t s) {
+  if (a.nA <= 0 || a.nB <= 0) return hipSuccess;
+  const int CT = a.zblk / 32;
+  const int QH = a.Qa / 2;
+  dim3 grid(a.nA, QH + 1, (a.H_pad / a.zblk) * a.tparts);
+  const size_t lds = step1_v2_lds_bytes(a.M, a.zblk, precision);
+  hipError_t e;
+  if (precision == 0) {
+#define FTK_S1(ct)                                              \
+  case ct: {                                                     \
+    auto k = step1_fp32_v2<2, ct>;                              \
+    if ((e = set_lds(k, lds)) != hipSuccess) return e;          \
+    hipLaunchKernelGGL(k, grid, dim3(256), lds, s, a);          \
+    break;                                                       \
+  }
+    switch (CT) {
+      FTK_S1(2)
+      FTK_S1(4)
+      default: return hipErrorInvalidValue;
+    }
+#undef FTK_S1
+  } else {
+#define FTK_S1(ct)                                              \
+  case ct: {                                                     \
+    auto k = step1_bf16_v2<2, ct>;                              \
+    if ((e = set_lds(k, lds)) != hipSuccess) return e;          \
+    hipLaunchKernelGGL(k, grid, dim3(256), lds, s, a);          \
+    break;                                                       \
+  }
+    switch (CT) {
+      FTK_S1(2)
+      FTK_S1(4)
+      default: return hipErrorInvalidValue;
+    }
+#undef FTK_S1
+  }
+  return hipGetLastError();
+}

@@ -32,8 +32,11 @@ struct Step1Args {
   // split-precision operands (bf16 hi/lo); unused by the FP32 kernel
   const uint16_t* b_hi;  // [nB][Qa][2M] bf16 of (re, im) interleaved
   const uint16_t* b_lo;
+  const float* r32;      // embedded template operand, FP32 lane order (tmpl_prep)
+  const void* r16;       // embedded template operand, bf16 hi/lo lane order (tmpl_prep)
   int nA, nB, M, Qa, H_pad, L;
   int zblk;              // zeta per workgroup (multiple of 64)
+  int tparts;            // template row tiles split over this many workgroups
   int tb;                // templates per workgroup (32 or 64)
   int qblk;              // q values per workgroup
 };
@@ -55,6 +58,13 @@ size_t step1_lds_bytes(const Step1Args& a);
 size_t step3_lds_bytes(int Qa, int nwaves);
 hipError_t launch_step1(const Step1Args& args, int precision, hipStream_t stream);
 hipError_t launch_step3(const Step3Args& args, int precision, hipStream_t stream);
+// Step 1 with the template operand embedded once per call (kern_step1.hip):
+// staging layout zs[pair][q][c][zeta], q = 0 .. Qa/2 (Qa/2 + 1 rows).
+size_t tmpl_prep_bytes(int nB, int M, int Qa, int precision);
+hipError_t launch_tmpl_prep(const float2* b, void* out, int nB, int M, int Qa, int precision, hipStream_t stream);
+size_t step1_v2_lds_bytes(int M, int zb, int precision);
+hipError_t launch_step1_v2(const Step1Args& args, int precision, hipStream_t stream);
+
 // split-bf16 forms of the two contractions (kern_align_bf16.hip)
 size_t step1_bf16_lds_bytes(const Step1Args& a);
 size_t step3_bf16_lds_bytes(int Qa, int nwaves);
