@@ -1,18 +1,4 @@
-// The pair-wise FTK contractions on MFMA (gfx950), FP32 form.
-//
-// Step 1 (eq. fbk3): for one image A and a block of templates B at a fixed
-// mode q,
-//     Zhat[B][zeta] = sum_m conj b_B(k_m; q) * P[zeta][m],
-//     P[zeta][m]    = 2 pi w_m G_zeta(k_m) a_A(k_m; q - l_zeta mod Qa),
-// written as a real GEMM with K = 2M (re/im of b) and 2 H columns
-// (re/im of Zhat): rows = templates, columns = (zeta, re|im).  The image
-// operand P is built on the fly in registers from an LDS window of the
-// image's mode rows q - l, l = -L..L, and the LDS table of 2 pi w G.
-// Only q = 0..Qa/2 is needed (Hermitian symmetry of a real inner
-// product); the Nyquist mode is packed into q = 0 as Zhat(0) + i Zhat(Qa/2).
-// The result is staged in HBM as [pair][q][zeta] (complex interleaved).
-//
-// Step 3 + Step 2: per pair,
+// Step 3 + Step 2 of the FTK (eq. fbk3), FP32 form.  Per pair,
 //     Xhat[delta][q] = sum_zeta Y[delta][zeta] Zhat[zeta][q]
 // as a real GEMM (rows = (delta, re|im), K = (zeta, re|im), columns = q)
 // with the shift panel read from L2 and Zhat staged in LDS; then for every
@@ -33,220 +19,6 @@ __device__ __forceinline__ f32x16 zero16() {
 #pragma unroll
   for (int i = 0; i < 16; ++i) z[i] = 0.f;
   return z;
-}
-
-// ---------------------------------------------------------------- Step 1
-
-template <int RT, int CPW>
-__global__ void __launch_bounds__(256) step1_fp32(Step1Args p) {
-  extern __shared__ float smem[];
-  constexpr int MAXKR = 24;  // template-tile prefetch registers per thread
-  const int tid = threadIdx.x;
-  const int lane = tid & 63;
-  const int wave = tid >> 6;
-  constexpr int TB = 32 * RT;
-  const int M = p.M, Qa = p.Qa, L = p.L, QH = Qa / 2;
-  const int nzb = p.H_pad / p.zblk;
-  const int bblk = blockIdx.x / nzb;
-  const int zb = blockIdx.x - bblk * nzb;
-  const int b0 = bblk * TB;
-  const int z0 = zb * p.zblk;
-  const int A = blockIdx.z;
-  // LDS: two template tiles [2M][RS], 2 pi w G rows [zblk][MS], l per zeta,
-  // and a ring of image mode rows [WR][MS] (complex).  Row strides are odd
-  // so that the 16 distinct zeta rows a half-wave reads hit distinct banks.
-  const int RS = TB + 1, MS = M + 1, WR = 2 * L + 2;
-  float* czs = smem + 4 * M * RS;
-  int* ellz = reinterpret_cast<int*>(czs + p.zblk * MS);
-  float2* ring = reinterpret_cast<float2*>(ellz + ((p.zblk + 1) & ~1));
-
-  const int nR = TB * M;
-  const int kr = (nR + 255) / 256;
-  const bool pref = kr <= MAXKR;
-  const float2* abase = p.a + static_cast<size_t>(A) * Qa * M;
-
-  auto r_elem = [&](int q, int i) -> float2 {
-    const int B = i / M;
-    const int m = i - B * M;
-    if (b0 + B < p.nB) return p.b[(static_cast<size_t>(b0 + B) * Qa + q) * M + m];
-    return make_float2(0.f, 0.f);
-  };
-  auto r_store = [&](int buf, int i, float2 v) {
-    const int B = i / M;
-    const int m = i - B * M;
-    float* R = smem + buf * (2 * M * RS);
-    R[(2 * m) * RS + B] = v.x;
-    R[(2 * m + 1) * RS + B] = v.y;
-  };
-  auto grow = [&](int r) -> const float2* {
-    r %= Qa;
-    r += (r < 0) ? Qa : 0;
-    return abase + static_cast<size_t>(r) * M;
-  };
-  auto slot = [&](int r) {
-    int sl = r % WR;
-    return sl + ((sl < 0) ? WR : 0);
-  };
-  auto load_window = [&](int q) {  // rows q-L .. q+L, between barriers
-    for (int i = tid; i < (2 * L + 1) * M; i += 256) {
-      const int li = i / M;
-      const int m = i - li * M;
-      const int r = q + L - li;
-      ring[slot(r) * MS + m] = grow(r)[m];
-    }
-  };
-
-  for (int i = tid; i < p.zblk * M; i += 256) {
-    const int z = i / M;
-    const int m = i - z * M;
-    czs[z * MS + m] = p.cz[static_cast<size_t>(z0 + z) * M + m];
-  }
-  for (int i = tid; i < p.zblk; i += 256) ellz[i] = p.ell[z0 + i];
-
-  const int r = lane >> 5;
-  const int c32 = lane & 31;
-  int zl[CPW], cc[CPW];
-#pragma unroll
-  for (int ct = 0; ct < CPW; ++ct) {
-    const int j = (wave * CPW + ct) * 32 + c32;
-    zl[ct] = j >> 1;
-    cc[ct] = j & 1;
-  }
-
-  // the q values of this block; the block holding q = 0 first does the
-  // Nyquist mode Qa/2, which is folded into q = 0 as i * Zhat(Qa/2)
-  const int qb0 = blockIdx.y * p.qblk;
-  const int qb1 = min(QH, qb0 + p.qblk);
-  const bool with_nyq = (qb0 == 0);
-  const int nlist = (qb1 - qb0) + (with_nyq ? 1 : 0);
-  auto qat = [&](int t) { return with_nyq ? (t == 0 ? QH : t - 1) : qb0 + t; };
-
-  {
-    const int q = qat(0);
-    for (int i = tid; i < nR; i += 256) r_store(0, i, r_elem(q, i));
-    load_window(q);
-  }
-  __syncthreads();
-
-  const int twoH = 2 * p.H_pad;
-  float* zbase = p.zs + static_cast<size_t>(A) * p.nB * QH * twoH;
-  f32x16 acc[RT][CPW];
-#pragma unroll
-  for (int rt = 0; rt < RT; ++rt)
-#pragma unroll
-    for (int ct = 0; ct < CPW; ++ct) acc[rt][ct] = zero16();
-
-  int cur = 0;
-  for (int t = 0; t < nlist; ++t) {
-    const int q = qat(t);
-    const int qn = (t + 1 < nlist) ? qat(t + 1) : -1;
-    const bool contig = (qn == q + 1);
-    float2 rreg[MAXKR];
-    float2 wreg[2];
-    if (qn >= 0 && pref) {
-#pragma unroll
-      for (int k = 0; k < MAXKR; ++k) {
-        const int i = tid + 256 * k;
-        if (k < kr && i < nR) rreg[k] = r_elem(qn, i);
-      }
-    }
-    if (qn >= 0 && contig) {
-      const float2* g = grow(qn + L);
-#pragma unroll
-      for (int k = 0; k < 2; ++k) {
-        const int i = tid + 256 * k;
-        if (i < M) wreg[k] = g[i];
-      }
-    }
-    // LDS addresses are formed from the shared base (never through a pointer
-    // table) so that the compiler keeps them in the LDS address space
-    const float* R = smem + (cur ? 2 * M * RS : 0) + r * RS + c32;
-    // column (zeta, c) of lane half r takes Re P (r == c, negated when r = 1)
-    // or Im P (r != c): one component of the ring row times 2 pi w G
-    const float* wcomp[CPW];
-    const float* crow[CPW];
-    float sgn[CPW];
-#pragma unroll
-    for (int ct = 0; ct < CPW; ++ct) {
-      const int comp = (r != cc[ct]) ? 1 : 0;
-      wcomp[ct] = reinterpret_cast<const float*>(ring + slot(q - ellz[zl[ct]]) * MS) + comp;
-      crow[ct] = czs + zl[ct] * MS;
-      sgn[ct] = (r == 1 && cc[ct] == 1) ? -1.f : 1.f;
-    }
-    auto mstep = [&](int m) {
-      float av[RT], bv[CPW];
-#pragma unroll
-      for (int rt = 0; rt < RT; ++rt) av[rt] = R[2 * m * RS + rt * 32];
-#pragma unroll
-      for (int ct = 0; ct < CPW; ++ct) bv[ct] = (sgn[ct] * crow[ct][m]) * wcomp[ct][2 * m];
-#pragma unroll
-      for (int rt = 0; rt < RT; ++rt)
-#pragma unroll
-        for (int ct = 0; ct < CPW; ++ct)
-          acc[rt][ct] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[rt], bv[ct], acc[rt][ct], 0, 0, 0);
-    };
-    const int M4 = M & ~3;
-    for (int m = 0; m < M4; m += 4) {
-      mstep(m);
-      mstep(m + 1);
-      mstep(m + 2);
-      mstep(m + 3);
-    }
-    for (int m = M4; m < M; ++m) mstep(m);
-    if (q == QH) {
-      // fold: the q = 0 result accumulates onto i * Zhat(Qa/2)
-#pragma unroll
-      for (int rt = 0; rt < RT; ++rt)
-#pragma unroll
-        for (int ct = 0; ct < CPW; ++ct)
-#pragma unroll
-          for (int i = 0; i < 16; ++i) {
-            const float other = __shfl_xor(acc[rt][ct][i], 1);
-            acc[rt][ct][i] = cc[ct] ? other : -other;
-          }
-    } else {
-#pragma unroll
-      for (int rt = 0; rt < RT; ++rt)
-#pragma unroll
-        for (int ct = 0; ct < CPW; ++ct) {
-          const int col = 2 * z0 + (wave * CPW + ct) * 32 + c32;
-#pragma unroll
-          for (int i = 0; i < 16; ++i) {
-            const int row = 8 * (i >> 2) + 4 * r + (i & 3);
-            const int B = b0 + rt * 32 + row;
-            if (B < p.nB) zbase[(static_cast<size_t>(B) * QH + q) * twoH + col] = acc[rt][ct][i];
-          }
-          acc[rt][ct] = zero16();
-        }
-    }
-    if (qn >= 0) {
-      // hand-over: the next template tile goes to the idle buffer and the
-      // next window row to ring slot (q+1+L) mod WR, which q does not read
-      if (pref) {
-#pragma unroll
-        for (int k = 0; k < MAXKR; ++k) {
-          const int i = tid + 256 * k;
-          if (k < kr && i < nR) r_store(cur ^ 1, i, rreg[k]);
-        }
-      }
-      if (contig) {
-        float2* dst = ring + slot(qn + L) * MS;
-#pragma unroll
-        for (int k = 0; k < 2; ++k) {
-          const int i = tid + 256 * k;
-          if (i < M) dst[i] = wreg[k];
-        }
-      }
-      __syncthreads();
-      if (!pref || !contig) {
-        if (!pref)
-          for (int i = tid; i < nR; i += 256) r_store(cur ^ 1, i, r_elem(qn, i));
-        if (!contig) load_window(qn);
-        __syncthreads();
-      }
-      cur ^= 1;
-    }
-  }
 }
 
 // ---------------------------------------------------------------- Step 3
@@ -454,47 +226,12 @@ __global__ void keys_to_poses_kernel(const unsigned long long* keys, PoseOut* po
 
 }  // namespace
 
-size_t step1_lds_bytes(const Step1Args& a) {
-  const size_t RS = a.tb + 1, MS = a.M + 1, WR = 2 * a.L + 2;
-  return sizeof(float) * (4 * a.M * RS + a.zblk * MS) + sizeof(int) * ((a.zblk + 1) & ~1) +
-         sizeof(float2) * WR * MS;
-}
-
 size_t step3_lds_bytes(int Qa, int nwaves) {
   const int QH = Qa / 2;
   const int ZS = (QH % 64 == 0) ? QH + 32 : QH;
   size_t k = sizeof(float) * 2 * 32 * ZS;
   size_t e = sizeof(float2) * static_cast<size_t>(nwaves) * 8 * QH;
   return sizeof(float2) * Qa + (k > e ? k : e);
-}
-
-template <int RT, int CPW>
-static hipError_t launch_step1_t(const Step1Args& a, hipStream_t s) {
-  const int nzb = a.H_pad / a.zblk;
-  const int nbb = (a.nB + 32 * RT - 1) / (32 * RT);
-  const int QH = a.Qa / 2;
-  dim3 grid(nbb * nzb, (QH + a.qblk - 1) / a.qblk, a.nA);
-  size_t lds = step1_lds_bytes(a);
-  auto kern = step1_fp32<RT, CPW>;
-  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(kern, grid, dim3(256), lds, s, a);
-  return hipGetLastError();
-}
-
-hipError_t launch_step1(const Step1Args& a, int precision, hipStream_t s) {
-  (void)precision;
-  if (a.nA <= 0 || a.nB <= 0) return hipSuccess;
-  const int cpw = a.zblk / 64;  // 2*zblk columns over 4 waves of 32-wide tiles
-  if (a.tb == 64) {
-    if (cpw == 1) return launch_step1_t<2, 1>(a, s);
-    if (cpw == 2) return launch_step1_t<2, 2>(a, s);
-  } else {
-    if (cpw == 1) return launch_step1_t<1, 1>(a, s);
-    if (cpw == 2) return launch_step1_t<1, 2>(a, s);
-  }
-  return hipErrorInvalidValue;
 }
 
 template <int CTQ, int MAXT>

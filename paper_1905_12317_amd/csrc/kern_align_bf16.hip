@@ -1,4 +1,4 @@
-// The pair-wise FTK contractions in split-bf16 form on gfx950 MFMA.
+// Step 3 of the FTK in split-bf16 form on gfx950 MFMA.
 //
 // Every operand x of the two contractions is written as x = hi + lo with
 // hi = bf16(x) and lo = bf16(x - hi) (round to nearest even), and each
@@ -8,9 +8,10 @@
 // and the rounding of lo are O(2^-16) relative).  The quadrature weights and
 // the operator SVD stay FP64 on the host; only their FP32 products enter.
 //
-// Data flow and layouts are those of the FP32 kernels (kern_align.hip):
-// Step 1 writes Zhat[pair][q][zeta] in FP32, Step 3 reads it, splits it
-// while staging it in LDS, and ends with the same rotation FFT and argmax.
+// Data flow and layouts are those of the FP32 form (kern_align.hip):
+// Step 1 (kern_step1.hip) writes Zhat[pair][q][c][zeta] in FP32, Step 3
+// reads it, splits it while staging it in LDS, and ends with the same
+// rotation FFT and argmax.
 // MFMA: v_mfma_f32_32x32x16_bf16; lane l holds rows/cols l % 32 and the
 // 8 consecutive k = 8 (l / 32) .. +7 of each 16-wide K step.
 #include "device_common.h"
@@ -55,221 +56,6 @@ __device__ __forceinline__ f32x16 mfma3(bf16x8 ahi, bf16x8 alo, bf16x8 bhi, bf16
   c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ahi, blo, c, 0, 0, 0);
   c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(alo, bhi, c, 0, 0, 0);
   return c;
-}
-
-// ---------------------------------------------------------------- Step 1
-
-template <int RT, int CPW>
-__global__ void __launch_bounds__(256) step1_bf16x3(Step1Args p) {
-  extern __shared__ float smem[];
-  const int tid = threadIdx.x;
-  const int lane = tid & 63;
-  const int wave = tid >> 6;
-  constexpr int TB = 32 * RT;
-  const int M = p.M, Qa = p.Qa, L = p.L, QH = Qa / 2;
-  const int nzb = p.H_pad / p.zblk;
-  const int bblk = blockIdx.x / nzb;
-  const int zb = blockIdx.x - bblk * nzb;
-  const int b0 = bblk * TB;
-  const int z0 = zb * p.zblk;
-  const int A = blockIdx.z;
-  // LDS (32-bit words): two template tiles of TB rows x RW words, each row
-  // = 2M bf16 hi then 2M bf16 lo (k' = 2m + re|im) plus 4 words of padding;
-  // 2 pi w G rows [zblk][MS]; l per zeta; ring of image rows [WR][MS2] (complex)
-  const int RW = 2 * M + 4, MS = M + 4, MS2 = M + 2, WR = 2 * L + 2;
-  const int tile_words = TB * RW;
-  float* czs = smem + 2 * tile_words;
-  int* ellz = reinterpret_cast<int*>(czs + p.zblk * MS);
-  float2* ring = reinterpret_cast<float2*>(ellz + ((p.zblk + 3) & ~3));
-  const float2* abase = p.a + static_cast<size_t>(A) * Qa * M;
-  const int nq4 = TB * (M / 2);  // float4 (two complex values) per template tile
-
-  auto r_fetch = [&](int q, int i) -> float4 {
-    const int B = i / (M / 2);
-    const int m2 = i - B * (M / 2);
-    if (b0 + B < p.nB)
-      return reinterpret_cast<const float4*>(p.b + (static_cast<size_t>(b0 + B) * Qa + q) * M)[m2];
-    return make_float4(0.f, 0.f, 0.f, 0.f);
-  };
-  auto r_put = [&](int buf, int i, float4 v) {
-    const int B = i / (M / 2);
-    const int m2 = i - B * (M / 2);
-    bf16x4 hi, lo;
-    split4(v, hi, lo);
-    float* row = smem + buf * tile_words + B * RW;
-    *reinterpret_cast<bf16x4*>(row + 2 * m2) = hi;       // k' = 4 m2 .. 4 m2 + 3
-    *reinterpret_cast<bf16x4*>(row + M + 2 * m2) = lo;
-  };
-  auto grow = [&](int r) -> const float2* {
-    r %= Qa;
-    r += (r < 0) ? Qa : 0;
-    return abase + static_cast<size_t>(r) * M;
-  };
-  auto slot = [&](int r) {
-    int sl = r % WR;
-    return sl + ((sl < 0) ? WR : 0);
-  };
-  auto load_window = [&](int q) {
-    for (int i = tid; i < (2 * L + 1) * M; i += 256) {
-      const int li = i / M;
-      const int m = i - li * M;
-      const int r = q + L - li;
-      ring[slot(r) * MS2 + m] = grow(r)[m];
-    }
-  };
-
-  for (int i = tid; i < p.zblk * M; i += 256) {
-    const int z = i / M;
-    const int m = i - z * M;
-    czs[z * MS + m] = p.cz[static_cast<size_t>(z0 + z) * M + m];
-  }
-  for (int i = tid; i < p.zblk; i += 256) ellz[i] = p.ell[z0 + i];
-
-  const int r = lane >> 5;
-  const int c32 = lane & 31;
-  int zl[CPW], cc[CPW];
-#pragma unroll
-  for (int ct = 0; ct < CPW; ++ct) {
-    const int j = (wave * CPW + ct) * 32 + c32;
-    zl[ct] = j >> 1;
-    cc[ct] = j & 1;
-  }
-
-  const int qb0 = blockIdx.y * p.qblk;
-  const int qb1 = min(QH, qb0 + p.qblk);
-  const bool with_nyq = (qb0 == 0);
-  const int nlist = (qb1 - qb0) + (with_nyq ? 1 : 0);
-  auto qat = [&](int t) { return with_nyq ? (t == 0 ? QH : t - 1) : qb0 + t; };
-
-  {
-    const int q = qat(0);
-    for (int i = tid; i < nq4; i += 256) r_put(0, i, r_fetch(q, i));
-    load_window(q);
-  }
-  __syncthreads();
-
-  constexpr int MAXK4 = 12;
-  const int kr = (nq4 + 255) / 256;
-  const bool pref = kr <= MAXK4;
-  const int twoH = 2 * p.H_pad;
-  float* zbase = p.zs + static_cast<size_t>(A) * p.nB * QH * twoH;
-  f32x16 acc[RT][CPW];
-#pragma unroll
-  for (int rt = 0; rt < RT; ++rt)
-#pragma unroll
-    for (int ct = 0; ct < CPW; ++ct) acc[rt][ct] = zero16();
-
-  int cur = 0;
-  for (int t = 0; t < nlist; ++t) {
-    const int q = qat(t);
-    const int qn = (t + 1 < nlist) ? qat(t + 1) : -1;
-    const bool contig = (qn == q + 1);
-    float4 rreg[MAXK4];
-    float2 wreg[2];
-    if (qn >= 0 && pref) {
-#pragma unroll
-      for (int k = 0; k < MAXK4; ++k) {
-        const int i = tid + 256 * k;
-        if (k < kr && i < nq4) rreg[k] = r_fetch(qn, i);
-      }
-    }
-    if (qn >= 0 && contig) {
-      const float2* g = grow(qn + L);
-#pragma unroll
-      for (int k = 0; k < 2; ++k) {
-        const int i = tid + 256 * k;
-        if (i < M) wreg[k] = g[i];
-      }
-    }
-    const float* Rb = smem + cur * tile_words + c32 * RW + 4 * r;
-    const float* wrow[CPW];
-    const float* crow[CPW];
-#pragma unroll
-    for (int ct = 0; ct < CPW; ++ct) {
-      wrow[ct] = reinterpret_cast<const float*>(ring + slot(q - ellz[zl[ct]]) * MS2);
-      crow[ct] = czs + zl[ct] * MS;
-    }
-    for (int s = 0; s < M / 8; ++s) {
-      // A: templates, k' = 16 s + 8 r .. +7
-      bf16x8 ahi[RT], alo[RT];
-#pragma unroll
-      for (int rt = 0; rt < RT; ++rt) {
-        const float* row = Rb + rt * 32 * RW + 8 * s;
-        ahi[rt] = *reinterpret_cast<const bf16x8*>(row);
-        alo[rt] = *reinterpret_cast<const bf16x8*>(row + M);
-      }
-      const int m0 = 8 * s + 4 * r;
-#pragma unroll
-      for (int ct = 0; ct < CPW; ++ct) {
-        const float4 cz4 = *reinterpret_cast<const float4*>(crow[ct] + m0);
-        const float4 w01 = *reinterpret_cast<const float4*>(wrow[ct] + 2 * m0);
-        const float4 w23 = *reinterpret_cast<const float4*>(wrow[ct] + 2 * m0 + 4);
-        const float pr[4] = {cz4.x * w01.x, cz4.y * w01.z, cz4.z * w23.x, cz4.w * w23.z};
-        const float pi[4] = {cz4.x * w01.y, cz4.y * w01.w, cz4.z * w23.y, cz4.w * w23.w};
-        float v[8];
-        // column (zeta, c): c = 0 takes (Re P, Im P), c = 1 takes (Im P, -Re P)
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          v[2 * e] = cc[ct] ? pi[e] : pr[e];
-          v[2 * e + 1] = cc[ct] ? -pr[e] : pi[e];
-        }
-        bf16x8 bhi, blo;
-        split8(v, bhi, blo);
-#pragma unroll
-        for (int rt = 0; rt < RT; ++rt) acc[rt][ct] = mfma3(ahi[rt], alo[rt], bhi, blo, acc[rt][ct]);
-      }
-    }
-    if (q == QH) {
-#pragma unroll
-      for (int rt = 0; rt < RT; ++rt)
-#pragma unroll
-        for (int ct = 0; ct < CPW; ++ct)
-#pragma unroll
-          for (int i = 0; i < 16; ++i) {
-            const float other = __shfl_xor(acc[rt][ct][i], 1);
-            acc[rt][ct][i] = cc[ct] ? other : -other;
-          }
-    } else {
-#pragma unroll
-      for (int rt = 0; rt < RT; ++rt)
-#pragma unroll
-        for (int ct = 0; ct < CPW; ++ct) {
-          const int col = 2 * z0 + (wave * CPW + ct) * 32 + c32;
-#pragma unroll
-          for (int i = 0; i < 16; ++i) {
-            const int row = 8 * (i >> 2) + 4 * r + (i & 3);
-            const int B = b0 + rt * 32 + row;
-            if (B < p.nB) zbase[(static_cast<size_t>(B) * QH + q) * twoH + col] = acc[rt][ct][i];
-          }
-          acc[rt][ct] = zero16();
-        }
-    }
-    if (qn >= 0) {
-      if (pref) {
-#pragma unroll
-        for (int k = 0; k < MAXK4; ++k) {
-          const int i = tid + 256 * k;
-          if (k < kr && i < nq4) r_put(cur ^ 1, i, rreg[k]);
-        }
-      }
-      if (contig) {
-        float2* dst = ring + slot(qn + L) * MS2;
-#pragma unroll
-        for (int k = 0; k < 2; ++k) {
-          const int i = tid + 256 * k;
-          if (i < M) dst[i] = wreg[k];
-        }
-      }
-      __syncthreads();
-      if (!pref || !contig) {
-        if (!pref)
-          for (int i = tid; i < nq4; i += 256) r_put(cur ^ 1, i, r_fetch(qn, i));
-        if (!contig) load_window(qn);
-        __syncthreads();
-      }
-      cur ^= 1;
-    }
-  }
 }
 
 // ---------------------------------------------------------------- Step 3
@@ -451,45 +237,11 @@ __global__ void __launch_bounds__(MAXT) step3_bf16x3(Step3Args p) {
 
 }  // namespace
 
-size_t step1_bf16_lds_bytes(const Step1Args& a) {
-  const size_t RW = 2 * a.M + 4, MS = a.M + 4, MS2 = a.M + 2, WR = 2 * a.L + 2;
-  return sizeof(float) * (2 * a.tb * RW + a.zblk * MS) + sizeof(int) * ((a.zblk + 3) & ~3) +
-         sizeof(float2) * WR * MS2;
-}
-
 size_t step3_bf16_lds_bytes(int Qa, int nwaves) {
   const size_t QH = Qa / 2;
   const size_t k = sizeof(float) * 2 * QH * 36;
   const size_t e = sizeof(float2) * static_cast<size_t>(nwaves) * 8 * QH;
   return sizeof(float2) * Qa + (k > e ? k : e);
-}
-
-template <int RT, int CPW>
-static hipError_t launch_step1_bf16_t(const Step1Args& a, hipStream_t s) {
-  const int nzb = a.H_pad / a.zblk;
-  const int nbb = (a.nB + 32 * RT - 1) / (32 * RT);
-  const int QH = a.Qa / 2;
-  dim3 grid(nbb * nzb, (QH + a.qblk - 1) / a.qblk, a.nA);
-  size_t lds = step1_bf16_lds_bytes(a);
-  auto kern = step1_bf16x3<RT, CPW>;
-  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(kern, grid, dim3(256), lds, s, a);
-  return hipGetLastError();
-}
-
-hipError_t launch_step1_bf16(const Step1Args& a, hipStream_t s) {
-  if (a.nA <= 0 || a.nB <= 0) return hipSuccess;
-  const int cpw = a.zblk / 64;
-  if (a.tb == 64) {
-    if (cpw == 1) return launch_step1_bf16_t<2, 1>(a, s);
-    if (cpw == 2) return launch_step1_bf16_t<2, 2>(a, s);
-  } else {
-    if (cpw == 1) return launch_step1_bf16_t<1, 1>(a, s);
-    if (cpw == 2) return launch_step1_bf16_t<1, 2>(a, s);
-  }
-  return hipErrorInvalidValue;
 }
 
 template <int CTQ, int MAXT>

@@ -21,29 +21,24 @@ struct TransformArgs {
 size_t transform_lds_bytes(int nf, int Qa, int nwaves);
 hipError_t launch_transform(const TransformArgs& args, int cnt, hipStream_t stream);
 
-// Step 1 (eq. fbk3): Zhat[pair][qq][zeta] for qq in [0, Qa/2), with the
-// Nyquist mode packed into qq = 0 as Zhat(0) + i Zhat(Qa/2).
+// Step 1 (eq. fbk3): Zhat[pair][q][c][zeta] for q = 0 .. Qa/2 (c = re|im).
 struct Step1Args {
   const float2* a;       // image coefficients [nA][Qa][M] (chunk base)
   const float2* b;       // template coefficients [nB][Qa][M]
   const float* cz;       // [H_pad][M]: 2 pi w_m Sigma v(k_m), 0 on padding
   const int* ell;        // [H_pad]: l_zeta, 0 on padding
-  float* zs;             // [nA][nB][Qa/2][2 H_pad] complex interleaved
-  // split-precision operands (bf16 hi/lo); unused by the FP32 kernel
-  const uint16_t* b_hi;  // [nB][Qa][2M] bf16 of (re, im) interleaved
-  const uint16_t* b_lo;
+  float* zs;             // [nA][nB][Qa/2 + 1][2][H_pad]
   const float* r32;      // embedded template operand, FP32 lane order (tmpl_prep)
   const void* r16;       // embedded template operand, bf16 hi/lo lane order (tmpl_prep)
   int nA, nB, M, Qa, H_pad, L;
-  int zblk;              // zeta per workgroup (multiple of 64)
+  int zblk;              // zeta per workgroup (64 or 128)
   int tparts;            // template row tiles split over this many workgroups
-  int tb;                // templates per workgroup (32 or 64)
-  int qblk;              // q values per workgroup
 };
 
-// Step 3 + rotation FFT + argmax.
+// Step 3 + rotation FFT + argmax.  Row Qa/2 of Zhat (the Nyquist mode) is
+// folded into row 0 as Zhat(0) + i Zhat(Qa/2) while staging.
 struct Step3Args {
-  const float* zs;       // [pairs][Qa/2][2 H_pad]
+  const float* zs;       // [pairs][Qa/2 + 1][2][H_pad]
   const float* yt;       // [2 H_pad][2 N_pad] real embedding of Y, transposed
   const uint16_t* yt_hi; // split-precision copies (bf16), same layout
   const uint16_t* yt_lo;
@@ -54,9 +49,7 @@ struct Step3Args {
   int nwaves;            // waves per workgroup; each wave owns 16 shifts
 };
 
-size_t step1_lds_bytes(const Step1Args& a);
 size_t step3_lds_bytes(int Qa, int nwaves);
-hipError_t launch_step1(const Step1Args& args, int precision, hipStream_t stream);
 hipError_t launch_step3(const Step3Args& args, int precision, hipStream_t stream);
 // Step 1 with the template operand embedded once per call (kern_step1.hip):
 // staging layout zs[pair][q][c][zeta], q = 0 .. Qa/2 (Qa/2 + 1 rows).
@@ -66,9 +59,7 @@ size_t step1_v2_lds_bytes(int M, int zb, int precision);
 hipError_t launch_step1_v2(const Step1Args& args, int precision, hipStream_t stream);
 
 // split-bf16 forms of the two contractions (kern_align_bf16.hip)
-size_t step1_bf16_lds_bytes(const Step1Args& a);
 size_t step3_bf16_lds_bytes(int Qa, int nwaves);
-hipError_t launch_step1_bf16(const Step1Args& args, hipStream_t stream);
 hipError_t launch_step3_bf16(const Step3Args& args, hipStream_t stream);
 
 hipError_t launch_keys_init(unsigned long long* keys, size_t count, hipStream_t stream);
