@@ -99,7 +99,7 @@ def recall(poses, inputs, shifts, Qa):
     return float(np.mean(best_t == inputs.true_template))
 
 
-def cpu_baseline(inputs, w, shifts, n_img=4, n_tmp=16):
+def cpu_baseline(inputs, w, shifts, n_img=8, n_tmp=48):
     """The FP64 oracle as it stands (direct NUDFT transform + FP64 FTK) on a
     bounded sample of the same workload, timed on the host."""
     from oracle import ftk as O

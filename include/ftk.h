@@ -177,6 +177,8 @@ int ftk_plan_tables(int n, int K, double W, double eps, const double* shifts_px,
  *   1 Step 1: image x template contraction per mode (eq. fbk3)
  *   2 Step 3 + rotation FFT + argmax (eq. fbk3, eq. 1dfft)
  *   3 bookkeeping (pose key init / conversion)
+ *   4 operand preparation (templates embedded, and split for bf16x3,
+ *     into Step 1's lane order, once per call)
  * ftk_plan_profile(plan, 1) enables (and clears), 0 disables.
  * ftk_plan_stage_times waits for the recorded events, writes per-stage sums
  * of elapsed milliseconds and launch counts into ms[nstages] and
@@ -184,6 +186,111 @@ int ftk_plan_tables(int n, int K, double W, double eps, const double* shifts_px,
  * Errors: FTK_EINVAL, FTK_EDEVICE. */
 int ftk_plan_profile(ftk_plan* plan, int enable);
 int ftk_plan_stage_times(ftk_plan* plan, double* ms, int64_t* launches, int nstages);
+
+/* Launch shapes of a plan's alignment kernels.  They change speed only:
+ * every choice gives the same results (each pair's sums are taken in the
+ * same order whatever the shape).  A field left 0 takes the built-in
+ * default (an FTK_STEP3_WAVES, FTK_STEP1_ZBLK or FTK_STAGE_MB environment
+ * variable, read at plan creation, overrides that default).
+ *   step3_waves : most waves per Step 3 workgroup, each wave owning 16
+ *                 shifts; 1..16, lowered to what LDS allows (default 16)
+ *   step1_zblk  : SVD terms per Step 1 workgroup, 64 or 128, lowered to 64
+ *                 when H (padded to 64) is not a multiple of 128 or the
+ *                 tile does not fit LDS (default 128)
+ *   step1_wgs   : Step 1 splits its template sweep until the grid holds
+ *                 about this many workgroups; 64..65536 (default 1024)
+ *   stage_mib   : the Step 1 -> Step 3 staging buffer, MiB; images are
+ *                 processed in chunks that fit; 16..65536 (default 2048) */
+typedef struct ftk_tuning_t {
+  int step3_waves;
+  int step1_zblk;
+  int step1_wgs;
+  int stage_mib;
+} ftk_tuning_t;
+
+/* Set (NULL fields checked, 0 = default) or read the plan's tuning.
+ * ftk_plan_get_tuning reports the values in force, defaults resolved.
+ * Errors: FTK_EINVAL (NULL pointer, value out of range). */
+int ftk_plan_set_tuning(ftk_plan* plan, const ftk_tuning_t* tuning);
+int ftk_plan_get_tuning(const ftk_plan* plan, ftk_tuning_t* out);
+
+/* ---- Ragged batches ---------------------------------------------------
+ * A batch runs many independent alignment problems ("stacks") whose plans
+ * differ in n, K, Q, W (hence H) and N, as one unit of work on one stream.
+ * The paper treats each problem on its own (the method of Section 4 per
+ * image-template set); the batch only schedules them:
+ *   - one device workspace per lane, sized at creation for the largest
+ *     stack, is lent to every plan while its stack runs, so running the
+ *     batch allocates nothing;
+ *   - stacks are ordered by a cost model (Step 1 + Step 3 flop of the
+ *     stack) and dealt to `lanes` streams forked from the caller's stream,
+ *     largest first onto the least loaded lane, so one lane's kernel tails
+ *     overlap the other's work;
+ *   - with FTK_BATCH_GRAPH, the first ftk_batch_run captures every launch
+ *     of every stack (fork and join included) into one hipGraph and each
+ *     run replays it with one hipGraphLaunch;
+ *   - with FTK_BATCH_AUTOTUNE, ftk_batch_create times candidate launch
+ *     shapes (ftk_tuning_t) of each stack's plan on a slice of that stack
+ *     and keeps the fastest; results are cached per shape in the process
+ *     and, if FTK_TUNE_CACHE names a file, across processes (one text line
+ *     per shape).  Tuning changes speed only, never results.
+ * Each stack's outputs equal those of ftk_align on the same plan and
+ * inputs.  The batch keeps the launch shapes of each stack (the plan's
+ * tuning at creation, or the autotuner's choice) and lends them to the
+ * plan while the stack runs; the plans' own tuning is left unchanged. */
+typedef struct ftk_batch ftk_batch;
+
+typedef struct ftk_stack {
+  ftk_plan* plan;          /* plan of this stack, shifts already set */
+  const float* images;     /* device float32 [nA][n][n] */
+  int nA;
+  const float* templates;  /* device float32 [nB][n][n] */
+  int nB;
+  float* X;                /* device float32 [nA][nB][N][Qa] or NULL */
+  ftk_pose* best;          /* device ftk_pose [nA][nB] or NULL */
+} ftk_stack;
+
+enum {
+  FTK_BATCH_GRAPH = 1,     /* capture once, replay as one hipGraph */
+  FTK_BATCH_AUTOTUNE = 2   /* time launch shapes per stack at creation */
+};
+
+typedef struct ftk_batch_info_t {
+  int count;               /* stacks */
+  int lanes;               /* streams the stacks are dealt to */
+  int graph_nodes;         /* nodes of the captured graph (0 before capture) */
+  size_t workspace_bytes;  /* device bytes of all lane workspaces */
+  double cost_gflop;       /* cost model total */
+  double tune_ms;          /* host time spent autotuning at creation */
+} ftk_batch_info_t;
+
+/* Create a batch over `count` stacks (the array is copied; the buffers and
+ * plans it names must outlive the batch and keep their addresses).  Every
+ * stack needs its plan's shifts set, nA, nB >= 0 and, if nA nB > 0, both
+ * pixel pointers and at least one of X, best.  Several stacks may share a
+ * plan.  lanes is 1 or 2.  All device memory the batch needs is allocated
+ * here.  With FTK_BATCH_AUTOTUNE the call runs kernels on `stream` over
+ * the first images and templates of each stack (into batch-owned buffers;
+ * the stacks' outputs are not written) and waits for them.
+ * Errors: FTK_EINVAL, FTK_ESTATE (shifts not set), FTK_ENOMEM,
+ * FTK_EDEVICE and those of ftk_align. */
+int ftk_batch_create(ftk_batch** out, const ftk_stack* stacks, int count, int lanes, int flags, void* stream);
+
+/* Run every stack once, asynchronously on `stream`.  Allocates nothing
+ * (workspaces were sized at creation).  With FTK_BATCH_GRAPH the first run
+ * captures the graph on `stream` (which must not be the null stream:
+ * FTK_EINVAL) and launches it; later runs only launch it.  Inputs may change between runs;
+ * shapes, plans and buffer addresses may not.  A batch is not thread safe
+ * and its runs on different streams must not overlap.  While a batch
+ * runs, its plans must not be used by other calls.  Errors: FTK_EINVAL,
+ * FTK_EDEVICE and those of ftk_align. */
+int ftk_batch_run(ftk_batch* batch, void* stream);
+
+int ftk_batch_info(const ftk_batch* batch, ftk_batch_info_t* out);
+
+/* Release the batch (graph, streams, workspaces).  NULL is allowed.  Work
+ * in flight must be finished first. */
+void ftk_batch_destroy(ftk_batch* batch);
 
 /* Static name of a status code. */
 const char* ftk_strerror(int status);

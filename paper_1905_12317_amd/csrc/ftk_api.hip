@@ -10,17 +10,13 @@
 #include <string>
 #include <vector>
 
-#include "ftk.h"
-#include "kernels.h"
-#include "planner.h"
+#include "plan_internal.h"
+
+namespace ftkint {
 
 namespace {
-
-constexpr double kPi = 3.14159265358979323846264338327950288;
-constexpr int kNufftWidth = 8;
-constexpr size_t kLdsLimit = 160 * 1024;
-
 thread_local std::string g_last_error;
+}  // namespace
 
 int fail(int code, const std::string& msg) {
   g_last_error = msg;
@@ -31,7 +27,78 @@ int hip_fail(hipError_t e, const char* where) {
   return fail(FTK_EDEVICE, std::string(where) + ": " + hipGetErrorString(e));
 }
 
-int round_up(int x, int m) { return (x + m - 1) / m * m; }
+size_t env_mib(const char* name, size_t dflt_mib) {
+  const char* v = std::getenv(name);
+  if (!v || !*v) return dflt_mib;
+  char* end = nullptr;
+  unsigned long long x = std::strtoull(v, &end, 10);
+  if (end == v || x == 0) return dflt_mib;
+  return static_cast<size_t>(x);
+}
+
+void DevBuf::release() {
+  if (ptr) (void)hipFree(ptr);
+  ptr = nullptr;
+  bytes = 0;
+}
+
+hipError_t DevBuf::ensure(size_t want) {
+  if (want <= bytes) return hipSuccess;
+  release();
+  hipError_t e = hipMalloc(&ptr, want);
+  if (e != hipSuccess) {
+    ptr = nullptr;
+    return e;
+  }
+  bytes = want;
+  return hipSuccess;
+}
+
+hipEvent_t StageTimer::get() {
+  if (!pool.empty()) {
+    hipEvent_t e = pool.back();
+    pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+hipEvent_t StageTimer::begin(hipStream_t s) {
+  if (!on) return nullptr;
+  hipEvent_t e = get();
+  if (e) (void)hipEventRecord(e, s);
+  return e;
+}
+
+void StageTimer::end(hipEvent_t a, hipStream_t s, int stage) {
+  if (!on || !a) return;
+  hipEvent_t b = get();
+  if (!b) return;
+  (void)hipEventRecord(b, s);
+  recs.push_back({a, b, stage});
+}
+
+void StageTimer::clear() {
+  for (auto& r : recs) {
+    pool.push_back(r.a);
+    pool.push_back(r.b);
+  }
+  recs.clear();
+}
+
+void StageTimer::destroy() {
+  clear();
+  for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+  pool.clear();
+}
+
+}  // namespace ftkint
+
+using namespace ftkint;
+
+namespace {
 
 // bf16 bits of a float, round to nearest even (NaN kept quiet)
 uint16_t bf16_rne(float f) {
@@ -48,51 +115,6 @@ double bf16_value(uint16_t h) {
   std::memcpy(&f, &u, 4);
   return f;
 }
-
-size_t env_bytes(const char* name, size_t dflt) {
-  const char* v = std::getenv(name);
-  if (!v || !*v) return dflt;
-  char* end = nullptr;
-  unsigned long long mb = std::strtoull(v, &end, 10);
-  if (end == v || mb == 0) return dflt;
-  return static_cast<size_t>(mb) << 20;
-}
-
-struct DevBuf {
-  void* ptr = nullptr;
-  size_t bytes = 0;
-  void release() {
-    if (ptr) (void)hipFree(ptr);
-    ptr = nullptr;
-    bytes = 0;
-  }
-  hipError_t ensure(size_t want) {
-    if (want <= bytes) return hipSuccess;
-    release();
-    hipError_t e = hipMalloc(&ptr, want);
-    if (e != hipSuccess) {
-      ptr = nullptr;
-      return e;
-    }
-    bytes = want;
-    return hipSuccess;
-  }
-  template <class T>
-  T* as() const {
-    return static_cast<T*>(ptr);
-  }
-};
-
-// Per-mode factor tables, FP64 (Section 4.5).
-struct HostTables {
-  int H = 0, L = 0;
-  double sigma_next = 0;
-  std::vector<int> ell, eta;
-  std::vector<double> sigma;
-  std::vector<double> k, w;  // radial rule
-  std::vector<double> G;     // [H][M] Sigma v(k_m / kmax), sign (-1)^l for l < 0
-  ftkplan::Truncation tr;
-};
 
 int build_tables(int n, int M, double W, double eps, HostTables& t) {
   const double kmax = 0.5 * kPi * n;
@@ -159,80 +181,6 @@ int build_Y(const HostTables& t, const double* shifts, int N, double W, std::vec
   }
   return FTK_OK;
 }
-
-}  // namespace
-
-// Events around kernel launches, per stage (see ftk_plan_profile).
-struct StageTimer {
-  static constexpr int kStages = 4;
-  bool on = false;
-  struct Rec {
-    hipEvent_t a, b;
-    int stage;
-  };
-  std::vector<Rec> recs;
-  std::vector<hipEvent_t> pool;
-  hipEvent_t get() {
-    if (!pool.empty()) {
-      hipEvent_t e = pool.back();
-      pool.pop_back();
-      return e;
-    }
-    hipEvent_t e = nullptr;
-    if (hipEventCreate(&e) != hipSuccess) return nullptr;
-    return e;
-  }
-  hipEvent_t begin(hipStream_t s) {
-    if (!on) return nullptr;
-    hipEvent_t e = get();
-    if (e) (void)hipEventRecord(e, s);
-    return e;
-  }
-  void end(hipEvent_t a, hipStream_t s, int stage) {
-    if (!on || !a) return;
-    hipEvent_t b = get();
-    if (!b) return;
-    (void)hipEventRecord(b, s);
-    recs.push_back({a, b, stage});
-  }
-  void clear() {
-    for (auto& r : recs) {
-      pool.push_back(r.a);
-      pool.push_back(r.b);
-    }
-    recs.clear();
-  }
-  void destroy() {
-    clear();
-    for (hipEvent_t e : pool) (void)hipEventDestroy(e);
-    pool.clear();
-  }
-};
-
-struct ftk_plan {
-  StageTimer timer;
-  int n = 0, M = 0, Qa = 0, precision = 0;
-  double W = 0, eps = 0, kmax = 0;
-  HostTables t;
-  int H_pad = 0, N = 0, N_pad = 0;
-  ftkplan::SpreadKernel sk;
-  // plan-owned device tables
-  DevBuf cz, ell, yt, yt_hi, yt_lo, tw_nf, tw_qa, deapod, ptbase, ptker;
-  // workspace
-  DevBuf ws_tr_h, ws_tr_g, ws_coef_a, ws_coef_b, ws_stage, ws_keys, ws_tmpl;
-  size_t device_bytes() const {
-    return cz.bytes + ell.bytes + yt.bytes + yt_hi.bytes + yt_lo.bytes + tw_nf.bytes + tw_qa.bytes +
-           deapod.bytes + ptbase.bytes + ptker.bytes + ws_tr_h.bytes + ws_tr_g.bytes + ws_coef_a.bytes +
-           ws_coef_b.bytes + ws_stage.bytes + ws_keys.bytes + ws_tmpl.bytes;
-  }
-  void release_all() {
-    for (DevBuf* b : {&cz, &ell, &yt, &yt_hi, &yt_lo, &tw_nf, &tw_qa, &deapod, &ptbase, &ptker, &ws_tr_h,
-                      &ws_tr_g, &ws_coef_a, &ws_coef_b, &ws_stage, &ws_keys, &ws_tmpl})
-      b->release();
-  }
-};
-
-namespace {
 
 template <class T>
 hipError_t upload(DevBuf& b, const std::vector<T>& v) {
@@ -315,6 +263,63 @@ int check_plan_args(int n, int K, int Q, double W, double eps, int precision) {
 
 }  // namespace
 
+namespace ftkint {
+
+ftk_tuning_t default_tuning() {
+  ftk_tuning_t t;
+  t.step3_waves = static_cast<int>(std::min<size_t>(16, env_mib("FTK_STEP3_WAVES", 16)));
+  t.step1_zblk = env_mib("FTK_STEP1_ZBLK", 128) == 64 ? 64 : 128;
+  t.step1_wgs = static_cast<int>(std::min<size_t>(65536, std::max<size_t>(64, env_mib("FTK_STEP1_WGS", 1024))));
+  t.stage_mib = static_cast<int>(std::min<size_t>(65536, std::max<size_t>(16, env_mib("FTK_STAGE_MB", 2048))));
+  return t;
+}
+
+int step3_waves(const ftk_plan* p) {
+  const int units = (p->N + 15) / 16;
+  // each wave owns 16 shifts; more than 8 waves only below Qa = 320, where
+  // the staging and FFT buffers of 16 waves still fit LDS
+  int maxw = std::max(1, std::min(p->tune.step3_waves, (p->Qa / 64 > 4) ? 8 : 16));
+  const bool split = p->precision == FTK_BF16X3;
+  auto lds = [&](int w) { return split ? step3_bf16_lds_bytes(p->Qa, w) : step3_lds_bytes(p->Qa, w); };
+  while (maxw > 1 && lds(maxw) > kLdsLimit) --maxw;
+  const int nblk = (units + maxw - 1) / maxw;
+  return (units + nblk - 1) / nblk;
+}
+
+int step1_zblk(const ftk_plan* p) {
+  const int prec = p->precision == FTK_BF16X3 ? 1 : 0;
+  int z = p->tune.step1_zblk;
+  if (p->H_pad % z != 0 || step1_v2_lds_bytes(p->M, z, prec) > kLdsLimit) z = 64;
+  return z;
+}
+
+Needs plan_needs(const ftk_plan* p, int nA, int nB, bool from_pixels) {
+  Needs d;
+  const size_t n = p->n, nf = p->sk.nf;
+  const size_t cb = static_cast<size_t>(8) * p->M * p->Qa;
+  if (from_pixels) {
+    const int cnt = std::max(nA, nB);
+    const size_t per_img = (n * nf + nf * nf) * sizeof(float2);
+    const size_t budget = env_mib("FTK_TRANSFORM_SCRATCH_MB", 512) << 20;
+    d.transform_chunk = static_cast<int>(std::min<size_t>(std::max<size_t>(1, budget / per_img), std::max(cnt, 1)));
+    d.tr_h = static_cast<size_t>(d.transform_chunk) * n * nf * sizeof(float2);
+    d.tr_g = static_cast<size_t>(d.transform_chunk) * nf * nf * sizeof(float2);
+    d.coef_a = cb * nA;
+    d.coef_b = cb * nB;
+  }
+  if (nA > 0 && nB > 0) {
+    const size_t per_pair = static_cast<size_t>(p->Qa / 2 + 1) * 2 * p->H_pad * sizeof(float);
+    const size_t budget = static_cast<size_t>(p->tune.stage_mib) << 20;
+    d.chunk_images = static_cast<int>(std::min<size_t>(nA, std::max<size_t>(1, budget / (per_pair * nB))));
+    d.stage = static_cast<size_t>(d.chunk_images) * nB * per_pair;
+    d.keys = static_cast<size_t>(nA) * nB * sizeof(unsigned long long);
+    d.tmpl = tmpl_prep_bytes(nB, p->M, p->Qa, p->precision == FTK_BF16X3 ? 1 : 0);
+  }
+  return d;
+}
+
+}  // namespace ftkint
+
 extern "C" {
 
 const char* ftk_strerror(int status) {
@@ -377,6 +382,7 @@ int ftk_plan_create(ftk_plan** out, int n, int K, int Q, double W, double eps, i
     p->eps = eps;
     p->precision = precision;
     p->kmax = 0.5 * kPi * n;
+    p->tune = default_tuning();
     build_tables(n, K, W, eps, p->t);
     p->H_pad = round_up(std::max(p->t.H, 1), 64);
     p->sk = ftkplan::spread_kernel(n, kNufftWidth);
@@ -490,23 +496,20 @@ int ftk_transform(ftk_plan* p, const float* imgs, int cnt, void* coeffs, void* s
   if (!imgs || !coeffs) return fail(FTK_EINVAL, "ftk_transform: NULL buffer");
   hipStream_t s = static_cast<hipStream_t>(stream);
   const int n = p->n, nf = p->sk.nf;
-  const size_t per_img = (static_cast<size_t>(n) * nf + static_cast<size_t>(nf) * nf) * sizeof(float2);
-  const size_t budget = env_bytes("FTK_TRANSFORM_SCRATCH_MB", size_t(512) << 20);
-  int chunk = static_cast<int>(std::max<size_t>(1, budget / per_img));
-  chunk = std::min(chunk, cnt);
-  hipError_t e;
-  if ((e = p->ws_tr_h.ensure(static_cast<size_t>(chunk) * n * nf * sizeof(float2))) != hipSuccess)
-    return fail(FTK_ENOMEM, "ftk_transform: scratch");
-  if ((e = p->ws_tr_g.ensure(static_cast<size_t>(chunk) * nf * nf * sizeof(float2))) != hipSuccess)
+  const Needs nd = plan_needs(p, cnt, 0, true);
+  const int chunk = nd.transform_chunk;
+  Workspace& ws = *p->ws;
+  if (ws.tr_h.ensure(nd.tr_h) != hipSuccess || ws.tr_g.ensure(nd.tr_g) != hipSuccess)
     return fail(FTK_ENOMEM, "ftk_transform: scratch");
   if (transform_lds_bytes(nf, p->Qa, 4) > kLdsLimit) return fail(FTK_EUNSUPPORTED, "ftk_transform: LDS");
+  hipError_t e;
   for (int c0 = 0; c0 < cnt; c0 += chunk) {
     const int c = std::min(chunk, cnt - c0);
     TransformArgs a;
     a.imgs = imgs + static_cast<size_t>(c0) * n * n;
     a.coeffs = static_cast<float2*>(coeffs) + static_cast<size_t>(c0) * p->Qa * p->M;
-    a.scratchH = p->ws_tr_h.as<float2>();
-    a.scratchG = p->ws_tr_g.as<float2>();
+    a.scratchH = ws.tr_h.as<float2>();
+    a.scratchG = ws.tr_g.as<float2>();
     a.deapod = p->deapod.as<float>();
     a.tw_nf = p->tw_nf.as<float2>();
     a.tw_qa = p->tw_qa.as<float2>();
@@ -535,46 +538,41 @@ int ftk_align_coeffs(ftk_plan* p, const void* img_coeffs, int nA, const void* tm
   hipStream_t s = static_cast<hipStream_t>(stream);
   const int QH = p->Qa / 2;
   const size_t pairs = static_cast<size_t>(nA) * nB;
-  const size_t per_pair = static_cast<size_t>(QH + 1) * 2 * p->H_pad * sizeof(float);
-  const size_t budget = env_bytes("FTK_STAGE_MB", size_t(2048) << 20);
   const bool split = p->precision == FTK_BF16X3;
-  int chunkA = static_cast<int>(std::max<size_t>(1, budget / (per_pair * nB)));
-  chunkA = std::min(chunkA, nA);
+  const int prec = split ? 1 : 0;
+  const Needs nd = plan_needs(p, nA, nB, false);
+  const int chunkA = nd.chunk_images;
+  Workspace& ws = *p->ws;
+  if (ws.stage.ensure(nd.stage) != hipSuccess) return fail(FTK_ENOMEM, "ftk_align: staging buffer");
+  if (ws.keys.ensure(nd.keys) != hipSuccess) return fail(FTK_ENOMEM, "ftk_align: key buffer");
+  if (ws.tmpl.ensure(nd.tmpl) != hipSuccess) return fail(FTK_ENOMEM, "ftk_align: template operand buffer");
+  const int zblk = step1_zblk(p);
+  if (step1_v2_lds_bytes(p->M, zblk, prec) > kLdsLimit) return fail(FTK_EUNSUPPORTED, "ftk_align: step 1 tiles exceed LDS");
+  unsigned long long* keys = ws.keys.as<unsigned long long>();
   hipError_t e;
-  if ((e = p->ws_stage.ensure(static_cast<size_t>(chunkA) * nB * per_pair)) != hipSuccess)
-    return fail(FTK_ENOMEM, "ftk_align: staging buffer");
-  if ((e = p->ws_keys.ensure(pairs * sizeof(unsigned long long))) != hipSuccess)
-    return fail(FTK_ENOMEM, "ftk_align: key buffer");
-  unsigned long long* keys = p->ws_keys.as<unsigned long long>();
   hipEvent_t ev = p->timer.begin(s);
   if ((e = launch_keys_init(keys, pairs, s)) != hipSuccess) return hip_fail(e, "ftk_align: keys init");
   p->timer.end(ev, s, 3);
   // template operand of Step 1: embedded (and split) once per call
-  const int prec = split ? 1 : 0;
-  if ((e = p->ws_tmpl.ensure(tmpl_prep_bytes(nB, p->M, p->Qa, prec))) != hipSuccess)
-    return fail(FTK_ENOMEM, "ftk_align: template operand buffer");
   ev = p->timer.begin(s);
-  if ((e = launch_tmpl_prep(static_cast<const float2*>(tmpl_coeffs), p->ws_tmpl.ptr, nB, p->M, p->Qa, prec, s)) !=
+  if ((e = launch_tmpl_prep(static_cast<const float2*>(tmpl_coeffs), ws.tmpl.ptr, nB, p->M, p->Qa, prec, s)) !=
       hipSuccess)
     return hip_fail(e, "ftk_align: template operand");
-  p->timer.end(ev, s, 1);
+  p->timer.end(ev, s, 4);
 
   Step1Args a1{};
   a1.cz = p->cz.as<float>();
   a1.ell = p->ell.as<int>();
-  a1.zs = p->ws_stage.as<float>();
+  a1.zs = ws.stage.as<float>();
   a1.b = static_cast<const float2*>(tmpl_coeffs);
-  a1.r32 = p->ws_tmpl.as<float>();
-  a1.r16 = p->ws_tmpl.ptr;
+  a1.r32 = ws.tmpl.as<float>();
+  a1.r16 = ws.tmpl.ptr;
   a1.nB = nB;
   a1.M = p->M;
   a1.Qa = p->Qa;
   a1.H_pad = p->H_pad;
   a1.L = p->t.L;
-  a1.zblk = (p->H_pad % 128 == 0) ? 128 : 64;
-  if (step1_v2_lds_bytes(p->M, a1.zblk, prec) > kLdsLimit) a1.zblk = 64;
-  if (step1_v2_lds_bytes(p->M, a1.zblk, prec) > kLdsLimit)
-    return fail(FTK_EUNSUPPORTED, "ftk_align: step 1 tiles exceed LDS");
+  a1.zblk = zblk;
   Step3Args a3{};
   a3.yt = p->yt.as<float>();
   a3.yt_hi = p->yt_hi.as<uint16_t>();
@@ -584,32 +582,22 @@ int ftk_align_coeffs(ftk_plan* p, const void* img_coeffs, int nA, const void* tm
   a3.H_pad = p->H_pad;
   a3.N = p->N;
   a3.N_pad = p->N_pad;
-  {
-    const int units = (p->N + 15) / 16;
-    // waves per workgroup: at most 8 lets two workgroups share a CU, so one
-    // workgroup's FFT epilogue overlaps the other's MFMA loop
-    int maxw = static_cast<int>(env_bytes("FTK_STEP3_MAXW", size_t(8) << 20) >> 20);
-    maxw = std::max(1, std::min(maxw, (p->Qa / 64 > 4) ? 8 : 16));
-    auto lds3 = [&](int w) { return split ? step3_bf16_lds_bytes(p->Qa, w) : step3_lds_bytes(p->Qa, w); };
-    while (maxw > 1 && lds3(maxw) > kLdsLimit) --maxw;
-    const int nblk = (units + maxw - 1) / maxw;
-    a3.nwaves = (units + nblk - 1) / nblk;
-  }
+  a3.nwaves = step3_waves(p);
   for (int A0 = 0; A0 < nA; A0 += chunkA) {
     const int na = std::min(chunkA, nA - A0);
     a1.a = static_cast<const float2*>(img_coeffs) + static_cast<size_t>(A0) * p->Qa * p->M;
     a1.nA = na;
     {
-      // split the template sweep until the grid holds about 4 workgroups per CU
+      // split the template sweep until the grid holds about step1_wgs workgroups
       const int base = na * (QH + 1) * (p->H_pad / a1.zblk);
       const int max_parts = std::max(1, ((nB + 15) / 16 + 7) / 8);
-      a1.tparts = std::min(max_parts, std::max(1, (1024 + base - 1) / base));
+      a1.tparts = std::min(max_parts, std::max(1, (p->tune.step1_wgs + base - 1) / base));
     }
     ev = p->timer.begin(s);
     e = launch_step1_v2(a1, prec, s);
     if (e != hipSuccess) return hip_fail(e, "ftk_align: step 1");
     p->timer.end(ev, s, 1);
-    a3.zs = p->ws_stage.as<float>();
+    a3.zs = ws.stage.as<float>();
     a3.pairs = na * nB;
     a3.keys = keys + static_cast<size_t>(A0) * nB;
     a3.X = X ? X + static_cast<size_t>(A0) * nB * p->N * p->Qa : nullptr;
@@ -635,15 +623,38 @@ int ftk_align(ftk_plan* p, const float* images, int nA, const float* templates, 
   if (nA == 0 || nB == 0) return FTK_OK;
   if (!X && !best) return fail(FTK_EINVAL, "ftk_align: X and best are both NULL");
   if (!images || !templates) return fail(FTK_EINVAL, "ftk_align: NULL images");
-  const size_t cb = static_cast<size_t>(8) * p->M * p->Qa;
-  hipError_t e;
-  if ((e = p->ws_coef_a.ensure(cb * nA)) != hipSuccess) return fail(FTK_ENOMEM, "ftk_align: coefficients");
-  if ((e = p->ws_coef_b.ensure(cb * nB)) != hipSuccess) return fail(FTK_ENOMEM, "ftk_align: coefficients");
-  int rc = ftk_transform(p, images, nA, p->ws_coef_a.ptr, stream);
+  const Needs nd = plan_needs(p, nA, nB, true);
+  Workspace& ws = *p->ws;
+  if (ws.coef_a.ensure(nd.coef_a) != hipSuccess || ws.coef_b.ensure(nd.coef_b) != hipSuccess)
+    return fail(FTK_ENOMEM, "ftk_align: coefficients");
+  int rc = ftk_transform(p, images, nA, ws.coef_a.ptr, stream);
   if (rc != FTK_OK) return rc;
-  rc = ftk_transform(p, templates, nB, p->ws_coef_b.ptr, stream);
+  rc = ftk_transform(p, templates, nB, ws.coef_b.ptr, stream);
   if (rc != FTK_OK) return rc;
-  return ftk_align_coeffs(p, p->ws_coef_a.ptr, nA, p->ws_coef_b.ptr, nB, X, best, stream);
+  return ftk_align_coeffs(p, ws.coef_a.ptr, nA, ws.coef_b.ptr, nB, X, best, stream);
+}
+
+int ftk_plan_set_tuning(ftk_plan* p, const ftk_tuning_t* t) {
+  if (!p || !t) return fail(FTK_EINVAL, "ftk_plan_set_tuning: NULL argument");
+  if (t->step3_waves < 0 || t->step3_waves > 16) return fail(FTK_EINVAL, "step3_waves must be in [0, 16]");
+  if (t->step1_zblk != 0 && t->step1_zblk != 64 && t->step1_zblk != 128)
+    return fail(FTK_EINVAL, "step1_zblk must be 0, 64 or 128");
+  if (t->step1_wgs != 0 && (t->step1_wgs < 64 || t->step1_wgs > 65536))
+    return fail(FTK_EINVAL, "step1_wgs must be 0 or in [64, 65536]");
+  if (t->stage_mib != 0 && (t->stage_mib < 16 || t->stage_mib > 65536))
+    return fail(FTK_EINVAL, "stage_mib must be 0 or in [16, 65536]");
+  const ftk_tuning_t d = default_tuning();
+  p->tune.step3_waves = t->step3_waves ? t->step3_waves : d.step3_waves;
+  p->tune.step1_zblk = t->step1_zblk ? t->step1_zblk : d.step1_zblk;
+  p->tune.step1_wgs = t->step1_wgs ? t->step1_wgs : d.step1_wgs;
+  p->tune.stage_mib = t->stage_mib ? t->stage_mib : d.stage_mib;
+  return FTK_OK;
+}
+
+int ftk_plan_get_tuning(const ftk_plan* p, ftk_tuning_t* out) {
+  if (!p || !out) return fail(FTK_EINVAL, "ftk_plan_get_tuning: NULL argument");
+  *out = p->tune;
+  return FTK_OK;
 }
 
 int ftk_plan_profile(ftk_plan* p, int enable) {

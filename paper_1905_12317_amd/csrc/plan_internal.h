@@ -1,0 +1,117 @@
+// Internal definition of the FTK plan object, shared by the C-ABI sources.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <complex>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "ftk.h"
+#include "kernels.h"
+#include "planner.h"
+
+namespace ftkint {
+
+constexpr double kPi = 3.14159265358979323846264338327950288;
+constexpr int kNufftWidth = 8;
+constexpr size_t kLdsLimit = 160 * 1024;
+
+int fail(int code, const std::string& msg);
+int hip_fail(hipError_t e, const char* where);
+size_t env_mib(const char* name, size_t dflt_mib);
+inline int round_up(int x, int m) { return (x + m - 1) / m * m; }
+
+// A device allocation that only grows.  ensure() never allocates when the
+// buffer is already large enough, so work issued during graph capture does
+// not allocate once the buffers are sized.
+struct DevBuf {
+  void* ptr = nullptr;
+  size_t bytes = 0;
+  void release();
+  hipError_t ensure(size_t want);
+  template <class T>
+  T* as() const {
+    return static_cast<T*>(ptr);
+  }
+};
+
+// Events around kernel launches, per stage (see ftk_plan_profile).
+struct StageTimer {
+  bool on = false;
+  struct Rec {
+    hipEvent_t a, b;
+    int stage;
+  };
+  std::vector<Rec> recs;
+  std::vector<hipEvent_t> pool;
+  hipEvent_t get();
+  hipEvent_t begin(hipStream_t s);
+  void end(hipEvent_t a, hipStream_t s, int stage);
+  void clear();
+  void destroy();
+};
+
+// Per-mode factor tables, FP64 (Section 4.5 of the paper).
+struct HostTables {
+  int H = 0, L = 0;
+  double sigma_next = 0;
+  std::vector<int> ell, eta;
+  std::vector<double> sigma;
+  std::vector<double> k, w;  // radial rule
+  std::vector<double> G;     // [H][M] Sigma v(k_m / kmax), sign (-1)^l for l < 0
+  ftkplan::Truncation tr;
+};
+
+// Scratch of the transform and the alignment.  A plan owns one; a batch
+// lends a shared one to each of its plans while it runs them.
+struct Workspace {
+  DevBuf tr_h, tr_g, coef_a, coef_b, stage, keys, tmpl;
+  size_t bytes() const {
+    return tr_h.bytes + tr_g.bytes + coef_a.bytes + coef_b.bytes + stage.bytes + keys.bytes + tmpl.bytes;
+  }
+  void release() {
+    for (DevBuf* b : {&tr_h, &tr_g, &coef_a, &coef_b, &stage, &keys, &tmpl}) b->release();
+  }
+};
+
+// Workspace sizes a call needs (the same formulas size and use the buffers).
+struct Needs {
+  size_t tr_h = 0, tr_g = 0, coef_a = 0, coef_b = 0, stage = 0, keys = 0, tmpl = 0;
+  int chunk_images = 0;     // images per Step 1 / Step 3 chunk
+  int transform_chunk = 0;  // images per transform launch
+};
+
+}  // namespace ftkint
+
+struct ftk_plan {
+  ftkint::StageTimer timer;
+  int n = 0, M = 0, Qa = 0, precision = 0;
+  double W = 0, eps = 0, kmax = 0;
+  ftkint::HostTables t;
+  int H_pad = 0, N = 0, N_pad = 0;
+  ftkplan::SpreadKernel sk;
+  ftk_tuning_t tune{};
+  // plan-owned device tables
+  ftkint::DevBuf cz, ell, yt, yt_hi, yt_lo, tw_nf, tw_qa, deapod, ptbase, ptker;
+  ftkint::Workspace own_ws;
+  ftkint::Workspace* ws = &own_ws;
+  size_t device_bytes() const {
+    return cz.bytes + ell.bytes + yt.bytes + yt_hi.bytes + yt_lo.bytes + tw_nf.bytes + tw_qa.bytes +
+           deapod.bytes + ptbase.bytes + ptker.bytes + own_ws.bytes();
+  }
+  void release_all() {
+    for (ftkint::DevBuf* b : {&cz, &ell, &yt, &yt_hi, &yt_lo, &tw_nf, &tw_qa, &deapod, &ptbase, &ptker}) b->release();
+    own_ws.release();
+  }
+};
+
+namespace ftkint {
+// Built-in launch shapes (environment overrides applied).
+ftk_tuning_t default_tuning();
+Needs plan_needs(const ftk_plan* p, int nA, int nB, bool from_pixels);
+// Step 3 waves per workgroup and Step 1 zeta block actually used by a plan.
+int step3_waves(const ftk_plan* p);
+int step1_zblk(const ftk_plan* p);
+}  // namespace ftkint

@@ -40,12 +40,39 @@ class PlanInfo(ctypes.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_}
 
 
+class Tuning(ctypes.Structure):
+    _fields_ = [("step3_waves", ctypes.c_int), ("step1_zblk", ctypes.c_int), ("step1_wgs", ctypes.c_int),
+                ("stage_mib", ctypes.c_int)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class Stack(ctypes.Structure):
+    _fields_ = [("plan", ctypes.c_void_p), ("images", ctypes.c_void_p), ("nA", ctypes.c_int),
+                ("templates", ctypes.c_void_p), ("nB", ctypes.c_int), ("X", ctypes.c_void_p),
+                ("best", ctypes.c_void_p)]
+
+
+class BatchInfo(ctypes.Structure):
+    _fields_ = [("count", ctypes.c_int), ("lanes", ctypes.c_int), ("graph_nodes", ctypes.c_int),
+                ("workspace_bytes", ctypes.c_size_t), ("cost_gflop", ctypes.c_double),
+                ("tune_ms", ctypes.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+FTK_BATCH_GRAPH = 1
+FTK_BATCH_AUTOTUNE = 2
+
 POSE_DTYPE = np.dtype([("value", np.float32), ("shift", np.int32), ("rot", np.int32)])
 
 #: every symbol include/ftk.h declares
 EXPORTS = ["ftk_plan_create", "ftk_plan_destroy", "ftk_plan_info", "ftk_set_shifts", "ftk_transform",
            "ftk_align_coeffs", "ftk_align", "ftk_plan_tables", "ftk_plan_profile", "ftk_plan_stage_times",
-           "ftk_strerror", "ftk_last_error_message"]
+           "ftk_plan_set_tuning", "ftk_plan_get_tuning", "ftk_batch_create", "ftk_batch_run", "ftk_batch_info",
+           "ftk_batch_destroy", "ftk_strerror", "ftk_last_error_message"]
 
 _lib = None
 
@@ -71,6 +98,13 @@ def lib() -> ctypes.CDLL:
                                   ctypes.POINTER(d)]
     L.ftk_plan_profile.argtypes = [vp, i]
     L.ftk_plan_stage_times.argtypes = [vp, vp, vp, i]
+    L.ftk_plan_set_tuning.argtypes = [vp, ctypes.POINTER(Tuning)]
+    L.ftk_plan_get_tuning.argtypes = [vp, ctypes.POINTER(Tuning)]
+    L.ftk_batch_create.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(Stack), i, i, i, vp]
+    L.ftk_batch_run.argtypes = [vp, vp]
+    L.ftk_batch_info.argtypes = [vp, ctypes.POINTER(BatchInfo)]
+    L.ftk_batch_destroy.argtypes = [vp]
+    L.ftk_batch_destroy.restype = None
     L.ftk_strerror.restype = ctypes.c_char_p
     L.ftk_strerror.argtypes = [i]
     L.ftk_last_error_message.restype = ctypes.c_char_p
@@ -165,7 +199,7 @@ class Plan:
         _check(lib().ftk_plan_info(self._h, ctypes.byref(inf)), "ftk_plan_info")
         return inf.as_dict()
 
-    STAGES = ("transform", "step1", "step3", "bookkeeping")
+    STAGES = ("transform", "step1", "step3", "bookkeeping", "operand_prep")
 
     def profile(self, enable: bool = True):
         _check(lib().ftk_plan_profile(self._h, 1 if enable else 0), "ftk_plan_profile")
@@ -177,6 +211,15 @@ class Plan:
         _check(lib().ftk_plan_stage_times(self._h, ms.ctypes.data, cnt.ctypes.data, len(self.STAGES)),
                "ftk_plan_stage_times")
         return {name: (float(ms[i]), int(cnt[i])) for i, name in enumerate(self.STAGES)}
+
+    def tuning(self) -> dict:
+        t = Tuning()
+        _check(lib().ftk_plan_get_tuning(self._h, ctypes.byref(t)), "ftk_plan_get_tuning")
+        return t.as_dict()
+
+    def set_tuning(self, step3_waves=0, step1_zblk=0, step1_wgs=0, stage_mib=0):
+        t = Tuning(step3_waves, step1_zblk, step1_wgs, stage_mib)
+        _check(lib().ftk_plan_set_tuning(self._h, ctypes.byref(t)), "ftk_plan_set_tuning")
 
     def set_shifts(self, shifts_px):
         sh = np.ascontiguousarray(shifts_px, dtype=np.float64).reshape(-1, 2)
@@ -218,6 +261,54 @@ class Plan:
         _check(lib().ftk_align(self._h, _ptr(images), images.shape[0], _ptr(templates), templates.shape[0],
                                _ptr(X), _ptr(best), _stream(stream)), "ftk_align")
         return X, best
+
+
+class Batch:
+    """Owns an ftk_batch over stacks (plan, images, templates[, X], best).
+
+    The torch tensors of every stack are kept referenced for the batch's
+    lifetime (the C object holds their addresses)."""
+
+    def __init__(self, stacks, lanes: int = 1, graph: bool = False, autotune: bool = False, stream=None):
+        import torch
+        arr = (Stack * max(1, len(stacks)))()
+        self._keep = []
+        for i, st in enumerate(stacks):
+            plan, imgs, tmps = st["plan"], st["images"], st["templates"]
+            _require_cuda(imgs, torch.float32, "images")
+            _require_cuda(tmps, torch.float32, "templates")
+            X, best = st.get("X"), st.get("best")
+            if best is not None:
+                _require_cuda(best, torch.int32, "best")
+            if X is not None:
+                _require_cuda(X, torch.float32, "X")
+            arr[i] = Stack(plan._h.value, imgs.data_ptr(), imgs.shape[0], tmps.data_ptr(), tmps.shape[0],
+                           X.data_ptr() if X is not None else None, best.data_ptr() if best is not None else None)
+            self._keep.append((plan, imgs, tmps, X, best))
+        flags = (FTK_BATCH_GRAPH if graph else 0) | (FTK_BATCH_AUTOTUNE if autotune else 0)
+        h = ctypes.c_void_p()
+        _check(lib().ftk_batch_create(ctypes.byref(h), arr, len(stacks), lanes, flags, _stream(stream)),
+               "ftk_batch_create")
+        self._h = h
+
+    def run(self, stream=None):
+        _check(lib().ftk_batch_run(self._h, _stream(stream)), "ftk_batch_run")
+
+    def info(self) -> dict:
+        inf = BatchInfo()
+        _check(lib().ftk_batch_info(self._h, ctypes.byref(inf)), "ftk_batch_info")
+        return inf.as_dict()
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().ftk_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def poses_numpy(best) -> np.ndarray:
