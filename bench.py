@@ -35,6 +35,29 @@ PEAK_FP32_MFMA = 157.3e12
 PEAK_BF16_MFMA = 2.5e15
 PEAK_HBM = 8.0e12
 
+# HBM bytes per Step 3 launch on this workload, from rocprofv3 FETCH_SIZE and
+# WRITE_SIZE (scaled by a 1 GiB copy: x2.000 and x1.000), with the SHA-1 of
+# the kernel sources they were taken on; a changed kernel reports null.
+# Source: profiles/step3_<form>_cryoem_n128.md.
+TRAFFIC = {
+    "bf16x3": {"bytes_per_launch": 1.979e9, "sources": ["kern_align_bf16.hip", "device_common.h", "kernels.h"],
+               "sha1": "198454c973ab97fce6fc65c1b050615ff55b03a3"},
+    "fp32": {"bytes_per_launch": 1.947e9, "sources": ["kern_align.hip", "device_common.h", "kernels.h"],
+             "sha1": "cabab2a75e782c8bc8b41310b0042a7371882c1f"},
+}
+
+
+def measured_traffic(form):
+    import hashlib
+    t = TRAFFIC.get(form)
+    if t is None:
+        return None
+    h = hashlib.sha1()
+    for name in t["sources"]:
+        with open(os.path.join(ROOT, "paper_1905_12317_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return t["bytes_per_launch"] if h.hexdigest() == t["sha1"] else None
+
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
@@ -183,6 +206,7 @@ def main():
     avg3 = ms3 / max(n3, 1) / 1e3
     achieved = s3 * per_launch_pairs / avg3 if avg3 > 0 else 0.0
     peak = PEAK_FP32_MFMA if chosen == "fp32" else PEAK_BF16_MFMA
+    traffic = measured_traffic(chosen)
     out = {
         "metric": METRIC, "value": r["pairs_per_s"], "unit": "pairs/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": r["ms_per_step"], "higher_is_better": True, "scaling": "weak",
@@ -200,7 +224,11 @@ def main():
                    "gflop_per_pair": (s1 + s3 + fft) / 1e9},
         "roofline": {"kernel": "step3 (shift contraction on MFMA + rotation FFT + argmax)", "bound": "mfma",
                      "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
-                     "frac": achieved / peak, "traffic": None,
+                     "frac": achieved / peak, "traffic": traffic,
+                     "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+                     "traffic_GBps": traffic / avg3 / 1e9 if traffic and avg3 > 0 else None,
+                     "products_per_mac": 3 if chosen == "bf16x3" else 1,
+                     "frac_of_form_ceiling": (achieved / (peak / 3) if chosen == "bf16x3" else achieved / peak),
                      "algorithmic_flop_per_pair": s3, "pairs_per_launch": per_launch_pairs,
                      "avg_launch_ms": avg3 * 1e3,
                      "step1_achieved": (s1 * pairs * args.steps / max(n1, 1)) / (ms1 / max(n1, 1) / 1e3) / 1e12
