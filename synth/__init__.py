@@ -197,3 +197,21 @@ def ragged_stack_specs(seed: int, count: int = 64, scale: float = 1.0):
                           n_templates=max(1, int(round(nB * scale))),
                           n_images=max(1, int(round(nA * scale)))))
     return specs
+
+
+def mlp_init(seed: int, dims) -> list:
+    """Initial MLP parameters [(W [out, in], b [out])], float32: He-normal
+    weights (std sqrt(2 / fan_in)) for the ReLU layers, std sqrt(1 / fan_in)
+    for the last (linear) layer, zero biases."""
+    rng = np.random.default_rng(seed)
+    params = []
+    for i in range(len(dims) - 1):
+        gain = 2.0 if i < len(dims) - 2 else 1.0
+        W = rng.standard_normal((dims[i + 1], dims[i])) * math.sqrt(gain / dims[i])
+        params.append((W.astype(np.float32), np.zeros(dims[i + 1], np.float32)))
+    return params
+
+
+def permutation(seed: int, n: int) -> np.ndarray:
+    """A seeded random permutation of 0..n-1 (int32), e.g. minibatch order."""
+    return np.random.default_rng(seed).permutation(n).astype(np.int32)
