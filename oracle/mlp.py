@@ -50,13 +50,39 @@ def features(coeffs_rings_modes: np.ndarray, n_r: int, n_q: int) -> np.ndarray:
     return (np.abs(a[:n_r, :n_q]) ** 2).reshape(-1)
 
 
+def cross_features(coeffs_rings_modes: np.ndarray, n_r: int, n_q: int) -> np.ndarray:
+    """Rotation-invariant products of two rings at one mode,
+    c(k1, k2; q) = a(k1; q) conj a(k2; q) (a rotation multiplies both by
+    the same phase, which cancels), for rings k1 <= k2 < n_r and modes
+    0 <= q < n_q, each taken through the signed square root
+    s(x) = sign(x) sqrt|x| (homogeneous of degree one in the image).
+    Per mode q a block of n_r^2 numbers: the real parts for k1 <= k2, then
+    the imaginary parts for k1 < k2, pairs in row-major (k1, then k2) order."""
+    a = np.asarray(coeffs_rings_modes)
+    out = []
+    for q in range(n_q):
+        re, im = [], []
+        for k1 in range(n_r):
+            for k2 in range(k1, n_r):
+                c = a[k1, q] * np.conj(a[k2, q])
+                re.append(c.real)
+                if k2 > k1:
+                    im.append(c.imag)
+        out.extend(re)
+        out.extend(im)
+    v = np.asarray(out, dtype=np.float64)
+    return np.sign(v) * np.sqrt(np.abs(v))
+
+
 def standardise(F: np.ndarray, mu: np.ndarray, inv_sigma: np.ndarray) -> np.ndarray:
     return (np.asarray(F, dtype=np.float64) - mu) * inv_sigma
 
 
-def forward(params, x):
+def forward(params, x, act_round=None):
     """params: list of (W [out, in], b [out]); x [B, in].  Returns the list of
-    layer inputs h_0..h_L-1, the pre-activations z_0..z_L-1 and the logits."""
+    layer inputs h_0..h_L-1, the pre-activations z_0..z_L-1 and the logits.
+    act_round (e.g. bf16_round) is applied to every hidden activation, the
+    operands a reduced-precision form feeds to the next product."""
     h = np.asarray(x, dtype=np.float64)
     hs, zs = [], []
     L = len(params)
@@ -65,6 +91,8 @@ def forward(params, x):
         z = h @ np.asarray(W, dtype=np.float64).T + np.asarray(b, dtype=np.float64)
         zs.append(z)
         h = np.maximum(z, 0.0) if l < L - 1 else z
+        if act_round is not None and l < L - 1:
+            h = act_round(h)
     return hs, zs, h
 
 
@@ -92,23 +120,28 @@ def loss_and_dlogits(logits, lab_t, lab_s, n_t: int, n_s: int):
     return loss, d
 
 
-def backward(params, hs, zs, dlogits):
+def backward(params, hs, zs, dlogits, grad_round=None):
     """Gradients [(dW, db)] by the chain rule through the linear layers and
-    the ReLUs of the hidden layers."""
+    the ReLUs of the hidden layers.  grad_round (e.g. bf16_round) is applied
+    to the gradient where it enters a product (dW and the gradient of the
+    layer input), not to the bias gradient, which is a plain sum."""
     grads = [None] * len(params)
     g = np.asarray(dlogits, dtype=np.float64)
     for l in range(len(params) - 1, -1, -1):
         W = np.asarray(params[l][0], dtype=np.float64)
-        grads[l] = (g.T @ hs[l], np.sum(g, axis=0))
+        gr = grad_round(g) if grad_round is not None else g
+        grads[l] = (gr.T @ hs[l], np.sum(g, axis=0))
         if l > 0:
-            g = (g @ W) * (zs[l - 1] > 0.0)
+            g = (gr @ W) * (zs[l - 1] > 0.0)
     return grads
 
 
-def loss_and_grads(params, x, lab_t, lab_s, n_t, n_s):
-    hs, zs, logits = forward(params, x)
+def loss_and_grads(params, x, lab_t, lab_s, n_t, n_s, rnd=None):
+    """Loss and gradients; rnd (e.g. bf16_round) rounds every product operand
+    that a reduced-precision form rounds: hidden activations and gradients."""
+    hs, zs, logits = forward(params, x, act_round=rnd)
     loss, d = loss_and_dlogits(logits, lab_t, lab_s, n_t, n_s)
-    return loss, backward(params, hs, zs, d)
+    return loss, backward(params, hs, zs, d, grad_round=rnd)
 
 
 def adamw(w, g, m, v, t: int, lr, beta1, beta2, eps, wd):

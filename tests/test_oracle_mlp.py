@@ -168,6 +168,36 @@ def test_features_are_rotation_invariant():
     assert np.max(np.abs(f2 - f0)) > 1e-3 * np.max(np.abs(f0))
 
 
+def test_cross_features_rotation_invariant_and_laid_out():
+    n, M, Qa = 32, 16, 64
+    img = synth.make_alignment_set(9, n, 1, 1, 20, 2.0, 0.1).images[0].copy()
+    img[0, :] = 0.0
+    img[:, 0] = 0.0
+    rot = np.roll(np.rot90(img), 1, axis=0)
+    plan = O.make_plan(n, M, Qa, 2.0, 1e-3)
+    a0 = O.fb_coefficients(img, plan)
+    a1 = O.fb_coefficients(rot, plan)
+    f0 = ML.cross_features(a0, 6, 5)
+    f1 = ML.cross_features(a1, 6, 5)
+    assert f0.shape == (5 * 36,)
+    # compare the products themselves: the square root magnifies rounding near 0
+    p0, p1 = np.sign(f0) * f0 ** 2, np.sign(f1) * f1 ** 2
+    assert np.max(np.abs(p1 - p0)) <= 1e-12 * np.max(np.abs(p0))
+    # without the conjugate the product is not invariant: a planted mistake fails
+    bad0 = a0[1, 2] * a0[3, 2]
+    bad1 = a1[1, 2] * a1[3, 2]
+    assert abs(bad1 - bad0) > 1e-3 * abs(bad0)
+    # the layout, entry by entry, for mode q = 2 (block offset 2 * 36)
+    s = lambda x: np.sign(x) * np.sqrt(abs(x))
+    c = a0[1, 2] * np.conj(a0[3, 2])
+    re_idx = [(k1, k2) for k1 in range(6) for k2 in range(k1, 6)].index((1, 3))
+    im_idx = 21 + [(k1, k2) for k1 in range(6) for k2 in range(k1 + 1, 6)].index((1, 3))
+    assert f0[72 + re_idx] == pytest.approx(s(c.real), rel=1e-12)
+    assert f0[72 + im_idx] == pytest.approx(s(c.imag), rel=1e-12)
+    # diagonal products are real and equal the power features
+    assert f0[72 + 0] == pytest.approx(math.sqrt(abs(a0[0, 2]) ** 2), rel=1e-12)
+
+
 def test_features_of_real_image_are_symmetric_in_q():
     n, M, Qa = 32, 16, 64
     img = synth.white_noise_images(2, 1, n)[0]
