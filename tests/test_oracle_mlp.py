@@ -184,8 +184,9 @@ def test_cross_features_rotation_invariant_and_laid_out():
     p0, p1 = np.sign(f0) * f0 ** 2, np.sign(f1) * f1 ** 2
     assert np.max(np.abs(p1 - p0)) <= 1e-12 * np.max(np.abs(p0))
     # without the conjugate the product is not invariant: a planted mistake fails
-    bad0 = a0[1, 2] * a0[3, 2]
-    bad1 = a1[1, 2] * a1[3, 2]
+    # (mode 1: a quarter turn multiplies each factor by -i, the product by -1)
+    bad0 = a0[1, 1] * a0[3, 1]
+    bad1 = a1[1, 1] * a1[3, 1]
     assert abs(bad1 - bad0) > 1e-3 * abs(bad0)
     # the layout, entry by entry, for mode q = 2 (block offset 2 * 36)
     s = lambda x: np.sign(x) * np.sqrt(abs(x))
