@@ -318,6 +318,19 @@ Needs plan_needs(const ftk_plan* p, int nA, int nB, bool from_pixels) {
   return d;
 }
 
+Needs plan_needs_lists(const ftk_plan* p, int nA, int K) {
+  Needs d;
+  if (nA <= 0 || K <= 0) return d;
+  const size_t per_pair = static_cast<size_t>(p->Qa / 2 + 1) * 2 * p->H_pad * sizeof(float);
+  const size_t budget = static_cast<size_t>(p->tune.stage_mib) << 20;
+  d.chunk_images = static_cast<int>(std::min<size_t>(nA, std::max<size_t>(1, budget / (per_pair * K))));
+  d.stage = static_cast<size_t>(d.chunk_images) * K * per_pair;
+  d.keys = static_cast<size_t>(nA) * K * sizeof(unsigned long long);
+  d.tmpl = tmpl_prep_tile_bytes(static_cast<size_t>(d.chunk_images) * ((K + 15) / 16), p->M, p->Qa,
+                                p->precision == FTK_BF16X3 ? 1 : 0);
+  return d;
+}
+
 }  // namespace ftkint
 
 extern "C" {
@@ -527,20 +540,22 @@ int ftk_transform(ftk_plan* p, const float* imgs, int cnt, void* coeffs, void* s
   return FTK_OK;
 }
 
-int ftk_align_coeffs(ftk_plan* p, const void* img_coeffs, int nA, const void* tmpl_coeffs, int nB, float* X,
-                     ftk_pose* best, void* stream) {
-  if (!p) return fail(FTK_EINVAL, "ftk_align_coeffs: NULL plan");
-  if (nA < 0 || nB < 0) return fail(FTK_EINVAL, "ftk_align_coeffs: negative count");
-  if (p->N <= 0) return fail(FTK_ESTATE, "ftk_align_coeffs: call ftk_set_shifts first");
-  if (nA == 0 || nB == 0) return FTK_OK;
-  if (!X && !best) return fail(FTK_EINVAL, "ftk_align_coeffs: X and best are both NULL");
-  if (!img_coeffs || !tmpl_coeffs) return fail(FTK_EINVAL, "ftk_align_coeffs: NULL coefficients");
+}  // extern "C"
+
+namespace {
+
+// Steps 1-3 + argmax for nA images against nB templates (lists == NULL) or
+// against K templates of their own (lists [nA][K]); results per pair
+// (image, template or list slot) in X [.][N][Qa] and best.
+int align_impl(ftk_plan* p, const void* img_coeffs, int nA, const void* tmpl_coeffs, int nB, const int32_t* lists,
+               int K, float* X, ftk_pose* best, void* stream) {
   hipStream_t s = static_cast<hipStream_t>(stream);
   const int QH = p->Qa / 2;
-  const size_t pairs = static_cast<size_t>(nA) * nB;
+  const int nBe = lists ? K : nB;  // templates per image
+  const size_t pairs = static_cast<size_t>(nA) * nBe;
   const bool split = p->precision == FTK_BF16X3;
   const int prec = split ? 1 : 0;
-  const Needs nd = plan_needs(p, nA, nB, false);
+  const Needs nd = lists ? plan_needs_lists(p, nA, K) : plan_needs(p, nA, nB, false);
   const int chunkA = nd.chunk_images;
   Workspace& ws = *p->ws;
   if (ws.stage.ensure(nd.stage) != hipSuccess) return fail(FTK_ENOMEM, "ftk_align: staging buffer");
@@ -553,21 +568,25 @@ int ftk_align_coeffs(ftk_plan* p, const void* img_coeffs, int nA, const void* tm
   hipEvent_t ev = p->timer.begin(s);
   if ((e = launch_keys_init(keys, pairs, s)) != hipSuccess) return hip_fail(e, "ftk_align: keys init");
   p->timer.end(ev, s, 3);
-  // template operand of Step 1: embedded (and split) once per call
-  ev = p->timer.begin(s);
-  if ((e = launch_tmpl_prep(static_cast<const float2*>(tmpl_coeffs), ws.tmpl.ptr, nB, p->M, p->Qa, prec, s)) !=
-      hipSuccess)
-    return hip_fail(e, "ftk_align: template operand");
-  p->timer.end(ev, s, 4);
+  const float2* bco = static_cast<const float2*>(tmpl_coeffs);
+  if (!lists) {
+    // template operand of Step 1: embedded (and split) once per call
+    ev = p->timer.begin(s);
+    if ((e = launch_tmpl_prep(bco, ws.tmpl.ptr, nB, p->M, p->Qa, prec, s)) != hipSuccess)
+      return hip_fail(e, "ftk_align: template operand");
+    p->timer.end(ev, s, 4);
+  }
 
   Step1Args a1{};
   a1.cz = p->cz.as<float>();
   a1.ell = p->ell.as<int>();
   a1.zs = ws.stage.as<float>();
-  a1.b = static_cast<const float2*>(tmpl_coeffs);
+  a1.b = bco;
   a1.r32 = ws.tmpl.as<float>();
   a1.r16 = ws.tmpl.ptr;
-  a1.nB = nB;
+  a1.nB = nBe;
+  a1.img_tiles = lists ? (K + 15) / 16 : 0;
+  a1.tiles_per_q = (nBe + 15) / 16;
   a1.M = p->M;
   a1.Qa = p->Qa;
   a1.H_pad = p->H_pad;
@@ -587,10 +606,18 @@ int ftk_align_coeffs(ftk_plan* p, const void* img_coeffs, int nA, const void* tm
     const int na = std::min(chunkA, nA - A0);
     a1.a = static_cast<const float2*>(img_coeffs) + static_cast<size_t>(A0) * p->Qa * p->M;
     a1.nA = na;
+    if (lists) {
+      // this chunk's own template operand, gathered through the lists
+      a1.tiles_per_q = na * a1.img_tiles;
+      ev = p->timer.begin(s);
+      if ((e = launch_tmpl_prep_lists(bco, ws.tmpl.ptr, nB, p->M, p->Qa, prec, lists, K, na, A0, s)) != hipSuccess)
+        return hip_fail(e, "ftk_align_lists: template operand");
+      p->timer.end(ev, s, 4);
+    }
     {
       // split the template sweep until the grid holds about step1_wgs workgroups
       const int base = na * (QH + 1) * (p->H_pad / a1.zblk);
-      const int max_parts = std::max(1, ((nB + 15) / 16 + 7) / 8);
+      const int max_parts = std::max(1, ((nBe + 15) / 16 + 7) / 8);
       a1.tparts = std::min(max_parts, std::max(1, (p->tune.step1_wgs + base - 1) / base));
     }
     ev = p->timer.begin(s);
@@ -598,9 +625,9 @@ int ftk_align_coeffs(ftk_plan* p, const void* img_coeffs, int nA, const void* tm
     if (e != hipSuccess) return hip_fail(e, "ftk_align: step 1");
     p->timer.end(ev, s, 1);
     a3.zs = ws.stage.as<float>();
-    a3.pairs = na * nB;
-    a3.keys = keys + static_cast<size_t>(A0) * nB;
-    a3.X = X ? X + static_cast<size_t>(A0) * nB * p->N * p->Qa : nullptr;
+    a3.pairs = na * nBe;
+    a3.keys = keys + static_cast<size_t>(A0) * nBe;
+    a3.X = X ? X + static_cast<size_t>(A0) * nBe * p->N * p->Qa : nullptr;
     ev = p->timer.begin(s);
     e = split ? launch_step3_bf16(a3, s) : launch_step3(a3, p->precision, s);
     if (e != hipSuccess) return hip_fail(e, "ftk_align: step 3");
@@ -613,6 +640,33 @@ int ftk_align_coeffs(ftk_plan* p, const void* img_coeffs, int nA, const void* tm
     p->timer.end(ev, s, 3);
   }
   return FTK_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ftk_align_coeffs(ftk_plan* p, const void* img_coeffs, int nA, const void* tmpl_coeffs, int nB, float* X,
+                     ftk_pose* best, void* stream) {
+  if (!p) return fail(FTK_EINVAL, "ftk_align_coeffs: NULL plan");
+  if (nA < 0 || nB < 0) return fail(FTK_EINVAL, "ftk_align_coeffs: negative count");
+  if (p->N <= 0) return fail(FTK_ESTATE, "ftk_align_coeffs: call ftk_set_shifts first");
+  if (nA == 0 || nB == 0) return FTK_OK;
+  if (!X && !best) return fail(FTK_EINVAL, "ftk_align_coeffs: X and best are both NULL");
+  if (!img_coeffs || !tmpl_coeffs) return fail(FTK_EINVAL, "ftk_align_coeffs: NULL coefficients");
+  return align_impl(p, img_coeffs, nA, tmpl_coeffs, nB, nullptr, 0, X, best, stream);
+}
+
+int ftk_align_lists(ftk_plan* p, const void* img_coeffs, int nA, const void* tmpl_coeffs, int nB,
+                    const int32_t* lists, int K, ftk_pose* best, void* stream) {
+  if (!p) return fail(FTK_EINVAL, "ftk_align_lists: NULL plan");
+  if (nA < 0 || nB < 0) return fail(FTK_EINVAL, "ftk_align_lists: negative count");
+  if (K < 1 || K > 4096) return fail(FTK_EINVAL, "ftk_align_lists: K must be in [1, 4096]");
+  if (p->N <= 0) return fail(FTK_ESTATE, "ftk_align_lists: call ftk_set_shifts first");
+  if (nA == 0) return FTK_OK;
+  if (nB == 0) return fail(FTK_EINVAL, "ftk_align_lists: lists need templates (nB = 0)");
+  if (!img_coeffs || !tmpl_coeffs || !lists || !best) return fail(FTK_EINVAL, "ftk_align_lists: NULL argument");
+  return align_impl(p, img_coeffs, nA, tmpl_coeffs, nB, lists, K, nullptr, best, stream);
 }
 
 int ftk_align(ftk_plan* p, const float* images, int nA, const float* templates, int nB, float* X, ftk_pose* best,

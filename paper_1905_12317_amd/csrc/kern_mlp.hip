@@ -1,0 +1,577 @@
+// Kernels of the template-proposal network: a tiled GEMM on MFMA (bf16 or
+// FP32 operands, FP32 accumulation) with bias / ReLU / ReLU-mask epilogues,
+// two-head softmax cross-entropy, column sums, AdamW, feature extraction,
+// standardised row gathers, per-row top-k and the small bookkeeping kernels
+// of the proposal search.
+#include <hip/hip_runtime.h>
+
+#include "mlp_kernels.h"
+
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+namespace {
+
+constexpr int kThreads = 256;
+
+__device__ __forceinline__ float wave_max(float v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v = fmaxf(v, __shfl_xor(v, o));
+  return v;
+}
+
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+// block-wide reductions over 256 threads (4 waves); red holds 4 floats
+__device__ float block_max(float v, float* red) {
+  v = wave_max(v);
+  const int w = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[w] = v;
+  __syncthreads();
+  return fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
+}
+
+__device__ float block_sum(float v, float* red) {
+  v = wave_sum(v);
+  const int w = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[w] = v;
+  __syncthreads();
+  return (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+template <typename T>
+__device__ __forceinline__ T from_float(float x) {
+  return static_cast<T>(x);
+}
+
+// ---------------------------------------------------------------- GEMM
+
+// 64 x 64 output tile per workgroup, 4 waves of 32 x 32 (one MFMA
+// accumulator each), K staged through LDS in chunks of 32.  Both operands
+// sit in LDS with k contiguous per row (A: [i][k], B: [j][k]).
+template <typename T>
+__global__ void __launch_bounds__(kThreads) gemm_kernel(GemmArgs g) {
+  constexpr bool BF = sizeof(T) == 2;
+  constexpr int TM = 64, TN = 64, KC = 32;
+  constexpr int LS = BF ? KC + 8 : KC + 1;  // row stride in elements
+  __shared__ __attribute__((aligned(16))) T As[TM * LS];
+  __shared__ __attribute__((aligned(16))) T Bs[TN * LS];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int i0 = blockIdx.y * TM, j0 = blockIdx.x * TN;
+  const int wi = (wave >> 1) * 32, wj = (wave & 1) * 32;
+  const T* A = static_cast<const T*>(g.A);
+  const T* B = static_cast<const T*>(g.B);
+  const T zero = from_float<T>(0.f);
+  f32x16 acc;
+#pragma unroll
+  for (int v = 0; v < 16; ++v) acc[v] = 0.f;
+  for (int k0 = 0; k0 < g.K; k0 += KC) {
+    if (g.sak == 1) {
+      const int i = tid >> 2, kk = (tid & 3) * 8;
+      const long long gi = i0 + i;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int gk = k0 + kk + e;
+        As[i * LS + kk + e] = (gi < g.M && gk < g.K) ? A[gi * g.sai + gk] : zero;
+      }
+    } else {
+      const int kk = tid >> 3, ii = (tid & 7) * 8;
+      const long long gk = k0 + kk;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int gi = i0 + ii + e;
+        As[(ii + e) * LS + kk] = (gi < g.M && gk < g.K) ? A[gi + gk * g.sak] : zero;
+      }
+    }
+    if (g.sbk == 1) {
+      const int j = tid >> 2, kk = (tid & 3) * 8;
+      const long long gj = j0 + j;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int gk = k0 + kk + e;
+        Bs[j * LS + kk + e] = (gj < g.N && gk < g.K) ? B[gk + gj * g.sbj] : zero;
+      }
+    } else {
+      const int kk = tid >> 3, jj = (tid & 7) * 8;
+      const long long gk = k0 + kk;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int gj = j0 + jj + e;
+        Bs[(jj + e) * LS + kk] = (gj < g.N && gk < g.K) ? B[gk * g.sbk + gj] : zero;
+      }
+    }
+    __syncthreads();
+    const int r = lane & 31, h = lane >> 5;
+    if constexpr (BF) {
+#pragma unroll
+      for (int s = 0; s < KC / 16; ++s) {
+        const bf16x8 a = *reinterpret_cast<const bf16x8*>(&As[(wi + r) * LS + 16 * s + 8 * h]);
+        const bf16x8 b = *reinterpret_cast<const bf16x8*>(&Bs[(wj + r) * LS + 16 * s + 8 * h]);
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
+      }
+    } else {
+#pragma unroll
+      for (int s = 0; s < KC / 2; ++s) {
+        const float a = As[(wi + r) * LS + 2 * s + h];
+        const float b = Bs[(wj + r) * LS + 2 * s + h];
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, acc, 0, 0, 0);
+      }
+    }
+    __syncthreads();
+  }
+  const int j = j0 + wj + (lane & 31);
+  if (j >= g.N) return;
+  const float bj = g.bias ? g.bias[j] : 0.f;
+#pragma unroll
+  for (int v = 0; v < 16; ++v) {
+    const long long i = i0 + wi + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+    if (i >= g.M) continue;
+    float z = acc[v] + bj;
+    if (g.mask && !(g.mask[i * g.ldm + j] > 0.f)) z = 0.f;
+    if (g.C) g.C[i * g.ldc + j] = z;
+    if (g.Cb) static_cast<T*>(g.Cb)[i * g.ldcb + j] = from_float<T>(g.relu ? fmaxf(z, 0.f) : z);
+  }
+}
+
+// ---------------------------------------------------------------- rows
+
+template <typename T>
+__global__ void standardise_kernel(const float* __restrict__ x, const int32_t* __restrict__ idx, int B, int D,
+                                   const float* __restrict__ mu, const float* __restrict__ is, T* __restrict__ X) {
+  const size_t total = static_cast<size_t>(B) * D;
+  for (size_t t = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x; t < total;
+       t += static_cast<size_t>(gridDim.x) * blockDim.x) {
+    const int b = static_cast<int>(t / D);
+    const int f = static_cast<int>(t - static_cast<size_t>(b) * D);
+    const size_t row = idx ? static_cast<size_t>(idx[b]) : static_cast<size_t>(b);
+    X[t] = from_float<T>((x[row * D + f] - mu[f]) * is[f]);
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kThreads) softmax_ce_kernel(const float* __restrict__ logits, int B, int D, int n_t,
+                                                              int n_s, const int32_t* __restrict__ lab_t,
+                                                              const int32_t* __restrict__ lab_s,
+                                                              const int32_t* __restrict__ idx, float* __restrict__ dZ,
+                                                              T* __restrict__ dZb, float* __restrict__ row_loss) {
+  __shared__ float red[4];
+  const int b = blockIdx.x;
+  const float* z = logits + static_cast<size_t>(b) * D;
+  const int r = idx ? idx[b] : b;
+  const float invB = 1.f / static_cast<float>(B);
+  float loss = 0.f;
+  for (int head = 0; head < 2; ++head) {
+    const int lo = head == 0 ? 0 : n_t;
+    const int width = head == 0 ? n_t : n_s;
+    if (width == 0) continue;
+    const int lab = lo + (head == 0 ? lab_t[r] : lab_s[r]);
+    float mx = -__builtin_inff();
+    for (int j = lo + threadIdx.x; j < lo + width; j += kThreads) mx = fmaxf(mx, z[j]);
+    mx = block_max(mx, red);
+    float se = 0.f;
+    for (int j = lo + threadIdx.x; j < lo + width; j += kThreads) se += __expf(z[j] - mx);
+    se = block_sum(se, red);
+    const float inv = 1.f / se;
+    for (int j = lo + threadIdx.x; j < lo + width; j += kThreads) {
+      const float d = (__expf(z[j] - mx) * inv - (j == lab ? 1.f : 0.f)) * invB;
+      dZ[static_cast<size_t>(b) * D + j] = d;
+      if (dZb) dZb[static_cast<size_t>(b) * D + j] = from_float<T>(d);
+    }
+    loss += __logf(se) + mx - z[lab];
+  }
+  if (threadIdx.x == 0) row_loss[b] = loss;
+}
+
+__global__ void __launch_bounds__(kThreads) mean_kernel(const float* __restrict__ v, int n, float* __restrict__ out) {
+  __shared__ float red[4];
+  float s = 0.f;
+  for (int i = threadIdx.x; i < n; i += kThreads) s += v[i];
+  s = block_sum(s, red);
+  if (threadIdx.x == 0) out[0] = s / static_cast<float>(n);
+}
+
+__global__ void colsum_kernel(const float* __restrict__ dZ, int B, int N, float* __restrict__ db) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= N) return;
+  float s = 0.f;
+  for (int b = 0; b < B; ++b) s += dZ[static_cast<size_t>(b) * N + j];
+  db[j] = s;
+}
+
+template <typename T>
+__global__ void adamw_kernel(float* __restrict__ w, const float* __restrict__ g, float* __restrict__ m,
+                             float* __restrict__ v, size_t n, float lr, float b1, float b2, float eps, float wd,
+                             float bc1, float bc2, T* __restrict__ wc) {
+  for (size_t t = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x; t < n;
+       t += static_cast<size_t>(gridDim.x) * blockDim.x) {
+    const float gt = g[t];
+    const float mt = b1 * m[t] + (1.f - b1) * gt;
+    const float vt = b2 * v[t] + (1.f - b2) * gt * gt;
+    m[t] = mt;
+    v[t] = vt;
+    const float mh = mt / bc1;
+    const float vh = vt / bc2;
+    const float wt = w[t];
+    const float wn = wt - lr * (mh / (sqrtf(vh) + eps) + wd * wt);
+    w[t] = wn;
+    if (wc) wc[t] = from_float<T>(wn);
+  }
+}
+
+template <typename T>
+__global__ void convert_kernel(const float* __restrict__ w, size_t n, T* __restrict__ wc) {
+  for (size_t t = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x; t < n;
+       t += static_cast<size_t>(gridDim.x) * blockDim.x)
+    wc[t] = from_float<T>(w[t]);
+}
+
+// kind 0: F[m n_q + q] = |a(k_m; q)|^2.
+// kind 1: per mode q a block of n_r^2 values s(Re c) for k1 <= k2, then
+// s(Im c) for k1 < k2 (row-major pairs), c = a(k1; q) conj a(k2; q),
+// s(x) = sign(x) sqrt|x|.
+__global__ void features_kernel(const float2* __restrict__ c, int nA, int Qa, int M, int kind, int n_r, int n_q,
+                                float* __restrict__ F) {
+  const size_t D = kind == 0 ? static_cast<size_t>(n_r) * n_q : static_cast<size_t>(n_r) * n_r * n_q;
+  const size_t total = static_cast<size_t>(nA) * D;
+  for (size_t t = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x; t < total;
+       t += static_cast<size_t>(gridDim.x) * blockDim.x) {
+    const size_t a = t / D;
+    const int f = static_cast<int>(t - a * D);
+    if (kind == 0) {
+      const int m = f / n_q;
+      const int q = f - m * n_q;
+      const float2 v = c[(a * Qa + q) * M + m];
+      F[t] = v.x * v.x + v.y * v.y;
+      continue;
+    }
+    const int blk = n_r * n_r;
+    const int q = f / blk;
+    int u = f - q * blk;
+    const int P = n_r * (n_r + 1) / 2;
+    const bool imag = u >= P;
+    if (imag) u -= P;
+    int k1 = 0;
+    int len = imag ? n_r - 1 : n_r;  // pairs in row k1
+    while (u >= len) {
+      u -= len;
+      ++k1;
+      --len;
+    }
+    const int k2 = k1 + u + (imag ? 1 : 0);
+    const float2 v1 = c[(a * Qa + q) * M + k1];
+    const float2 v2 = c[(a * Qa + q) * M + k2];
+    const float x = imag ? (v1.y * v2.x - v1.x * v2.y) : (v1.x * v2.x + v1.y * v2.y);
+    F[t] = copysignf(sqrtf(fabsf(x)), x);
+  }
+}
+
+// (value, index) order used by the proposal: larger value first, then the
+// lower index; NaN logits rank below every number
+__device__ __forceinline__ bool ranks_before(float v, int i, float w, int j) {
+  return v > w || (v == w && i < j);
+}
+
+__device__ __forceinline__ float clean(float x) { return (x == x) ? x : -__builtin_inff(); }
+
+__global__ void __launch_bounds__(kThreads) topk_kernel(const float* __restrict__ logits, int D, int n_t, int n_s,
+                                                        int k, int32_t* __restrict__ top, float* __restrict__ mass,
+                                                        int32_t* __restrict__ sbin) {
+  __shared__ float rv[4];
+  __shared__ int ri[4];
+  __shared__ float sel_v[64];
+  __shared__ int sel_i[64];
+  const int row = blockIdx.x;
+  const float* z = logits + static_cast<size_t>(row) * D;
+  float pv = __builtin_inff();
+  int pi = -1;
+  for (int r = 0; r < k; ++r) {
+    // the first element, in (value desc, index asc) order, after (pv, pi)
+    float bv = -__builtin_inff();
+    int bi = 0x7fffffff;
+    for (int j = threadIdx.x; j < n_t; j += kThreads) {
+      const float v = clean(z[j]);
+      if (ranks_before(pv, pi, v, j) && ranks_before(v, j, bv, bi)) {
+        bv = v;
+        bi = j;
+      }
+    }
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+      const float ov = __shfl_xor(bv, o);
+      const int oi = __shfl_xor(bi, o);
+      if (ranks_before(ov, oi, bv, bi)) {
+        bv = ov;
+        bi = oi;
+      }
+    }
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) {
+      rv[threadIdx.x >> 6] = bv;
+      ri[threadIdx.x >> 6] = bi;
+    }
+    __syncthreads();
+    bv = rv[0];
+    bi = ri[0];
+    for (int w = 1; w < 4; ++w)
+      if (ranks_before(rv[w], ri[w], bv, bi)) {
+        bv = rv[w];
+        bi = ri[w];
+      }
+    if (threadIdx.x == 0) {
+      sel_v[r] = bv;
+      sel_i[r] = bi;
+    }
+    pv = bv;
+    pi = bi;
+  }
+  __syncthreads();
+  const float mx = sel_v[0];
+  float se = 0.f;
+  for (int j = threadIdx.x; j < n_t; j += kThreads) se += __expf(clean(z[j]) - mx);
+  __shared__ float red[4];
+  se = block_sum(se, red);
+  if (threadIdx.x == 0) {
+    float ms = 0.f;
+    for (int r = 0; r < k; ++r) {
+      top[static_cast<size_t>(row) * k + r] = sel_i[r];
+      ms += __expf(sel_v[r] - mx);
+    }
+    mass[row] = ms / se;
+    int sb = 0;
+    float sv = -__builtin_inff();
+    for (int j = 0; j < n_s; ++j) {
+      const float v = clean(z[n_t + j]);
+      if (v > sv) {
+        sv = v;
+        sb = j;
+      }
+    }
+    sbin[row] = sb;
+  }
+}
+
+struct Pose {
+  float value;
+  int32_t shift;
+  int32_t rot;
+};
+
+__global__ void best_template_kernel(const Pose* __restrict__ poses, const int32_t* __restrict__ lists, int nA, int K,
+                                     int32_t* __restrict__ best_t, Pose* __restrict__ best_pose) {
+  const int a = blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= nA) return;
+  float bv = -__builtin_inff();
+  int bt = -1, bj = -1;
+  for (int j = 0; j < K; ++j) {
+    const Pose p = poses[static_cast<size_t>(a) * K + j];
+    const int t = lists ? lists[static_cast<size_t>(a) * K + j] : j;
+    if (!(p.value == p.value)) continue;
+    if (p.value > bv || (p.value == bv && t < bt)) {
+      bv = p.value;
+      bt = t;
+      bj = j;
+    }
+  }
+  best_t[a] = bt;
+  Pose o;
+  if (bj >= 0) {
+    o = poses[static_cast<size_t>(a) * K + bj];
+  } else {
+    o.value = __builtin_nanf("");
+    o.shift = -1;
+    o.rot = -1;
+  }
+  best_pose[a] = o;
+}
+
+// one workgroup: rows with mass < tau in increasing order (block scan)
+__global__ void __launch_bounds__(kThreads) select_below_kernel(const float* __restrict__ mass, int nA, float tau,
+                                                                int32_t* __restrict__ list,
+                                                                int32_t* __restrict__ count,
+                                                                int32_t* __restrict__ flag) {
+  __shared__ int wsum[4];
+  __shared__ int base_s;
+  if (threadIdx.x == 0) base_s = 0;
+  __syncthreads();
+  for (int c0 = 0; c0 < nA; c0 += kThreads) {
+    const int i = c0 + threadIdx.x;
+    const int f = (i < nA && !(mass[i] >= tau)) ? 1 : 0;
+    if (i < nA && flag) flag[i] = f;
+    // inclusive scan within the wave
+    int x = f;
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const int y = __shfl_up(x, o);
+      if (lane >= o) x += y;
+    }
+    if (lane == 63) wsum[threadIdx.x >> 6] = x;
+    __syncthreads();
+    int before = base_s;
+    for (int w = 0; w < (threadIdx.x >> 6); ++w) before += wsum[w];
+    if (f) list[before + x - 1] = i;
+    __syncthreads();
+    if (threadIdx.x == 0) base_s += wsum[0] + wsum[1] + wsum[2] + wsum[3];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) count[0] = base_s;
+}
+
+__global__ void gather_rows_kernel(const uint2* __restrict__ src, const int32_t* __restrict__ list, int count,
+                                   size_t words, uint2* __restrict__ dst) {
+  const size_t total = static_cast<size_t>(count) * words;
+  for (size_t t = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x; t < total;
+       t += static_cast<size_t>(gridDim.x) * blockDim.x) {
+    const size_t r = t / words;
+    const size_t w = t - r * words;
+    dst[t] = src[static_cast<size_t>(list[r]) * words + w];
+  }
+}
+
+__global__ void scatter_results_kernel(const int32_t* __restrict__ bt, const Pose* __restrict__ bp,
+                                       const int32_t* __restrict__ list, int count, int32_t* __restrict__ dt,
+                                       Pose* __restrict__ dp) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  const int a = list[i];
+  dt[a] = bt[i];
+  dp[a] = bp[i];
+}
+
+unsigned grid_for(size_t n) {
+  size_t b = (n + kThreads - 1) / kThreads;
+  if (b < 1) b = 1;
+  if (b > 65536) b = 65536;
+  return static_cast<unsigned>(b);
+}
+
+}  // namespace
+
+hipError_t launch_gemm(const GemmArgs& g, int bf16, hipStream_t s) {
+  if (g.M <= 0 || g.N <= 0) return hipSuccess;
+  if (!((g.sak == 1) || (g.sai == 1)) || !((g.sbk == 1) || (g.sbj == 1))) return hipErrorInvalidValue;
+  dim3 grid((g.N + 63) / 64, (g.M + 63) / 64);
+  if (grid.y > 65535) return hipErrorInvalidValue;
+  if (bf16)
+    hipLaunchKernelGGL(gemm_kernel<__bf16>, grid, dim3(kThreads), 0, s, g);
+  else
+    hipLaunchKernelGGL(gemm_kernel<float>, grid, dim3(kThreads), 0, s, g);
+  return hipGetLastError();
+}
+
+hipError_t launch_standardise(const float* x, const int32_t* idx, int B, int D, const float* mu,
+                              const float* inv_sigma, void* X, int bf16, hipStream_t s) {
+  if (B <= 0) return hipSuccess;
+  const unsigned grid = grid_for(static_cast<size_t>(B) * D);
+  if (bf16)
+    hipLaunchKernelGGL(standardise_kernel<__bf16>, dim3(grid), dim3(kThreads), 0, s, x, idx, B, D, mu, inv_sigma,
+                       static_cast<__bf16*>(X));
+  else
+    hipLaunchKernelGGL(standardise_kernel<float>, dim3(grid), dim3(kThreads), 0, s, x, idx, B, D, mu, inv_sigma,
+                       static_cast<float*>(X));
+  return hipGetLastError();
+}
+
+hipError_t launch_softmax_ce(const float* logits, int B, int D, int n_t, int n_s, const int32_t* lab_t,
+                             const int32_t* lab_s, const int32_t* idx, float* dZ, void* dZb, int bf16,
+                             float* row_loss, hipStream_t s) {
+  if (B <= 0) return hipSuccess;
+  if (bf16)
+    hipLaunchKernelGGL(softmax_ce_kernel<__bf16>, dim3(B), dim3(kThreads), 0, s, logits, B, D, n_t, n_s, lab_t,
+                       lab_s, idx, dZ, static_cast<__bf16*>(dZb), row_loss);
+  else
+    hipLaunchKernelGGL(softmax_ce_kernel<float>, dim3(B), dim3(kThreads), 0, s, logits, B, D, n_t, n_s, lab_t, lab_s,
+                       idx, dZ, static_cast<float*>(dZb), row_loss);
+  return hipGetLastError();
+}
+
+hipError_t launch_mean(const float* row_loss, int B, float* loss, hipStream_t s) {
+  if (B <= 0) return hipSuccess;
+  hipLaunchKernelGGL(mean_kernel, dim3(1), dim3(kThreads), 0, s, row_loss, B, loss);
+  return hipGetLastError();
+}
+
+hipError_t launch_colsum(const float* dZ, int B, int N, float* db, hipStream_t s) {
+  if (N <= 0) return hipSuccess;
+  hipLaunchKernelGGL(colsum_kernel, dim3((N + kThreads - 1) / kThreads), dim3(kThreads), 0, s, dZ, B, N, db);
+  return hipGetLastError();
+}
+
+hipError_t launch_adamw(float* w, const float* g, float* m, float* v, size_t n, float lr, float beta1, float beta2,
+                        float eps, float wd, float bc1, float bc2, void* wc, int bf16, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  if (bf16)
+    hipLaunchKernelGGL(adamw_kernel<__bf16>, dim3(grid_for(n)), dim3(kThreads), 0, s, w, g, m, v, n, lr, beta1,
+                       beta2, eps, wd, bc1, bc2, static_cast<__bf16*>(wc));
+  else
+    hipLaunchKernelGGL(adamw_kernel<float>, dim3(grid_for(n)), dim3(kThreads), 0, s, w, g, m, v, n, lr, beta1,
+                       beta2, eps, wd, bc1, bc2, static_cast<float*>(wc));
+  return hipGetLastError();
+}
+
+hipError_t launch_convert(const float* w, size_t n, void* wc, int bf16, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  if (bf16)
+    hipLaunchKernelGGL(convert_kernel<__bf16>, dim3(grid_for(n)), dim3(kThreads), 0, s, w, n,
+                       static_cast<__bf16*>(wc));
+  else
+    hipLaunchKernelGGL(convert_kernel<float>, dim3(grid_for(n)), dim3(kThreads), 0, s, w, n, static_cast<float*>(wc));
+  return hipGetLastError();
+}
+
+hipError_t launch_features(const float2* coeffs, int nA, int Qa, int M, int kind, int n_r, int n_q, float* F,
+                           hipStream_t s) {
+  if (nA <= 0) return hipSuccess;
+  const size_t D = kind == 0 ? static_cast<size_t>(n_r) * n_q : static_cast<size_t>(n_r) * n_r * n_q;
+  hipLaunchKernelGGL(features_kernel, dim3(grid_for(static_cast<size_t>(nA) * D)), dim3(kThreads), 0, s, coeffs, nA,
+                     Qa, M, kind, n_r, n_q, F);
+  return hipGetLastError();
+}
+
+hipError_t launch_topk(const float* logits, int rows, int D, int n_t, int n_s, int k, int32_t* top, float* mass,
+                       int32_t* sbin, hipStream_t s) {
+  if (rows <= 0) return hipSuccess;
+  if (k < 1 || k > 64 || k > n_t) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(topk_kernel, dim3(rows), dim3(kThreads), 0, s, logits, D, n_t, n_s, k, top, mass, sbin);
+  return hipGetLastError();
+}
+
+hipError_t launch_best_template(const void* poses, const int32_t* lists, int nA, int K, int32_t* best_t,
+                                void* best_pose, hipStream_t s) {
+  if (nA <= 0) return hipSuccess;
+  hipLaunchKernelGGL(best_template_kernel, dim3((nA + kThreads - 1) / kThreads), dim3(kThreads), 0, s,
+                     static_cast<const Pose*>(poses), lists, nA, K, best_t, static_cast<Pose*>(best_pose));
+  return hipGetLastError();
+}
+
+hipError_t launch_select_below(const float* mass, int nA, float tau, int32_t* list, int32_t* count, int32_t* flag,
+                               hipStream_t s) {
+  hipLaunchKernelGGL(select_below_kernel, dim3(1), dim3(kThreads), 0, s, mass, nA, tau, list, count, flag);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather_rows(const void* src, const int32_t* list, int count, size_t row_bytes, void* dst,
+                              hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  if (row_bytes % 8) return hipErrorInvalidValue;
+  const size_t words = row_bytes / 8;
+  hipLaunchKernelGGL(gather_rows_kernel, dim3(grid_for(static_cast<size_t>(count) * words)), dim3(kThreads), 0, s,
+                     static_cast<const uint2*>(src), list, count, words, static_cast<uint2*>(dst));
+  return hipGetLastError();
+}
+
+hipError_t launch_scatter_results(const int32_t* bt, const void* bp, const int32_t* list, int count, int32_t* dst_t,
+                                  void* dst_p, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(scatter_results_kernel, dim3((count + kThreads - 1) / kThreads), dim3(kThreads), 0, s, bt,
+                     static_cast<const Pose*>(bp), list, count, dst_t, static_cast<Pose*>(dst_p));
+  return hipGetLastError();
+}

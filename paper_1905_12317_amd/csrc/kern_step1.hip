@@ -40,10 +40,27 @@ __device__ __forceinline__ float embed(float2 b, int c, int cp) {
 
 // ---- template operand preparation -------------------------------------
 
+// Template of row tile rt, slot s (0..15).  Plain mode: template rt 16 + s.
+// List mode (lists != null): tiles come in groups of nRTk per image of the
+// chunk; slot j = (rt % nRTk) 16 + s of image a0 + rt / nRTk is template
+// lists[image][j] (j < K), else none (-1).
+__device__ __forceinline__ int tile_template(int rt, int s, int nB, const int* __restrict__ lists, int K, int nRTk,
+                                             int a0) {
+  if (!lists) {
+    const int B = rt * 16 + s;
+    return B < nB ? B : -1;
+  }
+  const int img = rt / nRTk;
+  const int j = (rt - img * nRTk) * 16 + s;
+  if (j >= K) return -1;
+  const int B = lists[static_cast<size_t>(a0 + img) * K + j];
+  return (B >= 0 && B < nB) ? B : -1;
+}
+
 // FP32 form, 32x32x2 MFMA: one K step is one m (k' = 2m + c').
 // Layout [q][row tile][m][lane] floats; lane l: row l % 32 -> (B, c), c' = l / 32.
 __global__ void tmpl_prep_fp32(const float2* __restrict__ b, float* __restrict__ out, int nB, int nRT, int M,
-                               int Qa, int NQ) {
+                               int Qa, int NQ, const int* __restrict__ lists, int K, int nRTk, int a0) {
   const size_t total = static_cast<size_t>(NQ) * nRT * M * 64;
   for (size_t t = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x; t < total;
        t += static_cast<size_t>(gridDim.x) * blockDim.x) {
@@ -54,9 +71,9 @@ __global__ void tmpl_prep_fp32(const float2* __restrict__ b, float* __restrict__
     const int rt = static_cast<int>(u % nRT);
     const int q = static_cast<int>(u / nRT);
     const int row = lane & 31;
-    const int B = rt * 16 + (row >> 1);
+    const int B = tile_template(rt, row >> 1, nB, lists, K, nRTk, a0);
     float v = 0.f;
-    if (B < nB) v = embed(b[(static_cast<size_t>(B) * Qa + q) * M + m], row & 1, lane >> 5);
+    if (B >= 0) v = embed(b[(static_cast<size_t>(B) * Qa + q) * M + m], row & 1, lane >> 5);
     out[t] = v;
   }
 }
@@ -64,7 +81,7 @@ __global__ void tmpl_prep_fp32(const float2* __restrict__ b, float* __restrict__
 // Split form, 32x32x16 MFMA: one K step is 8 m (k' = 16 ks + 8 (l/32) + e).
 // Layout [q][row tile][ks][lane][8 hi, 8 lo] bf16.
 __global__ void tmpl_prep_bf16(const float2* __restrict__ b, __bf16* __restrict__ out, int nB, int nRT, int M,
-                               int Qa, int NQ) {
+                               int Qa, int NQ, const int* __restrict__ lists, int K, int nRTk, int a0) {
   const int nks = M / 8;
   const size_t total = static_cast<size_t>(NQ) * nRT * nks * 64;
   for (size_t t = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x; t < total;
@@ -76,14 +93,14 @@ __global__ void tmpl_prep_bf16(const float2* __restrict__ b, __bf16* __restrict_
     const int rt = static_cast<int>(u % nRT);
     const int q = static_cast<int>(u / nRT);
     const int row = lane & 31;
-    const int B = rt * 16 + (row >> 1);
+    const int B = tile_template(rt, row >> 1, nB, lists, K, nRTk, a0);
     const int c = row & 1;
     bf16x8 hi, lo;
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
       const int kp = ks * 16 + 8 * (lane >> 5) + e;
       float v = 0.f;
-      if (B < nB) v = embed(b[(static_cast<size_t>(B) * Qa + q) * M + (kp >> 1)], c, kp & 1);
+      if (B >= 0) v = embed(b[(static_cast<size_t>(B) * Qa + q) * M + (kp >> 1)], c, kp & 1);
       const __bf16 h = static_cast<__bf16>(v);
       hi[e] = h;
       lo[e] = static_cast<__bf16>(v - static_cast<float>(h));
@@ -131,7 +148,8 @@ __global__ void __launch_bounds__(256) step1_fp32_v2(Step1Args p) {
   const int twoH = 2 * p.H_pad;
   const float* Pb = smem + r * PS + c32;
   float* zbase = p.zs + static_cast<size_t>(A) * p.nB * NQ * twoH + static_cast<size_t>(q) * twoH;
-  const float* rq = p.r32 + static_cast<size_t>(q) * nRT * M * 64 + lane;
+  const float* rq =
+      p.r32 + (static_cast<size_t>(q) * p.tiles_per_q + static_cast<size_t>(A) * p.img_tiles) * M * 64 + lane;
   for (int rt0 = (part * 4 + wave) * RT; rt0 < nRT; rt0 += 4 * RT * p.tparts) {
     f32x16 acc[RT][CT];
 #pragma unroll
@@ -231,7 +249,9 @@ __global__ void __launch_bounds__(256) step1_bf16_v2(Step1Args p) {
   const int twoH = 2 * p.H_pad;
   const float* Pb = smem + c32 * RW + 4 * r;
   float* zbase = p.zs + static_cast<size_t>(A) * p.nB * NQ * twoH + static_cast<size_t>(q) * twoH;
-  const bf16x8* rq = reinterpret_cast<const bf16x8*>(p.r16) + (static_cast<size_t>(q) * nRT * nks * 64 + lane) * 2;
+  const bf16x8* rq =
+      reinterpret_cast<const bf16x8*>(p.r16) +
+      ((static_cast<size_t>(q) * p.tiles_per_q + static_cast<size_t>(A) * p.img_tiles) * nks * 64 + lane) * 2;
   for (int rt0 = (part * 4 + wave) * RT; rt0 < nRT; rt0 += 4 * RT * p.tparts) {
     f32x16 acc[RT][CT];
 #pragma unroll
@@ -294,23 +314,34 @@ hipError_t set_lds(K kern, size_t lds) {
 
 }  // namespace
 
+size_t tmpl_prep_tile_bytes(size_t tiles, int M, int Qa, int precision) {
+  const size_t NQ = Qa / 2 + 1;
+  if (precision == 0) return NQ * tiles * M * 64 * sizeof(float);
+  return NQ * tiles * (M / 8) * 64 * 32;
+}
+
 size_t tmpl_prep_bytes(int nB, int M, int Qa, int precision) {
-  const size_t nRT = (nB + 15) / 16, NQ = Qa / 2 + 1;
-  if (precision == 0) return NQ * nRT * M * 64 * sizeof(float);
-  return NQ * nRT * (M / 8) * 64 * 32;
+  return tmpl_prep_tile_bytes((nB + 15) / 16, M, Qa, precision);
 }
 
 hipError_t launch_tmpl_prep(const float2* b, void* out, int nB, int M, int Qa, int precision, hipStream_t s) {
-  if (nB <= 0) return hipSuccess;
-  const int nRT = (nB + 15) / 16, NQ = Qa / 2 + 1;
+  return launch_tmpl_prep_lists(b, out, nB, M, Qa, precision, nullptr, 0, 0, 0, s);
+}
+
+hipError_t launch_tmpl_prep_lists(const float2* b, void* out, int nB, int M, int Qa, int precision, const int* lists,
+                                  int K, int na, int a0, hipStream_t s) {
+  if (nB <= 0 || (lists && (K <= 0 || na <= 0))) return hipSuccess;
+  const int nRTk = lists ? (K + 15) / 16 : 0;
+  const int nRT = lists ? na * nRTk : (nB + 15) / 16;
+  const int NQ = Qa / 2 + 1;
   const size_t total = static_cast<size_t>(NQ) * nRT * (precision == 0 ? M : M / 8) * 64;
   const int blocks = static_cast<int>(std::min<size_t>((total + 255) / 256, 65536));
   if (precision == 0)
     hipLaunchKernelGGL(tmpl_prep_fp32, dim3(blocks), dim3(256), 0, s, b, static_cast<float*>(out), nB, nRT, M, Qa,
-                       NQ);
+                       NQ, lists, K, nRTk, a0);
   else
     hipLaunchKernelGGL(tmpl_prep_bf16, dim3(blocks), dim3(256), 0, s, b, static_cast<__bf16*>(out), nB, nRT, M,
-                       Qa, NQ);
+                       Qa, NQ, lists, K, nRTk, a0);
   return hipGetLastError();
 }
 

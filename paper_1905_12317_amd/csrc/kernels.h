@@ -33,6 +33,12 @@ struct Step1Args {
   int nA, nB, M, Qa, H_pad, L;
   int zblk;              // zeta per workgroup (64 or 128)
   int tparts;            // template row tiles split over this many workgroups
+  // template operand addressing: row tile t of image A at mode q is tile
+  // q tiles_per_q + A img_tiles + t.  Plain: tiles_per_q = ceil(nB/16),
+  // img_tiles = 0; per-image lists: nB = K, img_tiles = ceil(K/16),
+  // tiles_per_q = nA img_tiles
+  int tiles_per_q;
+  int img_tiles;
 };
 
 // Step 3 + rotation FFT + argmax.  Row Qa/2 of Zhat (the Nyquist mode) is
@@ -54,7 +60,11 @@ hipError_t launch_step3(const Step3Args& args, int precision, hipStream_t stream
 // Step 1 with the template operand embedded once per call (kern_step1.hip):
 // staging layout zs[pair][q][c][zeta], q = 0 .. Qa/2 (Qa/2 + 1 rows).
 size_t tmpl_prep_bytes(int nB, int M, int Qa, int precision);
+size_t tmpl_prep_tile_bytes(size_t tiles, int M, int Qa, int precision);
 hipError_t launch_tmpl_prep(const float2* b, void* out, int nB, int M, int Qa, int precision, hipStream_t stream);
+// per-image template lists [.][K] for images a0 .. a0 + na - 1 of the call
+hipError_t launch_tmpl_prep_lists(const float2* b, void* out, int nB, int M, int Qa, int precision, const int* lists,
+                                  int K, int na, int a0, hipStream_t stream);
 size_t step1_v2_lds_bytes(int M, int zb, int precision);
 hipError_t launch_step1_v2(const Step1Args& args, int precision, hipStream_t stream);
 

@@ -111,6 +111,8 @@ namespace ftkint {
 // Built-in launch shapes (environment overrides applied).
 ftk_tuning_t default_tuning();
 Needs plan_needs(const ftk_plan* p, int nA, int nB, bool from_pixels);
+// alignment of nA images against K listed templates each
+Needs plan_needs_lists(const ftk_plan* p, int nA, int K);
 // Step 3 waves per workgroup and Step 1 zeta block actually used by a plan.
 int step3_waves(const ftk_plan* p);
 int step1_zblk(const ftk_plan* p);

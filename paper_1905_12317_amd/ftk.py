@@ -72,7 +72,26 @@ POSE_DTYPE = np.dtype([("value", np.float32), ("shift", np.int32), ("rot", np.in
 EXPORTS = ["ftk_plan_create", "ftk_plan_destroy", "ftk_plan_info", "ftk_set_shifts", "ftk_transform",
            "ftk_align_coeffs", "ftk_align", "ftk_plan_tables", "ftk_plan_profile", "ftk_plan_stage_times",
            "ftk_plan_set_tuning", "ftk_plan_get_tuning", "ftk_batch_create", "ftk_batch_run", "ftk_batch_info",
-           "ftk_batch_destroy", "ftk_strerror", "ftk_last_error_message"]
+           "ftk_batch_destroy", "ftk_strerror", "ftk_last_error_message",
+           # include/ftk_mlp.h
+           "ftk_mlp_create", "ftk_mlp_destroy", "ftk_mlp_info", "ftk_mlp_set_layer", "ftk_mlp_get_layer",
+           "ftk_mlp_set_input_norm", "ftk_features", "ftk_mlp_forward", "ftk_mlp_gradients", "ftk_mlp_get_grad",
+           "ftk_mlp_train_step", "ftk_propose", "ftk_align_lists", "ftk_best_template", "ftk_align_proposed"]
+
+FTK_MLP_FP32 = 0
+FTK_MLP_BF16 = 1
+MLP_PRECISIONS = {"fp32": FTK_MLP_FP32, "bf16": FTK_MLP_BF16}
+
+
+class MLPInfo(ctypes.Structure):
+    _fields_ = [("nlayers", ctypes.c_int), ("dims", ctypes.c_int * 9), ("n_template", ctypes.c_int),
+                ("n_shift", ctypes.c_int), ("precision", ctypes.c_int), ("max_batch", ctypes.c_int),
+                ("step", ctypes.c_int64), ("param_count", ctypes.c_size_t), ("device_bytes", ctypes.c_size_t)]
+
+    def as_dict(self):
+        d = {f: getattr(self, f) for f, _ in self._fields_}
+        d["dims"] = list(self.dims)[:self.nlayers + 1]
+        return d
 
 _lib = None
 
@@ -105,6 +124,23 @@ def lib() -> ctypes.CDLL:
     L.ftk_batch_info.argtypes = [vp, ctypes.POINTER(BatchInfo)]
     L.ftk_batch_destroy.argtypes = [vp]
     L.ftk_batch_destroy.restype = None
+    L.ftk_mlp_create.argtypes = [ctypes.POINTER(vp), vp, i, i, i, i, i]
+    L.ftk_mlp_destroy.argtypes = [vp]
+    L.ftk_mlp_destroy.restype = None
+    L.ftk_mlp_info.argtypes = [vp, ctypes.POINTER(MLPInfo)]
+    L.ftk_mlp_set_layer.argtypes = [vp, i, vp, vp]
+    L.ftk_mlp_get_layer.argtypes = [vp, i, vp, vp]
+    L.ftk_mlp_set_input_norm.argtypes = [vp, vp, vp]
+    L.ftk_features.argtypes = [vp, vp, i, i, i, i, vp, vp]
+    L.ftk_mlp_forward.argtypes = [vp, vp, i, vp, vp]
+    L.ftk_mlp_gradients.argtypes = [vp, vp, vp, vp, vp, i, vp, vp]
+    L.ftk_mlp_get_grad.argtypes = [vp, i, vp, vp]
+    f = ctypes.c_float
+    L.ftk_mlp_train_step.argtypes = [vp, vp, vp, vp, vp, i, f, f, f, f, f, vp, vp]
+    L.ftk_propose.argtypes = [vp, vp, i, i, vp, vp, vp, vp]
+    L.ftk_align_lists.argtypes = [vp, vp, i, vp, i, vp, i, vp, vp]
+    L.ftk_best_template.argtypes = [vp, vp, i, i, vp, vp, vp]
+    L.ftk_align_proposed.argtypes = [vp, vp, vp, i, vp, i, i, i, i, i, f, vp, vp, vp, ctypes.POINTER(i), vp]
     L.ftk_strerror.restype = ctypes.c_char_p
     L.ftk_strerror.argtypes = [i]
     L.ftk_last_error_message.restype = ctypes.c_char_p
@@ -309,6 +345,176 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+def _i32(t, name):
+    import torch
+    _require_cuda(t, torch.int32, name)
+    return _ptr(t)
+
+
+class MLP:
+    """Owns an ftk_mlp (the template-proposal network)."""
+
+    def __init__(self, dims, n_template: int, n_shift: int, precision="bf16", max_batch: int = 1024):
+        dims = [int(d) for d in dims]
+        arr = (ctypes.c_int * len(dims))(*dims)
+        prec = MLP_PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+        h = ctypes.c_void_p()
+        _check(lib().ftk_mlp_create(ctypes.byref(h), ctypes.cast(arr, ctypes.c_void_p), len(dims) - 1, n_template,
+                                    n_shift, prec, max_batch), "ftk_mlp_create")
+        self._h = h
+        self.dims, self.n_template, self.n_shift, self.max_batch = dims, n_template, n_shift, max_batch
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().ftk_mlp_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def info(self) -> dict:
+        inf = MLPInfo()
+        _check(lib().ftk_mlp_info(self._h, ctypes.byref(inf)), "ftk_mlp_info")
+        return inf.as_dict()
+
+    def set_layer(self, layer: int, W, b):
+        W = np.ascontiguousarray(W, dtype=np.float32)
+        b = np.ascontiguousarray(b, dtype=np.float32)
+        if W.shape != (self.dims[layer + 1], self.dims[layer]) or b.shape != (self.dims[layer + 1],):
+            raise ValueError("layer shape mismatch")
+        _check(lib().ftk_mlp_set_layer(self._h, layer, W.ctypes.data, b.ctypes.data), "ftk_mlp_set_layer")
+
+    def get_layer(self, layer: int):
+        W = np.zeros((self.dims[layer + 1], self.dims[layer]), np.float32)
+        b = np.zeros(self.dims[layer + 1], np.float32)
+        _check(lib().ftk_mlp_get_layer(self._h, layer, W.ctypes.data, b.ctypes.data), "ftk_mlp_get_layer")
+        return W, b
+
+    def set_params(self, params):
+        for l, (W, b) in enumerate(params):
+            self.set_layer(l, W, b)
+
+    def params(self):
+        return [self.get_layer(l) for l in range(len(self.dims) - 1)]
+
+    def set_input_norm(self, mu, inv_sigma):
+        mu = np.ascontiguousarray(mu, dtype=np.float32)
+        inv_sigma = np.ascontiguousarray(inv_sigma, dtype=np.float32)
+        _check(lib().ftk_mlp_set_input_norm(self._h, mu.ctypes.data, inv_sigma.ctypes.data), "ftk_mlp_set_input_norm")
+
+    def forward(self, x, logits=None, stream=None):
+        import torch
+        _require_cuda(x, torch.float32, "x")
+        if logits is None:
+            logits = torch.empty((x.shape[0], self.dims[-1]), dtype=torch.float32, device=x.device)
+        _check(lib().ftk_mlp_forward(self._h, _ptr(x), x.shape[0], _ptr(logits), _stream(stream)), "ftk_mlp_forward")
+        return logits
+
+    def gradients(self, x_all, lab_t, lab_s, idx, loss=None, stream=None):
+        import torch
+        _require_cuda(x_all, torch.float32, "x_all")
+        if loss is None:
+            loss = torch.empty(1, dtype=torch.float32, device=x_all.device)
+        _check(lib().ftk_mlp_gradients(self._h, _ptr(x_all), _i32(lab_t, "lab_t"),
+                                       _i32(lab_s, "lab_s") if lab_s is not None else None, _i32(idx, "idx"),
+                                       idx.shape[0], _ptr(loss), _stream(stream)), "ftk_mlp_gradients")
+        return loss
+
+    def grad(self, layer: int):
+        dW = np.zeros((self.dims[layer + 1], self.dims[layer]), np.float32)
+        db = np.zeros(self.dims[layer + 1], np.float32)
+        _check(lib().ftk_mlp_get_grad(self._h, layer, dW.ctypes.data, db.ctypes.data), "ftk_mlp_get_grad")
+        return dW, db
+
+    def train_step(self, x_all, lab_t, lab_s, idx, lr, beta1=0.9, beta2=0.999, eps=1e-8, wd=0.0, loss=None,
+                   stream=None):
+        import torch
+        _require_cuda(x_all, torch.float32, "x_all")
+        if loss is None:
+            loss = torch.empty(1, dtype=torch.float32, device=x_all.device)
+        _check(lib().ftk_mlp_train_step(self._h, _ptr(x_all), _i32(lab_t, "lab_t"),
+                                        _i32(lab_s, "lab_s") if lab_s is not None else None, _i32(idx, "idx"),
+                                        idx.shape[0], lr, beta1, beta2, eps, wd, _ptr(loss), _stream(stream)),
+               "ftk_mlp_train_step")
+        return loss
+
+    def propose(self, x, topk: int, stream=None):
+        import torch
+        _require_cuda(x, torch.float32, "x")
+        n = x.shape[0]
+        top = torch.empty((n, topk), dtype=torch.int32, device=x.device)
+        mass = torch.empty(n, dtype=torch.float32, device=x.device)
+        sbin = torch.empty(n, dtype=torch.int32, device=x.device)
+        _check(lib().ftk_propose(self._h, _ptr(x), n, topk, _ptr(top), _ptr(mass), _ptr(sbin), _stream(stream)),
+               "ftk_propose")
+        return top, mass, sbin
+
+
+FTK_FEATURES_POWER = 0
+FTK_FEATURES_CROSS = 1
+FEATURE_KINDS = {"power": FTK_FEATURES_POWER, "cross": FTK_FEATURES_CROSS}
+
+
+def feature_count(kind, n_r: int, n_q: int) -> int:
+    k = FEATURE_KINDS[kind] if isinstance(kind, str) else int(kind)
+    return n_r * n_q if k == FTK_FEATURES_POWER else n_r * n_r * n_q
+
+
+def features(plan: "Plan", coeffs, n_r: int, n_q: int, kind="power", out=None, stream=None):
+    import torch
+    _require_cuda(coeffs, torch.complex64, "coeffs")
+    k = FEATURE_KINDS[kind] if isinstance(kind, str) else int(kind)
+    if out is None:
+        out = torch.empty((coeffs.shape[0], feature_count(k, n_r, n_q)), dtype=torch.float32, device=coeffs.device)
+    _check(lib().ftk_features(plan._h, _ptr(coeffs), coeffs.shape[0], k, n_r, n_q, _ptr(out), _stream(stream)),
+           "ftk_features")
+    return out
+
+
+def best_template(poses, lists=None, stream=None):
+    """Per-image best over the pairs of poses [nA][K][3] (int32 view)."""
+    import torch
+    _require_cuda(poses, torch.int32, "poses")
+    nA, K = poses.shape[0], poses.shape[1]
+    bt = torch.empty(nA, dtype=torch.int32, device=poses.device)
+    bp = torch.empty((nA, 3), dtype=torch.int32, device=poses.device)
+    _check(lib().ftk_best_template(_ptr(poses), _i32(lists, "lists") if lists is not None else None, nA, K, _ptr(bt),
+                                   _ptr(bp), _stream(stream)), "ftk_best_template")
+    return bt, bp
+
+
+def align_lists(plan: "Plan", a, b, lists, stream=None):
+    import torch
+    _require_cuda(a, torch.complex64, "img_coeffs")
+    _require_cuda(b, torch.complex64, "tmpl_coeffs")
+    nA, K = lists.shape
+    best = torch.empty((nA, K, 3), dtype=torch.int32, device=a.device)
+    _check(lib().ftk_align_lists(plan._h, _ptr(a), a.shape[0], _ptr(b), b.shape[0], _i32(lists, "lists"), K,
+                                 _ptr(best), _stream(stream)), "ftk_align_lists")
+    return best
+
+
+def align_proposed(plan: "Plan", mlp: MLP, images, tmpl_coeffs, n_r: int, n_q: int, topk: int, tau: float,
+                   kind="power", stream=None):
+    """Proposal search: (best template [nA], best pose [nA][3], fallback flags [nA], fallback count)."""
+    import torch
+    _require_cuda(images, torch.float32, "images")
+    _require_cuda(tmpl_coeffs, torch.complex64, "tmpl_coeffs")
+    nA = images.shape[0]
+    k = FEATURE_KINDS[kind] if isinstance(kind, str) else int(kind)
+    bt = torch.empty(nA, dtype=torch.int32, device=images.device)
+    bp = torch.empty((nA, 3), dtype=torch.int32, device=images.device)
+    fb = torch.empty(nA, dtype=torch.int32, device=images.device)
+    cnt = ctypes.c_int(0)
+    _check(lib().ftk_align_proposed(plan._h, mlp._h, _ptr(images), nA, _ptr(tmpl_coeffs), tmpl_coeffs.shape[0], k,
+                                    n_r, n_q, topk, tau, _ptr(bt), _ptr(bp), _ptr(fb), ctypes.byref(cnt),
+                                    _stream(stream)), "ftk_align_proposed")
+    return bt, bp, fb, cnt.value
 
 
 def poses_numpy(best) -> np.ndarray:

@@ -108,15 +108,17 @@ class AlignmentSet:
     true_theta: np.ndarray  # (nA,) rotation applied to the template
     true_shift: np.ndarray  # (nA, 2) shift applied after the rotation (px)
     noise_sigma: np.ndarray  # (nA,)
+    clean: np.ndarray | None = None  # (nA, n, n) noise-free images if kept
 
 
 def make_alignment_set(seed: int, n: int, n_templates: int, n_images: int,
                        nblob: int, shift_radius_px: float, snr: float | None,
-                       disk_px: float = 8.0, sigma_px=(1.0, 3.0)) -> AlignmentSet:
+                       disk_px: float = 8.0, sigma_px=(1.0, 3.0), keep_clean: bool = False) -> AlignmentSet:
     """Templates are blob sums at unit L2; images are moved templates + noise.
 
     snr is mean(clean^2) / noise_variance over the full frame; None gives
-    noise-free images.
+    noise-free images.  keep_clean also returns the noise-free images (the
+    random stream, hence every other output, is unchanged).
     """
     rng = np.random.default_rng(seed)
     tb, temps, scales = [], [], []
@@ -128,7 +130,7 @@ def make_alignment_set(seed: int, n: int, n_templates: int, n_images: int,
         tb.append(b)
         temps.append(img * sc)
         scales.append(sc)
-    ib, imgs = [], []
+    ib, imgs, cleans = [], [], []
     tt = np.zeros(n_images, dtype=np.int64)
     th = np.zeros(n_images)
     sh = np.zeros((n_images, 2))
@@ -147,9 +149,11 @@ def make_alignment_set(seed: int, n: int, n_templates: int, n_images: int,
             noisy = clean
         tt[a], th[a], sh[a], ns[a] = t, theta, s, sig
         ib.append(mb)
+        if keep_clean:
+            cleans.append(clean)
         imgs.append(noisy)
     return AlignmentSet(n, np.array(temps), np.array(imgs), tb, ib,
-                        np.array(scales), tt, th, sh, ns)
+                        np.array(scales), tt, th, sh, ns, np.array(cleans) if keep_clean else None)
 
 
 def white_noise_images(seed: int, count: int, n: int) -> np.ndarray:
@@ -215,3 +219,15 @@ def mlp_init(seed: int, dims) -> list:
 def permutation(seed: int, n: int) -> np.ndarray:
     """A seeded random permutation of 0..n-1 (int32), e.g. minibatch order."""
     return np.random.default_rng(seed).permutation(n).astype(np.int32)
+
+
+def gaussian_noise(seed: int, sigmas, n: int, device="cuda"):
+    """Fresh white noise for re-noising clean images on the device:
+    sigmas[i] * N(0, 1) per pixel, shape (len(sigmas), n, n), float32, from
+    a seeded torch generator on `device`."""
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed))
+    sig = torch.as_tensor(np.asarray(sigmas, dtype=np.float32), device=device)
+    z = torch.randn((sig.shape[0], n, n), generator=g, device=device, dtype=torch.float32)
+    return z * sig[:, None, None]

@@ -29,8 +29,11 @@ def _lib():
 
 def test_library_exports_every_declared_symbol():
     L = _lib()
-    hdr = open(os.path.join(ROOT, "include", "ftk.h")).read()
-    declared = set(re.findall(r"^\s*(?:int|void|const char\*)\s+(ftk_\w+)\s*\(", hdr, re.M))
+    declared = set()
+    for name in sorted(os.listdir(os.path.join(ROOT, "include"))):
+        if name.endswith(".h"):
+            hdr = open(os.path.join(ROOT, "include", name)).read()
+            declared |= set(re.findall(r"^\s*(?:int|void|const char\*)\s+(ftk_\w+)\s*\(", hdr, re.M))
     assert declared == set(ftk.EXPORTS)
     for name in declared:
         assert hasattr(L, name), name
