@@ -146,9 +146,181 @@ def cpu_baseline(inputs, w, shifts, n_img=8, n_tmp=48):
                       f"{dt:.1f} s"}
 
 
+RAGGED = dict(name="ragged_c4", stacks=64, seed=4, scale=0.25, nblob=60, snr=0.05, eps=1e-3)
+PROPOSAL = dict(name="proposal_n128", n=128, M=64, Qa=256, R=4.0, n_templates=1024, n_clean=16384, n_val=1024,
+                n_test=2048, nblob=60, snr=0.05, eps=1e-3, epochs=20, n_r=16, n_q=8, topk=32, hidden=1024, seed=5)
+
+
+def bench_ragged(args):
+    """64 stacks of uneven n, template and image counts and shift radii (the
+    ragged workload, image and template counts scaled by RAGGED['scale']),
+    split-bf16 form: one ftk_batch run (two lanes, one hipGraph, autotuned
+    launch shapes) against the same stacks aligned one ftk_align at a time."""
+    import torch
+    import synth
+    from paper_1905_12317_amd import ftk
+    w = RAGGED
+    t0 = time.perf_counter()
+    specs = synth.ragged_stack_specs(w["seed"], count=w["stacks"], scale=w["scale"])
+    stacks, flop = [], 0.0
+    for i, sp in enumerate(specs):
+        s = synth.make_alignment_set(1000 * w["seed"] + i, sp["n"], sp["n_templates"], sp["n_images"], w["nblob"],
+                                     sp["R"], w["snr"])
+        shifts = synth.shift_lattice(sp["R"])
+        P = ftk.Plan(sp["n"], sp["M"], sp["Qa"], sp["R"], w["eps"], "bf16x3")
+        P.set_shifts(shifts)
+        inf = P.info()
+        imgs = torch.as_tensor(s.images, dtype=torch.float32, device="cuda")
+        tmps = torch.as_tensor(s.templates, dtype=torch.float32, device="cuda")
+        best = torch.empty((imgs.shape[0], tmps.shape[0], 3), dtype=torch.int32, device="cuda")
+        stacks.append(dict(plan=P, images=imgs, templates=tmps, best=best))
+        flop += imgs.shape[0] * tmps.shape[0] * sum(flops_per_pair(inf["H"], inf["M"], inf["N"], inf["Qa"])[:2])
+        if i % 16 == 15:
+            log(f"  {i + 1} stacks generated ({time.perf_counter() - t0:.1f} s)")
+    pairs = sum(st["images"].shape[0] * st["templates"].shape[0] for st in stacks)
+    log(f"ragged inputs in {time.perf_counter() - t0:.1f} s: {len(stacks)} stacks, {pairs} pairs")
+    stream = torch.cuda.Stream()
+    t0 = time.perf_counter()
+    B = ftk.Batch(stacks, lanes=2, graph=True, autotune=True, stream=stream)
+    tune_s = time.perf_counter() - t0
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    for _ in range(args.warmup + 1):  # the first run captures the graph
+        B.run(stream)
+    stream.synchronize()
+    ev0.record(stream)
+    for _ in range(args.steps):
+        B.run(stream)
+    ev1.record(stream)
+    stream.synchronize()
+    ms_batch = ev0.elapsed_time(ev1) / args.steps
+    # the same stacks one call at a time, default launch shapes
+    with torch.cuda.stream(stream):
+        for st in stacks:
+            st["plan"].align(st["images"], st["templates"], best=st["best"], stream=stream)
+        stream.synchronize()
+        ev0.record(stream)
+        for _ in range(args.steps):
+            for st in stacks:
+                st["plan"].align(st["images"], st["templates"], best=st["best"], stream=stream)
+        ev1.record(stream)
+        stream.synchronize()
+    ms_seq = ev0.elapsed_time(ev1) / args.steps
+    info = B.info()
+    achieved = flop / (ms_batch / 1e3)
+    out = {
+        "metric": "pairs/s over a ragged batch of 64 stacks (uneven n, templates, images, shift radius)",
+        "value": pairs / (ms_batch / 1e3), "unit": "pairs/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_batch, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "bf16x3->f32", "data": "synthetic",
+        "config": {"workload": f"{w['name']}: 64 stacks, n in {{64,96,128,192}}, M=n/2, Qa=2n, templates "
+                               f"log-uniform 100-4000 and images 16-256 scaled by {w['scale']}, shift radius "
+                               f"2-8 px (0.5 px lattice), 60-blob templates, SNR {w['snr']}, eps={w['eps']}",
+                   "pairs": pairs, "lanes": info["lanes"], "graph_nodes": info["graph_nodes"],
+                   "autotune_s": tune_s, "sequential_ms_per_step": ms_seq, "batch_speedup": ms_seq / ms_batch},
+        "roofline": {"kernel": "whole batch (Step 1 + Step 3 algorithmic flop)", "bound": "mfma",
+                     "achieved": achieved / 1e12, "peak": PEAK_BF16_MFMA / 1e12, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_BF16_MFMA, "traffic": None},
+    }
+    print(json.dumps(out), flush=True)
+
+
+def bench_proposal(args):
+    """Learned proposal at n = 128: train on re-noised images labelled by the
+    full FTK each epoch, choose the threshold on a validation split, then time
+    the proposal search against the full search on a test split."""
+    import torch
+    import synth
+    from paper_1905_12317_amd import ftk
+    from paper_1905_12317_amd import proposal as PR
+    w = PROPOSAL
+    t0 = time.perf_counter()
+    n_all = w["n_clean"] + w["n_val"] + w["n_test"]
+    s = synth.make_alignment_set(w["seed"], w["n"], w["n_templates"], n_all, w["nblob"], w["R"], w["snr"],
+                                 keep_clean=True)
+    gen_s = time.perf_counter() - t0
+    shifts = synth.shift_lattice(w["R"])
+    bins = PR.shift_bins(shifts)
+    n_t, n_s, kind = w["n_templates"], int(bins.max()) + 1, "cross"
+    P = ftk.Plan(w["n"], w["M"], w["Qa"], w["R"], w["eps"], "bf16x3")
+    P.set_shifts(shifts)
+    tmps = torch.as_tensor(s.templates, dtype=torch.float32, device="cuda")
+    tc = P.transform(tmps)
+    nc = w["n_clean"]
+    clean = torch.as_tensor(s.clean[:nc], dtype=torch.float32, device="cuda")
+    sig = s.noise_sigma[:nc]
+    dims = [ftk.feature_count(kind, w["n_r"], w["n_q"]), w["hidden"], w["hidden"], w["hidden"], n_t + n_s]
+    net = ftk.MLP(dims, n_t, n_s, "bf16", max_batch=1024)
+    net.set_params(synth.mlp_init(w["seed"], dims))
+    perms = [synth.permutation(100 + e, nc) for e in range(w["epochs"])]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    losses = PR.train_online(net, P, clean, tc, bins, lambda e: synth.gaussian_noise(7000 + e, sig, w["n"]), perms,
+                             kind, w["n_r"], w["n_q"], batch=256, lr=2e-3, wd=1e-2)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    # training-step throughput of the network kernels alone
+    feats = ftk.features(P, P.transform(clean[:8192].contiguous()), w["n_r"], w["n_q"], kind=kind)
+    lab = torch.zeros(8192, dtype=torch.int32, device="cuda")
+    idx = torch.arange(256, dtype=torch.int32, device="cuda")
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    net.gradients(feats, lab, lab, idx)
+    e0.record()
+    for _ in range(20):
+        net.gradients(feats, lab, lab, idx)
+    e1.record()
+    torch.cuda.synchronize()
+    ms_grad = e0.elapsed_time(e1) / 20
+    mlp_flop = 6.0 * 256 * sum(dims[i] * dims[i + 1] for i in range(len(dims) - 1))
+    # threshold on the validation split
+    vi = torch.as_tensor(s.images[nc:nc + w["n_val"]], dtype=torch.float32, device="cuda")
+    vlab, _, _ = PR.ftk_labels(P, vi, tmps, bins)
+    vf = ftk.features(P, P.transform(vi), w["n_r"], w["n_q"], kind=kind)
+    top, mass, _ = net.propose(vf, w["topk"])
+    hit = (top.cpu().numpy() == vlab.cpu().numpy()[:, None]).any(axis=1)
+    tau = PR.choose_tau(mass.cpu().numpy(), hit, max_miss=0.003)
+    # test split: proposal search vs full search, timed
+    ti = torch.as_tensor(s.images[nc + w["n_val"]:], dtype=torch.float32, device="cuda")
+    nA = ti.shape[0]
+    ftk.align_proposed(P, net, ti, tc, w["n_r"], w["n_q"], w["topk"], tau, kind=kind)
+    _, full = P.align_coeffs(P.transform(ti), tc)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    bt, bp, fb, nfb = ftk.align_proposed(P, net, ti, tc, w["n_r"], w["n_q"], w["topk"], tau, kind=kind)
+    torch.cuda.synchronize()
+    t_prop = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    _, full = P.align_coeffs(P.transform(ti), tc)
+    fbt, fbp = ftk.best_template(full)
+    torch.cuda.synchronize()
+    t_full = time.perf_counter() - t0
+    same = (bt.cpu().numpy() == fbt.cpu().numpy()) & np.all(bp.cpu().numpy() == fbp.cpu().numpy(), axis=1)
+    eff = nA * n_t / t_prop
+    out = {
+        "metric": "effective pairs/s of the proposal search (images x all templates / time), recall of the full "
+                  "search's best pose", "value": eff, "unit": "pairs/s", "n_gpus": 1, "steps": 1, "warmup": 1,
+        "ms_per_step": t_prop * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "bf16 MLP + bf16x3 FTK", "data": "synthetic",
+        "config": {"workload": f"{w['name']}: {n_t} 60-blob templates n=128, M=64, Qa=256, N=197 shifts, SNR "
+                               f"{w['snr']}; {nc} training images re-noised and relabelled by the full FTK each of "
+                               f"{w['epochs']} epochs; cross-ring features n_r={w['n_r']} n_q={w['n_q']} "
+                               f"({dims[0]} inputs), MLP {dims}; top-{w['topk']}; test {nA} images",
+                   "recall": float(same.mean()), "fallback": int(nfb), "tau": tau,
+                   "validation_topk_hit": float(hit.mean()), "full_search_pairs_per_s": nA * n_t / t_full,
+                   "speedup_vs_full_search": t_full / t_prop, "train_s": train_s, "generate_s": gen_s,
+                   "loss_first_last": [losses[0], losses[-1]]},
+        "roofline": {"kernel": "MLP loss + gradients (bf16 MFMA GEMMs), batch 256", "bound": "mfma",
+                     "achieved": mlp_flop / (ms_grad / 1e3) / 1e12, "peak": PEAK_BF16_MFMA / 1e12, "unit": "TFLOP/s",
+                     "frac": mlp_flop / (ms_grad / 1e3) / PEAK_BF16_MFMA, "traffic": None},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--workload", default="cryoem_n128", choices=["cryoem_n128", "ragged", "proposal"],
+                    help="cryoem_n128 (default): the headline metric; ragged / proposal: the batch and the "
+                         "learned-proposal measurements, each printing its own JSON line")
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--form", default="all", choices=["fp32", "bf16x3", "all"])
@@ -175,6 +347,10 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py: no GPU visible", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "ragged":
+        return bench_ragged(args)
+    if args.workload == "proposal":
+        return bench_proposal(args)
     import synth
     w = WORKLOAD
     t = time.perf_counter()

@@ -37,19 +37,19 @@ __device__ __forceinline__ void step3_epilogue(const Step3Args& p, f32x16 (&acc)
   const int Qa = 2 * QH;
   const int r = lane >> 5;
   const int c32 = lane & 31;
-  float2* fb2 = fb + 4 * QH;
+  float2* fb2 = fb + 2 * QH;
   float bv = -__builtin_inff();
   uint32_t bi = 0xffffffffu;
   float* Xp = p.X ? p.X + static_cast<size_t>(pair) * p.N * Qa : nullptr;
+  // 8 groups of 2 shifts (one per half-wave), two rows of QH modes each
 #pragma unroll
-  for (int g = 0; g < 4; ++g) {
+  for (int gg = 0; gg < 8; ++gg) {
+    const int g = gg >> 1, d = gg & 1;
 #pragma unroll
     for (int ct = 0; ct < CTQ; ++ct)
-#pragma unroll
-      for (int d = 0; d < 2; ++d)
-        fb[(2 * r + d) * QH + ct * 32 + c32] = make_float2(acc[ct][4 * g + 2 * d], acc[ct][4 * g + 2 * d + 1]);
+      fb[r * QH + ct * 32 + c32] = make_float2(acc[ct][4 * g + 2 * d], acc[ct][4 * g + 2 * d + 1]);
     wave_sync();
-    for (int t = lane; t < 4 * QH; t += 64) {
+    for (int t = lane; t < 2 * QH; t += 64) {
       const int row = t / QH;
       const int k = t - row * QH;
       const float2 P = fb[t];
@@ -65,11 +65,11 @@ __device__ __forceinline__ void step3_epilogue(const Step3Args& p, f32x16 (&acc)
       fb2[t] = Z;
     }
     wave_sync();
-    float2* res = ct_fft<QH, 1, 4, false, 64, 2>(fb2, fb, tw, lane, WaveSync());
-    for (int t = lane; t < 4 * QH; t += 64) {
+    float2* res = ct_fft<QH, 1, 2, false, 64, 2>(fb2, fb, tw, lane, WaveSync());
+    for (int t = lane; t < 2 * QH; t += 64) {
       const int row = t / QH;
       const int s = t - row * QH;
-      const int delta = d0 + 4 * g + row;
+      const int delta = d0 + 4 * g + 2 * row + d;
       if (delta < p.N) {
         const float2 z = res[t];
         const uint32_t idx = static_cast<uint32_t>(delta) * Qa + 2 * s;
@@ -191,7 +191,7 @@ __global__ void __launch_bounds__(MAXT) step3_fp32(Step3Args p) {
   }
   __syncthreads();
   if (!active) return;
-  float2* fb = reinterpret_cast<float2*>(region) + wave * 8 * QH;
+  float2* fb = reinterpret_cast<float2*>(region) + wave * 4 * QH;
   step3_epilogue<CTQ>(p, acc, pair, d0, fb, twl, lane);
 }
 
@@ -230,7 +230,7 @@ size_t step3_lds_bytes(int Qa, int nwaves) {
   const int QH = Qa / 2;
   const int ZS = (QH % 64 == 0) ? QH + 32 : QH;
   size_t k = sizeof(float) * 2 * 32 * ZS;
-  size_t e = sizeof(float2) * static_cast<size_t>(nwaves) * 8 * QH;
+  size_t e = sizeof(float2) * static_cast<size_t>(nwaves) * 4 * QH;
   return sizeof(float2) * Qa + (k > e ? k : e);
 }
 
