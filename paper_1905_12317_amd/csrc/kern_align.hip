@@ -7,6 +7,7 @@
 // (delta, r) reduced with wave shuffles and a 64-bit atomicMax per pair.
 #include "device_common.h"
 #include "kernels.h"
+#include "step3_epilogue.h"
 
 using namespace ftkdev;
 
@@ -22,72 +23,6 @@ __device__ __forceinline__ f32x16 zero16() {
 }
 
 // ---------------------------------------------------------------- Step 3
-
-__device__ __forceinline__ void better(float& bv, uint32_t& bi, float v, uint32_t i) {
-  if (v > bv || (v == bv && i < bi)) {
-    bv = v;
-    bi = i;
-  }
-}
-
-template <int CTQ>
-__device__ __forceinline__ void step3_epilogue(const Step3Args& p, f32x16 (&acc)[CTQ], int pair, int d0,
-                                               float2* fb, const float2* tw, int lane) {
-  constexpr int QH = 32 * CTQ;
-  const int Qa = 2 * QH;
-  const int r = lane >> 5;
-  const int c32 = lane & 31;
-  float2* fb2 = fb + 2 * QH;
-  float bv = -__builtin_inff();
-  uint32_t bi = 0xffffffffu;
-  float* Xp = p.X ? p.X + static_cast<size_t>(pair) * p.N * Qa : nullptr;
-  // 8 groups of 2 shifts (one per half-wave), two rows of QH modes each
-#pragma unroll
-  for (int gg = 0; gg < 8; ++gg) {
-    const int g = gg >> 1, d = gg & 1;
-#pragma unroll
-    for (int ct = 0; ct < CTQ; ++ct)
-      fb[r * QH + ct * 32 + c32] = make_float2(acc[ct][4 * g + 2 * d], acc[ct][4 * g + 2 * d + 1]);
-    wave_sync();
-    for (int t = lane; t < 2 * QH; t += 64) {
-      const int row = t / QH;
-      const int k = t - row * QH;
-      const float2 P = fb[t];
-      float2 Z;
-      if (k == 0) {
-        Z = make_float2(P.x + P.y, P.x - P.y);
-      } else {
-        const float2 Qc = cconj(fb[row * QH + QH - k]);
-        const float2 s = cadd(P, Qc);
-        const float2 u = cmul(csub(P, Qc), tw[k]);
-        Z = make_float2(s.x - u.y, s.y + u.x);
-      }
-      fb2[t] = Z;
-    }
-    wave_sync();
-    float2* res = ct_fft<QH, 1, 2, false, 64, 2>(fb2, fb, tw, lane, WaveSync());
-    for (int t = lane; t < 2 * QH; t += 64) {
-      const int row = t / QH;
-      const int s = t - row * QH;
-      const int delta = d0 + 4 * g + 2 * row + d;
-      if (delta < p.N) {
-        const float2 z = res[t];
-        const uint32_t idx = static_cast<uint32_t>(delta) * Qa + 2 * s;
-        better(bv, bi, z.x, idx);
-        better(bv, bi, z.y, idx + 1);
-        if (Xp) reinterpret_cast<float2*>(Xp + static_cast<size_t>(delta) * Qa)[s] = z;
-      }
-    }
-    wave_sync();
-  }
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) {
-    const float ov = __shfl_xor(bv, off);
-    const uint32_t oi = static_cast<uint32_t>(__shfl_xor(static_cast<int>(bi), off));
-    better(bv, bi, ov, oi);
-  }
-  if (lane == 0 && bi != 0xffffffffu) atomicMax(p.keys + pair, pose_key(bv, bi));
-}
 
 template <int CTQ, int MAXT>
 __global__ void __launch_bounds__(MAXT) step3_fp32(Step3Args p) {
@@ -191,8 +126,8 @@ __global__ void __launch_bounds__(MAXT) step3_fp32(Step3Args p) {
   }
   __syncthreads();
   if (!active) return;
-  float2* fb = reinterpret_cast<float2*>(region) + wave * 4 * QH;
-  step3_epilogue<CTQ>(p, acc, pair, d0, fb, twl, lane);
+  float2* T = reinterpret_cast<float2*>(region) + wave * (epilogue_lds_bytes_per_wave() / sizeof(float2));
+  step3_epilogue_reg<CTQ>(p, acc, pair, d0, T, twl, lane);
 }
 
 __global__ void keys_init_kernel(unsigned long long* keys, size_t count) {
@@ -230,7 +165,7 @@ size_t step3_lds_bytes(int Qa, int nwaves) {
   const int QH = Qa / 2;
   const int ZS = (QH % 64 == 0) ? QH + 32 : QH;
   size_t k = sizeof(float) * 2 * 32 * ZS;
-  size_t e = sizeof(float2) * static_cast<size_t>(nwaves) * 4 * QH;
+  size_t e = static_cast<size_t>(nwaves) * epilogue_lds_bytes_per_wave();
   return sizeof(float2) * Qa + (k > e ? k : e);
 }
 

@@ -1,0 +1,245 @@
+// Rotation FFT + argmax of Step 3 (Step 2 of eq. fbk3, eq. 1dfft), shared by
+// the FP32 and split-bf16 forms, working mostly in registers.
+//
+// Input: the wave's MFMA accumulators acc[ct][v] of the shift contraction:
+// lane l (h = l / 32, j = l % 32) holds column q = 32 ct + j (mode) for rows
+// 8 (v / 4) + 4 h + (v % 4); row 2 dl + c is shift d0 + dl, c = 0 real and
+// c = 1 imaginary part of Xhat(delta, q), q = 0 .. QH - 1 (QH = Qa / 2; the
+// Nyquist mode was folded into q = 0 as Xhat(0) + i Xhat(QH)).
+//
+// For each shift the Qa real outputs X(delta, r) = Re sum_q ... come from a
+// length-QH complex FFT of the packed sequence
+//     Z[k] = (P[k] + conj P[QH - k]) + i W^k (P[k] - conj P[QH - k]),
+//     Z[0] = (Re P0 + Im P0) + i (Re P0 - Im P0),  W = exp(-2 pi i / Qa),
+// with X(2s) = Re z[s], X(2s + 1) = Im z[s].  The FFT splits k = 32 ct + j and
+// s = s1 + CTQ m:
+//   (1) a CTQ-point DFT over ct in registers, then the twiddle w^{j s1}
+//       (w = exp(-2 pi i / QH));
+//   (2) per s1 a 32-point DFT over the lanes j of each half-wave: one LDS
+//       transpose gives each quad of lanes one sequence (lane a of the quad
+//       holds elements 4 b + a), an 8-point FFT runs in each lane, and a
+//       radix-4 step across the quad uses DPP lane permutes.
+// The argmax over (shift, rotation) is kept per lane and reduced with wave
+// shuffles; one 64-bit atomicMax per wave publishes it.
+#pragma once
+
+#include "device_common.h"
+#include "kernels.h"
+
+namespace ftkdev {
+
+typedef float f32x16_e __attribute__((ext_vector_type(16)));
+
+constexpr int kEpiRowStride = 36;  // float2 per transpose row (32 + 4: conflict-free)
+constexpr int kEpiRounds = 2;      // FFT rounds staged in LDS at a time
+
+// LDS bytes of the epilogue per wave: kEpiRounds x two half-waves x 8 rows
+__host__ __device__ constexpr size_t epilogue_lds_bytes_per_wave() {
+  return sizeof(float2) * kEpiRounds * 2 * 8 * kEpiRowStride;
+}
+
+__device__ __forceinline__ void ep_better(float& bv, uint32_t& bi, float v, uint32_t i) {
+  if (v > bv || (v == bv && i < bi)) {
+    bv = v;
+    bi = i;
+  }
+}
+
+// value of the lane `lane ^ x` of the same quad (x = 1 or 2)
+template <int CTRL>
+__device__ __forceinline__ float quad_swap(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), CTRL, 0xF, 0xF, false));
+}
+// exp(-i pi k / 12), k = 0 .. 23 (every CTQ in {1, 2, 3, 4, 6} divides 12)
+__device__ __forceinline__ float2 ep_unit12(int k) {
+  const float sg = k < 12 ? 1.f : -1.f;
+  k = k < 12 ? k : k - 12;
+  constexpr float cs[12] = {1.f, 0.96592582628906829f, 0.86602540378443865f, 0.70710678118654752f, 0.5f,
+                            0.25881904510252076f, 0.f, -0.25881904510252076f, -0.5f, -0.70710678118654752f,
+                            -0.86602540378443865f, -0.96592582628906829f};
+  constexpr float sn[12] = {0.f, 0.25881904510252076f, 0.5f, 0.70710678118654752f, 0.86602540378443865f,
+                            0.96592582628906829f, 1.f, 0.96592582628906829f, 0.86602540378443865f,
+                            0.70710678118654752f, 0.5f, 0.25881904510252076f};
+  return make_float2(sg * cs[k], -sg * sn[k]);
+}
+constexpr int kQuadXor1 = 0xB1;  // quad_perm [1, 0, 3, 2]
+constexpr int kQuadXor2 = 0x4E;  // quad_perm [2, 3, 0, 1]
+
+template <int CTQ, class Acc>
+__device__ __forceinline__ void step3_epilogue_reg(const Step3Args& p, Acc (&acc)[CTQ], int pair, int d0, float2* T,
+                                                   const float2* __restrict__ tw, int lane) {
+  constexpr int QH = 32 * CTQ;
+  constexpr int Qa = 2 * QH;
+  const int h = lane >> 5;
+  const int j = lane & 31;
+  const int src = (h << 5) | ((32 - j) & 31);  // lane of column QH - k for j > 0
+  // twiddles from one table read each: W^{32 ct + j} = W^j exp(-i pi ct / CTQ),
+  // w^{j s1} = (w^j)^{s1}, exp(-2 pi i a s' / 32) = (exp(-2 pi i a / 32))^{s'}
+  const float2 wj = tw[j];
+
+  // ---- (0) real-output packing, in place: acc[ct][(u)] <- Z_u[32 ct + j]
+  // u = 2 v4 + d is the shift 4 v4 + 2 h + d of this lane; its (re, im) sit
+  // in registers 4 v4 + 2 d and 4 v4 + 2 d + 1.
+#pragma unroll
+  for (int u = 0; u < 8; ++u) {
+    const int vr = 4 * (u >> 1) + 2 * (u & 1);
+    float2 P[CTQ], Pp[CTQ];
+#pragma unroll
+    for (int ct = 0; ct < CTQ; ++ct) P[ct] = make_float2(acc[ct][vr], acc[ct][vr + 1]);
+    // partner of column k = 32 ct + j: lane 32 - j at tile CTQ - 1 - ct (j > 0),
+    // this lane at tile CTQ - ct (j = 0)
+#pragma unroll
+    for (int ct = 0; ct < CTQ; ++ct) {
+      const float2 o = P[CTQ - 1 - ct];
+      Pp[ct] = make_float2(__shfl(o.x, src), __shfl(o.y, src));
+      if (j == 0) Pp[ct] = P[(CTQ - ct) % CTQ];
+    }
+#pragma unroll
+    for (int ct = 0; ct < CTQ; ++ct) {
+      float2 Z;
+      if (ct == 0 && j == 0) {
+        Z = make_float2(P[0].x + P[0].y, P[0].x - P[0].y);
+      } else {
+        const float2 Qc = cconj(Pp[ct]);
+        const float2 s = cadd(P[ct], Qc);
+        const float2 uu = cmul(csub(P[ct], Qc), ct == 0 ? wj : cmul(wj, ep_unit12(12 * ct / CTQ)));
+        Z = make_float2(s.x - uu.y, s.y + uu.x);
+      }
+      acc[ct][vr] = Z.x;
+      acc[ct][vr + 1] = Z.y;
+    }
+    // keep each shift's lane exchanges next to their use (register pressure)
+    __builtin_amdgcn_sched_barrier(0);
+  }
+
+  // ---- (1) CTQ-point DFT over ct and the twiddle w^{j s1}, in place
+#pragma unroll
+  for (int u = 0; u < 8; ++u) {
+    const int vr = 4 * (u >> 1) + 2 * (u & 1);
+    float2 v[CTQ];
+#pragma unroll
+    for (int ct = 0; ct < CTQ; ++ct) v[ct] = make_float2(acc[ct][vr], acc[ct][vr + 1]);
+    const float2 w1 = tw[(2 * j) % Qa];
+    if constexpr (CTQ == 2) {
+      dft2<false>(v);
+    } else if constexpr (CTQ == 3) {
+      dft3<false>(v);
+    } else if constexpr (CTQ == 4) {
+      dft4<false>(v);
+    } else if constexpr (CTQ > 4) {
+      float2 y[CTQ];
+#pragma unroll
+      for (int s1 = 0; s1 < CTQ; ++s1) {
+        y[s1] = v[0];
+#pragma unroll
+        for (int ct = 1; ct < CTQ; ++ct) y[s1] = cadd(y[s1], cmul(v[ct], ep_unit12(24 * ((ct * s1) % CTQ) / CTQ)));
+      }
+#pragma unroll
+      for (int s1 = 0; s1 < CTQ; ++s1) v[s1] = y[s1];
+    }
+    float2 wp = w1;
+#pragma unroll
+    for (int s1 = 0; s1 < CTQ; ++s1) {
+      float2 y = v[s1];
+      if (s1 > 0) {
+        y = cmul(y, wp);
+        wp = cmul(wp, w1);
+      }
+      acc[s1][vr] = y.x;
+      acc[s1][vr + 1] = y.y;
+    }
+  }
+
+  // ---- (2) per s1: 32-point DFT over j through an LDS transpose.  The
+  // rounds are staged kEpiRounds at a time, so that the accumulators of
+  // those rounds are dead before the FFT temporaries are needed.
+  float bv = -__builtin_inff();
+  uint32_t bi = 0xffffffffu;
+  float* Xp = p.X ? p.X + static_cast<size_t>(pair) * p.N * Qa : nullptr;
+  const int Q = j >> 2;  // the sequence (shift u = Q) this lane's quad transforms
+  const int a = j & 3;
+  const int a0 = a & 1, a1 = a >> 1;
+  const int dl = 4 * (Q >> 1) + 2 * h + (Q & 1);
+  const int delta = d0 + dl;
+  constexpr float c8 = 0.70710678118654752440f;
+  constexpr int RP = CTQ < kEpiRounds ? CTQ : kEpiRounds;
+#pragma unroll
+  for (int s0 = 0; s0 < CTQ; s0 += RP) {
+#pragma unroll
+    for (int rr = 0; rr < RP; ++rr) {
+      const int s1 = s0 + rr;
+      if (s1 >= CTQ) break;
+      float2* Th = T + (2 * rr + h) * 8 * kEpiRowStride;
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int vr = 4 * (u >> 1) + 2 * (u & 1);
+        Th[u * kEpiRowStride + j] = make_float2(acc[s1][vr], acc[s1][vr + 1]);
+      }
+    }
+    wave_sync();
+#pragma unroll
+    for (int rr = 0; rr < RP; ++rr) {
+      const int s1 = s0 + rr;
+      if (s1 >= CTQ) break;
+      const float2* Th = T + (2 * rr + h) * 8 * kEpiRowStride;
+      float2 x[8];
+#pragma unroll
+      for (int b = 0; b < 8; ++b) x[b] = Th[Q * kEpiRowStride + 4 * b + a];
+      // 8-point DFT of x[b] (elements 4 b + a of the sequence) in registers
+      float2 e[4] = {x[0], x[2], x[4], x[6]};
+      float2 o[4] = {x[1], x[3], x[5], x[7]};
+      dft4<false>(e);
+      dft4<false>(o);
+      const float2 w8[4] = {make_float2(1.f, 0.f), make_float2(c8, -c8), make_float2(0.f, -1.f),
+                            make_float2(-c8, -c8)};
+      float2 Y[8];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const float2 t = cmul(o[k], w8[k]);
+        Y[k] = cadd(e[k], t);
+        Y[k + 4] = csub(e[k], t);
+      }
+      // twiddle exp(-2 pi i a s' / 32), then the radix-4 DFT over the quad
+      {
+        const float2 wa = tw[a * (Qa / 32)];
+        float2 wq = wa;
+#pragma unroll
+        for (int sp = 1; sp < 8; ++sp) {
+          Y[sp] = cmul(Y[sp], wq);
+          wq = cmul(wq, wa);
+        }
+      }
+#pragma unroll
+      for (int sp = 0; sp < 8; ++sp) {
+        const float2 oy = make_float2(quad_swap<kQuadXor2>(Y[sp].x), quad_swap<kQuadXor2>(Y[sp].y));
+        float2 U = a1 ? csub(oy, Y[sp]) : cadd(Y[sp], oy);
+        if (a0 && a1) U = make_float2(U.y, -U.x);
+        const float2 ou = make_float2(quad_swap<kQuadXor1>(U.x), quad_swap<kQuadXor1>(U.y));
+        Y[sp] = a0 ? csub(ou, U) : cadd(U, ou);
+      }
+      // lane a holds z[s1 + CTQ (s' + 8 (a1 + 2 a0))]
+      if (delta < p.N) {
+#pragma unroll
+        for (int sp = 0; sp < 8; ++sp) {
+          const int m = sp + 8 * (a1 + 2 * a0);
+          const int s = s1 + CTQ * m;
+          const uint32_t idx = static_cast<uint32_t>(delta) * Qa + 2 * s;
+          ep_better(bv, bi, Y[sp].x, idx);
+          ep_better(bv, bi, Y[sp].y, idx + 1);
+          if (Xp) reinterpret_cast<float2*>(Xp + static_cast<size_t>(delta) * Qa)[s] = Y[sp];
+        }
+      }
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    wave_sync();
+  }
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+    const float ov = __shfl_xor(bv, off);
+    const uint32_t oi = static_cast<uint32_t>(__shfl_xor(static_cast<int>(bi), off));
+    ep_better(bv, bi, ov, oi);
+  }
+  if (lane == 0 && bi != 0xffffffffu) atomicMax(p.keys + pair, pose_key(bv, bi));
+}
+
+}  // namespace ftkdev
