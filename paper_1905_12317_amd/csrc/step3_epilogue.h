@@ -62,6 +62,10 @@ __device__ __forceinline__ float2 ep_unit12(int k) {
                             0.70710678118654752f, 0.5f, 0.25881904510252076f};
   return make_float2(sg * cs[k], -sg * sn[k]);
 }
+// value of lane addr / 4 (ds_bpermute with a precomputed byte address)
+__device__ __forceinline__ float ep_bperm(float v, int addr) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_ds_bpermute(addr, __builtin_bit_cast(int, v)));
+}
 constexpr int kQuadXor1 = 0xB1;  // quad_perm [1, 0, 3, 2]
 constexpr int kQuadXor2 = 0x4E;  // quad_perm [2, 3, 0, 1]
 
@@ -72,7 +76,7 @@ __device__ __forceinline__ void step3_epilogue_reg(const Step3Args& p, Acc (&acc
   constexpr int Qa = 2 * QH;
   const int h = lane >> 5;
   const int j = lane & 31;
-  const int src = (h << 5) | ((32 - j) & 31);  // lane of column QH - k for j > 0
+  const int src4 = ((h << 5) | ((32 - j) & 31)) << 2;  // byte address of the lane of column QH - k (j > 0)
   // twiddles from one table read each: W^{32 ct + j} = W^j exp(-i pi ct / CTQ),
   // w^{j s1} = (w^j)^{s1}, exp(-2 pi i a s' / 32) = (exp(-2 pi i a / 32))^{s'}
   const float2 wj = tw[j];
@@ -91,7 +95,7 @@ __device__ __forceinline__ void step3_epilogue_reg(const Step3Args& p, Acc (&acc
 #pragma unroll
     for (int ct = 0; ct < CTQ; ++ct) {
       const float2 o = P[CTQ - 1 - ct];
-      Pp[ct] = make_float2(__shfl(o.x, src), __shfl(o.y, src));
+      Pp[ct] = make_float2(ep_bperm(o.x, src4), ep_bperm(o.y, src4));
       if (j == 0) Pp[ct] = P[(CTQ - ct) % CTQ];
     }
 #pragma unroll
@@ -126,6 +130,23 @@ __device__ __forceinline__ void step3_epilogue_reg(const Step3Args& p, Acc (&acc
       dft3<false>(v);
     } else if constexpr (CTQ == 4) {
       dft4<false>(v);
+    } else if constexpr (CTQ == 6) {
+      // 6 = 3 x 2: n = 3 n1 + n2, k = k1 + 2 k2
+      float2 A0[2] = {v[0], v[3]}, A1[2] = {v[1], v[4]}, A2[2] = {v[2], v[5]};
+      dft2<false>(A0);
+      dft2<false>(A1);
+      dft2<false>(A2);
+      A1[1] = cmul(A1[1], ep_unit12(4));  // W6^1
+      A2[1] = cmul(A2[1], ep_unit12(8));  // W6^2
+      float2 B0[3] = {A0[0], A1[0], A2[0]}, B1[3] = {A0[1], A1[1], A2[1]};
+      dft3<false>(B0);
+      dft3<false>(B1);
+      v[0] = B0[0];
+      v[2] = B0[1];
+      v[4] = B0[2];
+      v[1] = B1[0];
+      v[3] = B1[1];
+      v[5] = B1[2];
     } else if constexpr (CTQ > 4) {
       float2 y[CTQ];
 #pragma unroll
