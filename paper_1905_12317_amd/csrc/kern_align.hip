@@ -24,7 +24,10 @@ __device__ __forceinline__ f32x16 zero16() {
 
 // ---------------------------------------------------------------- Step 3
 
-template <int CTQ, int MAXT>
+// PREF: enough threads to prefetch a whole chunk in MAXF4 float4 per thread
+// (double buffering through registers); otherwise each chunk is fetched after
+// the MFMAs of the previous one.
+template <int CTQ, int MAXT, bool PREF>
 __global__ void __launch_bounds__(MAXT) step3_fp32(Step3Args p) {
   extern __shared__ float smem[];
   constexpr int QH = 32 * CTQ;
@@ -48,77 +51,77 @@ __global__ void __launch_bounds__(MAXT) step3_fp32(Step3Args p) {
   for (int i = tid; i < 2 * QH; i += nthr) twl[i] = p.tw_qa[i];
   constexpr int MAXF4 = 2;
   const int nf4 = QH * 8;  // float4 per K-chunk
-  const int per = (nf4 + nthr - 1) / nthr;
-  const bool pref = per <= MAXF4;
   // Zhat rows are [q][c][zeta] (K index k' = c H_pad + zeta); row Qa/2 (the
-  // Nyquist mode) is folded into row 0 as Zhat(0) + i Zhat(Qa/2)
-  auto fetch = [&](int kc, int t) {
-    const int qq = t >> 3;
-    const int k = kc + (t & 7) * 4;
-    float4 v = *reinterpret_cast<const float4*>(zsp + static_cast<size_t>(qq) * nk + k);
-    if (qq == 0) {
-      const float* ny = zsp + static_cast<size_t>(QH) * nk;
-      if (k < p.H_pad) {
-        const float4 w = *reinterpret_cast<const float4*>(ny + k + p.H_pad);
-        v.x -= w.x; v.y -= w.y; v.z -= w.z; v.w -= w.w;
-      } else {
-        const float4 w = *reinterpret_cast<const float4*>(ny + k - p.H_pad);
-        v.x += w.x; v.y += w.y; v.z += w.z; v.w += w.w;
-      }
-    }
-    return v;
+  // Nyquist mode) is folded into row 0 as Zhat(0) + i Zhat(Qa/2).  The loads
+  // (with the Nyquist partner w) are issued unconditionally, the fold is
+  // applied when the chunk is stored, after the MFMAs of the current chunk.
+  auto load_v = [&](int kc, int t) {
+    return *reinterpret_cast<const float4*>(zsp + static_cast<size_t>(t >> 3) * nk + kc + (t & 7) * 4);
   };
-  auto put = [&](float* dst, int t, float4 v) {
+  auto load_w = [&](int kc, int t) {
+    const int k = kc + (t & 7) * 4;
+    return *reinterpret_cast<const float4*>(zsp + static_cast<size_t>(QH) * nk + (k < p.H_pad ? k + p.H_pad : k - p.H_pad));
+  };
+  auto put = [&](float* dst, int t, float4 v, int kc, float4 w) {
     const int qq = t >> 3;
     const int k4 = (t & 7) * 4;
+    if (qq == 0) {
+      const float sg = (kc + k4 < p.H_pad) ? -1.f : 1.f;
+      v.x += sg * w.x; v.y += sg * w.y; v.z += sg * w.z; v.w += sg * w.w;
+    }
     dst[(k4 + 0) * ZS + qq] = v.x;
     dst[(k4 + 1) * ZS + qq] = v.y;
     dst[(k4 + 2) * ZS + qq] = v.z;
     dst[(k4 + 3) * ZS + qq] = v.w;
   };
-  for (int t = tid; t < nf4; t += nthr) put(region, t, fetch(0, t));
+  for (int t = tid; t < nf4; t += nthr) put(region, t, load_v(0, t), 0, load_w(0, t));
   __syncthreads();
   f32x16 acc[CTQ];
 #pragma unroll
   for (int ct = 0; ct < CTQ; ++ct) acc[ct] = zero16();
   const bool active = d0 < p.N;
+  // waves past the last shift tile load a valid column and never use it
+  const int dcol = 2 * min(d0, p.N_pad - 16) + c32;
   int cur = 0;
   for (int kc = 0; kc < nk; kc += 32) {
     const bool more = kc + 32 < nk;
-    float4 nreg[MAXF4];
-    if (more && pref) {
+    // this chunk's shift-panel operands first: loads retire in order, so
+    // waiting for them does not wait for the prefetch issued after them
+    float av[16];
+#pragma unroll
+    for (int z = 0; z < 16; ++z) av[z] = p.yt[static_cast<size_t>(kc + 2 * z + r) * ystride + dcol];
+    __builtin_amdgcn_sched_barrier(0);
+    float4 nreg[MAXF4], nny[MAXF4];
+    if (PREF) {
+      const int kn = more ? kc + 32 : kc;  // the last chunk re-reads itself
 #pragma unroll
       for (int k = 0; k < MAXF4; ++k) {
-        const int t = tid + k * nthr;
-        if (k < per && t < nf4) nreg[k] = fetch(kc + 32, t);
+        const int t = min(tid + k * nthr, nf4 - 1);
+        nreg[k] = load_v(kn, t);
+        nny[k] = load_w(kn, t);
       }
     }
+    __builtin_amdgcn_sched_barrier(0);
     if (active) {
       const float* Z = region + cur * (32 * ZS) + r * ZS + c32;
 #pragma unroll
-      for (int half = 0; half < 2; ++half) {
-        float av[8];
+      for (int z = 0; z < 16; ++z)
 #pragma unroll
-        for (int z = 0; z < 8; ++z)
-          av[z] = p.yt[static_cast<size_t>(kc + 16 * half + 2 * z + r) * ystride + 2 * d0 + c32];
-#pragma unroll
-        for (int z = 0; z < 8; ++z)
-#pragma unroll
-          for (int ct = 0; ct < CTQ; ++ct) {
-            const float b = Z[(16 * half + 2 * z) * ZS + ct * 32];
-            acc[ct] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[z], b, acc[ct], 0, 0, 0);
-          }
-      }
+        for (int ct = 0; ct < CTQ; ++ct) {
+          const float b = Z[(2 * z) * ZS + ct * 32];
+          acc[ct] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[z], b, acc[ct], 0, 0, 0);
+        }
     }
     if (more) {
-      if (pref) {
+      if (PREF) {
 #pragma unroll
         for (int k = 0; k < MAXF4; ++k) {
           const int t = tid + k * nthr;
-          if (k < per && t < nf4) put(region + (cur ^ 1) * (32 * ZS), t, nreg[k]);
+          if (t < nf4) put(region + (cur ^ 1) * (32 * ZS), t, nreg[k], kc + 32, nny[k]);
         }
       } else {
-        for (int t = tid; t < nf4; t += nthr) put(region + (cur ^ 1) * (32 * ZS), t, fetch(kc + 32, t));
+        for (int t = tid; t < nf4; t += nthr)
+          put(region + (cur ^ 1) * (32 * ZS), t, load_v(kc + 32, t), kc + 32, load_w(kc + 32, t));
       }
       __syncthreads();
       cur ^= 1;
@@ -174,7 +177,8 @@ static hipError_t launch_step3_t(const Step3Args& a, hipStream_t s) {
   const int per_blk = 16 * a.nwaves;
   dim3 grid(a.pairs, (a.N + per_blk - 1) / per_blk, 1);
   size_t lds = step3_lds_bytes(a.Qa, a.nwaves);
-  auto kern = step3_fp32<CTQ, MAXT>;
+  const int nf4 = 32 * CTQ * 8, nthr = 64 * a.nwaves;
+  auto kern = (nf4 + nthr - 1) / nthr <= 2 ? step3_fp32<CTQ, MAXT, true> : step3_fp32<CTQ, MAXT, false>;
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
   if (e != hipSuccess) return e;

@@ -61,7 +61,10 @@ __device__ __forceinline__ f32x16 mfma3(bf16x8 ahi, bf16x8 alo, bf16x8 bhi, bf16
 
 // ---------------------------------------------------------------- Step 3
 
-template <int CTQ, int MAXT>
+// PREF: the block has enough threads to prefetch a whole chunk in MAXF4
+// float4 per thread (double buffering through registers); otherwise each
+// chunk is fetched after the MFMAs of the previous one.
+template <int CTQ, int MAXT, bool PREF>
 __global__ void __launch_bounds__(MAXT) step3_bf16x3(Step3Args p) {
   extern __shared__ float smem[];
   constexpr int QH = 32 * CTQ;
@@ -84,80 +87,102 @@ __global__ void __launch_bounds__(MAXT) step3_bf16x3(Step3Args p) {
   for (int i = tid; i < 2 * QH; i += nthr) twl[i] = p.tw_qa[i];
   constexpr int MAXF4 = 2;
   const int nf4 = QH * (KC / 4);
-  const int per = (nf4 + nthr - 1) / nthr;
-  const bool pref = per <= MAXF4;
-  // Zhat rows are [q][c][zeta]; row Qa/2 is folded into row 0 (see the FP32 form)
-  auto fetch = [&](int kc, int t) {
+  // Zhat rows are [q][c][zeta]; row Qa/2 is folded into row 0 (see the FP32
+  // form).  fetch only issues the loads (the Nyquist partner w for row 0);
+  // the fold is applied in put, after the loads had a whole chunk of MFMA
+  // work to arrive, so no wave waits on its prefetch.
+  auto fetch = [&](int kc, int t, float4& w) {
     const int qq = t >> 3;
     const int k = kc + (t & 7) * 4;
-    float4 v = *reinterpret_cast<const float4*>(zsp + static_cast<size_t>(qq) * nk + k);
+    const float4 v = *reinterpret_cast<const float4*>(zsp + static_cast<size_t>(qq) * nk + k);
     if (qq == 0) {
       const float* ny = zsp + static_cast<size_t>(QH) * nk;
-      if (k < p.H_pad) {
-        const float4 w = *reinterpret_cast<const float4*>(ny + k + p.H_pad);
-        v.x -= w.x; v.y -= w.y; v.z -= w.z; v.w -= w.w;
-      } else {
-        const float4 w = *reinterpret_cast<const float4*>(ny + k - p.H_pad);
-        v.x += w.x; v.y += w.y; v.z += w.z; v.w += w.w;
-      }
+      w = *reinterpret_cast<const float4*>(ny + (k < p.H_pad ? k + p.H_pad : k - p.H_pad));
     }
     return v;
   };
-  auto put = [&](int buf, int t, float4 v) {
+  auto put = [&](int buf, int t, float4 v, int kc, float4 w) {
     const int qq = t >> 3;
     const int k4 = (t & 7) * 4;
+    if (qq == 0) {
+      const float sg = (kc + k4 < p.H_pad) ? -1.f : 1.f;
+      v.x += sg * w.x; v.y += sg * w.y; v.z += sg * w.z; v.w += sg * w.w;
+    }
     bf16x4 hi, lo;
     split4(v, hi, lo);
     float* row = region + buf * buf_words + qq * ROWW;
     *reinterpret_cast<bf16x4*>(row + k4 / 2) = hi;
     *reinterpret_cast<bf16x4*>(row + 16 + k4 / 2) = lo;
   };
-  for (int t = tid; t < nf4; t += nthr) put(0, t, fetch(0, t));
+  for (int t = tid; t < nf4; t += nthr) {
+    float4 w = make_float4(0.f, 0.f, 0.f, 0.f);
+    const float4 v = fetch(0, t, w);
+    put(0, t, v, 0, w);
+  }
   __syncthreads();
   f32x16 acc[CTQ];
 #pragma unroll
   for (int ct = 0; ct < CTQ; ++ct) acc[ct] = zero16();
   const bool active = d0 < p.N;
   // shift panel in MFMA lane order: [row tile][K step][lane][8] for hi and lo
-  const size_t tile = static_cast<size_t>(d0 / 16) * nks;
+  const size_t tile = static_cast<size_t>(min(d0, p.N_pad - 16) / 16) * nks;
   const bf16x8* yhi = reinterpret_cast<const bf16x8*>(p.yt_hi) + tile * 64 + lane;
   const bf16x8* ylo = reinterpret_cast<const bf16x8*>(p.yt_lo) + tile * 64 + lane;
   int cur = 0;
   for (int kc = 0; kc < nk; kc += KC) {
     const bool more = kc + KC < nk;
-    float4 nreg[MAXF4];
-    if (more && pref) {
+    // this chunk's shift-panel operands are loaded before the next chunk's
+    // prefetch: loads retire in order, so waiting for them does not wait
+    // for the prefetch
+    // Every wave issues the same unconditional loads (clamped to valid
+    // addresses), so the waits before the MFMAs cover exactly the operands.
+    bf16x8 ahi[KC / 16], alo[KC / 16];
+#pragma unroll
+    for (int s = 0; s < KC / 16; ++s) {
+      ahi[s] = yhi[(kc / 16 + s) * 64];
+      alo[s] = ylo[(kc / 16 + s) * 64];
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    float4 nreg[MAXF4], nny[MAXF4];
+    if (PREF) {
+      // the last chunk re-reads itself, so the loads need no condition
+      const int kn = more ? kc + KC : kc;
 #pragma unroll
       for (int k = 0; k < MAXF4; ++k) {
-        const int t = tid + k * nthr;
-        if (k < per && t < nf4) nreg[k] = fetch(kc + KC, t);
+        const int t = min(tid + k * nthr, nf4 - 1);
+        const int kk = kn + (t & 7) * 4;
+        nreg[k] = *reinterpret_cast<const float4*>(zsp + static_cast<size_t>(t >> 3) * nk + kk);
+        nny[k] = *reinterpret_cast<const float4*>(zsp + static_cast<size_t>(QH) * nk +
+                                                  (kk < p.H_pad ? kk + p.H_pad : kk - p.H_pad));
       }
     }
+    __builtin_amdgcn_sched_barrier(0);
     if (active) {
       const float* Zb = region + cur * buf_words + c32 * ROWW + 4 * r;
 #pragma unroll
       for (int s = 0; s < KC / 16; ++s) {
-        const int ks = kc / 16 + s;
-        const bf16x8 ahi = yhi[ks * 64];
-        const bf16x8 alo = ylo[ks * 64];
 #pragma unroll
         for (int ct = 0; ct < CTQ; ++ct) {
           const float* row = Zb + ct * 32 * ROWW + 8 * s;
           const bf16x8 bhi = *reinterpret_cast<const bf16x8*>(row);
           const bf16x8 blo = *reinterpret_cast<const bf16x8*>(row + 16);
-          acc[ct] = mfma3(ahi, alo, bhi, blo, acc[ct]);
+          acc[ct] = mfma3(ahi[s], alo[s], bhi, blo, acc[ct]);
         }
       }
     }
     if (more) {
-      if (pref) {
+      if (PREF) {
 #pragma unroll
         for (int k = 0; k < MAXF4; ++k) {
           const int t = tid + k * nthr;
-          if (k < per && t < nf4) put(cur ^ 1, t, nreg[k]);
+          if (t < nf4) put(cur ^ 1, t, nreg[k], kc + KC, nny[k]);
         }
       } else {
-        for (int t = tid; t < nf4; t += nthr) put(cur ^ 1, t, fetch(kc + KC, t));
+        for (int t = tid; t < nf4; t += nthr) {
+          float4 w = make_float4(0.f, 0.f, 0.f, 0.f);
+          const float4 v = fetch(kc + KC, t, w);
+          put(cur ^ 1, t, v, kc + KC, w);
+        }
       }
       __syncthreads();
       cur ^= 1;
@@ -183,7 +208,8 @@ static hipError_t launch_step3_bf16_t(const Step3Args& a, hipStream_t s) {
   const int per_blk = 16 * a.nwaves;
   dim3 grid(a.pairs, (a.N + per_blk - 1) / per_blk, 1);
   size_t lds = step3_bf16_lds_bytes(a.Qa, a.nwaves);
-  auto kern = step3_bf16x3<CTQ, MAXT>;
+  const int nf4 = 32 * CTQ * 8, nthr = 64 * a.nwaves;
+  auto kern = (nf4 + nthr - 1) / nthr <= 2 ? step3_bf16x3<CTQ, MAXT, true> : step3_bf16x3<CTQ, MAXT, false>;
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
   if (e != hipSuccess) return e;
