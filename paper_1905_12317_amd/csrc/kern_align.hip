@@ -35,8 +35,9 @@ __global__ void __launch_bounds__(MAXT) step3_fp32(Step3Args p) {
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
-  const int pair = blockIdx.x;
-  const int d0 = (blockIdx.y * p.nwaves + wave) * 16;
+  int pair, yb;
+  step3_block(blockIdx.x, p.nblk, p.pairs, pair, yb);
+  const int d0 = (yb * p.nwaves + wave) * 16;
   const int r = lane >> 5;
   const int c32 = lane & 31;
   const int nk = 2 * p.H_pad;
@@ -173,9 +174,13 @@ size_t step3_lds_bytes(int Qa, int nwaves) {
 }
 
 template <int CTQ, int MAXT>
-static hipError_t launch_step3_t(const Step3Args& a, hipStream_t s) {
+static hipError_t launch_step3_t(const Step3Args& a0, hipStream_t s) {
+  Step3Args a = a0;
   const int per_blk = 16 * a.nwaves;
-  dim3 grid(a.pairs, (a.N + per_blk - 1) / per_blk, 1);
+  a.nblk = (a.N + per_blk - 1) / per_blk;
+  const size_t nwg = static_cast<size_t>(a.pairs) * a.nblk;
+  if (nwg * 64 * a.nwaves > 0xffffffffull) return hipErrorInvalidConfiguration;
+  const dim3 grid(static_cast<unsigned>(nwg));
   size_t lds = step3_lds_bytes(a.Qa, a.nwaves);
   const int nf4 = 32 * CTQ * 8, nthr = 64 * a.nwaves;
   auto kern = (nf4 + nthr - 1) / nthr <= 2 ? step3_fp32<CTQ, MAXT, true> : step3_fp32<CTQ, MAXT, false>;

@@ -53,6 +53,7 @@ struct Step3Args {
   const float2* tw_qa;   // [Qa]
   int pairs, Qa, H_pad, N, N_pad;
   int nwaves;            // waves per workgroup; each wave owns 16 shifts
+  int nblk;              // workgroups per pair (shift blocks); 1-D grid of pairs * nblk
 };
 
 size_t step3_lds_bytes(int Qa, int nwaves);

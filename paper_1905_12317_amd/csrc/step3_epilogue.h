@@ -39,10 +39,9 @@ __host__ __device__ constexpr size_t epilogue_lds_bytes_per_wave() {
 }
 
 __device__ __forceinline__ void ep_better(float& bv, uint32_t& bi, float v, uint32_t i) {
-  if (v > bv || (v == bv && i < bi)) {
-    bv = v;
-    bi = i;
-  }
+  const bool g = v > bv || (v == bv && i < bi);
+  bv = g ? v : bv;
+  bi = g ? i : bi;
 }
 
 // value of the lane `lane ^ x` of the same quad (x = 1 or 2)
@@ -62,6 +61,24 @@ __device__ __forceinline__ float2 ep_unit12(int k) {
                             0.70710678118654752f, 0.5f, 0.25881904510252076f};
   return make_float2(sg * cs[k], -sg * sn[k]);
 }
+// Pair and shift block of workgroup b in the 1-D grid of pairs * nblk.
+// Workgroups are dealt to the 8 XCDs round-robin, so blocks b and b + 8 share
+// an XCD: in each full group of 8 nblk workgroups, the nblk shift blocks of a
+// pair sit 8 apart and the later ones find the pair's Zhat in that XCD's L2.
+// A last, partial group takes its pairs' blocks consecutively.
+__device__ __forceinline__ void step3_block(int b, int nblk, int pairs, int& pair, int& yb) {
+  const int gs = 8 * nblk;
+  const int g = b / gs;
+  const int i = b - g * gs;
+  if (8 * (g + 1) <= pairs) {
+    pair = 8 * g + (i & 7);
+    yb = i >> 3;
+  } else {
+    pair = 8 * g + i / nblk;
+    yb = i - (i / nblk) * nblk;
+  }
+}
+
 // value of lane addr / 4 (ds_bpermute with a precomputed byte address)
 __device__ __forceinline__ float ep_bperm(float v, int addr) {
   return __builtin_bit_cast(float, __builtin_amdgcn_ds_bpermute(addr, __builtin_bit_cast(int, v)));
@@ -182,6 +199,10 @@ __device__ __forceinline__ void step3_epilogue_reg(const Step3Args& p, Acc (&acc
   const int a0 = a & 1, a1 = a >> 1;
   const int dl = 4 * (Q >> 1) + 2 * h + (Q & 1);
   const int delta = d0 + dl;
+  const bool valid = delta < p.N;
+  const float sg1 = a1 ? -1.f : 1.f;  // first radix-2 stage: y + x or x' - x
+  const float sg0 = a0 ? -1.f : 1.f;  // second stage
+  const bool rot = a0 && a1;
   constexpr float c8 = 0.70710678118654752440f;
   constexpr int RP = CTQ < kEpiRounds ? CTQ : kEpiRounds;
 #pragma unroll
@@ -230,25 +251,33 @@ __device__ __forceinline__ void step3_epilogue_reg(const Step3Args& p, Acc (&acc
           wq = cmul(wq, wa);
         }
       }
+      // butterflies as sign FMAs (x * (+-1) + y is exact: same values as
+      // y +- x); lane 3 of the quad also rotates its difference by -i
 #pragma unroll
       for (int sp = 0; sp < 8; ++sp) {
         const float2 oy = make_float2(quad_swap<kQuadXor2>(Y[sp].x), quad_swap<kQuadXor2>(Y[sp].y));
-        float2 U = a1 ? csub(oy, Y[sp]) : cadd(Y[sp], oy);
-        if (a0 && a1) U = make_float2(U.y, -U.x);
+        float2 U = make_float2(__builtin_fmaf(sg1, Y[sp].x, oy.x), __builtin_fmaf(sg1, Y[sp].y, oy.y));
+        if (rot) U = make_float2(U.y, -U.x);
         const float2 ou = make_float2(quad_swap<kQuadXor1>(U.x), quad_swap<kQuadXor1>(U.y));
-        Y[sp] = a0 ? csub(ou, U) : cadd(U, ou);
+        Y[sp] = make_float2(__builtin_fmaf(sg0, U.x, ou.x), __builtin_fmaf(sg0, U.y, ou.y));
       }
-      // lane a holds z[s1 + CTQ (s' + 8 (a1 + 2 a0))]
-      if (delta < p.N) {
+      // lane a holds z[s1 + CTQ (s' + 8 (a1 + 2 a0))]: its 16 outputs have
+      // flat indices delta Qa + 2 s (+1) that grow with s'.  Their maximum
+      // (fmaxf skips NaN, as ep_better does), then the lowest output equal
+      // to it; the compares are independent, so no select waits on another.
+      float rv = Y[0].x;
 #pragma unroll
-        for (int sp = 0; sp < 8; ++sp) {
-          const int m = sp + 8 * (a1 + 2 * a0);
-          const int s = s1 + CTQ * m;
-          const uint32_t idx = static_cast<uint32_t>(delta) * Qa + 2 * s;
-          ep_better(bv, bi, Y[sp].x, idx);
-          ep_better(bv, bi, Y[sp].y, idx + 1);
-          if (Xp) reinterpret_cast<float2*>(Xp + static_cast<size_t>(delta) * Qa)[s] = Y[sp];
-        }
+      for (int k = 1; k < 16; ++k) rv = fmaxf(rv, (k & 1) ? Y[k >> 1].y : Y[k >> 1].x);
+      int rk = -1;
+#pragma unroll
+      for (int k = 15; k >= 0; --k) rk = (((k & 1) ? Y[k >> 1].y : Y[k >> 1].x) == rv) ? k : rk;
+      const bool ok = valid && rk >= 0;
+      const uint32_t ridx = static_cast<uint32_t>(delta) * Qa + 2 * (s1 + CTQ * (8 * (a1 + 2 * a0) + (rk >> 1))) + (rk & 1);
+      ep_better(bv, bi, ok ? rv : -__builtin_inff(), ok ? ridx : 0xffffffffu);
+      if (Xp && valid) {
+        float2* xr = reinterpret_cast<float2*>(Xp + static_cast<size_t>(delta) * Qa);
+#pragma unroll
+        for (int sp = 0; sp < 8; ++sp) xr[s1 + CTQ * (sp + 8 * (a1 + 2 * a0))] = Y[sp];
       }
       __builtin_amdgcn_sched_barrier(0);
     }
