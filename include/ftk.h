@@ -198,7 +198,7 @@ int ftk_plan_stage_times(ftk_plan* plan, double* ms, int64_t* launches, int nsta
  *                 when H (padded to 64) is not a multiple of 128 or the
  *                 tile does not fit LDS (default 128)
  *   step1_wgs   : Step 1 splits its template sweep until the grid holds
- *                 about this many workgroups; 64..65536 (default 1024)
+ *                 about this many workgroups; 64..65536 (default 4096)
  *   stage_mib   : the Step 1 -> Step 3 staging buffer, MiB; images are
  *                 processed in chunks that fit; 16..65536 (default 2048) */
 typedef struct ftk_tuning_t {

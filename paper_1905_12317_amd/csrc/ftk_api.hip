@@ -269,7 +269,7 @@ ftk_tuning_t default_tuning() {
   ftk_tuning_t t;
   t.step3_waves = static_cast<int>(std::min<size_t>(16, env_mib("FTK_STEP3_WAVES", 16)));
   t.step1_zblk = env_mib("FTK_STEP1_ZBLK", 128) == 64 ? 64 : 128;
-  t.step1_wgs = static_cast<int>(std::min<size_t>(65536, std::max<size_t>(64, env_mib("FTK_STEP1_WGS", 1024))));
+  t.step1_wgs = static_cast<int>(std::min<size_t>(65536, std::max<size_t>(64, env_mib("FTK_STEP1_WGS", 4096))));
   t.stage_mib = static_cast<int>(std::min<size_t>(65536, std::max<size_t>(16, env_mib("FTK_STAGE_MB", 2048))));
   return t;
 }
@@ -308,7 +308,7 @@ Needs plan_needs(const ftk_plan* p, int nA, int nB, bool from_pixels) {
     d.coef_b = cb * nB;
   }
   if (nA > 0 && nB > 0) {
-    const size_t per_pair = static_cast<size_t>(p->Qa / 2 + 1) * 2 * p->H_pad * sizeof(float);
+    const size_t per_pair = static_cast<size_t>(p->Qa / 2) * 2 * p->H_pad * sizeof(float);
     const size_t budget = static_cast<size_t>(p->tune.stage_mib) << 20;
     d.chunk_images = static_cast<int>(std::min<size_t>(nA, std::max<size_t>(1, budget / (per_pair * nB))));
     d.stage = static_cast<size_t>(d.chunk_images) * nB * per_pair;
@@ -321,7 +321,7 @@ Needs plan_needs(const ftk_plan* p, int nA, int nB, bool from_pixels) {
 Needs plan_needs_lists(const ftk_plan* p, int nA, int K) {
   Needs d;
   if (nA <= 0 || K <= 0) return d;
-  const size_t per_pair = static_cast<size_t>(p->Qa / 2 + 1) * 2 * p->H_pad * sizeof(float);
+  const size_t per_pair = static_cast<size_t>(p->Qa / 2) * 2 * p->H_pad * sizeof(float);
   const size_t budget = static_cast<size_t>(p->tune.stage_mib) << 20;
   d.chunk_images = static_cast<int>(std::min<size_t>(nA, std::max<size_t>(1, budget / (per_pair * K))));
   d.stage = static_cast<size_t>(d.chunk_images) * K * per_pair;
@@ -580,7 +580,7 @@ int align_impl(ftk_plan* p, const void* img_coeffs, int nA, const void* tmpl_coe
   Step1Args a1{};
   a1.cz = p->cz.as<float>();
   a1.ell = p->ell.as<int>();
-  a1.zs = ws.stage.as<float>();
+  a1.zs = ws.stage.ptr;
   a1.b = bco;
   a1.r32 = ws.tmpl.as<float>();
   a1.r16 = ws.tmpl.ptr;
@@ -616,7 +616,7 @@ int align_impl(ftk_plan* p, const void* img_coeffs, int nA, const void* tmpl_coe
     }
     {
       // split the template sweep until the grid holds about step1_wgs workgroups
-      const int base = na * (QH + 1) * (p->H_pad / a1.zblk);
+      const int base = na * (QH - 1 + a1.zblk / 32) * (p->H_pad / a1.zblk);
       const int max_parts = std::max(1, ((nBe + 15) / 16 + 7) / 8);
       a1.tparts = std::min(max_parts, std::max(1, (p->tune.step1_wgs + base - 1) / base));
     }
@@ -624,7 +624,7 @@ int align_impl(ftk_plan* p, const void* img_coeffs, int nA, const void* tmpl_coe
     e = launch_step1_v2(a1, prec, s);
     if (e != hipSuccess) return hip_fail(e, "ftk_align: step 1");
     p->timer.end(ev, s, 1);
-    a3.zs = ws.stage.as<float>();
+    a3.zs = ws.stage.ptr;
     a3.pairs = na * nBe;
     a3.keys = keys + static_cast<size_t>(A0) * nBe;
     a3.X = X ? X + static_cast<size_t>(A0) * nBe * p->N * p->Qa : nullptr;

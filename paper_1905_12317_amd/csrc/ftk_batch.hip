@@ -247,7 +247,7 @@ int autotune_stack(ftk_batch* b, size_t i, hipStream_t s) {
   if (rc == FTK_OK) {
     const int waves[] = {4, 8, 16};
     const int zblks[] = {64, 128};
-    const int wgs[] = {512, 2048};
+    const int wgs[] = {1024, 16384};
     for (int pass = 0; pass < 3 && rc == FTK_OK; ++pass) {
       std::vector<ftk_tuning_t> cands;
       if (pass == 0)

@@ -42,7 +42,7 @@ __global__ void __launch_bounds__(MAXT) step3_fp32(Step3Args p) {
   const int c32 = lane & 31;
   const int nk = 2 * p.H_pad;
   const int ystride = 2 * p.N_pad;
-  const float* zsp = p.zs + static_cast<size_t>(pair) * (QH + 1) * nk;
+  const float* zsp = static_cast<const float*>(p.zs) + static_cast<size_t>(pair) * QH * nk;
   // LDS: twiddles [Qa] (complex), then two staging buffers [32][ZS] for the
   // K-chunks of Zhat, reused by the FFT epilogue once the K loop is done
   float2* twl = reinterpret_cast<float2*>(smem);
@@ -52,30 +52,20 @@ __global__ void __launch_bounds__(MAXT) step3_fp32(Step3Args p) {
   for (int i = tid; i < 2 * QH; i += nthr) twl[i] = p.tw_qa[i];
   constexpr int MAXF4 = 2;
   const int nf4 = QH * 8;  // float4 per K-chunk
-  // Zhat rows are [q][c][zeta] (K index k' = c H_pad + zeta); row Qa/2 (the
-  // Nyquist mode) is folded into row 0 as Zhat(0) + i Zhat(Qa/2).  The loads
-  // (with the Nyquist partner w) are issued unconditionally, the fold is
-  // applied when the chunk is stored, after the MFMAs of the current chunk.
+  // Zhat rows are [q][k'] (k' = c H_pad + zeta), row 0 already holding the
+  // Nyquist fold; a chunk of 32 k' is stored transposed, [k'][q]
   auto load_v = [&](int kc, int t) {
     return *reinterpret_cast<const float4*>(zsp + static_cast<size_t>(t >> 3) * nk + kc + (t & 7) * 4);
   };
-  auto load_w = [&](int kc, int t) {
-    const int k = kc + (t & 7) * 4;
-    return *reinterpret_cast<const float4*>(zsp + static_cast<size_t>(QH) * nk + (k < p.H_pad ? k + p.H_pad : k - p.H_pad));
-  };
-  auto put = [&](float* dst, int t, float4 v, int kc, float4 w) {
+  auto put = [&](float* dst, int t, float4 v) {
     const int qq = t >> 3;
     const int k4 = (t & 7) * 4;
-    if (qq == 0) {
-      const float sg = (kc + k4 < p.H_pad) ? -1.f : 1.f;
-      v.x += sg * w.x; v.y += sg * w.y; v.z += sg * w.z; v.w += sg * w.w;
-    }
     dst[(k4 + 0) * ZS + qq] = v.x;
     dst[(k4 + 1) * ZS + qq] = v.y;
     dst[(k4 + 2) * ZS + qq] = v.z;
     dst[(k4 + 3) * ZS + qq] = v.w;
   };
-  for (int t = tid; t < nf4; t += nthr) put(region, t, load_v(0, t), 0, load_w(0, t));
+  for (int t = tid; t < nf4; t += nthr) put(region, t, load_v(0, t));
   __syncthreads();
   f32x16 acc[CTQ];
 #pragma unroll
@@ -92,15 +82,11 @@ __global__ void __launch_bounds__(MAXT) step3_fp32(Step3Args p) {
 #pragma unroll
     for (int z = 0; z < 16; ++z) av[z] = p.yt[static_cast<size_t>(kc + 2 * z + r) * ystride + dcol];
     __builtin_amdgcn_sched_barrier(0);
-    float4 nreg[MAXF4], nny[MAXF4];
+    float4 nreg[MAXF4];
     if (PREF) {
       const int kn = more ? kc + 32 : kc;  // the last chunk re-reads itself
 #pragma unroll
-      for (int k = 0; k < MAXF4; ++k) {
-        const int t = min(tid + k * nthr, nf4 - 1);
-        nreg[k] = load_v(kn, t);
-        nny[k] = load_w(kn, t);
-      }
+      for (int k = 0; k < MAXF4; ++k) nreg[k] = load_v(kn, min(tid + k * nthr, nf4 - 1));
     }
     __builtin_amdgcn_sched_barrier(0);
     if (active) {
@@ -118,11 +104,10 @@ __global__ void __launch_bounds__(MAXT) step3_fp32(Step3Args p) {
 #pragma unroll
         for (int k = 0; k < MAXF4; ++k) {
           const int t = tid + k * nthr;
-          if (t < nf4) put(region + (cur ^ 1) * (32 * ZS), t, nreg[k], kc + 32, nny[k]);
+          if (t < nf4) put(region + (cur ^ 1) * (32 * ZS), t, nreg[k]);
         }
       } else {
-        for (int t = tid; t < nf4; t += nthr)
-          put(region + (cur ^ 1) * (32 * ZS), t, load_v(kc + 32, t), kc + 32, load_w(kc + 32, t));
+        for (int t = tid; t < nf4; t += nthr) put(region + (cur ^ 1) * (32 * ZS), t, load_v(kc + 32, t));
       }
       __syncthreads();
       cur ^= 1;

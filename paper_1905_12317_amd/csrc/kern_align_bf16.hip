@@ -8,10 +8,10 @@
 // and the rounding of lo are O(2^-16) relative).  The quadrature weights and
 // the operator SVD stay FP64 on the host; only their FP32 products enter.
 //
-// Data flow and layouts are those of the FP32 form (kern_align.hip):
-// Step 1 (kern_step1.hip) writes Zhat[pair][q][c][zeta] in FP32, Step 3
-// reads it, splits it while staging it in LDS, and ends with the same
-// rotation FFT and argmax.
+// Data flow is that of the FP32 form (kern_align.hip): Step 1
+// (kern_step1.hip) writes Zhat, already split into hi + lo and in chunks of
+// 32 k' laid out as Step 3 stages them, Step 3 copies the chunks into LDS
+// and ends with the same rotation FFT and argmax.
 // MFMA: v_mfma_f32_32x32x16_bf16; lane l holds rows/cols l % 32 and the
 // 8 consecutive k = 8 (l / 32) .. +7 of each 16-wide K step.
 #include "device_common.h"
@@ -22,7 +22,6 @@ using namespace ftkdev;
 
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 
 namespace {
 
@@ -31,25 +30,6 @@ __device__ __forceinline__ f32x16 zero16() {
 #pragma unroll
   for (int i = 0; i < 16; ++i) z[i] = 0.f;
   return z;
-}
-
-__device__ __forceinline__ void split8(const float (&v)[8], bf16x8& hi, bf16x8& lo) {
-#pragma unroll
-  for (int i = 0; i < 8; ++i) {
-    const __bf16 h = static_cast<__bf16>(v[i]);
-    hi[i] = h;
-    lo[i] = static_cast<__bf16>(v[i] - static_cast<float>(h));
-  }
-}
-
-__device__ __forceinline__ void split4(float4 v, bf16x4& hi, bf16x4& lo) {
-  const float x[4] = {v.x, v.y, v.z, v.w};
-#pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const __bf16 h = static_cast<__bf16>(x[i]);
-    hi[i] = h;
-    lo[i] = static_cast<__bf16>(x[i] - static_cast<float>(h));
-  }
 }
 
 __device__ __forceinline__ f32x16 mfma3(bf16x8 ahi, bf16x8 alo, bf16x8 bhi, bf16x8 blo, f32x16 c) {
@@ -80,7 +60,9 @@ __global__ void __launch_bounds__(MAXT) step3_bf16x3(Step3Args p) {
   const int c32 = lane & 31;
   const int nk = 2 * p.H_pad;
   const int nks = nk / 16;
-  const float* zsp = p.zs + static_cast<size_t>(pair) * (QH + 1) * nk;
+  // this pair's chunks of Zhat, already split: chunk c is QH rows of 128
+  // bytes (16 words hi, 16 words lo), 8 float4 per row, contiguous
+  const float4* zsp = static_cast<const float4*>(p.zs) + static_cast<size_t>(pair) * QH * (nk / 4);
   float2* twl = reinterpret_cast<float2*>(smem);
   float* region = smem + 4 * QH;
   const int buf_words = QH * ROWW;
@@ -88,38 +70,12 @@ __global__ void __launch_bounds__(MAXT) step3_bf16x3(Step3Args p) {
   for (int i = tid; i < 2 * QH; i += nthr) twl[i] = p.tw_qa[i];
   constexpr int MAXF4 = 2;
   const int nf4 = QH * (KC / 4);
-  // Zhat rows are [q][c][zeta]; row Qa/2 is folded into row 0 (see the FP32
-  // form).  fetch only issues the loads (the Nyquist partner w for row 0);
-  // the fold is applied in put, after the loads had a whole chunk of MFMA
-  // work to arrive, so no wave waits on its prefetch.
-  auto fetch = [&](int kc, int t, float4& w) {
-    const int qq = t >> 3;
-    const int k = kc + (t & 7) * 4;
-    const float4 v = *reinterpret_cast<const float4*>(zsp + static_cast<size_t>(qq) * nk + k);
-    if (qq == 0) {
-      const float* ny = zsp + static_cast<size_t>(QH) * nk;
-      w = *reinterpret_cast<const float4*>(ny + (k < p.H_pad ? k + p.H_pad : k - p.H_pad));
-    }
-    return v;
+  auto fetch = [&](int kc, int t) { return zsp[static_cast<size_t>(kc / KC) * nf4 + t]; };
+  // unit t = 8 q + u of a chunk goes to words 4 u .. 4 u + 3 of LDS row q
+  auto put = [&](int buf, int t, float4 v) {
+    *reinterpret_cast<float4*>(region + buf * buf_words + (t >> 3) * ROWW + (t & 7) * 4) = v;
   };
-  auto put = [&](int buf, int t, float4 v, int kc, float4 w) {
-    const int qq = t >> 3;
-    const int k4 = (t & 7) * 4;
-    if (qq == 0) {
-      const float sg = (kc + k4 < p.H_pad) ? -1.f : 1.f;
-      v.x += sg * w.x; v.y += sg * w.y; v.z += sg * w.z; v.w += sg * w.w;
-    }
-    bf16x4 hi, lo;
-    split4(v, hi, lo);
-    float* row = region + buf * buf_words + qq * ROWW;
-    *reinterpret_cast<bf16x4*>(row + k4 / 2) = hi;
-    *reinterpret_cast<bf16x4*>(row + 16 + k4 / 2) = lo;
-  };
-  for (int t = tid; t < nf4; t += nthr) {
-    float4 w = make_float4(0.f, 0.f, 0.f, 0.f);
-    const float4 v = fetch(0, t, w);
-    put(0, t, v, 0, w);
-  }
+  for (int t = tid; t < nf4; t += nthr) put(0, t, fetch(0, t));
   __syncthreads();
   f32x16 acc[CTQ];
 #pragma unroll
@@ -144,18 +100,12 @@ __global__ void __launch_bounds__(MAXT) step3_bf16x3(Step3Args p) {
       alo[s] = ylo[(kc / 16 + s) * 64];
     }
     __builtin_amdgcn_sched_barrier(0);
-    float4 nreg[MAXF4], nny[MAXF4];
+    float4 nreg[MAXF4];
     if (PREF) {
       // the last chunk re-reads itself, so the loads need no condition
       const int kn = more ? kc + KC : kc;
 #pragma unroll
-      for (int k = 0; k < MAXF4; ++k) {
-        const int t = min(tid + k * nthr, nf4 - 1);
-        const int kk = kn + (t & 7) * 4;
-        nreg[k] = *reinterpret_cast<const float4*>(zsp + static_cast<size_t>(t >> 3) * nk + kk);
-        nny[k] = *reinterpret_cast<const float4*>(zsp + static_cast<size_t>(QH) * nk +
-                                                  (kk < p.H_pad ? kk + p.H_pad : kk - p.H_pad));
-      }
+      for (int k = 0; k < MAXF4; ++k) nreg[k] = fetch(kn, min(tid + k * nthr, nf4 - 1));
     }
     __builtin_amdgcn_sched_barrier(0);
     if (active) {
@@ -176,14 +126,10 @@ __global__ void __launch_bounds__(MAXT) step3_bf16x3(Step3Args p) {
 #pragma unroll
         for (int k = 0; k < MAXF4; ++k) {
           const int t = tid + k * nthr;
-          if (t < nf4) put(cur ^ 1, t, nreg[k], kc + KC, nny[k]);
+          if (t < nf4) put(cur ^ 1, t, nreg[k]);
         }
       } else {
-        for (int t = tid; t < nf4; t += nthr) {
-          float4 w = make_float4(0.f, 0.f, 0.f, 0.f);
-          const float4 v = fetch(kc + KC, t, w);
-          put(cur ^ 1, t, v, kc + KC, w);
-        }
+        for (int t = tid; t < nf4; t += nthr) put(cur ^ 1, t, fetch(kc + KC, t));
       }
       __syncthreads();
       cur ^= 1;

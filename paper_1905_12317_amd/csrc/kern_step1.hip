@@ -113,69 +113,79 @@ __global__ void tmpl_prep_bf16(const float2* __restrict__ b, __bf16* __restrict_
 
 // ---- Step 1, FP32 form --------------------------------------------------
 
-// Grid: x = image in chunk, y = q in [0, Qa/2], z = zeta block.
+// Grid: x = image in chunk, y = mode slot, z = zeta block x template part.
+// Slots y < CT are the Nyquist fold: slot y covers the 32 zeta of column tile
+// y of the block for mode 0 and accumulates Zhat(0) + i Zhat(Qa/2) as one
+// GEMM with K = 2 x 2M (the image operand of the second half is i P(Qa/2),
+// the template operand that of mode Qa/2).  Slots y >= CT are the modes
+// q = y - CT + 1 .. Qa/2 - 1 over the whole block.
 // LDS: image operand P[k'][zeta] (k' = 2m + c', zeta contiguous, stride PS).
-template <int RT, int CT>
-__global__ void __launch_bounds__(256) step1_fp32_v2(Step1Args p) {
-  extern __shared__ float smem[];
+template <int RT, int CT, bool FOLD>
+__device__ __forceinline__ void step1_fp32_tile(const Step1Args& p, float* smem, int q, int z0, int part) {
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
   const int M = p.M, Qa = p.Qa, QH = Qa / 2;
   const int A = blockIdx.x;
-  const int q = blockIdx.y;
-  const int z0 = (blockIdx.z / p.tparts) * (32 * CT);
-  const int part = blockIdx.z % p.tparts;  // this workgroup's share of the template row tiles
   constexpr int ZB = 32 * CT;
   constexpr int PS = (ZB % 64 == 0) ? ZB + 32 : ZB;  // row stride == 32 mod 64 words
+  constexpr int NP = FOLD ? 2 : 1;
+  const int MK = NP * M;
   const float2* arow = p.a + static_cast<size_t>(A) * Qa * M;
-  for (int i = tid; i < ZB * M; i += 256) {
-    const int z = i / M;
-    const int m = i - z * M;
-    int row = q - p.ell[z0 + z];
+  for (int i = tid; i < ZB * MK; i += 256) {
+    const int z = i / MK;
+    const int mm = i - z * MK;
+    const bool ny = FOLD && mm >= M;
+    const int m = ny ? mm - M : mm;
+    int row = (ny ? QH : q) - p.ell[z0 + z];
     row %= Qa;
     row += (row < 0) ? Qa : 0;
     const float2 av = arow[static_cast<size_t>(row) * M + m];
     const float cm = p.cz[static_cast<size_t>(z0 + z) * M + m];
-    smem[(2 * m) * PS + z] = cm * av.x;
-    smem[(2 * m + 1) * PS + z] = cm * av.y;
+    // i (x + i y) = -y + i x for the Nyquist half
+    smem[(2 * mm) * PS + z] = ny ? -cm * av.y : cm * av.x;
+    smem[(2 * mm + 1) * PS + z] = ny ? cm * av.x : cm * av.y;
   }
   __syncthreads();
   const int r = lane >> 5;
   const int c32 = lane & 31;
-  const int NQ = QH + 1;
   const int nRT = (p.nB + 15) / 16;
   const int twoH = 2 * p.H_pad;
   const float* Pb = smem + r * PS + c32;
-  float* zbase = p.zs + static_cast<size_t>(A) * p.nB * NQ * twoH + static_cast<size_t>(q) * twoH;
-  const float* rq =
-      p.r32 + (static_cast<size_t>(q) * p.tiles_per_q + static_cast<size_t>(A) * p.img_tiles) * M * 64 + lane;
+  float* zbase = static_cast<float*>(p.zs) + static_cast<size_t>(A) * p.nB * QH * twoH + static_cast<size_t>(q) * twoH;
+  const size_t img_off = static_cast<size_t>(A) * p.img_tiles;
   for (int rt0 = (part * 4 + wave) * RT; rt0 < nRT; rt0 += 4 * RT * p.tparts) {
     f32x16 acc[RT][CT];
 #pragma unroll
     for (int i = 0; i < RT; ++i)
 #pragma unroll
       for (int j = 0; j < CT; ++j) acc[i][j] = zero16();
-    const float* ra[RT];
 #pragma unroll
-    for (int i = 0; i < RT; ++i) ra[i] = rq + static_cast<size_t>(min(rt0 + i, nRT - 1)) * M * 64;
-    float an[RT];
+    for (int pass = 0; pass < NP; ++pass) {
+      const int qt = pass ? QH : q;  // mode of the template operand
+      const float* rq = p.r32 + (static_cast<size_t>(qt) * p.tiles_per_q + img_off) * M * 64 + lane;
+      const float* ra[RT];
 #pragma unroll
-    for (int i = 0; i < RT; ++i) an[i] = ra[i][0];
-    for (int m = 0; m < M; ++m) {
-      float av[RT];
+      for (int i = 0; i < RT; ++i) ra[i] = rq + static_cast<size_t>(min(rt0 + i, nRT - 1)) * M * 64;
+      float an[RT];
 #pragma unroll
-      for (int i = 0; i < RT; ++i) av[i] = an[i];
-      if (m + 1 < M) {
+      for (int i = 0; i < RT; ++i) an[i] = ra[i][0];
+      const float* Pp = Pb + pass * (2 * M) * PS;
+      for (int m = 0; m < M; ++m) {
+        float av[RT];
 #pragma unroll
-        for (int i = 0; i < RT; ++i) an[i] = ra[i][(m + 1) * 64];
-      }
+        for (int i = 0; i < RT; ++i) av[i] = an[i];
+        if (m + 1 < M) {
 #pragma unroll
-      for (int j = 0; j < CT; ++j) {
-        const float bv = Pb[(2 * m) * PS + j * 32];
+          for (int i = 0; i < RT; ++i) an[i] = ra[i][(m + 1) * 64];
+        }
 #pragma unroll
-        for (int i = 0; i < RT; ++i)
-          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[i], bv, acc[i][j], 0, 0, 0);
+        for (int j = 0; j < CT; ++j) {
+          const float bv = Pp[(2 * m) * PS + j * 32];
+#pragma unroll
+          for (int i = 0; i < RT; ++i)
+            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[i], bv, acc[i][j], 0, 0, 0);
+        }
       }
     }
 #pragma unroll
@@ -188,10 +198,22 @@ __global__ void __launch_bounds__(256) step1_fp32_v2(Step1Args p) {
           const int row = 8 * (v >> 2) + 4 * r + (v & 3);
           const int B = (rt0 + i) * 16 + (row >> 1);
           if (B < p.nB)
-            zbase[static_cast<size_t>(B) * NQ * twoH + (row & 1) * p.H_pad + z0 + j * 32 + c32] = acc[i][j][v];
+            zbase[static_cast<size_t>(B) * QH * twoH + (row & 1) * p.H_pad + z0 + j * 32 + c32] = acc[i][j][v];
         }
     }
   }
+}
+
+template <int RT, int CT>
+__global__ void __launch_bounds__(256) step1_fp32_v2(Step1Args p) {
+  extern __shared__ float smem[];
+  const int y = blockIdx.y;
+  const int zb = (blockIdx.z / p.tparts) * (32 * CT);
+  const int part = blockIdx.z % p.tparts;
+  if (y < CT)
+    step1_fp32_tile<RT, 1, true>(p, smem, 0, zb + 32 * y, part);
+  else
+    step1_fp32_tile<RT, CT, false>(p, smem, y - CT + 1, zb, part);
 }
 
 // ---- Step 1, split-bf16 form -------------------------------------------
@@ -203,32 +225,48 @@ __device__ __forceinline__ f32x16 mfma3(bf16x8 ahi, bf16x8 alo, bf16x8 bhi, bf16
   return c;
 }
 
-// LDS: image operand per zeta row: [2M bf16 hi][2M bf16 lo] + 4 words pad.
-template <int RT, int CT>
-__global__ void __launch_bounds__(256) step1_bf16_v2(Step1Args p) {
-  extern __shared__ float smem[];
+__device__ __forceinline__ uint32_t bf16_bits(__bf16 h) {
+  return static_cast<uint32_t>(__builtin_bit_cast(uint16_t, h));
+}
+
+// Same work split and Nyquist fold as the FP32 form.  LDS: image operand per
+// zeta row: [2 MK bf16 hi][2 MK bf16 lo] + 4 words pad (MK = M, or 2M when
+// folding).  The result is split into bf16 hi + lo and written in Step 3's
+// chunk layout [pair][k' / 32][q][32 hi][32 lo]: lanes j and j + 1 (adjacent
+// zeta) trade halves so that the even lane stores the hi pair and the odd
+// lane the lo pair as 32-bit words.
+template <int RT, int CT, bool FOLD>
+__device__ __forceinline__ void step1_bf16_tile(const Step1Args& p, float* smem, int q, int z0, int part) {
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
   const int M = p.M, Qa = p.Qa, QH = Qa / 2;
   const int A = blockIdx.x;
-  const int q = blockIdx.y;
   constexpr int ZB = 32 * CT;
-  const int z0 = (blockIdx.z / p.tparts) * ZB;
-  const int part = blockIdx.z % p.tparts;
-  const int RW = 2 * M + 4;  // words per zeta row
+  constexpr int NP = FOLD ? 2 : 1;
+  const int MK = NP * M;
+  const int RW = 2 * MK + 4;  // words per zeta row
   const float2* arow = p.a + static_cast<size_t>(A) * Qa * M;
-  // two m per item: (Pr, Pi) of m and m+1 -> 4 consecutive k'
-  for (int i = tid; i < ZB * (M / 2); i += 256) {
-    const int z = i / (M / 2);
-    const int m2 = i - z * (M / 2);
-    int row = q - p.ell[z0 + z];
+  // two m per item: (Pr, Pi) of m and m+1 -> 4 consecutive k' (M is even,
+  // so both lie in the same half)
+  for (int i = tid; i < ZB * (MK / 2); i += 256) {
+    const int z = i / (MK / 2);
+    const int m2 = i - z * (MK / 2);
+    const bool ny = FOLD && 2 * m2 >= M;
+    const int ml = ny ? m2 - M / 2 : m2;
+    int row = (ny ? QH : q) - p.ell[z0 + z];
     row %= Qa;
     row += (row < 0) ? Qa : 0;
-    const float4 av = reinterpret_cast<const float4*>(arow + static_cast<size_t>(row) * M)[m2];
-    const float2 cm = reinterpret_cast<const float2*>(p.cz + static_cast<size_t>(z0 + z) * M)[m2];
-    const float4 pv = make_float4(cm.x * av.x, cm.x * av.y, cm.y * av.z, cm.y * av.w);
-    const float x[4] = {pv.x, pv.y, pv.z, pv.w};
+    const float4 av = reinterpret_cast<const float4*>(arow + static_cast<size_t>(row) * M)[ml];
+    const float2 cm = reinterpret_cast<const float2*>(p.cz + static_cast<size_t>(z0 + z) * M)[ml];
+    float x[4] = {cm.x * av.x, cm.x * av.y, cm.y * av.z, cm.y * av.w};
+    if (ny) {  // i (x + i y) = -y + i x
+      const float t0 = x[0], t2 = x[2];
+      x[0] = -x[1];
+      x[1] = t0;
+      x[2] = -x[3];
+      x[3] = t2;
+    }
     bf16x4 hi, lo;
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
@@ -238,72 +276,109 @@ __global__ void __launch_bounds__(256) step1_bf16_v2(Step1Args p) {
     }
     float* dst = smem + z * RW + 2 * m2;
     *reinterpret_cast<bf16x4*>(dst) = hi;
-    *reinterpret_cast<bf16x4*>(dst + M) = lo;
+    *reinterpret_cast<bf16x4*>(dst + MK) = lo;
   }
   __syncthreads();
   const int r = lane >> 5;
   const int c32 = lane & 31;
-  const int NQ = QH + 1;
   const int nRT = (p.nB + 15) / 16;
   const int nks = M / 8;
-  const int twoH = 2 * p.H_pad;
+  const size_t pair_words = static_cast<size_t>(QH) * 2 * p.H_pad;
   const float* Pb = smem + c32 * RW + 4 * r;
-  float* zbase = p.zs + static_cast<size_t>(A) * p.nB * NQ * twoH + static_cast<size_t>(q) * twoH;
-  const bf16x8* rq =
-      reinterpret_cast<const bf16x8*>(p.r16) +
-      ((static_cast<size_t>(q) * p.tiles_per_q + static_cast<size_t>(A) * p.img_tiles) * nks * 64 + lane) * 2;
+  // word of this lane in a 128-byte (32-word) row: even lanes hi, odd lanes lo
+  const int odd = c32 & 1;
+  const int wsel = odd ? 16 + (c32 >> 1) : (c32 >> 1);
+  uint32_t* zw = static_cast<uint32_t*>(p.zs) + static_cast<size_t>(A) * p.nB * pair_words +
+                 static_cast<size_t>(q) * 32 + wsel;
+  const size_t img_off = static_cast<size_t>(A) * p.img_tiles;
   for (int rt0 = (part * 4 + wave) * RT; rt0 < nRT; rt0 += 4 * RT * p.tparts) {
     f32x16 acc[RT][CT];
 #pragma unroll
     for (int i = 0; i < RT; ++i)
 #pragma unroll
       for (int j = 0; j < CT; ++j) acc[i][j] = zero16();
-    const bf16x8* ra[RT];
 #pragma unroll
-    for (int i = 0; i < RT; ++i) ra[i] = rq + static_cast<size_t>(min(rt0 + i, nRT - 1)) * nks * 128;
-    bf16x8 nhi[RT], nlo[RT];
+    for (int pass = 0; pass < NP; ++pass) {
+      const int qt = pass ? QH : q;
+      const bf16x8* rq = reinterpret_cast<const bf16x8*>(p.r16) +
+                         ((static_cast<size_t>(qt) * p.tiles_per_q + img_off) * nks * 64 + lane) * 2;
+      const bf16x8* ra[RT];
 #pragma unroll
-    for (int i = 0; i < RT; ++i) {
-      nhi[i] = ra[i][0];
-      nlo[i] = ra[i][1];
-    }
-    for (int ks = 0; ks < nks; ++ks) {
-      bf16x8 ahi[RT], alo[RT];
+      for (int i = 0; i < RT; ++i) ra[i] = rq + static_cast<size_t>(min(rt0 + i, nRT - 1)) * nks * 128;
+      bf16x8 nhi[RT], nlo[RT];
 #pragma unroll
       for (int i = 0; i < RT; ++i) {
-        ahi[i] = nhi[i];
-        alo[i] = nlo[i];
+        nhi[i] = ra[i][0];
+        nlo[i] = ra[i][1];
       }
-      if (ks + 1 < nks) {
+      const float* Pp = Pb + pass * M;  // the Nyquist half starts at k' = 2M (M words)
+      for (int ks = 0; ks < nks; ++ks) {
+        bf16x8 ahi[RT], alo[RT];
 #pragma unroll
         for (int i = 0; i < RT; ++i) {
-          nhi[i] = ra[i][(ks + 1) * 128];
-          nlo[i] = ra[i][(ks + 1) * 128 + 1];
+          ahi[i] = nhi[i];
+          alo[i] = nlo[i];
+        }
+        if (ks + 1 < nks) {
+#pragma unroll
+          for (int i = 0; i < RT; ++i) {
+            nhi[i] = ra[i][(ks + 1) * 128];
+            nlo[i] = ra[i][(ks + 1) * 128 + 1];
+          }
+        }
+#pragma unroll
+        for (int j = 0; j < CT; ++j) {
+          const float* prow = Pp + j * 32 * RW + 8 * ks;
+          const bf16x8 bhi = *reinterpret_cast<const bf16x8*>(prow);
+          const bf16x8 blo = *reinterpret_cast<const bf16x8*>(prow + MK);
+#pragma unroll
+          for (int i = 0; i < RT; ++i) acc[i][j] = mfma3(ahi[i], alo[i], bhi, blo, acc[i][j]);
         }
       }
-#pragma unroll
-      for (int j = 0; j < CT; ++j) {
-        const float* prow = Pb + j * 32 * RW + 8 * ks;
-        const bf16x8 bhi = *reinterpret_cast<const bf16x8*>(prow);
-        const bf16x8 blo = *reinterpret_cast<const bf16x8*>(prow + M);
-#pragma unroll
-        for (int i = 0; i < RT; ++i) acc[i][j] = mfma3(ahi[i], alo[i], bhi, blo, acc[i][j]);
-      }
     }
+    // tiles whose 16 templates all exist store without a per-row test
 #pragma unroll
     for (int i = 0; i < RT; ++i) {
-      if (rt0 + i >= nRT) continue;
+      const int rt = rt0 + i;
+      if (rt >= nRT) break;
+      const bool full = (rt + 1) * 16 <= p.nB;
 #pragma unroll
-      for (int j = 0; j < CT; ++j)
+      for (int j = 0; j < CT; ++j) {
 #pragma unroll
         for (int v = 0; v < 16; ++v) {
+          const float x = acc[i][j][v];
+          const __bf16 h = static_cast<__bf16>(x);
+          const uint32_t hb = bf16_bits(h);
+          const uint32_t lb = bf16_bits(static_cast<__bf16>(x - static_cast<float>(h)));
+          // even lane sends its lo, odd lane its hi; both receive the other's
+          const uint32_t got = static_cast<uint32_t>(
+              __builtin_amdgcn_mov_dpp(static_cast<int>(odd ? hb : lb), 0xB1, 0xF, 0xF, false));
+          const uint32_t word = odd ? (got | (lb << 16)) : (hb | (got << 16));
           const int row = 8 * (v >> 2) + 4 * r + (v & 3);
-          const int B = (rt0 + i) * 16 + (row >> 1);
-          if (B < p.nB)
-            zbase[static_cast<size_t>(B) * NQ * twoH + (row & 1) * p.H_pad + z0 + j * 32 + c32] = acc[i][j][v];
+          const int B = rt * 16 + (row >> 1);
+          // k' = c H_pad + z0 + 32 j + c32: chunk (c H_pad + z0) / 32 + j
+          const int chunk = ((row & 1) * p.H_pad + z0) / 32 + j;
+          if (full || B < p.nB) zw[static_cast<size_t>(B) * pair_words + static_cast<size_t>(chunk) * QH * 32] = word;
+          if ((v & 3) == 3) __builtin_amdgcn_sched_barrier(0);
         }
+      }
     }
   }
+}
+
+// At least 2 waves per SIMD: left free, the compiler keeps the accumulators
+// in AGPRs and copies them all to VGPRs for the split at the end (about 300
+// registers, 1 wave per SIMD).
+template <int RT, int CT>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) step1_bf16_v2(Step1Args p) {
+  extern __shared__ float smem[];
+  const int y = blockIdx.y;
+  const int zb = (blockIdx.z / p.tparts) * (32 * CT);
+  const int part = blockIdx.z % p.tparts;
+  if (y < CT)
+    step1_bf16_tile<RT, 1, true>(p, smem, 0, zb + 32 * y, part);
+  else
+    step1_bf16_tile<RT, CT, false>(p, smem, y - CT + 1, zb, part);
 }
 
 template <class K>
@@ -346,18 +421,25 @@ hipError_t launch_tmpl_prep_lists(const float2* b, void* out, int nB, int M, int
 }
 
 size_t step1_v2_lds_bytes(int M, int zb, int precision) {
+  // the larger of a plain slot (zb zeta, K = 2M) and a fold slot (32 zeta, K = 4M)
+  size_t plain, fold;
   if (precision == 0) {
     const int PS = (zb % 64 == 0) ? zb + 32 : zb;
-    return sizeof(float) * 2 * M * PS;
+    plain = sizeof(float) * 2 * M * PS;
+    fold = sizeof(float) * 4 * M * 32;
+  } else {
+    plain = sizeof(float) * zb * (2 * M + 4);
+    fold = sizeof(float) * 32 * (4 * M + 4);
   }
-  return sizeof(float) * zb * (2 * M + 4);
+  return plain > fold ? plain : fold;
 }
 
 hipError_t launch_step1_v2(const Step1Args& a, int precision, hipStream_t s) {
   if (a.nA <= 0 || a.nB <= 0) return hipSuccess;
   const int CT = a.zblk / 32;
   const int QH = a.Qa / 2;
-  dim3 grid(a.nA, QH + 1, (a.H_pad / a.zblk) * a.tparts);
+  // QH - 1 plain modes and CT slots of the Nyquist fold per zeta block
+  dim3 grid(a.nA, QH - 1 + CT, (a.H_pad / a.zblk) * a.tparts);
   const size_t lds = step1_v2_lds_bytes(a.M, a.zblk, precision);
   hipError_t e;
   if (precision == 0) {

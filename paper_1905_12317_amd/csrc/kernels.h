@@ -21,13 +21,13 @@ struct TransformArgs {
 size_t transform_lds_bytes(int nf, int Qa, int nwaves);
 hipError_t launch_transform(const TransformArgs& args, int cnt, hipStream_t stream);
 
-// Step 1 (eq. fbk3): Zhat[pair][q][c][zeta] for q = 0 .. Qa/2 (c = re|im).
+// Step 1 (eq. fbk3): Zhat of every pair of the call, into the staging below.
 struct Step1Args {
   const float2* a;       // image coefficients [nA][Qa][M] (chunk base)
   const float2* b;       // template coefficients [nB][Qa][M]
   const float* cz;       // [H_pad][M]: 2 pi w_m Sigma v(k_m), 0 on padding
   const int* ell;        // [H_pad]: l_zeta, 0 on padding
-  float* zs;             // [nA][nB][Qa/2 + 1][2][H_pad]
+  void* zs;              // Zhat staging, layout by form (below)
   const float* r32;      // embedded template operand, FP32 lane order (tmpl_prep)
   const void* r16;       // embedded template operand, bf16 hi/lo lane order (tmpl_prep)
   int nA, nB, M, Qa, H_pad, L;
@@ -41,10 +41,17 @@ struct Step1Args {
   int img_tiles;
 };
 
-// Step 3 + rotation FFT + argmax.  Row Qa/2 of Zhat (the Nyquist mode) is
-// folded into row 0 as Zhat(0) + i Zhat(Qa/2) while staging.
+// Zhat staging written by Step 1 and read by Step 3: Qa/2 rows of q per pair,
+// row 0 holding Zhat(0) + i Zhat(Qa/2) (the Nyquist mode folded in), and
+// K index k' = c H_pad + zeta (c = 0 real, 1 imaginary part).  4 Qa H_pad
+// bytes per pair in both forms:
+//   FP32:       [pair][q][k'] float
+//   split-bf16: [pair][k' / 32][q][32 bf16 hi of k' % 32][32 bf16 lo]
+//               (one 128-byte row per q and chunk of 32 k': Step 3 copies
+//               whole chunks into LDS without converting them)
+// Step 3 + rotation FFT + argmax.
 struct Step3Args {
-  const float* zs;       // [pairs][Qa/2 + 1][2][H_pad]
+  const void* zs;        // Zhat staging (above)
   const float* yt;       // [2 H_pad][2 N_pad] real embedding of Y, transposed
   const uint16_t* yt_hi; // split-precision copies (bf16), same layout
   const uint16_t* yt_lo;
@@ -59,7 +66,8 @@ struct Step3Args {
 size_t step3_lds_bytes(int Qa, int nwaves);
 hipError_t launch_step3(const Step3Args& args, int precision, hipStream_t stream);
 // Step 1 with the template operand embedded once per call (kern_step1.hip):
-// staging layout zs[pair][q][c][zeta], q = 0 .. Qa/2 (Qa/2 + 1 rows).
+// Zhat staging as described above Step3Args; the template operand still
+// covers q = 0 .. Qa/2 (Qa/2 + 1 slices).
 size_t tmpl_prep_bytes(int nB, int M, int Qa, int precision);
 size_t tmpl_prep_tile_bytes(size_t tiles, int M, int Qa, int precision);
 hipError_t launch_tmpl_prep(const float2* b, void* out, int nB, int M, int Qa, int precision, hipStream_t stream);
