@@ -85,28 +85,34 @@ __global__ void __launch_bounds__(MAXT) step3_bf16x3(Step3Args p) {
   const size_t tile = static_cast<size_t>(min(d0, p.N_pad - 16) / 16) * nks;
   const bf16x8* yhi = reinterpret_cast<const bf16x8*>(p.yt_hi) + tile * 64 + lane;
   const bf16x8* ylo = reinterpret_cast<const bf16x8*>(p.yt_lo) + tile * 64 + lane;
-  int cur = 0;
-  for (int kc = 0; kc < nk; kc += KC) {
-    const bool more = kc + KC < nk;
-    // this chunk's shift-panel operands are loaded before the next chunk's
-    // prefetch: loads retire in order, so waiting for them does not wait
-    // for the prefetch
-    // Every wave issues the same unconditional loads (clamped to valid
-    // addresses), so the waits before the MFMAs cover exactly the operands.
-    bf16x8 ahi[KC / 16], alo[KC / 16];
+  // shift-panel operands of the chunk at kc (past the end: the last chunk
+  // again, so the loads need no condition)
+  auto load_y = [&](int kc, bf16x8 (&yh)[KC / 16], bf16x8 (&yl)[KC / 16]) {
+    const int kk = min(kc, nk - KC);
 #pragma unroll
     for (int s = 0; s < KC / 16; ++s) {
-      ahi[s] = yhi[(kc / 16 + s) * 64];
-      alo[s] = ylo[(kc / 16 + s) * 64];
+      yh[s] = yhi[(kk / 16 + s) * 64];
+      yl[s] = ylo[(kk / 16 + s) * 64];
     }
-    __builtin_amdgcn_sched_barrier(0);
+  };
+  // One chunk: the MFMAs on LDS buffer (kc / KC) % 2 with the panel operands
+  // loaded one chunk earlier, then the next chunk is stored into the other
+  // buffer.  Loads retire in order, so each chunk issues its loads in the
+  // order they are consumed (next chunk's Zhat, then the panel operands of the
+  // chunk after it) and the waits before the MFMAs cover no load issued in
+  // this chunk.  Every wave issues the same unconditional loads (clamped to
+  // valid addresses), so the wait counts are exact.
+  auto chunk = [&](int kc, const bf16x8 (&ah)[KC / 16], const bf16x8 (&al)[KC / 16], bf16x8 (&nh)[KC / 16],
+                   bf16x8 (&nl)[KC / 16]) {
+    const int cur = (kc / KC) & 1;
+    const bool more = kc + KC < nk;
     float4 nreg[MAXF4];
     if (PREF) {
-      // the last chunk re-reads itself, so the loads need no condition
-      const int kn = more ? kc + KC : kc;
+      const int kn = more ? kc + KC : kc;  // the last chunk re-reads itself
 #pragma unroll
       for (int k = 0; k < MAXF4; ++k) nreg[k] = fetch(kn, min(tid + k * nthr, nf4 - 1));
     }
+    load_y(kc + KC, nh, nl);
     __builtin_amdgcn_sched_barrier(0);
     if (active) {
       const float* Zb = region + cur * buf_words + c32 * ROWW + 4 * r;
@@ -117,7 +123,7 @@ __global__ void __launch_bounds__(MAXT) step3_bf16x3(Step3Args p) {
           const float* row = Zb + ct * 32 * ROWW + 8 * s;
           const bf16x8 bhi = *reinterpret_cast<const bf16x8*>(row);
           const bf16x8 blo = *reinterpret_cast<const bf16x8*>(row + 16);
-          acc[ct] = mfma3(ahi[s], alo[s], bhi, blo, acc[ct]);
+          acc[ct] = mfma3(ah[s], al[s], bhi, blo, acc[ct]);
         }
       }
     }
@@ -132,8 +138,14 @@ __global__ void __launch_bounds__(MAXT) step3_bf16x3(Step3Args p) {
         for (int t = tid; t < nf4; t += nthr) put(cur ^ 1, t, fetch(kc + KC, t));
       }
       __syncthreads();
-      cur ^= 1;
     }
+  };
+  bf16x8 yah[KC / 16], yal[KC / 16], ybh[KC / 16], ybl[KC / 16];
+  load_y(0, yah, yal);
+  // nk / KC is even (H_pad is a multiple of 64)
+  for (int kc = 0; kc < nk; kc += 2 * KC) {
+    chunk(kc, yah, yal, ybh, ybl);
+    chunk(kc + KC, ybh, ybl, yah, yal);
   }
   __syncthreads();
   if (!active) return;
