@@ -113,6 +113,29 @@ __global__ void tmpl_prep_bf16(const float2* __restrict__ b, __bf16* __restrict_
 
 // ---- Step 1, FP32 form --------------------------------------------------
 
+// Workgroup b of the 1-D grid.  A group is one (mode slot y, zeta block x
+// template part zp); its nA images run on one XCD one after another
+// (workgroups are dealt to the 8 XCDs round-robin, so b and b + 8 share an
+// XCD), and the group's template operand comes from HBM once and from that
+// XCD's L2 for the other images.  Group g = 8 gl + x goes to XCD x; the grid
+// holds whole rounds of 8 groups and the padding workgroups exit.
+__device__ __forceinline__ int step1_groups(const Step1Args& p, int CT) {
+  return (p.Qa / 2 - 1 + CT) * (p.H_pad / p.zblk) * p.tparts;
+}
+__device__ __forceinline__ bool step1_block(int b, const Step1Args& p, int CT, int& A, int& y, int& zp) {
+  const int S = p.Qa / 2 - 1 + CT;
+  const int x = b & 7;
+  const int s = b >> 3;
+  const int gl = s / p.nA;
+  A = s - gl * p.nA;
+  const int g = 8 * gl + x;
+  if (g >= step1_groups(p, CT)) return false;
+  y = g % S;
+  zp = g / S;
+  return true;
+}
+
+
 // Grid: x = image in chunk, y = mode slot, z = zeta block x template part.
 // Slots y < CT are the Nyquist fold: slot y covers the 32 zeta of column tile
 // y of the block for mode 0 and accumulates Zhat(0) + i Zhat(Qa/2) as one
@@ -121,12 +144,11 @@ __global__ void tmpl_prep_bf16(const float2* __restrict__ b, __bf16* __restrict_
 // q = y - CT + 1 .. Qa/2 - 1 over the whole block.
 // LDS: image operand P[k'][zeta] (k' = 2m + c', zeta contiguous, stride PS).
 template <int RT, int CT, bool FOLD>
-__device__ __forceinline__ void step1_fp32_tile(const Step1Args& p, float* smem, int q, int z0, int part) {
+__device__ __forceinline__ void step1_fp32_tile(const Step1Args& p, float* smem, int A, int q, int z0, int part) {
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
   const int M = p.M, Qa = p.Qa, QH = Qa / 2;
-  const int A = blockIdx.x;
   constexpr int ZB = 32 * CT;
   constexpr int PS = (ZB % 64 == 0) ? ZB + 32 : ZB;  // row stride == 32 mod 64 words
   constexpr int NP = FOLD ? 2 : 1;
@@ -207,13 +229,14 @@ __device__ __forceinline__ void step1_fp32_tile(const Step1Args& p, float* smem,
 template <int RT, int CT>
 __global__ void __launch_bounds__(256) step1_fp32_v2(Step1Args p) {
   extern __shared__ float smem[];
-  const int y = blockIdx.y;
-  const int zb = (blockIdx.z / p.tparts) * (32 * CT);
-  const int part = blockIdx.z % p.tparts;
+  int A, y, zp;
+  if (!step1_block(blockIdx.x, p, CT, A, y, zp)) return;
+  const int zb = (zp / p.tparts) * (32 * CT);
+  const int part = zp % p.tparts;
   if (y < CT)
-    step1_fp32_tile<RT, 1, true>(p, smem, 0, zb + 32 * y, part);
+    step1_fp32_tile<RT, 1, true>(p, smem, A, 0, zb + 32 * y, part);
   else
-    step1_fp32_tile<RT, CT, false>(p, smem, y - CT + 1, zb, part);
+    step1_fp32_tile<RT, CT, false>(p, smem, A, y - CT + 1, zb, part);
 }
 
 // ---- Step 1, split-bf16 form -------------------------------------------
@@ -236,12 +259,11 @@ __device__ __forceinline__ uint32_t bf16_bits(__bf16 h) {
 // zeta) trade halves so that the even lane stores the hi pair and the odd
 // lane the lo pair as 32-bit words.
 template <int RT, int CT, bool FOLD>
-__device__ __forceinline__ void step1_bf16_tile(const Step1Args& p, float* smem, int q, int z0, int part) {
+__device__ __forceinline__ void step1_bf16_tile(const Step1Args& p, float* smem, int A, int q, int z0, int part) {
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
   const int M = p.M, Qa = p.Qa, QH = Qa / 2;
-  const int A = blockIdx.x;
   constexpr int ZB = 32 * CT;
   constexpr int NP = FOLD ? 2 : 1;
   const int MK = NP * M;
@@ -372,13 +394,14 @@ __device__ __forceinline__ void step1_bf16_tile(const Step1Args& p, float* smem,
 template <int RT, int CT>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) step1_bf16_v2(Step1Args p) {
   extern __shared__ float smem[];
-  const int y = blockIdx.y;
-  const int zb = (blockIdx.z / p.tparts) * (32 * CT);
-  const int part = blockIdx.z % p.tparts;
+  int A, y, zp;
+  if (!step1_block(blockIdx.x, p, CT, A, y, zp)) return;
+  const int zb = (zp / p.tparts) * (32 * CT);
+  const int part = zp % p.tparts;
   if (y < CT)
-    step1_bf16_tile<RT, 1, true>(p, smem, 0, zb + 32 * y, part);
+    step1_bf16_tile<RT, 1, true>(p, smem, A, 0, zb + 32 * y, part);
   else
-    step1_bf16_tile<RT, CT, false>(p, smem, y - CT + 1, zb, part);
+    step1_bf16_tile<RT, CT, false>(p, smem, A, y - CT + 1, zb, part);
 }
 
 template <class K>
@@ -438,8 +461,12 @@ hipError_t launch_step1_v2(const Step1Args& a, int precision, hipStream_t s) {
   if (a.nA <= 0 || a.nB <= 0) return hipSuccess;
   const int CT = a.zblk / 32;
   const int QH = a.Qa / 2;
-  // QH - 1 plain modes and CT slots of the Nyquist fold per zeta block
-  dim3 grid(a.nA, QH - 1 + CT, (a.H_pad / a.zblk) * a.tparts);
+  // QH - 1 plain modes and CT slots of the Nyquist fold per zeta block and
+  // template part; nA workgroups per group, whole rounds of 8 groups
+  const size_t groups = static_cast<size_t>(QH - 1 + CT) * (a.H_pad / a.zblk) * a.tparts;
+  const size_t nwg = 8 * static_cast<size_t>(a.nA) * ((groups + 7) / 8);
+  if (nwg > 0x7fffffffull) return hipErrorInvalidConfiguration;
+  const dim3 grid(static_cast<unsigned>(nwg));
   const size_t lds = step1_v2_lds_bytes(a.M, a.zblk, precision);
   hipError_t e;
   if (precision == 0) {
