@@ -59,7 +59,13 @@ typedef enum ftk_status {
 
 typedef enum ftk_precision {
   FTK_FP32 = 0,   /* both contractions on FP32 MFMA */
-  FTK_BF16X3 = 1  /* split bf16 (hi + lo) with three products, FP32 accumulate */
+  FTK_BF16X3 = 1, /* split bf16 (hi + lo) with three products, FP32 accumulate */
+  FTK_FP16 = 2    /* one fp16 product per term, FP32 accumulate; operands scaled by
+                     powers of two per call (max |a|, max |b|) and per SVD term
+                     (the 2 pi w G rows and the shift panel), Section 4.5 factors
+                     kept in FP64 on the host.  About 11 significant bits per
+                     operand: errors of a few 1e-4 of the pair scale, for
+                     eps >= 1e-3 */
 } ftk_precision;
 
 /* Best pose of one image-template pair: the largest Re X over the shift

@@ -109,6 +109,27 @@ uint16_t bf16_rne(float f) {
   return static_cast<uint16_t>(u >> 16);
 }
 
+// IEEE binary16 bits of x, round to nearest even (overflow to infinity,
+// subnormals kept)
+uint16_t f16_rne(double x) {
+  if (std::isnan(x)) return 0x7e00;
+  const uint16_t sign = std::signbit(x) ? 0x8000 : 0;
+  const double a = std::fabs(x);
+  if (a >= 65520.0) return sign | 0x7c00;
+  if (a < std::ldexp(1.0, -14))  // subnormal: units of 2^-24 (1024 units is the smallest normal)
+    return sign | static_cast<uint16_t>(std::nearbyint(a * std::ldexp(1.0, 24)));
+  int e;
+  const double f = std::frexp(a, &e);  // a = f 2^e, f in [0.5, 1): a = (2f) 2^(e-1)
+  uint32_t m = static_cast<uint32_t>(std::nearbyint((2.0 * f - 1.0) * 1024.0));
+  int ef = e - 1 + 15;
+  if (m == 1024) {
+    m = 0;
+    ++ef;
+  }
+  if (ef >= 31) return sign | 0x7c00;
+  return sign | static_cast<uint16_t>((ef << 10) | m);
+}
+
 double bf16_value(uint16_t h) {
   const uint32_t u = static_cast<uint32_t>(h) << 16;
   float f;
@@ -199,14 +220,34 @@ std::vector<float> twiddles(int L) {
   return t;
 }
 
+// power of two at or above x > 0 (1 for x = 0)
+double pow2_at_or_above(double x) {
+  if (!(x > 0.0)) return 1.0;
+  int e;
+  const double f = std::frexp(x, &e);  // x = f 2^e, f in [0.5, 1)
+  return std::ldexp(1.0, f == 0.5 ? e - 1 : e);
+}
+
 int upload_plan_tables(ftk_plan* p) {
   const int M = p->M, H = p->t.H, Hp = p->H_pad;
   std::vector<float> cz(static_cast<size_t>(Hp) * M, 0.f);
   std::vector<int> ell(Hp, 0);
+  p->zeta_scale.assign(Hp, 1.f);
   for (int z = 0; z < H; ++z) {
     ell[z] = p->t.ell[z];
+    double sg = 1.0;
+    if (p->precision == FTK_FP16) {
+      // the FP16 form stores the row divided by the power of two at or above
+      // its largest entry; the shift panel carries that factor
+      double mx = 0.0;
+      for (int m = 0; m < M; ++m)
+        mx = std::max(mx, std::fabs(2.0 * kPi * p->t.w[m] * p->t.G[static_cast<size_t>(z) * M + m]));
+      sg = pow2_at_or_above(mx);
+      p->zeta_scale[z] = static_cast<float>(sg);
+    }
     for (int m = 0; m < M; ++m)
-      cz[static_cast<size_t>(z) * M + m] = static_cast<float>(2.0 * kPi * p->t.w[m] * p->t.G[static_cast<size_t>(z) * M + m]);
+      cz[static_cast<size_t>(z) * M + m] =
+          static_cast<float>(2.0 * kPi * p->t.w[m] * p->t.G[static_cast<size_t>(z) * M + m] / sg);
   }
   // NUFFT: deapodisation with all scale factors, and per-point kernel weights
   const int n = p->n, nf = p->sk.nf, w = p->sk.w, Qa = p->Qa, half = Qa / 2;
@@ -252,9 +293,10 @@ int check_plan_args(int n, int K, int Q, double W, double eps, int precision) {
   if (Q < 8 || Q > 4096 || (Q & 1)) return fail(FTK_EINVAL, "Q must be even and in [8, 4096]");
   if (!(W > 0.0) || W > n / 4.0) return fail(FTK_EINVAL, "W (shift radius, px) must be in (0, n/4]");
   if (!(eps > 0.0) || !(eps < 1.0)) return fail(FTK_EINVAL, "eps must be in (0, 1)");
-  if (precision != FTK_FP32 && precision != FTK_BF16X3) return fail(FTK_EINVAL, "unknown precision");
-  if (precision == FTK_BF16X3 && K % 8 != 0)
-    return fail(FTK_EUNSUPPORTED, "the bf16x3 form needs K (radial nodes) to be a multiple of 8");
+  if (precision != FTK_FP32 && precision != FTK_BF16X3 && precision != FTK_FP16)
+    return fail(FTK_EINVAL, "unknown precision");
+  if (precision != FTK_FP32 && K % 8 != 0)
+    return fail(FTK_EUNSUPPORTED, "the bf16x3 and fp16 forms need K (radial nodes) to be a multiple of 8");
   if (!ftkplan::fft_supported(Q) || Q % 64 != 0 || Q > 384)
     return fail(FTK_EUNSUPPORTED, "Q must be a multiple of 64 of the form 2^a 3^b, at most 384");
   if (ftkplan::fft_size(2 * n) > 4096) return fail(FTK_EUNSUPPORTED, "image too large for the transform");
@@ -279,15 +321,18 @@ int step3_waves(const ftk_plan* p) {
   // each wave owns 16 shifts; more than 8 waves only below Qa = 320, where
   // the staging and FFT buffers of 16 waves still fit LDS
   int maxw = std::max(1, std::min(p->tune.step3_waves, (p->Qa / 64 > 4) ? 8 : 16));
-  const bool split = p->precision == FTK_BF16X3;
-  auto lds = [&](int w) { return split ? step3_bf16_lds_bytes(p->Qa, w) : step3_lds_bytes(p->Qa, w); };
+  const int prec = prec_code(p);
+  auto lds = [&](int w) {
+    return prec == 1 ? step3_bf16_lds_bytes(p->Qa, w)
+                     : (prec == 2 ? step3_fp16_lds_bytes(p->Qa, w) : step3_lds_bytes(p->Qa, w));
+  };
   while (maxw > 1 && lds(maxw) > kLdsLimit) --maxw;
   const int nblk = (units + maxw - 1) / maxw;
   return (units + nblk - 1) / nblk;
 }
 
 int step1_zblk(const ftk_plan* p) {
-  const int prec = p->precision == FTK_BF16X3 ? 1 : 0;
+  const int prec = prec_code(p);
   int z = p->tune.step1_zblk;
   if (p->H_pad % z != 0 || step1_v2_lds_bytes(p->M, z, prec) > kLdsLimit) z = 64;
   return z;
@@ -308,12 +353,13 @@ Needs plan_needs(const ftk_plan* p, int nA, int nB, bool from_pixels) {
     d.coef_b = cb * nB;
   }
   if (nA > 0 && nB > 0) {
-    const size_t per_pair = static_cast<size_t>(p->Qa / 2) * 2 * p->H_pad * sizeof(float);
+    const size_t per_pair = static_cast<size_t>(p->Qa / 2) * 2 * p->H_pad * (prec_code(p) == 2 ? 2 : 4);
     const size_t budget = static_cast<size_t>(p->tune.stage_mib) << 20;
     d.chunk_images = static_cast<int>(std::min<size_t>(nA, std::max<size_t>(1, budget / (per_pair * nB))));
     d.stage = static_cast<size_t>(d.chunk_images) * nB * per_pair;
     d.keys = static_cast<size_t>(nA) * nB * sizeof(unsigned long long);
-    d.tmpl = tmpl_prep_bytes(nB, p->M, p->Qa, p->precision == FTK_BF16X3 ? 1 : 0);
+    d.tmpl = tmpl_prep_bytes(nB, p->M, p->Qa, prec_code(p));
+    d.scales = prec_code(p) == 2 ? 64 : 0;
   }
   return d;
 }
@@ -321,13 +367,13 @@ Needs plan_needs(const ftk_plan* p, int nA, int nB, bool from_pixels) {
 Needs plan_needs_lists(const ftk_plan* p, int nA, int K) {
   Needs d;
   if (nA <= 0 || K <= 0) return d;
-  const size_t per_pair = static_cast<size_t>(p->Qa / 2) * 2 * p->H_pad * sizeof(float);
+  const size_t per_pair = static_cast<size_t>(p->Qa / 2) * 2 * p->H_pad * (prec_code(p) == 2 ? 2 : 4);
   const size_t budget = static_cast<size_t>(p->tune.stage_mib) << 20;
   d.chunk_images = static_cast<int>(std::min<size_t>(nA, std::max<size_t>(1, budget / (per_pair * K))));
   d.stage = static_cast<size_t>(d.chunk_images) * K * per_pair;
   d.keys = static_cast<size_t>(nA) * K * sizeof(unsigned long long);
-  d.tmpl = tmpl_prep_tile_bytes(static_cast<size_t>(d.chunk_images) * ((K + 15) / 16), p->M, p->Qa,
-                                p->precision == FTK_BF16X3 ? 1 : 0);
+  d.tmpl = tmpl_prep_tile_bytes(static_cast<size_t>(d.chunk_images) * ((K + 15) / 16), p->M, p->Qa, prec_code(p));
+  d.scales = prec_code(p) == 2 ? 64 : 0;
   return d;
 }
 
@@ -497,6 +543,34 @@ int ftk_set_shifts(ftk_plan* p, const double* shifts_px, int N) {
     if ((e = upload(p->yt_hi, hi)) != hipSuccess) return hip_fail(e, "ftk_set_shifts: upload");
     if ((e = upload(p->yt_lo, lo)) != hipSuccess) return hip_fail(e, "ftk_set_shifts: upload");
   }
+  if (p->precision == FTK_FP16) {
+    // fp16 panel in MFMA lane order (as the split form's hi part), column
+    // zeta multiplied by sg_zeta and the whole panel divided by the power of
+    // two s_y at or above its largest entry
+    const int nrt = 2 * Np / 32, nks = 2 * Hp / 16;
+    auto entry = [&](int row, int k) {
+      const int d = row >> 1, z = k % Hp;
+      if (d >= N || z >= H) return 0.0;
+      const std::complex<double> y = Y[static_cast<size_t>(d) * H + z];
+      const int c = row & 1, cp = k / Hp;
+      return ((c == cp) ? y.real() : (c == 0 ? -y.imag() : y.imag())) * p->zeta_scale[z];
+    };
+    double mx = 0.0;
+    for (int row = 0; row < 2 * N; ++row)
+      for (int k = 0; k < 2 * Hp; ++k) mx = std::max(mx, std::fabs(entry(row, k)));
+    const double sy = pow2_at_or_above(mx);
+    std::vector<uint16_t> h16(static_cast<size_t>(nrt) * nks * 512);
+    for (int rt = 0; rt < nrt; ++rt)
+      for (int ks = 0; ks < nks; ++ks)
+        for (int l = 0; l < 64; ++l)
+          for (int e8 = 0; e8 < 8; ++e8) {
+            const int row = rt * 32 + (l & 31);
+            const int k = ks * 16 + 8 * (l >> 5) + e8;
+            h16[((static_cast<size_t>(rt) * nks + ks) * 64 + l) * 8 + e8] = f16_rne(entry(row, k) / sy);
+          }
+    if ((e = upload(p->yt_hi, h16)) != hipSuccess) return hip_fail(e, "ftk_set_shifts: upload");
+    p->y_scale = static_cast<float>(sy);
+  }
   p->N = N;
   p->N_pad = Np;
   return FTK_OK;
@@ -553,14 +627,14 @@ int align_impl(ftk_plan* p, const void* img_coeffs, int nA, const void* tmpl_coe
   const int QH = p->Qa / 2;
   const int nBe = lists ? K : nB;  // templates per image
   const size_t pairs = static_cast<size_t>(nA) * nBe;
-  const bool split = p->precision == FTK_BF16X3;
-  const int prec = split ? 1 : 0;
+  const int prec = prec_code(p);
   const Needs nd = lists ? plan_needs_lists(p, nA, K) : plan_needs(p, nA, nB, false);
   const int chunkA = nd.chunk_images;
   Workspace& ws = *p->ws;
   if (ws.stage.ensure(nd.stage) != hipSuccess) return fail(FTK_ENOMEM, "ftk_align: staging buffer");
   if (ws.keys.ensure(nd.keys) != hipSuccess) return fail(FTK_ENOMEM, "ftk_align: key buffer");
   if (ws.tmpl.ensure(nd.tmpl) != hipSuccess) return fail(FTK_ENOMEM, "ftk_align: template operand buffer");
+  if (ws.scales.ensure(nd.scales) != hipSuccess) return fail(FTK_ENOMEM, "ftk_align: scale buffer");
   const int zblk = step1_zblk(p);
   if (step1_v2_lds_bytes(p->M, zblk, prec) > kLdsLimit) return fail(FTK_EUNSUPPORTED, "ftk_align: step 1 tiles exceed LDS");
   unsigned long long* keys = ws.keys.as<unsigned long long>();
@@ -569,10 +643,21 @@ int align_impl(ftk_plan* p, const void* img_coeffs, int nA, const void* tmpl_coe
   if ((e = launch_keys_init(keys, pairs, s)) != hipSuccess) return hip_fail(e, "ftk_align: keys init");
   p->timer.end(ev, s, 3);
   const float2* bco = static_cast<const float2*>(tmpl_coeffs);
-  if (!lists) {
-    // template operand of Step 1: embedded (and split) once per call
+  // FP16 form: the per-call data scales, [max|a|, max|b|, 1/s_a, 1/s_b, s_a s_b s_y]
+  float* scales = prec == 2 ? ws.scales.as<float>() : nullptr;
+  if (scales) {
     ev = p->timer.begin(s);
-    if ((e = launch_tmpl_prep(bco, ws.tmpl.ptr, nB, p->M, p->Qa, prec, s)) != hipSuccess)
+    const size_t per = static_cast<size_t>(2) * p->Qa * p->M;
+    if ((e = launch_fp16_scales(static_cast<const float*>(img_coeffs), per * nA, reinterpret_cast<const float*>(bco),
+                                per * nB, p->y_scale, scales, s)) != hipSuccess)
+      return hip_fail(e, "ftk_align: fp16 scales");
+    p->timer.end(ev, s, 4);
+  }
+  if (!lists) {
+    // template operand of Step 1: embedded (and split or scaled) once per call
+    ev = p->timer.begin(s);
+    if ((e = launch_tmpl_prep(bco, ws.tmpl.ptr, nB, p->M, p->Qa, prec, scales ? scales + 2 : nullptr, s)) !=
+        hipSuccess)
       return hip_fail(e, "ftk_align: template operand");
     p->timer.end(ev, s, 4);
   }
@@ -584,6 +669,7 @@ int align_impl(ftk_plan* p, const void* img_coeffs, int nA, const void* tmpl_coe
   a1.b = bco;
   a1.r32 = ws.tmpl.as<float>();
   a1.r16 = ws.tmpl.ptr;
+  a1.dscale = scales ? scales + 2 : nullptr;
   a1.nB = nBe;
   a1.img_tiles = lists ? (K + 15) / 16 : 0;
   a1.tiles_per_q = (nBe + 15) / 16;
@@ -596,6 +682,7 @@ int align_impl(ftk_plan* p, const void* img_coeffs, int nA, const void* tmpl_coe
   a3.yt = p->yt.as<float>();
   a3.yt_hi = p->yt_hi.as<uint16_t>();
   a3.yt_lo = p->yt_lo.as<uint16_t>();
+  a3.xscale = scales ? scales + 4 : nullptr;
   a3.tw_qa = p->tw_qa.as<float2>();
   a3.Qa = p->Qa;
   a3.H_pad = p->H_pad;
@@ -610,7 +697,8 @@ int align_impl(ftk_plan* p, const void* img_coeffs, int nA, const void* tmpl_coe
       // this chunk's own template operand, gathered through the lists
       a1.tiles_per_q = na * a1.img_tiles;
       ev = p->timer.begin(s);
-      if ((e = launch_tmpl_prep_lists(bco, ws.tmpl.ptr, nB, p->M, p->Qa, prec, lists, K, na, A0, s)) != hipSuccess)
+      if ((e = launch_tmpl_prep_lists(bco, ws.tmpl.ptr, nB, p->M, p->Qa, prec, scales ? scales + 2 : nullptr, lists,
+                                      K, na, A0, s)) != hipSuccess)
         return hip_fail(e, "ftk_align_lists: template operand");
       p->timer.end(ev, s, 4);
     }
@@ -629,13 +717,13 @@ int align_impl(ftk_plan* p, const void* img_coeffs, int nA, const void* tmpl_coe
     a3.keys = keys + static_cast<size_t>(A0) * nBe;
     a3.X = X ? X + static_cast<size_t>(A0) * nBe * p->N * p->Qa : nullptr;
     ev = p->timer.begin(s);
-    e = split ? launch_step3_bf16(a3, s) : launch_step3(a3, p->precision, s);
+    e = prec == 1 ? launch_step3_bf16(a3, s) : (prec == 2 ? launch_step3_fp16(a3, s) : launch_step3(a3, p->precision, s));
     if (e != hipSuccess) return hip_fail(e, "ftk_align: step 3");
     p->timer.end(ev, s, 2);
   }
   if (best) {
     ev = p->timer.begin(s);
-    if ((e = launch_keys_to_poses(keys, best, pairs, p->Qa, s)) != hipSuccess)
+    if ((e = launch_keys_to_poses(keys, best, pairs, p->Qa, scales ? scales + 4 : nullptr, s)) != hipSuccess)
       return hip_fail(e, "ftk_align: poses");
     p->timer.end(ev, s, 3);
   }

@@ -43,6 +43,7 @@ void needs_max(Needs& a, const Needs& b) {
   a.stage = std::max(a.stage, b.stage);
   a.keys = std::max(a.keys, b.keys);
   a.tmpl = std::max(a.tmpl, b.tmpl);
+  a.scales = std::max(a.scales, b.scales);
 }
 
 hipError_t ensure_all(Workspace& w, const Needs& d) {
@@ -53,7 +54,8 @@ hipError_t ensure_all(Workspace& w, const Needs& d) {
   if ((e = w.coef_b.ensure(d.coef_b)) != hipSuccess) return e;
   if ((e = w.stage.ensure(d.stage)) != hipSuccess) return e;
   if ((e = w.keys.ensure(d.keys)) != hipSuccess) return e;
-  return w.tmpl.ensure(d.tmpl);
+  if ((e = w.tmpl.ensure(d.tmpl)) != hipSuccess) return e;
+  return w.scales.ensure(d.scales);
 }
 
 // ---- autotuner cache -------------------------------------------------------

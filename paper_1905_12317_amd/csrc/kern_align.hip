@@ -130,7 +130,8 @@ struct PoseOut {
   int32_t rot;
 };
 
-__global__ void keys_to_poses_kernel(const unsigned long long* keys, PoseOut* poses, size_t count, int Qa) {
+__global__ void keys_to_poses_kernel(const unsigned long long* keys, PoseOut* poses, size_t count, int Qa,
+                                     const float* vscale) {
   size_t i = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= count) return;
   const unsigned long long k = keys[i];
@@ -141,7 +142,7 @@ __global__ void keys_to_poses_kernel(const unsigned long long* keys, PoseOut* po
     o.rot = -1;
   } else {
     const uint32_t idx = key_index(k);
-    o.value = key_value(k);
+    o.value = key_value(k) * (vscale ? *vscale : 1.f);
     o.shift = static_cast<int32_t>(idx / Qa);
     o.rot = static_cast<int32_t>(idx % Qa);
   }
@@ -196,9 +197,9 @@ hipError_t launch_keys_init(unsigned long long* keys, size_t count, hipStream_t 
 }
 
 hipError_t launch_keys_to_poses(const unsigned long long* keys, void* poses, size_t count, int Qa,
-                                hipStream_t s) {
+                                const float* vscale, hipStream_t s) {
   if (count == 0) return hipSuccess;
   hipLaunchKernelGGL(keys_to_poses_kernel, dim3((count + 255) / 256), dim3(256), 0, s, keys,
-                     static_cast<PoseOut*>(poses), count, Qa);
+                     static_cast<PoseOut*>(poses), count, Qa, vscale);
   return hipGetLastError();
 }

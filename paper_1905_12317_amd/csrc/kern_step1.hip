@@ -23,6 +23,9 @@ using namespace ftkdev;
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x4 __attribute__((ext_vector_type(4)));
+typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
 
 namespace {
 
@@ -108,6 +111,37 @@ __global__ void tmpl_prep_bf16(const float2* __restrict__ b, __bf16* __restrict_
     bf16x8* o = reinterpret_cast<bf16x8*>(out) + t * 2;
     o[0] = hi;
     o[1] = lo;
+  }
+}
+
+// FP16 form, 32x32x16 MFMA: one K step is 8 m (k' = 16 ks + 8 (l/32) + e),
+// b scaled by 1/s_b.  Layout [q][row tile][ks][lane][8] fp16.
+__global__ void tmpl_prep_fp16(const float2* __restrict__ b, _Float16* __restrict__ out, int nB, int nRT, int M,
+                               int Qa, int NQ, const int* __restrict__ lists, int K, int nRTk, int a0,
+                               const float* __restrict__ dscale) {
+  const float sb = dscale[1];
+  const int nks = M / 8;
+  const size_t total = static_cast<size_t>(NQ) * nRT * nks * 64;
+  for (size_t t = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x; t < total;
+       t += static_cast<size_t>(gridDim.x) * blockDim.x) {
+    const int lane = static_cast<int>(t & 63);
+    size_t u = t >> 6;
+    const int ks = static_cast<int>(u % nks);
+    u /= nks;
+    const int rt = static_cast<int>(u % nRT);
+    const int q = static_cast<int>(u / nRT);
+    const int row = lane & 31;
+    const int B = tile_template(rt, row >> 1, nB, lists, K, nRTk, a0);
+    const int c = row & 1;
+    f16x8 h;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int kp = ks * 16 + 8 * (lane >> 5) + e;
+      float v = 0.f;
+      if (B >= 0) v = embed(b[(static_cast<size_t>(B) * Qa + q) * M + (kp >> 1)], c, kp & 1) * sb;
+      h[e] = static_cast<_Float16>(v);
+    }
+    reinterpret_cast<f16x8*>(out)[t] = h;
   }
 }
 
@@ -404,6 +438,140 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) s
     step1_bf16_tile<RT, CT, false>(p, smem, A, y - CT + 1, zb, part);
 }
 
+// ---- Step 1, FP16 form --------------------------------------------------
+
+// Same work split and Nyquist fold as the other forms, one FP16 product per
+// term.  The image operand is P / (s_a sg_zeta) (the 2 pi w G table of an
+// FP16 plan is stored divided by its per-zeta power of two sg_zeta), the
+// template operand b / s_b, both rounded to fp16; accumulation in FP32.
+// LDS: per zeta row [2 MK fp16] + 4 words pad.  The result is rounded to
+// fp16 and written in Step 3's chunk layout [pair][k' / 64][q][64 fp16]:
+// accumulator rows v (real part) and v + 1 (imaginary part) of one template
+// are traded between adjacent lanes (adjacent zeta), so that the even lane
+// stores the real-part pair and the odd lane the imaginary-part pair, each as
+// one 32-bit word.
+template <int RT, int CT, bool FOLD>
+__device__ __forceinline__ void step1_fp16_tile(const Step1Args& p, float* smem, int A, int q, int z0, int part) {
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int M = p.M, Qa = p.Qa, QH = Qa / 2;
+  constexpr int ZB = 32 * CT;
+  constexpr int NP = FOLD ? 2 : 1;
+  const int MK = NP * M;
+  const int RW = MK + 4;  // words per zeta row
+  const float sa = p.dscale[0];
+  const float2* arow = p.a + static_cast<size_t>(A) * Qa * M;
+  for (int i = tid; i < ZB * (MK / 2); i += 256) {
+    const int z = i / (MK / 2);
+    const int m2 = i - z * (MK / 2);
+    const bool ny = FOLD && 2 * m2 >= M;
+    const int ml = ny ? m2 - M / 2 : m2;
+    int row = (ny ? QH : q) - p.ell[z0 + z];
+    row %= Qa;
+    row += (row < 0) ? Qa : 0;
+    const float4 av = reinterpret_cast<const float4*>(arow + static_cast<size_t>(row) * M)[ml];
+    const float2 cm = reinterpret_cast<const float2*>(p.cz + static_cast<size_t>(z0 + z) * M)[ml];
+    const float c0 = cm.x * sa, c1 = cm.y * sa;
+    float x[4] = {c0 * av.x, c0 * av.y, c1 * av.z, c1 * av.w};
+    if (ny) {  // i (x + i y) = -y + i x
+      const float t0 = x[0], t2 = x[2];
+      x[0] = -x[1];
+      x[1] = t0;
+      x[2] = -x[3];
+      x[3] = t2;
+    }
+    f16x4 h;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) h[e] = static_cast<_Float16>(x[e]);
+    *reinterpret_cast<f16x4*>(smem + z * RW + 2 * m2) = h;
+  }
+  __syncthreads();
+  const int r = lane >> 5;
+  const int c32 = lane & 31;
+  const int nRT = (p.nB + 15) / 16;
+  const int nks = M / 8;
+  const size_t pair_words = static_cast<size_t>(QH) * p.H_pad;
+  const float* Pb = smem + c32 * RW + 4 * r;
+  const int odd = c32 & 1;
+  uint32_t* zw = static_cast<uint32_t*>(p.zs) + static_cast<size_t>(A) * p.nB * pair_words + static_cast<size_t>(q) * 32;
+  const size_t img_off = static_cast<size_t>(A) * p.img_tiles;
+  for (int rt0 = (part * 4 + wave) * RT; rt0 < nRT; rt0 += 4 * RT * p.tparts) {
+    f32x16 acc[RT][CT];
+#pragma unroll
+    for (int i = 0; i < RT; ++i)
+#pragma unroll
+      for (int j = 0; j < CT; ++j) acc[i][j] = zero16();
+#pragma unroll
+    for (int pass = 0; pass < NP; ++pass) {
+      const int qt = pass ? QH : q;
+      const f16x8* rq = reinterpret_cast<const f16x8*>(p.r16) +
+                        (static_cast<size_t>(qt) * p.tiles_per_q + img_off) * nks * 64 + lane;
+      const f16x8* ra[RT];
+#pragma unroll
+      for (int i = 0; i < RT; ++i) ra[i] = rq + static_cast<size_t>(min(rt0 + i, nRT - 1)) * nks * 64;
+      f16x8 nh[RT];
+#pragma unroll
+      for (int i = 0; i < RT; ++i) nh[i] = ra[i][0];
+      const float* Pp = Pb + pass * M;  // the Nyquist half starts at k' = 2M (M words)
+      for (int ks = 0; ks < nks; ++ks) {
+        f16x8 ah[RT];
+#pragma unroll
+        for (int i = 0; i < RT; ++i) ah[i] = nh[i];
+        if (ks + 1 < nks) {
+#pragma unroll
+          for (int i = 0; i < RT; ++i) nh[i] = ra[i][(ks + 1) * 64];
+        }
+#pragma unroll
+        for (int j = 0; j < CT; ++j) {
+          const f16x8 bv = *reinterpret_cast<const f16x8*>(Pp + j * 32 * RW + 8 * ks);
+#pragma unroll
+          for (int i = 0; i < RT; ++i) acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah[i], bv, acc[i][j], 0, 0, 0);
+        }
+      }
+    }
+    // tiles whose 16 templates all exist store without a per-row test
+#pragma unroll
+    for (int i = 0; i < RT; ++i) {
+      const int rt = rt0 + i;
+      if (rt >= nRT) break;
+      const bool full = (rt + 1) * 16 <= p.nB;
+#pragma unroll
+      for (int j = 0; j < CT; ++j) {
+        // k' = c H_pad + z0 + 32 j + (c32 & ~1) for the pair this lane stores
+        const int kp = odd * p.H_pad + z0 + 32 * j + (c32 & ~1);
+        const size_t at = static_cast<size_t>(kp >> 6) * QH * 32 + ((kp & 63) >> 1);
+#pragma unroll
+        for (int v = 0; v < 16; v += 2) {
+          const float xr = acc[i][j][v], xi = acc[i][j][v + 1];
+          // even lane sends its imaginary part, odd lane its real part
+          const float got = __builtin_bit_cast(
+              float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, odd ? xr : xi), 0xB1, 0xF, 0xF, false));
+          f16x2 w;
+          w[0] = static_cast<_Float16>(odd ? got : xr);
+          w[1] = static_cast<_Float16>(odd ? xi : got);
+          const int row = 8 * (v >> 2) + 4 * r + (v & 3);
+          const int B = rt * 16 + (row >> 1);
+          if (full || B < p.nB) zw[static_cast<size_t>(B) * pair_words + at] = __builtin_bit_cast(uint32_t, w);
+        }
+      }
+    }
+  }
+}
+
+template <int RT, int CT>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) step1_fp16_v2(Step1Args p) {
+  extern __shared__ float smem[];
+  int A, y, zp;
+  if (!step1_block(blockIdx.x, p, CT, A, y, zp)) return;
+  const int zb = (zp / p.tparts) * (32 * CT);
+  const int part = zp % p.tparts;
+  if (y < CT)
+    step1_fp16_tile<RT, 1, true>(p, smem, A, 0, zb + 32 * y, part);
+  else
+    step1_fp16_tile<RT, CT, false>(p, smem, A, y - CT + 1, zb, part);
+}
+
 template <class K>
 hipError_t set_lds(K kern, size_t lds) {
   return hipFuncSetAttribute(reinterpret_cast<const void*>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -415,6 +583,7 @@ hipError_t set_lds(K kern, size_t lds) {
 size_t tmpl_prep_tile_bytes(size_t tiles, int M, int Qa, int precision) {
   const size_t NQ = Qa / 2 + 1;
   if (precision == 0) return NQ * tiles * M * 64 * sizeof(float);
+  if (precision == 2) return NQ * tiles * (M / 8) * 64 * 16;
   return NQ * tiles * (M / 8) * 64 * 32;
 }
 
@@ -422,13 +591,15 @@ size_t tmpl_prep_bytes(int nB, int M, int Qa, int precision) {
   return tmpl_prep_tile_bytes((nB + 15) / 16, M, Qa, precision);
 }
 
-hipError_t launch_tmpl_prep(const float2* b, void* out, int nB, int M, int Qa, int precision, hipStream_t s) {
-  return launch_tmpl_prep_lists(b, out, nB, M, Qa, precision, nullptr, 0, 0, 0, s);
+hipError_t launch_tmpl_prep(const float2* b, void* out, int nB, int M, int Qa, int precision, const float* dscale,
+                            hipStream_t s) {
+  return launch_tmpl_prep_lists(b, out, nB, M, Qa, precision, dscale, nullptr, 0, 0, 0, s);
 }
 
-hipError_t launch_tmpl_prep_lists(const float2* b, void* out, int nB, int M, int Qa, int precision, const int* lists,
-                                  int K, int na, int a0, hipStream_t s) {
+hipError_t launch_tmpl_prep_lists(const float2* b, void* out, int nB, int M, int Qa, int precision,
+                                  const float* dscale, const int* lists, int K, int na, int a0, hipStream_t s) {
   if (nB <= 0 || (lists && (K <= 0 || na <= 0))) return hipSuccess;
+  if (precision == 2 && !dscale) return hipErrorInvalidValue;
   const int nRTk = lists ? (K + 15) / 16 : 0;
   const int nRT = lists ? na * nRTk : (nB + 15) / 16;
   const int NQ = Qa / 2 + 1;
@@ -437,6 +608,9 @@ hipError_t launch_tmpl_prep_lists(const float2* b, void* out, int nB, int M, int
   if (precision == 0)
     hipLaunchKernelGGL(tmpl_prep_fp32, dim3(blocks), dim3(256), 0, s, b, static_cast<float*>(out), nB, nRT, M, Qa,
                        NQ, lists, K, nRTk, a0);
+  else if (precision == 2)
+    hipLaunchKernelGGL(tmpl_prep_fp16, dim3(blocks), dim3(256), 0, s, b, static_cast<_Float16*>(out), nB, nRT, M,
+                       Qa, NQ, lists, K, nRTk, a0, dscale);
   else
     hipLaunchKernelGGL(tmpl_prep_bf16, dim3(blocks), dim3(256), 0, s, b, static_cast<__bf16*>(out), nB, nRT, M,
                        Qa, NQ, lists, K, nRTk, a0);
@@ -450,6 +624,9 @@ size_t step1_v2_lds_bytes(int M, int zb, int precision) {
     const int PS = (zb % 64 == 0) ? zb + 32 : zb;
     plain = sizeof(float) * 2 * M * PS;
     fold = sizeof(float) * 4 * M * 32;
+  } else if (precision == 2) {
+    plain = sizeof(float) * zb * (M + 4);
+    fold = sizeof(float) * 32 * (2 * M + 4);
   } else {
     plain = sizeof(float) * zb * (2 * M + 4);
     fold = sizeof(float) * 32 * (4 * M + 4);
@@ -473,6 +650,21 @@ hipError_t launch_step1_v2(const Step1Args& a, int precision, hipStream_t s) {
 #define FTK_S1(ct)                                              \
   case ct: {                                                     \
     auto k = step1_fp32_v2<2, ct>;                              \
+    if ((e = set_lds(k, lds)) != hipSuccess) return e;          \
+    hipLaunchKernelGGL(k, grid, dim3(256), lds, s, a);          \
+    break;                                                       \
+  }
+    switch (CT) {
+      FTK_S1(2)
+      FTK_S1(4)
+      default: return hipErrorInvalidValue;
+    }
+#undef FTK_S1
+  } else if (precision == 2) {
+    if (!a.dscale) return hipErrorInvalidValue;
+#define FTK_S1(ct)                                              \
+  case ct: {                                                     \
+    auto k = step1_fp16_v2<2, ct>;                              \
     if ((e = set_lds(k, lds)) != hipSuccess) return e;          \
     hipLaunchKernelGGL(k, grid, dim3(256), lds, s, a);          \
     break;                                                       \

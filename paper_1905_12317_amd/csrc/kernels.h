@@ -29,7 +29,8 @@ struct Step1Args {
   const int* ell;        // [H_pad]: l_zeta, 0 on padding
   void* zs;              // Zhat staging, layout by form (below)
   const float* r32;      // embedded template operand, FP32 lane order (tmpl_prep)
-  const void* r16;       // embedded template operand, bf16 hi/lo lane order (tmpl_prep)
+  const void* r16;       // embedded template operand, bf16 hi/lo or fp16 lane order (tmpl_prep)
+  const float* dscale;   // FP16 form: device [1/s_a, 1/s_b] (power-of-two data scales); else null
   int nA, nB, M, Qa, H_pad, L;
   int zblk;              // zeta per workgroup (64 or 128)
   int tparts;            // template row tiles split over this many workgroups
@@ -44,11 +45,13 @@ struct Step1Args {
 // Zhat staging written by Step 1 and read by Step 3: Qa/2 rows of q per pair,
 // row 0 holding Zhat(0) + i Zhat(Qa/2) (the Nyquist mode folded in), and
 // K index k' = c H_pad + zeta (c = 0 real, 1 imaginary part).  4 Qa H_pad
-// bytes per pair in both forms:
+// bytes per pair in the FP32 and split forms, half that in the FP16 form:
 //   FP32:       [pair][q][k'] float
 //   split-bf16: [pair][k' / 32][q][32 bf16 hi of k' % 32][32 bf16 lo]
 //               (one 128-byte row per q and chunk of 32 k': Step 3 copies
 //               whole chunks into LDS without converting them)
+//   FP16:       [pair][k' / 64][q][64 fp16 of k' % 64] (the same 128-byte
+//               rows, 64 k' each), scaled by 1 / (s_a s_b sg_zeta)
 // Step 3 + rotation FFT + argmax.
 struct Step3Args {
   const void* zs;        // Zhat staging (above)
@@ -56,6 +59,7 @@ struct Step3Args {
   const uint16_t* yt_hi; // split-precision copies (bf16), same layout
   const uint16_t* yt_lo;
   float* X;              // [pairs][N][Qa] or nullptr
+  const float* xscale;   // device scalar multiplying the X outputs (FP16 form), or null
   unsigned long long* keys;  // [pairs]
   const float2* tw_qa;   // [Qa]
   int pairs, Qa, H_pad, N, N_pad;
@@ -70,10 +74,12 @@ hipError_t launch_step3(const Step3Args& args, int precision, hipStream_t stream
 // covers q = 0 .. Qa/2 (Qa/2 + 1 slices).
 size_t tmpl_prep_bytes(int nB, int M, int Qa, int precision);
 size_t tmpl_prep_tile_bytes(size_t tiles, int M, int Qa, int precision);
-hipError_t launch_tmpl_prep(const float2* b, void* out, int nB, int M, int Qa, int precision, hipStream_t stream);
+// precision: 0 FP32, 1 split-bf16, 2 FP16 (then dscale[1] = 1/s_b scales b)
+hipError_t launch_tmpl_prep(const float2* b, void* out, int nB, int M, int Qa, int precision, const float* dscale,
+                            hipStream_t stream);
 // per-image template lists [.][K] for images a0 .. a0 + na - 1 of the call
-hipError_t launch_tmpl_prep_lists(const float2* b, void* out, int nB, int M, int Qa, int precision, const int* lists,
-                                  int K, int na, int a0, hipStream_t stream);
+hipError_t launch_tmpl_prep_lists(const float2* b, void* out, int nB, int M, int Qa, int precision,
+                                  const float* dscale, const int* lists, int K, int na, int a0, hipStream_t stream);
 size_t step1_v2_lds_bytes(int M, int zb, int precision);
 hipError_t launch_step1_v2(const Step1Args& args, int precision, hipStream_t stream);
 
@@ -81,6 +87,17 @@ hipError_t launch_step1_v2(const Step1Args& args, int precision, hipStream_t str
 size_t step3_bf16_lds_bytes(int Qa, int nwaves);
 hipError_t launch_step3_bf16(const Step3Args& args, hipStream_t stream);
 
+// FP16 form (kern_align_fp16.hip): Step 3 with one FP16 product per term
+// (same LDS footprint as the split form), and the per-call data scales:
+// scales[0..1] = max |a|, max |b| (as float bits, reduced here), then
+// scales[2] = 1/s_a, scales[3] = 1/s_b, scales[4] = s_a s_b s_y, with s the
+// power of two at or above each maximum (1 for an all-zero input).
+size_t step3_fp16_lds_bytes(int Qa, int nwaves);
+hipError_t launch_step3_fp16(const Step3Args& args, hipStream_t stream);
+hipError_t launch_fp16_scales(const float* a, size_t a_count, const float* b, size_t b_count, float s_y,
+                              float* scales, hipStream_t stream);
+
 hipError_t launch_keys_init(unsigned long long* keys, size_t count, hipStream_t stream);
+// vscale: device scalar multiplying the pose values (FP16 form), or null
 hipError_t launch_keys_to_poses(const unsigned long long* keys, void* poses, size_t count, int Qa,
-                                hipStream_t stream);
+                                const float* vscale, hipStream_t stream);

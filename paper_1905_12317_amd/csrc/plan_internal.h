@@ -67,18 +67,20 @@ struct HostTables {
 // Scratch of the transform and the alignment.  A plan owns one; a batch
 // lends a shared one to each of its plans while it runs them.
 struct Workspace {
-  DevBuf tr_h, tr_g, coef_a, coef_b, stage, keys, tmpl;
+  DevBuf tr_h, tr_g, coef_a, coef_b, stage, keys, tmpl, scales;
   size_t bytes() const {
-    return tr_h.bytes + tr_g.bytes + coef_a.bytes + coef_b.bytes + stage.bytes + keys.bytes + tmpl.bytes;
+    return tr_h.bytes + tr_g.bytes + coef_a.bytes + coef_b.bytes + stage.bytes + keys.bytes + tmpl.bytes +
+           scales.bytes;
   }
   void release() {
-    for (DevBuf* b : {&tr_h, &tr_g, &coef_a, &coef_b, &stage, &keys, &tmpl}) b->release();
+    for (DevBuf* b : {&tr_h, &tr_g, &coef_a, &coef_b, &stage, &keys, &tmpl, &scales}) b->release();
   }
 };
 
 // Workspace sizes a call needs (the same formulas size and use the buffers).
 struct Needs {
   size_t tr_h = 0, tr_g = 0, coef_a = 0, coef_b = 0, stage = 0, keys = 0, tmpl = 0;
+  size_t scales = 0;        // FP16 form: the per-call data scales
   int chunk_images = 0;     // images per Step 1 / Step 3 chunk
   int transform_chunk = 0;  // images per transform launch
 };
@@ -91,6 +93,10 @@ struct ftk_plan {
   double W = 0, eps = 0, kmax = 0;
   ftkint::HostTables t;
   int H_pad = 0, N = 0, N_pad = 0;
+  // FP16 form: per-zeta powers of two sg_zeta dividing the 2 pi w G table and
+  // multiplying the shift panel, and the power of two s_y of that panel
+  std::vector<float> zeta_scale;
+  float y_scale = 1.f;
   ftkplan::SpreadKernel sk;
   ftk_tuning_t tune{};
   // plan-owned device tables
@@ -113,6 +119,10 @@ ftk_tuning_t default_tuning();
 Needs plan_needs(const ftk_plan* p, int nA, int nB, bool from_pixels);
 // alignment of nA images against K listed templates each
 Needs plan_needs_lists(const ftk_plan* p, int nA, int K);
+// kernel precision code of a plan: 0 FP32, 1 split-bf16, 2 FP16
+inline int prec_code(const ftk_plan* p) {
+  return p->precision == FTK_BF16X3 ? 1 : (p->precision == FTK_FP16 ? 2 : 0);
+}
 // Step 3 waves per workgroup and Step 1 zeta block actually used by a plan.
 int step3_waves(const ftk_plan* p);
 int step1_zblk(const ftk_plan* p);

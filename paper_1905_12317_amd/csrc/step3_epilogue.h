@@ -1,5 +1,5 @@
 // Rotation FFT + argmax of Step 3 (Step 2 of eq. fbk3, eq. 1dfft), shared by
-// the FP32 and split-bf16 forms, working mostly in registers.
+// the FP32, split-bf16 and FP16 forms, working mostly in registers.
 //
 // Input: the wave's MFMA accumulators acc[ct][v] of the shift contraction:
 // lane l (h = l / 32, j = l % 32) holds column q = 32 ct + j (mode) for rows
@@ -194,6 +194,9 @@ __device__ __forceinline__ void step3_epilogue_reg(const Step3Args& p, Acc (&acc
   float bv = -__builtin_inff();
   uint32_t bi = 0xffffffffu;
   float* Xp = p.X ? p.X + static_cast<size_t>(pair) * p.N * Qa : nullptr;
+  // scale of the stored X values (the FP16 form computes X / (s_a s_b s_y));
+  // the argmax does not depend on it
+  const float xs = (Xp && p.xscale) ? *p.xscale : 1.f;
   const int Q = j >> 2;  // the sequence (shift u = Q) this lane's quad transforms
   const int a = j & 3;
   const int a0 = a & 1, a1 = a >> 1;
@@ -277,7 +280,8 @@ __device__ __forceinline__ void step3_epilogue_reg(const Step3Args& p, Acc (&acc
       if (Xp && valid) {
         float2* xr = reinterpret_cast<float2*>(Xp + static_cast<size_t>(delta) * Qa);
 #pragma unroll
-        for (int sp = 0; sp < 8; ++sp) xr[s1 + CTQ * (sp + 8 * (a1 + 2 * a0))] = Y[sp];
+        for (int sp = 0; sp < 8; ++sp)
+          xr[s1 + CTQ * (sp + 8 * (a1 + 2 * a0))] = make_float2(Y[sp].x * xs, Y[sp].y * xs);
       }
       __builtin_amdgcn_sched_barrier(0);
     }

@@ -19,7 +19,8 @@ LIB_PATH = os.path.join(_PKG, "libftk.so")
 FTK_OK = 0
 FTK_FP32 = 0
 FTK_BF16X3 = 1
-PRECISIONS = {"fp32": FTK_FP32, "bf16x3": FTK_BF16X3}
+FTK_FP16 = 2
+PRECISIONS = {"fp32": FTK_FP32, "bf16x3": FTK_BF16X3, "fp16": FTK_FP16}
 
 
 class FTKError(RuntimeError):

@@ -169,7 +169,7 @@ def test_features_and_proposal_match_oracle(ftk):
     assert _rel(mass.cpu().numpy(), omass) <= 1e-5
 
 
-@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3", "fp16"])
 def test_list_alignment_equals_full_alignment(ftk, prec):
     n, M, Qa, R = 64, 32, 128, 2.0
     s = synth.make_alignment_set(12, n, 45, 9, 20, R, 0.1)
