@@ -188,7 +188,7 @@ __device__ __forceinline__ void step1_fp32_tile(const Step1Args& p, float* smem,
   constexpr int NP = FOLD ? 2 : 1;
   const int MK = NP * M;
   const float2* arow = p.a + static_cast<size_t>(A) * Qa * M;
-  for (int i = tid; i < ZB * MK; i += 256) {
+  for (int i = tid; i < ZB * MK; i += static_cast<int>(blockDim.x)) {
     const int z = i / MK;
     const int mm = i - z * MK;
     const bool ny = FOLD && mm >= M;
@@ -210,7 +210,8 @@ __device__ __forceinline__ void step1_fp32_tile(const Step1Args& p, float* smem,
   const float* Pb = smem + r * PS + c32;
   float* zbase = static_cast<float*>(p.zs) + static_cast<size_t>(A) * p.nB * QH * twoH + static_cast<size_t>(q) * twoH;
   const size_t img_off = static_cast<size_t>(A) * p.img_tiles;
-  for (int rt0 = (part * 4 + wave) * RT; rt0 < nRT; rt0 += 4 * RT * p.tparts) {
+  const int nw = static_cast<int>(blockDim.x) >> 6;
+  for (int rt0 = (part * nw + wave) * RT; rt0 < nRT; rt0 += nw * RT * p.tparts) {
     f32x16 acc[RT][CT];
 #pragma unroll
     for (int i = 0; i < RT; ++i)
@@ -305,7 +306,7 @@ __device__ __forceinline__ void step1_bf16_tile(const Step1Args& p, float* smem,
   const float2* arow = p.a + static_cast<size_t>(A) * Qa * M;
   // two m per item: (Pr, Pi) of m and m+1 -> 4 consecutive k' (M is even,
   // so both lie in the same half)
-  for (int i = tid; i < ZB * (MK / 2); i += 256) {
+  for (int i = tid; i < ZB * (MK / 2); i += static_cast<int>(blockDim.x)) {
     const int z = i / (MK / 2);
     const int m2 = i - z * (MK / 2);
     const bool ny = FOLD && 2 * m2 >= M;
@@ -347,7 +348,8 @@ __device__ __forceinline__ void step1_bf16_tile(const Step1Args& p, float* smem,
   uint32_t* zw = static_cast<uint32_t*>(p.zs) + static_cast<size_t>(A) * p.nB * pair_words +
                  static_cast<size_t>(q) * 32 + wsel;
   const size_t img_off = static_cast<size_t>(A) * p.img_tiles;
-  for (int rt0 = (part * 4 + wave) * RT; rt0 < nRT; rt0 += 4 * RT * p.tparts) {
+  const int nw = static_cast<int>(blockDim.x) >> 6;
+  for (int rt0 = (part * nw + wave) * RT; rt0 < nRT; rt0 += nw * RT * p.tparts) {
     f32x16 acc[RT][CT];
 #pragma unroll
     for (int i = 0; i < RT; ++i)
@@ -425,8 +427,8 @@ __device__ __forceinline__ void step1_bf16_tile(const Step1Args& p, float* smem,
 // At least 2 waves per SIMD: left free, the compiler keeps the accumulators
 // in AGPRs and copies them all to VGPRs for the split at the end (about 300
 // registers, 1 wave per SIMD).
-template <int RT, int CT>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) step1_bf16_v2(Step1Args p) {
+template <int RT, int CT, int NW>
+__global__ void __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(NW == 8 ? 4 : 2))) step1_bf16_v2(Step1Args p) {
   extern __shared__ float smem[];
   int A, y, zp;
   if (!step1_block(blockIdx.x, p, CT, A, y, zp)) return;
@@ -462,7 +464,7 @@ __device__ __forceinline__ void step1_fp16_tile(const Step1Args& p, float* smem,
   const int RW = MK + 4;  // words per zeta row
   const float sa = p.dscale[0];
   const float2* arow = p.a + static_cast<size_t>(A) * Qa * M;
-  for (int i = tid; i < ZB * (MK / 2); i += 256) {
+  for (int i = tid; i < ZB * (MK / 2); i += static_cast<int>(blockDim.x)) {
     const int z = i / (MK / 2);
     const int m2 = i - z * (MK / 2);
     const bool ny = FOLD && 2 * m2 >= M;
@@ -496,7 +498,8 @@ __device__ __forceinline__ void step1_fp16_tile(const Step1Args& p, float* smem,
   const int odd = c32 & 1;
   uint32_t* zw = static_cast<uint32_t*>(p.zs) + static_cast<size_t>(A) * p.nB * pair_words + static_cast<size_t>(q) * 32;
   const size_t img_off = static_cast<size_t>(A) * p.img_tiles;
-  for (int rt0 = (part * 4 + wave) * RT; rt0 < nRT; rt0 += 4 * RT * p.tparts) {
+  const int nw = static_cast<int>(blockDim.x) >> 6;
+  for (int rt0 = (part * nw + wave) * RT; rt0 < nRT; rt0 += nw * RT * p.tparts) {
     f32x16 acc[RT][CT];
 #pragma unroll
     for (int i = 0; i < RT; ++i)
@@ -634,6 +637,9 @@ size_t step1_v2_lds_bytes(int M, int zb, int precision) {
   return plain > fold ? plain : fold;
 }
 
+// split form: template row tiles per wave and waves per workgroup
+constexpr int kBf16RT = 2, kBf16NW = 4;
+
 hipError_t launch_step1_v2(const Step1Args& a, int precision, hipStream_t s) {
   if (a.nA <= 0 || a.nB <= 0) return hipSuccess;
   const int CT = a.zblk / 32;
@@ -676,12 +682,12 @@ hipError_t launch_step1_v2(const Step1Args& a, int precision, hipStream_t s) {
     }
 #undef FTK_S1
   } else {
-#define FTK_S1(ct)                                              \
-  case ct: {                                                     \
-    auto k = step1_bf16_v2<2, ct>;                              \
-    if ((e = set_lds(k, lds)) != hipSuccess) return e;          \
-    hipLaunchKernelGGL(k, grid, dim3(256), lds, s, a);          \
-    break;                                                       \
+#define FTK_S1(ct)                                                        \
+  case ct: {                                                               \
+    auto k = step1_bf16_v2<kBf16RT, ct, kBf16NW>;                         \
+    if ((e = set_lds(k, lds)) != hipSuccess) return e;                    \
+    hipLaunchKernelGGL(k, grid, dim3(64 * kBf16NW), lds, s, a);           \
+    break;                                                                 \
   }
     switch (CT) {
       FTK_S1(2)
