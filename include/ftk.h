@@ -206,7 +206,7 @@ int ftk_plan_stage_times(ftk_plan* plan, double* ms, int64_t* launches, int nsta
  *   step1_wgs   : Step 1 splits its template sweep until the grid holds
  *                 about this many workgroups; 64..65536 (default 4096)
  *   stage_mib   : the Step 1 -> Step 3 staging buffer, MiB; images are
- *                 processed in chunks that fit; 16..65536 (default 2048) */
+ *                 processed in chunks that fit; 16..65536 (default 8192) */
 typedef struct ftk_tuning_t {
   int step3_waves;
   int step1_zblk;

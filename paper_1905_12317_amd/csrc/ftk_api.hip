@@ -312,7 +312,7 @@ ftk_tuning_t default_tuning() {
   t.step3_waves = static_cast<int>(std::min<size_t>(16, env_mib("FTK_STEP3_WAVES", 16)));
   t.step1_zblk = env_mib("FTK_STEP1_ZBLK", 128) == 64 ? 64 : 128;
   t.step1_wgs = static_cast<int>(std::min<size_t>(65536, std::max<size_t>(64, env_mib("FTK_STEP1_WGS", 4096))));
-  t.stage_mib = static_cast<int>(std::min<size_t>(65536, std::max<size_t>(16, env_mib("FTK_STAGE_MB", 2048))));
+  t.stage_mib = static_cast<int>(std::min<size_t>(65536, std::max<size_t>(16, env_mib("FTK_STAGE_MB", 8192))));
   return t;
 }
 
