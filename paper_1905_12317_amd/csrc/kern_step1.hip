@@ -26,6 +26,8 @@ typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 typedef _Float16 f16x4 __attribute__((ext_vector_type(4)));
 typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
 
 namespace {
 
@@ -145,6 +147,61 @@ __global__ void tmpl_prep_fp16(const float2* __restrict__ b, _Float16* __restric
   }
 }
 
+// Fill of the image operand in LDS, U items per thread at a time: the index
+// loads (ell) of all U items, then their data loads, then the LDS stores, so
+// a batch costs two memory round trips instead of two per item.  Items past
+// `total` load a valid item (the last) and store nothing.
+template <int U, class FI, class FD, class FS>
+__device__ __forceinline__ void batched_fill(int total, FI load_index, FD load_data, FS store) {
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  for (int i0 = tid; i0 < total; i0 += U * nthr) {
+    decltype(load_index(0)) ix[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) ix[u] = load_index(min(i0 + u * nthr, total - 1));
+    decltype(load_data(ix[0], 0)) dv[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) dv[u] = load_data(ix[u], min(i0 + u * nthr, total - 1));
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (i0 + u * nthr < total) store(dv[u], i0 + u * nthr);
+  }
+}
+
+// Items of two m (split and FP16 forms): (Pr, Pi) of m and m + 1, the 4
+// consecutive k' of one zeta row (M is even, so both m lie in the same half).
+struct FillData {
+  float4 av;  // a(k_m; row), a(k_{m+1}; row)
+  float2 cm;  // the 2 pi w G entries of m, m + 1
+};
+__device__ __forceinline__ FillData fill_load(const Step1Args& p, const float2* arow, int ell, int i, int MK, int M,
+                                              int q, int QH, int Qa, int z0, bool fold) {
+  const int z = i / (MK / 2);
+  const int m2 = i - z * (MK / 2);
+  const bool ny = fold && 2 * m2 >= M;
+  const int ml = ny ? m2 - M / 2 : m2;
+  int row = (ny ? QH : q) - ell;
+  row %= Qa;
+  row += (row < 0) ? Qa : 0;
+  return FillData{reinterpret_cast<const float4*>(arow + static_cast<size_t>(row) * M)[ml],
+                  reinterpret_cast<const float2*>(p.cz + static_cast<size_t>(z0 + z) * M)[ml]};
+}
+// the 4 values (times scale), multiplied by i in the Nyquist half:
+// i (x + i y) = -y + i x
+__device__ __forceinline__ void fill_value(const FillData& d, bool ny, float scale, float (&x)[4]) {
+  const float c0 = d.cm.x * scale, c1 = d.cm.y * scale;
+  x[0] = c0 * d.av.x;
+  x[1] = c0 * d.av.y;
+  x[2] = c1 * d.av.z;
+  x[3] = c1 * d.av.w;
+  if (ny) {
+    const float t0 = x[0], t2 = x[2];
+    x[0] = -x[1];
+    x[1] = t0;
+    x[2] = -x[3];
+    x[3] = t2;
+  }
+}
+
 // ---- Step 1, FP32 form --------------------------------------------------
 
 // Workgroup b of the 1-D grid.  A group is one (mode slot y, zeta block x
@@ -188,20 +245,30 @@ __device__ __forceinline__ void step1_fp32_tile(const Step1Args& p, float* smem,
   constexpr int NP = FOLD ? 2 : 1;
   const int MK = NP * M;
   const float2* arow = p.a + static_cast<size_t>(A) * Qa * M;
-  for (int i = tid; i < ZB * MK; i += static_cast<int>(blockDim.x)) {
-    const int z = i / MK;
-    const int mm = i - z * MK;
-    const bool ny = FOLD && mm >= M;
-    const int m = ny ? mm - M : mm;
-    int row = (ny ? QH : q) - p.ell[z0 + z];
-    row %= Qa;
-    row += (row < 0) ? Qa : 0;
-    const float2 av = arow[static_cast<size_t>(row) * M + m];
-    const float cm = p.cz[static_cast<size_t>(z0 + z) * M + m];
-    // i (x + i y) = -y + i x for the Nyquist half
-    smem[(2 * mm) * PS + z] = ny ? -cm * av.y : cm * av.x;
-    smem[(2 * mm + 1) * PS + z] = ny ? cm * av.x : cm * av.y;
-  }
+  struct D {
+    float2 av;
+    float cm;
+  };
+  batched_fill<8>(
+      ZB * MK, [&](int i) { return p.ell[z0 + i / MK]; },
+      [&](int ell, int i) {
+        const int z = i / MK;
+        const int mm = i - z * MK;
+        const bool ny = FOLD && mm >= M;
+        const int m = ny ? mm - M : mm;
+        int row = (ny ? QH : q) - ell;
+        row %= Qa;
+        row += (row < 0) ? Qa : 0;
+        return D{arow[static_cast<size_t>(row) * M + m], p.cz[static_cast<size_t>(z0 + z) * M + m]};
+      },
+      [&](const D& d, int i) {
+        const int z = i / MK;
+        const int mm = i - z * MK;
+        const bool ny = FOLD && mm >= M;
+        // i (x + i y) = -y + i x for the Nyquist half
+        smem[(2 * mm) * PS + z] = ny ? -d.cm * d.av.y : d.cm * d.av.x;
+        smem[(2 * mm + 1) * PS + z] = ny ? d.cm * d.av.x : d.cm * d.av.y;
+      });
   __syncthreads();
   const int r = lane >> 5;
   const int c32 = lane & 31;
@@ -297,7 +364,7 @@ template <int RT, int CT, bool FOLD>
 __device__ __forceinline__ void step1_bf16_tile(const Step1Args& p, float* smem, int A, int q, int z0, int part) {
   const int tid = threadIdx.x;
   const int lane = tid & 63;
-  const int wave = tid >> 6;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int M = p.M, Qa = p.Qa, QH = Qa / 2;
   constexpr int ZB = 32 * CT;
   constexpr int NP = FOLD ? 2 : 1;
@@ -306,35 +373,25 @@ __device__ __forceinline__ void step1_bf16_tile(const Step1Args& p, float* smem,
   const float2* arow = p.a + static_cast<size_t>(A) * Qa * M;
   // two m per item: (Pr, Pi) of m and m+1 -> 4 consecutive k' (M is even,
   // so both lie in the same half)
-  for (int i = tid; i < ZB * (MK / 2); i += static_cast<int>(blockDim.x)) {
-    const int z = i / (MK / 2);
-    const int m2 = i - z * (MK / 2);
-    const bool ny = FOLD && 2 * m2 >= M;
-    const int ml = ny ? m2 - M / 2 : m2;
-    int row = (ny ? QH : q) - p.ell[z0 + z];
-    row %= Qa;
-    row += (row < 0) ? Qa : 0;
-    const float4 av = reinterpret_cast<const float4*>(arow + static_cast<size_t>(row) * M)[ml];
-    const float2 cm = reinterpret_cast<const float2*>(p.cz + static_cast<size_t>(z0 + z) * M)[ml];
-    float x[4] = {cm.x * av.x, cm.x * av.y, cm.y * av.z, cm.y * av.w};
-    if (ny) {  // i (x + i y) = -y + i x
-      const float t0 = x[0], t2 = x[2];
-      x[0] = -x[1];
-      x[1] = t0;
-      x[2] = -x[3];
-      x[3] = t2;
-    }
-    bf16x4 hi, lo;
+  batched_fill<8>(
+      ZB * (MK / 2), [&](int i) { return p.ell[z0 + i / (MK / 2)]; },
+      [&](int ell, int i) { return fill_load(p, arow, ell, i, MK, M, q, QH, Qa, z0, FOLD); },
+      [&](const FillData& d, int i) {
+        const int z = i / (MK / 2);
+        const int m2 = i - z * (MK / 2);
+        float x[4];
+        fill_value(d, FOLD && 2 * m2 >= M, 1.f, x);
+        bf16x4 hi, lo;
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const __bf16 h = static_cast<__bf16>(x[e]);
-      hi[e] = h;
-      lo[e] = static_cast<__bf16>(x[e] - static_cast<float>(h));
-    }
-    float* dst = smem + z * RW + 2 * m2;
-    *reinterpret_cast<bf16x4*>(dst) = hi;
-    *reinterpret_cast<bf16x4*>(dst + MK) = lo;
-  }
+        for (int e = 0; e < 4; ++e) {
+          const __bf16 h = static_cast<__bf16>(x[e]);
+          hi[e] = h;
+          lo[e] = static_cast<__bf16>(x[e] - static_cast<float>(h));
+        }
+        float* dst = smem + z * RW + 2 * m2;
+        *reinterpret_cast<bf16x4*>(dst) = hi;
+        *reinterpret_cast<bf16x4*>(dst + MK) = lo;
+      });
   __syncthreads();
   const int r = lane >> 5;
   const int c32 = lane & 31;
@@ -405,19 +462,21 @@ __device__ __forceinline__ void step1_bf16_tile(const Step1Args& p, float* smem,
 #pragma unroll
         for (int v = 0; v < 16; ++v) {
           const float x = acc[i][j][v];
-          const __bf16 h = static_cast<__bf16>(x);
-          const uint32_t hb = bf16_bits(h);
-          const uint32_t lb = bf16_bits(static_cast<__bf16>(x - static_cast<float>(h)));
-          // even lane sends its lo, odd lane its hi; both receive the other's
+          // hi = bf16(x), lo = bf16(x - hi), packed (hi, lo) in one word
+          const float xh = static_cast<float>(static_cast<__bf16>(x));
+          const uint32_t w = __builtin_bit_cast(uint32_t, __builtin_convertvector(f32x2{x, x - xh}, bf16x2));
+          // even lane sends its lo half, odd lane its hi half; the even lane
+          // stores (hi, hi of the odd lane), the odd lane (lo of the even, lo)
           const uint32_t got = static_cast<uint32_t>(
-              __builtin_amdgcn_mov_dpp(static_cast<int>(odd ? hb : lb), 0xB1, 0xF, 0xF, false));
-          const uint32_t word = odd ? (got | (lb << 16)) : (hb | (got << 16));
-          const int row = 8 * (v >> 2) + 4 * r + (v & 3);
-          const int B = rt * 16 + (row >> 1);
-          // k' = c H_pad + z0 + 32 j + c32: chunk (c H_pad + z0) / 32 + j
-          const int chunk = ((row & 1) * p.H_pad + z0) / 32 + j;
+              __builtin_amdgcn_mov_dpp(static_cast<int>(odd ? w : (w >> 16)), 0xB1, 0xF, 0xF, false));
+          const uint32_t word = odd ? ((got & 0xffffu) | (w & 0xffff0000u)) : ((w & 0xffffu) | (got << 16));
+          // accumulator row 8 (v / 4) + 4 r + v % 4: template rt 16 + kv + 2 r,
+          // part c = v % 2; k' = c H_pad + z0 + 32 j + c32 lies in chunk
+          // (c H_pad + z0) / 32 + j
+          const int kv = 4 * (v >> 2) + ((v & 3) >> 1);
+          const int B = rt * 16 + kv + 2 * r;
+          const int chunk = ((v & 1) * p.H_pad + z0) / 32 + j;
           if (full || B < p.nB) zw[static_cast<size_t>(B) * pair_words + static_cast<size_t>(chunk) * QH * 32] = word;
-          if ((v & 3) == 3) __builtin_amdgcn_sched_barrier(0);
         }
       }
     }
@@ -464,30 +523,19 @@ __device__ __forceinline__ void step1_fp16_tile(const Step1Args& p, float* smem,
   const int RW = MK + 4;  // words per zeta row
   const float sa = p.dscale[0];
   const float2* arow = p.a + static_cast<size_t>(A) * Qa * M;
-  for (int i = tid; i < ZB * (MK / 2); i += static_cast<int>(blockDim.x)) {
-    const int z = i / (MK / 2);
-    const int m2 = i - z * (MK / 2);
-    const bool ny = FOLD && 2 * m2 >= M;
-    const int ml = ny ? m2 - M / 2 : m2;
-    int row = (ny ? QH : q) - p.ell[z0 + z];
-    row %= Qa;
-    row += (row < 0) ? Qa : 0;
-    const float4 av = reinterpret_cast<const float4*>(arow + static_cast<size_t>(row) * M)[ml];
-    const float2 cm = reinterpret_cast<const float2*>(p.cz + static_cast<size_t>(z0 + z) * M)[ml];
-    const float c0 = cm.x * sa, c1 = cm.y * sa;
-    float x[4] = {c0 * av.x, c0 * av.y, c1 * av.z, c1 * av.w};
-    if (ny) {  // i (x + i y) = -y + i x
-      const float t0 = x[0], t2 = x[2];
-      x[0] = -x[1];
-      x[1] = t0;
-      x[2] = -x[3];
-      x[3] = t2;
-    }
-    f16x4 h;
+  batched_fill<8>(
+      ZB * (MK / 2), [&](int i) { return p.ell[z0 + i / (MK / 2)]; },
+      [&](int ell, int i) { return fill_load(p, arow, ell, i, MK, M, q, QH, Qa, z0, FOLD); },
+      [&](const FillData& d, int i) {
+        const int z = i / (MK / 2);
+        const int m2 = i - z * (MK / 2);
+        float x[4];
+        fill_value(d, FOLD && 2 * m2 >= M, sa, x);
+        f16x4 h;
 #pragma unroll
-    for (int e = 0; e < 4; ++e) h[e] = static_cast<_Float16>(x[e]);
-    *reinterpret_cast<f16x4*>(smem + z * RW + 2 * m2) = h;
-  }
+        for (int e = 0; e < 4; ++e) h[e] = static_cast<_Float16>(x[e]);
+        *reinterpret_cast<f16x4*>(smem + z * RW + 2 * m2) = h;
+      });
   __syncthreads();
   const int r = lane >> 5;
   const int c32 = lane & 31;
