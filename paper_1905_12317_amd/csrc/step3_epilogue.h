@@ -94,9 +94,14 @@ __device__ __forceinline__ void step3_epilogue_reg(const Step3Args& p, Acc (&acc
   const int h = lane >> 5;
   const int j = lane & 31;
   const int src4 = ((h << 5) | ((32 - j) & 31)) << 2;  // byte address of the lane of column QH - k (j > 0)
-  // twiddles from one table read each: W^{32 ct + j} = W^j exp(-i pi ct / CTQ),
-  // w^{j s1} = (w^j)^{s1}, exp(-2 pi i a s' / 32) = (exp(-2 pi i a / 32))^{s'}
-  const float2 wj = tw[j];
+  // W^{32 ct + j}, and the powers w^{j s1} (w = exp(-2 pi i / QH)), from the
+  // table: the same for every shift of the lane
+  float2 wk[CTQ], wjs[CTQ];
+#pragma unroll
+  for (int ct = 0; ct < CTQ; ++ct) {
+    wk[ct] = tw[32 * ct + j];
+    wjs[ct] = tw[(2 * j * ct) % Qa];
+  }
 
   // ---- (0) real-output packing, in place: acc[ct][(u)] <- Z_u[32 ct + j]
   // u = 2 v4 + d is the shift 4 v4 + 2 h + d of this lane; its (re, im) sit
@@ -123,7 +128,7 @@ __device__ __forceinline__ void step3_epilogue_reg(const Step3Args& p, Acc (&acc
       } else {
         const float2 Qc = cconj(Pp[ct]);
         const float2 s = cadd(P[ct], Qc);
-        const float2 uu = cmul(csub(P[ct], Qc), ct == 0 ? wj : cmul(wj, ep_unit12(12 * ct / CTQ)));
+        const float2 uu = cmul(csub(P[ct], Qc), wk[ct]);
         Z = make_float2(s.x - uu.y, s.y + uu.x);
       }
       acc[ct][vr] = Z.x;
@@ -140,7 +145,6 @@ __device__ __forceinline__ void step3_epilogue_reg(const Step3Args& p, Acc (&acc
     float2 v[CTQ];
 #pragma unroll
     for (int ct = 0; ct < CTQ; ++ct) v[ct] = make_float2(acc[ct][vr], acc[ct][vr + 1]);
-    const float2 w1 = tw[(2 * j) % Qa];
     if constexpr (CTQ == 2) {
       dft2<false>(v);
     } else if constexpr (CTQ == 3) {
@@ -175,14 +179,9 @@ __device__ __forceinline__ void step3_epilogue_reg(const Step3Args& p, Acc (&acc
 #pragma unroll
       for (int s1 = 0; s1 < CTQ; ++s1) v[s1] = y[s1];
     }
-    float2 wp = w1;
 #pragma unroll
     for (int s1 = 0; s1 < CTQ; ++s1) {
-      float2 y = v[s1];
-      if (s1 > 0) {
-        y = cmul(y, wp);
-        wp = cmul(wp, w1);
-      }
+      const float2 y = s1 > 0 ? cmul(v[s1], wjs[s1]) : v[s1];
       acc[s1][vr] = y.x;
       acc[s1][vr + 1] = y.y;
     }
@@ -244,16 +243,10 @@ __device__ __forceinline__ void step3_epilogue_reg(const Step3Args& p, Acc (&acc
         Y[k] = cadd(e[k], t);
         Y[k + 4] = csub(e[k], t);
       }
-      // twiddle exp(-2 pi i a s' / 32), then the radix-4 DFT over the quad
-      {
-        const float2 wa = tw[a * (Qa / 32)];
-        float2 wq = wa;
+      // twiddle exp(-2 pi i a s' / 32) (from the table), then the radix-4
+      // DFT over the quad
 #pragma unroll
-        for (int sp = 1; sp < 8; ++sp) {
-          Y[sp] = cmul(Y[sp], wq);
-          wq = cmul(wq, wa);
-        }
-      }
+      for (int sp = 1; sp < 8; ++sp) Y[sp] = cmul(Y[sp], tw[a * sp * (Qa / 32)]);
       // butterflies as sign FMAs (x * (+-1) + y is exact: same values as
       // y +- x); lane 3 of the quad also rotates its difference by -i
 #pragma unroll
