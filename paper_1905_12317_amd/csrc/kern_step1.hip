@@ -322,7 +322,7 @@ __device__ __forceinline__ void step1_fp32_tile(const Step1Args& p, float* smem,
           const int row = 8 * (v >> 2) + 4 * r + (v & 3);
           const int B = (rt0 + i) * 16 + (row >> 1);
           if (B < p.nB)
-            zbase[static_cast<size_t>(B) * QH * twoH + (row & 1) * p.H_pad + z0 + j * 32 + c32] = acc[i][j][v];
+            __builtin_nontemporal_store(acc[i][j][v], zbase + static_cast<size_t>(B) * QH * twoH + (row & 1) * p.H_pad + z0 + j * 32 + c32);
         }
     }
   }
@@ -476,7 +476,9 @@ __device__ __forceinline__ void step1_bf16_tile(const Step1Args& p, float* smem,
           const int kv = 4 * (v >> 2) + ((v & 3) >> 1);
           const int B = rt * 16 + kv + 2 * r;
           const int chunk = ((v & 1) * p.H_pad + z0) / 32 + j;
-          if (full || B < p.nB) zw[static_cast<size_t>(B) * pair_words + static_cast<size_t>(chunk) * QH * 32] = word;
+          // streaming store: the staging is read back once, by Step 3
+          if (full || B < p.nB)
+            __builtin_nontemporal_store(word, zw + static_cast<size_t>(B) * pair_words + static_cast<size_t>(chunk) * QH * 32);
         }
       }
     }
@@ -603,7 +605,8 @@ __device__ __forceinline__ void step1_fp16_tile(const Step1Args& p, float* smem,
           w[1] = static_cast<_Float16>(odd ? xi : got);
           const int row = 8 * (v >> 2) + 4 * r + (v & 3);
           const int B = rt * 16 + (row >> 1);
-          if (full || B < p.nB) zw[static_cast<size_t>(B) * pair_words + at] = __builtin_bit_cast(uint32_t, w);
+          if (full || B < p.nB)
+            __builtin_nontemporal_store(__builtin_bit_cast(uint32_t, w), zw + static_cast<size_t>(B) * pair_words + at);
         }
       }
     }
