@@ -55,7 +55,7 @@ __global__ void __launch_bounds__(MAXT) step3_fp32(Step3Args p) {
   // Zhat rows are [q][k'] (k' = c H_pad + zeta), row 0 already holding the
   // Nyquist fold; a chunk of 32 k' is stored transposed, [k'][q]
   auto load_v = [&](int kc, int t) {
-    return *reinterpret_cast<const float4*>(zsp + static_cast<size_t>(t >> 3) * nk + kc + (t & 7) * 4);
+    return load_stream(reinterpret_cast<const float4*>(zsp + static_cast<size_t>(t >> 3) * nk + kc + (t & 7) * 4));
   };
   auto put = [&](float* dst, int t, float4 v) {
     const int qq = t >> 3;

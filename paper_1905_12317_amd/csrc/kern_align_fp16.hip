@@ -69,7 +69,7 @@ __global__ void __launch_bounds__(MAXT) step3_fp16(Step3Args p) {
   for (int i = tid; i < 2 * QH; i += nthr) twl[i] = p.tw_qa[i];
   constexpr int MAXF4 = 2;
   const int nf4 = QH * 8;
-  auto fetch = [&](int kc, int t) { return zsp[static_cast<size_t>(kc / KC) * nf4 + t]; };
+  auto fetch = [&](int kc, int t) { return load_stream(zsp + static_cast<size_t>(kc / KC) * nf4 + t); };
   // unit t = 8 q + u of a chunk goes to words 4 u .. 4 u + 3 of LDS row q
   auto put = [&](int buf, int t, float4 v) {
     *reinterpret_cast<float4*>(region + buf * buf_words + (t >> 3) * ROWW + (t & 7) * 4) = v;

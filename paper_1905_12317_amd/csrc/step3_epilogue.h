@@ -79,6 +79,13 @@ __device__ __forceinline__ void step3_block(int b, int nblk, int pairs, int& pai
   }
 }
 
+// streaming 16-byte load of the staging (read once, by one workgroup: not
+// kept in the caches, which then keep Step 1's template operand)
+__device__ __forceinline__ float4 load_stream(const float4* p) {
+  typedef float v4f __attribute__((ext_vector_type(4)));
+  const v4f x = __builtin_nontemporal_load(reinterpret_cast<const v4f*>(p));
+  return make_float4(x[0], x[1], x[2], x[3]);
+}
 // value of lane addr / 4 (ds_bpermute with a precomputed byte address)
 __device__ __forceinline__ float ep_bperm(float v, int addr) {
   return __builtin_bit_cast(float, __builtin_amdgcn_ds_bpermute(addr, __builtin_bit_cast(int, v)));
