@@ -166,7 +166,7 @@ PROPOSAL = dict(name="proposal_n128", n=128, M=64, Qa=256, R=4.0, n_templates=10
 def bench_ragged(args):
     """64 stacks of uneven n, template and image counts and shift radii (the
     ragged workload, image and template counts scaled by RAGGED['scale']),
-    split-bf16 form: one ftk_batch run (two lanes, one hipGraph, autotuned
+    split-bf16 form: one ftk_batch run (--lanes lanes, one hipGraph, autotuned
     launch shapes) against the same stacks aligned one ftk_align at a time."""
     import torch
     import synth
@@ -193,7 +193,7 @@ def bench_ragged(args):
     log(f"ragged inputs in {time.perf_counter() - t0:.1f} s: {len(stacks)} stacks, {pairs} pairs")
     stream = torch.cuda.Stream()
     t0 = time.perf_counter()
-    B = ftk.Batch(stacks, lanes=2, graph=True, autotune=True, stream=stream)
+    B = ftk.Batch(stacks, lanes=args.lanes, graph=True, autotune=True, stream=stream)
     tune_s = time.perf_counter() - t0
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     for _ in range(args.warmup + 1):  # the first run captures the graph
@@ -336,6 +336,7 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--form", default="all", choices=["fp32", "bf16x3", "fp16", "all"])
+    ap.add_argument("--lanes", type=int, default=4, help="ragged workload: concurrent lanes of the batch (1-4)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="only run a plain device-to-device copy of this many MiB (3 times) and exit; "

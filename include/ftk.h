@@ -274,7 +274,7 @@ typedef struct ftk_batch_info_t {
  * plans it names must outlive the batch and keep their addresses).  Every
  * stack needs its plan's shifts set, nA, nB >= 0 and, if nA nB > 0, both
  * pixel pointers and at least one of X, best.  Several stacks may share a
- * plan.  lanes is 1 or 2.  All device memory the batch needs is allocated
+ * plan.  lanes is 1 to 4 (one hardware queue each).  All device memory the batch needs is allocated
  * here.  With FTK_BATCH_AUTOTUNE the call runs kernels on `stream` over
  * the first images and templates of each stack (into batch-owned buffers;
  * the stacks' outputs are not written) and waits for them.

@@ -310,7 +310,7 @@ int ftk_batch_create(ftk_batch** out, const ftk_stack* stacks, int count, int la
   if (!out) return fail(FTK_EINVAL, "ftk_batch_create: out is NULL");
   *out = nullptr;
   if (count < 0 || (count > 0 && !stacks)) return fail(FTK_EINVAL, "ftk_batch_create: invalid stack array");
-  if (lanes < 1 || lanes > 2) return fail(FTK_EINVAL, "ftk_batch_create: lanes must be 1 or 2");
+  if (lanes < 1 || lanes > 4) return fail(FTK_EINVAL, "ftk_batch_create: lanes must be 1 to 4");
   if (flags & ~(FTK_BATCH_GRAPH | FTK_BATCH_AUTOTUNE)) return fail(FTK_EINVAL, "ftk_batch_create: unknown flag");
   for (int i = 0; i < count; ++i) {
     const int rc = check_stack(stacks[i], i);

@@ -169,6 +169,23 @@ def test_batch_graph_two_lanes_autotuned(ftk, stacks, tmp_path):
     B.close()
 
 
+def test_batch_graph_four_lanes(ftk, stacks):
+    """Four lanes (one hardware queue each), one graph: bitwise equal to the
+    single-stack alignments over replays."""
+    refs = [_reference(st) for st in stacks]
+    stream = torch.cuda.Stream()
+    B = ftk.Batch(stacks, lanes=4, graph=True, stream=stream)
+    _say(f"[batch graph 4 lanes] {B.info()}")
+    assert B.info()["lanes"] == 4
+    for rep in range(2):
+        _poison(stacks)
+        B.run(stream)
+        stream.synchronize()
+        _compare(stacks, refs, f"4 lanes, replay {rep}")
+        torch.cuda.synchronize()
+    B.close()
+
+
 def test_batch_eager_one_lane(ftk, stacks):
     refs = [_reference(st) for st in stacks]
     B = ftk.Batch(stacks, lanes=1)
@@ -218,7 +235,7 @@ def test_largest_stack_shape_against_oracle(ftk, prec, tol):
 
 def test_batch_errors(ftk, stacks):
     with pytest.raises(ftk.FTKError) as e:
-        ftk.Batch(stacks[:1], lanes=3)
+        ftk.Batch(stacks[:1], lanes=5)
     assert e.value.code == -1
     P = ftk.Plan(32, 16, 64, 2.0, 1e-3)  # shifts never set
     imgs = torch.zeros((1, 32, 32), device="cuda")
