@@ -416,7 +416,7 @@ __global__ void __launch_bounds__(kThreads) select_below_kernel(const float* __r
     if (lane == 63) wsum[threadIdx.x >> 6] = x;
     __syncthreads();
     int before = base_s;
-    for (int w = 0; w < (threadIdx.x >> 6); ++w) before += wsum[w];
+    for (int w = 0; w < static_cast<int>(threadIdx.x >> 6); ++w) before += wsum[w];
     if (f) list[before + x - 1] = i;
     __syncthreads();
     if (threadIdx.x == 0) base_s += wsum[0] + wsum[1] + wsum[2] + wsum[3];

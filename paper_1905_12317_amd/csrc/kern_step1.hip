@@ -350,10 +350,6 @@ __device__ __forceinline__ f32x16 mfma3(bf16x8 ahi, bf16x8 alo, bf16x8 bhi, bf16
   return c;
 }
 
-__device__ __forceinline__ uint32_t bf16_bits(__bf16 h) {
-  return static_cast<uint32_t>(__builtin_bit_cast(uint16_t, h));
-}
-
 // Same work split and Nyquist fold as the FP32 form.  LDS: image operand per
 // zeta row: [2 MK bf16 hi][2 MK bf16 lo] + 4 words pad (MK = M, or 2M when
 // folding).  The result is split into bf16 hi + lo and written in Step 3's
