@@ -161,6 +161,24 @@ int ftk_align_coeffs(ftk_plan* plan, const void* img_coeffs, int nA, const void*
 int ftk_align(ftk_plan* plan, const float* images, int nA, const float* templates, int nB,
               float* X, ftk_pose* best, void* stream);
 
+/* Two-pass alignment from coefficients: `coarse` (for example an FTK_FP16
+ * plan) aligns every pair into best; then, per image, the k templates with
+ * the largest coarse best values (ties: lower template number) are aligned
+ * again by `fine` (for example an FTK_BF16X3 plan), and those k poses
+ * replace the coarse ones in best.  Each pose is the argmax over shifts and
+ * rotations of the inner products of eq. fbk3, as in ftk_align_coeffs.  The
+ * plans must come from the same ftk_plan_create arguments except the
+ * precision, with the same shifts (FTK_EINVAL if n, K, Q, W, eps, N or H
+ * differ); ftk_transform gives the same coefficients under either plan.
+ *   best      : device ftk_pose [nA][nB], every pair
+ *   best_t    : device int32 [nA]: per image, the template with the largest
+ *               refined value (ties: lower template number), or NULL
+ *   best_pose : device ftk_pose [nA], its pose, or NULL (with best_t)
+ * 1 <= k <= min(nB, 64).  Workspace of the fine plan grows on demand.
+ * Errors: FTK_EINVAL, FTK_ESTATE, FTK_ENOMEM, FTK_EDEVICE. */
+int ftk_align_refined(ftk_plan* coarse, ftk_plan* fine, const void* img_coeffs, int nA, const void* tmpl_coeffs,
+                      int nB, int k, ftk_pose* best, int32_t* best_t, ftk_pose* best_pose, void* stream);
+
 /* FP64 planning tables, host only (no device work, usable without a GPU):
  * the same truncation and factor tables a plan with these arguments uses.
  * Pass NULL for any output not wanted; sizes come from *H_out (call once

@@ -68,12 +68,13 @@ struct HostTables {
 // lends a shared one to each of its plans while it runs them.
 struct Workspace {
   DevBuf tr_h, tr_g, coef_a, coef_b, stage, keys, tmpl, scales;
+  DevBuf refine;  // lists and poses of the two-pass alignment
   size_t bytes() const {
     return tr_h.bytes + tr_g.bytes + coef_a.bytes + coef_b.bytes + stage.bytes + keys.bytes + tmpl.bytes +
-           scales.bytes;
+           scales.bytes + refine.bytes;
   }
   void release() {
-    for (DevBuf* b : {&tr_h, &tr_g, &coef_a, &coef_b, &stage, &keys, &tmpl, &scales}) b->release();
+    for (DevBuf* b : {&tr_h, &tr_g, &coef_a, &coef_b, &stage, &keys, &tmpl, &scales, &refine}) b->release();
   }
 };
 

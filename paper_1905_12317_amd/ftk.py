@@ -77,7 +77,8 @@ EXPORTS = ["ftk_plan_create", "ftk_plan_destroy", "ftk_plan_info", "ftk_set_shif
            # include/ftk_mlp.h
            "ftk_mlp_create", "ftk_mlp_destroy", "ftk_mlp_info", "ftk_mlp_set_layer", "ftk_mlp_get_layer",
            "ftk_mlp_set_input_norm", "ftk_features", "ftk_mlp_forward", "ftk_mlp_gradients", "ftk_mlp_get_grad",
-           "ftk_mlp_train_step", "ftk_propose", "ftk_align_lists", "ftk_best_template", "ftk_align_proposed"]
+           "ftk_mlp_train_step", "ftk_propose", "ftk_align_lists", "ftk_best_template", "ftk_align_proposed",
+           "ftk_align_refined"]
 
 FTK_MLP_FP32 = 0
 FTK_MLP_BF16 = 1
@@ -140,6 +141,7 @@ def lib() -> ctypes.CDLL:
     L.ftk_mlp_train_step.argtypes = [vp, vp, vp, vp, vp, i, f, f, f, f, f, vp, vp]
     L.ftk_propose.argtypes = [vp, vp, i, i, vp, vp, vp, vp]
     L.ftk_align_lists.argtypes = [vp, vp, i, vp, i, vp, i, vp, vp]
+    L.ftk_align_refined.argtypes = [vp, vp, vp, i, vp, i, i, vp, vp, vp, vp]
     L.ftk_best_template.argtypes = [vp, vp, i, i, vp, vp, vp]
     L.ftk_align_proposed.argtypes = [vp, vp, vp, i, vp, i, i, i, i, i, f, vp, vp, vp, ctypes.POINTER(i), vp]
     L.ftk_strerror.restype = ctypes.c_char_p
@@ -487,6 +489,22 @@ def best_template(poses, lists=None, stream=None):
     _check(lib().ftk_best_template(_ptr(poses), _i32(lists, "lists") if lists is not None else None, nA, K, _ptr(bt),
                                    _ptr(bp), _stream(stream)), "ftk_best_template")
     return bt, bp
+
+
+def align_refined(coarse: "Plan", fine: "Plan", a, b, k: int, best=None, stream=None):
+    """Two-pass alignment (ftk_align_refined): poses of every pair [nA][nB][3],
+    then the best template [nA] and its pose [nA][3] after refinement."""
+    import torch
+    _require_cuda(a, torch.complex64, "img_coeffs")
+    _require_cuda(b, torch.complex64, "tmpl_coeffs")
+    nA, nB = a.shape[0], b.shape[0]
+    if best is None:
+        best = torch.empty((nA, nB, 3), dtype=torch.int32, device=a.device)
+    bt = torch.empty(nA, dtype=torch.int32, device=a.device)
+    bp = torch.empty((nA, 3), dtype=torch.int32, device=a.device)
+    _check(lib().ftk_align_refined(coarse._h, fine._h, _ptr(a), nA, _ptr(b), nB, k, _ptr(best), _ptr(bt), _ptr(bp),
+                                   _stream(stream)), "ftk_align_refined")
+    return best, bt, bp
 
 
 def align_lists(plan: "Plan", a, b, lists, stream=None):
