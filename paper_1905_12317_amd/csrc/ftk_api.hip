@@ -228,6 +228,33 @@ double pow2_at_or_above(double x) {
   return std::ldexp(1.0, f == 0.5 ? e - 1 : e);
 }
 
+// The FP16 form's rotation transform tables T_E, T_O (the real map from the
+// packed modes to the Qa rotations, split by the parity of the mode), fp16,
+// in the fragment order the Step 3 kernel reads (kernels.h).
+std::vector<uint16_t> rotation_tables_f16(int Qa) {
+  const int QH = Qa / 2, NT = QH / 16, NS = QH / 32;
+  std::vector<uint16_t> out(static_cast<size_t>(2) * NT * NS * 64 * 8);
+  for (int par = 0; par < 2; ++par)
+    for (int t = 0; t < NT; ++t)
+      for (int s = 0; s < NS; ++s)
+        for (int l = 0; l < 64; ++l)
+          for (int e = 0; e < 8; ++e) {
+            const int r = 16 * t + l % 16;
+            const int kk = 32 * s + 8 * (l / 16) + e;
+            const int m = kk / 2, c = kk % 2, q = 2 * m + par;
+            double v;
+            if (q == 0) {
+              v = c == 0 ? 1.0 : ((r & 1) ? -1.0 : 1.0);
+            } else {
+              // angle 2 pi q r / Qa, reduced exactly in integers first
+              const double th = 2.0 * kPi * static_cast<double>((static_cast<long>(q) * r) % Qa) / Qa;
+              v = 2.0 * (c == 0 ? std::cos(th) : std::sin(th));
+            }
+            out[((static_cast<size_t>(par * NT + t) * NS + s) * 64 + l) * 8 + e] = f16_rne(v);
+          }
+  return out;
+}
+
 int upload_plan_tables(ftk_plan* p) {
   const int M = p->M, H = p->t.H, Hp = p->H_pad;
   std::vector<float> cz(static_cast<size_t>(Hp) * M, 0.f);
@@ -284,6 +311,9 @@ int upload_plan_tables(ftk_plan* p) {
   if ((e = upload(p->deapod, dea)) != hipSuccess) return hip_fail(e, "upload deapod");
   if ((e = upload(p->ptbase, pb)) != hipSuccess) return hip_fail(e, "upload ptbase");
   if ((e = upload(p->ptker, pk)) != hipSuccess) return hip_fail(e, "upload ptker");
+  if (p->precision == FTK_FP16 && rot16_table_bytes(Qa) > 0) {
+    if ((e = upload(p->rot16, rotation_tables_f16(Qa))) != hipSuccess) return hip_fail(e, "upload rot16");
+  }
   return FTK_OK;
 }
 
@@ -324,7 +354,8 @@ int step3_waves(const ftk_plan* p) {
   const int prec = prec_code(p);
   auto lds = [&](int w) {
     return prec == 1 ? step3_bf16_lds_bytes(p->Qa, w)
-                     : (prec == 2 ? step3_fp16_lds_bytes(p->Qa, w) : step3_lds_bytes(p->Qa, w));
+                     : (prec == 2 ? (p->rot16.ptr ? step3_fp16_rot_lds_bytes(p->Qa, w) : step3_fp16_lds_bytes(p->Qa, w))
+                                  : step3_lds_bytes(p->Qa, w));
   };
   while (maxw > 1 && lds(maxw) > kLdsLimit) --maxw;
   const int nblk = (units + maxw - 1) / maxw;
@@ -684,6 +715,7 @@ int align_impl(ftk_plan* p, const void* img_coeffs, int nA, const void* tmpl_coe
   a3.yt_lo = p->yt_lo.as<uint16_t>();
   a3.xscale = scales ? scales + 4 : nullptr;
   a3.tw_qa = p->tw_qa.as<float2>();
+  a3.rot16 = prec == 2 ? p->rot16.ptr : nullptr;
   a3.Qa = p->Qa;
   a3.H_pad = p->H_pad;
   a3.N = p->N;

@@ -28,6 +28,7 @@ using namespace ftkdev;
 
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+typedef float float2_v __attribute__((ext_vector_type(2)));
 
 namespace {
 
@@ -38,23 +39,37 @@ __device__ __forceinline__ f32x16 zero16() {
   return z;
 }
 
+// The K loop of Step 3 for one pair and one shift block: Zhat chunks staged
+// through LDS (two buffers of QH rows at `region`), one FP16 MFMA per term,
+// accumulators acc[ct] of the 32 x 32 tile (rows 2 dl + c of the wave's 16
+// shifts, columns q = 32 ct + lane % 32).  The first chunk is in buffer 0
+// and visible to the block on entry (fp16_first_chunk); ends after the last
+// chunk's MFMAs (no barrier).  With next_pair >= 0 (PREF only), the last
+// chunk's prefetch fetches the first chunk of next_pair instead and stores
+// it into buffer 0 after its MFMAs: visible after the caller's next barrier.
 // PREF: the block has enough threads to hold a whole chunk in MAXF4 float4
 // per thread, and the next chunk is prefetched through registers while the
 // current one is multiplied; otherwise each chunk is fetched after the MFMAs
 // of the previous one.
-template <int CTQ, int MAXT, bool PREF>
-__global__ void __launch_bounds__(MAXT) step3_fp16(Step3Args p) {
-  extern __shared__ float smem[];
+// The first Zhat chunk of `pair` (QH rows of 128 bytes) into LDS buffer 0.
+template <int CTQ>
+__device__ __forceinline__ void fp16_first_chunk(const Step3Args& p, float* region, int pair) {
+  constexpr int QH = 32 * CTQ;
+  const int nf4 = QH * 8;
+  const float4* zsp = static_cast<const float4*>(p.zs) + static_cast<size_t>(pair) * QH * (p.H_pad / 4);
+  for (int t = threadIdx.x; t < nf4; t += blockDim.x)
+    *reinterpret_cast<float4*>(region + (t >> 3) * 36 + (t & 7) * 4) = load_stream(zsp + t);
+}
+
+template <int CTQ, bool PREF>
+__device__ __forceinline__ void fp16_kloop(const Step3Args& p, float* region, int pair, int d0, bool active,
+                                           f32x16 (&acc)[CTQ], int next_pair) {
   constexpr int QH = 32 * CTQ;
   constexpr int KC = 64;     // k' per staged chunk (4 MFMA K steps)
   constexpr int KS = KC / 16;
   constexpr int ROWW = 36;   // LDS words per q row: 32 data, 4 pad
   const int tid = threadIdx.x;
   const int lane = tid & 63;
-  const int wave = tid >> 6;
-  int pair, yb;
-  step3_block(blockIdx.x, p.nblk, p.pairs, pair, yb);
-  const int d0 = (yb * p.nwaves + wave) * 16;
   const int r = lane >> 5;
   const int c32 = lane & 31;
   const int nk = 2 * p.H_pad;
@@ -62,24 +77,19 @@ __global__ void __launch_bounds__(MAXT) step3_fp16(Step3Args p) {
   // this pair's chunks of Zhat: chunk c is QH rows of 128 bytes, 8 float4 per
   // row, contiguous
   const float4* zsp = static_cast<const float4*>(p.zs) + static_cast<size_t>(pair) * QH * (nk / 8);
-  float2* twl = reinterpret_cast<float2*>(smem);
-  float* region = smem + 4 * QH;
   const int buf_words = QH * ROWW;
   const int nthr = blockDim.x;
-  for (int i = tid; i < 2 * QH; i += nthr) twl[i] = p.tw_qa[i];
   constexpr int MAXF4 = 2;
   const int nf4 = QH * 8;
   auto fetch = [&](int kc, int t) { return load_stream(zsp + static_cast<size_t>(kc / KC) * nf4 + t); };
+  const float4* znext =
+      static_cast<const float4*>(p.zs) + static_cast<size_t>(next_pair < 0 ? pair : next_pair) * QH * (nk / 8);
   // unit t = 8 q + u of a chunk goes to words 4 u .. 4 u + 3 of LDS row q
   auto put = [&](int buf, int t, float4 v) {
     *reinterpret_cast<float4*>(region + buf * buf_words + (t >> 3) * ROWW + (t & 7) * 4) = v;
   };
-  for (int t = tid; t < nf4; t += nthr) put(0, t, fetch(0, t));
-  __syncthreads();
-  f32x16 acc[CTQ];
 #pragma unroll
   for (int ct = 0; ct < CTQ; ++ct) acc[ct] = zero16();
-  const bool active = d0 < p.N;
   // shift panel in MFMA lane order: [row tile][K step][lane][8] fp16
   const size_t tile = static_cast<size_t>(min(d0, p.N_pad - 16) / 16) * nks;
   const f16x8* yp = reinterpret_cast<const f16x8*>(p.yt_hi) + tile * 64 + lane;
@@ -100,9 +110,14 @@ __global__ void __launch_bounds__(MAXT) step3_fp16(Step3Args p) {
     const bool more = kc + KC < nk;
     float4 nreg[MAXF4];
     if (PREF) {
-      const int kn = more ? kc + KC : kc;  // the last chunk re-reads itself
+      if (more || next_pair < 0) {
+        const int kn = more ? kc + KC : kc;  // the last chunk re-reads itself
 #pragma unroll
-      for (int k = 0; k < MAXF4; ++k) nreg[k] = fetch(kn, min(tid + k * nthr, nf4 - 1));
+        for (int k = 0; k < MAXF4; ++k) nreg[k] = fetch(kn, min(tid + k * nthr, nf4 - 1));
+      } else {
+#pragma unroll
+        for (int k = 0; k < MAXF4; ++k) nreg[k] = load_stream(znext + min(tid + k * nthr, nf4 - 1));
+      }
     }
     load_y(kc + KC, ny);
     __builtin_amdgcn_sched_barrier(0);
@@ -128,6 +143,13 @@ __global__ void __launch_bounds__(MAXT) step3_fp16(Step3Args p) {
         for (int t = tid; t < nf4; t += nthr) put(cur ^ 1, t, fetch(kc + KC, t));
       }
       __syncthreads();
+    } else if (PREF && next_pair >= 0) {
+      // the last chunk is in buffer 1 (an even number of chunks): buffer 0 is free
+#pragma unroll
+      for (int k = 0; k < MAXF4; ++k) {
+        const int t = tid + k * nthr;
+        if (t < nf4) put(0, t, nreg[k]);
+      }
     }
   };
   f16x8 y0[KS], y1[KS];
@@ -137,10 +159,205 @@ __global__ void __launch_bounds__(MAXT) step3_fp16(Step3Args p) {
     chunk(kc, y0, y1);
     chunk(kc + KC, y1, y0);
   }
+}
+
+template <int CTQ, int MAXT, bool PREF>
+__global__ void __launch_bounds__(MAXT) step3_fp16(Step3Args p) {
+  extern __shared__ float smem[];
+  constexpr int QH = 32 * CTQ;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  int pair, yb;
+  step3_block(blockIdx.x, p.nblk, p.pairs, pair, yb);
+  const int d0 = (yb * p.nwaves + wave) * 16;
+  float2* twl = reinterpret_cast<float2*>(smem);
+  float* region = smem + 4 * QH;
+  for (int i = tid; i < 2 * QH; i += blockDim.x) twl[i] = p.tw_qa[i];
+  const bool active = d0 < p.N;
+  fp16_first_chunk<CTQ>(p, region, pair);
+  __syncthreads();
+  f32x16 acc[CTQ];
+  fp16_kloop<CTQ, PREF>(p, region, pair, d0, active, acc, -1);
   __syncthreads();
   if (!active) return;
   float2* T = reinterpret_cast<float2*>(region) + wave * (epilogue_lds_bytes_per_wave() / sizeof(float2));
   step3_epilogue_reg<CTQ>(p, acc, pair, d0, T, twl, lane);
+}
+
+// ---- rotation transform on MFMA (Qa <= 256) --------------------------------
+//
+// The Qa real outputs of a shift are a real linear map of the packed modes
+// P(q) = Xhat(q), q = 0 .. QH - 1 (P(0) = Xhat(0) + i Xhat(QH)):
+//   X(r) = Re P(0) + (-1)^r Im P(0)
+//          + sum_{q >= 1} 2 (Re P(q) cos(2 pi q r / Qa) + Im P(q) sin(2 pi q r / Qa)).
+// Split by the parity of q, X(r) = E(r) + O(r) and X(r + QH) = E(r) - O(r)
+// for r < QH (the odd-q terms change sign under r -> r + QH, the even ones
+// and the Nyquist term do not).  E and O are two real products
+//   E[r][dl] = sum_k T_E[r][k] V_E[k][dl],  O likewise,
+// with k = 2 m + c over the modes q = 2 m (E) or 2 m + 1 (O), c = 0 real and
+// 1 imaginary part: each is a (QH x QH) by (QH x 16 shifts) product, done
+// with v_mfma_f32_16x16x32_f16 (fp16 operands, FP32 accumulation).  The
+// tables T_E and T_O (fp16, built on the host, laid out as the MFMA's
+// A-operand fragments: [E/O][row tile t][K step s][lane][8]) stay in LDS for
+// the whole kernel, which loops over its pairs (one workgroup per CU).
+//
+// 16x16x32 operand layouts: A lane l holds A[l % 16][8 (l / 16) + e],
+// B lane l holds B[8 (l / 16) + e][l % 16], e = 0 .. 7; the result lane l
+// holds D[4 (l / 16) + v][l % 16], v = 0 .. 3.
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__host__ __device__ constexpr int rot_row_words(int QH) { return QH / 2 + 4; }  // transpose row: QH/2 words + pad
+
+template <int CTQ>
+__device__ __forceinline__ void rot_epilogue(const Step3Args& p, f32x16 (&acc)[CTQ], int pair, int d0,
+                                             const float4* __restrict__ tbl, uint32_t* sc, int lane) {
+  constexpr int QH = 32 * CTQ;
+  constexpr int Qa = 2 * QH;
+  constexpr int NT = QH / 16;  // row tiles (16 rotations each)
+  constexpr int NS = QH / 32;  // K steps of 32
+  constexpr int RS = rot_row_words(QH);
+  const int jj = lane & 31;
+  const int hh = lane >> 5;
+  // (1) fp16 (re, im) pairs: acc rows 2 dl + c, register v = 2 g + c holds
+  // shift dl = 4 (g / 2) + 2 hh + g % 2 of column q = 32 ct + jj
+  uint32_t h2[CTQ][8];
+#pragma unroll
+  for (int ct = 0; ct < CTQ; ++ct)
+#pragma unroll
+    for (int g = 0; g < 8; ++g) {
+      typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
+      const f16x2 v = __builtin_convertvector((float2_v{acc[ct][2 * g], acc[ct][2 * g + 1]}), f16x2);
+      h2[ct][g] = __builtin_bit_cast(uint32_t, v);
+    }
+  // (2) transpose through this wave's LDS rows: row dl holds words m =
+  // 0 .. QH/2 - 1, the (re, im) of mode 2 m + parity; even columns first
+  f16x8 BE[NS], BO[NS];
+  uint32_t* const wbase = sc + 2 * hh * RS + (jj >> 1);            // + compile-time offsets
+  const uint32_t* const rbase = sc + (lane & 15) * RS + 4 * (lane >> 4);
+#pragma unroll
+  for (int par = 0; par < 2; ++par) {
+    if ((jj & 1) == par) {
+#pragma unroll
+      for (int ct = 0; ct < CTQ; ++ct)
+#pragma unroll
+        for (int g = 0; g < 8; ++g) wbase[(4 * (g >> 1) + (g & 1)) * RS + 16 * ct] = h2[ct][g];
+    }
+    wave_sync();
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      const f16x8 v = *reinterpret_cast<const f16x8*>(rbase + 16 * s);
+      if (par == 0)
+        BE[s] = v;
+      else
+        BO[s] = v;
+    }
+    wave_sync();
+  }
+  // (3) 16 rotations per tile: E and O products, X(r) = E + O and
+  // X(r + QH) = E - O; per lane one shift, rotations r = 16 t + 4 (l / 16) + v
+  const int dl = lane & 15;
+  const int delta = d0 + dl;
+  const bool valid = delta < p.N;
+  const int r4 = 4 * (lane >> 4);
+  float* xr = (p.X && valid) ? p.X + (static_cast<size_t>(pair) * p.N + delta) * Qa + r4 : nullptr;
+  const float xs = (xr && p.xscale) ? *p.xscale : 1.f;
+  const f16x8* tb = reinterpret_cast<const f16x8*>(tbl) + lane;
+  float bv0 = -__builtin_inff(), bv1 = -__builtin_inff();
+  int bs0 = -1, bs1 = -1;  // step 4 t + v of the best in each half
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    f32x4 dE = {0.f, 0.f, 0.f, 0.f}, dO = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      dE = __builtin_amdgcn_mfma_f32_16x16x32_f16(tb[64 * (t * NS + s)], BE[s], dE, 0, 0, 0);
+      dO = __builtin_amdgcn_mfma_f32_16x16x32_f16(tb[64 * ((NT + t) * NS + s)], BO[s], dO, 0, 0, 0);
+    }
+    f32x4 x0, x1;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      x0[v] = dE[v] + dO[v];
+      x1[v] = dE[v] - dO[v];
+      // increasing r within each half: a later equal value never replaces
+      // (the lowest index wins ties); NaN never compares greater
+      if (x0[v] > bv0) {
+        bv0 = x0[v];
+        bs0 = 4 * t + v;
+      }
+      if (x1[v] > bv1) {
+        bv1 = x1[v];
+        bs1 = 4 * t + v;
+      }
+    }
+    if (xr) {
+      *reinterpret_cast<float4*>(xr + 16 * t) = make_float4(x0[0] * xs, x0[1] * xs, x0[2] * xs, x0[3] * xs);
+      *reinterpret_cast<float4*>(xr + QH + 16 * t) = make_float4(x1[0] * xs, x1[1] * xs, x1[2] * xs, x1[3] * xs);
+    }
+  }
+  // the lane's best: the first half wins ties (lower index)
+  const bool take1 = bs1 >= 0 && (bs0 < 0 || bv1 > bv0);
+  const int bs = take1 ? bs1 : bs0;
+  float bv = take1 ? bv1 : bv0;
+  uint32_t bi = 0xffffffffu;
+  if (valid && bs >= 0)
+    bi = static_cast<uint32_t>(delta) * Qa + (take1 ? QH : 0) + 16 * (bs >> 2) + r4 + (bs & 3);
+  else
+    bv = -__builtin_inff();
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+    const float ov = __shfl_xor(bv, off);
+    const uint32_t oi = static_cast<uint32_t>(__shfl_xor(static_cast<int>(bi), off));
+    ep_better(bv, bi, ov, oi);
+  }
+  if (lane == 0 && bi != 0xffffffffu) atomicMax(p.keys + pair, pose_key(bv, bi));
+}
+
+// SEP: the transpose rows have LDS of their own after the Zhat buffers (the
+// next pair's first chunk is then stored during the last chunk of the
+// current one); otherwise they reuse the Zhat buffers.
+template <int CTQ, bool PREF, bool SEP>
+__global__ void __launch_bounds__(1024) step3_fp16_rot(Step3Args p) {
+  extern __shared__ float smem[];
+  constexpr int QH = 32 * CTQ;
+  constexpr int NFRAG = 2 * (QH / 16) * (QH / 32);  // 1 KB each
+  constexpr int RS = rot_row_words(QH);
+  const int tid = threadIdx.x;
+  const int wave = tid >> 6;
+  float4* tbl = reinterpret_cast<float4*>(smem);
+  const float4* tsrc = static_cast<const float4*>(p.rot16);
+  for (int i = tid; i < NFRAG * 64; i += blockDim.x) tbl[i] = tsrc[i];
+  float* region = smem + NFRAG * 256;
+  uint32_t* sc = reinterpret_cast<uint32_t*>(region + (SEP ? 2 * QH * 36 : 0)) + wave * 16 * RS;
+  const int total = p.pairs * p.nblk;
+  int b = blockIdx.x;
+  if (b >= total) return;
+  int pair, yb;
+  step3_block(b, p.nblk, p.pairs, pair, yb);
+  fp16_first_chunk<CTQ>(p, region, pair);
+  __syncthreads();
+  for (;;) {
+    const int d0 = (yb * p.nwaves + wave) * 16;
+    const bool active = d0 < p.N;
+    const int bn = b + gridDim.x;
+    int pn = 0, ybn = 0;
+    if (bn < total) step3_block(bn, p.nblk, p.pairs, pn, ybn);
+    constexpr bool early = SEP && PREF;  // next first chunk stored inside the K loop
+    f32x16 acc[CTQ];
+    fp16_kloop<CTQ, PREF>(p, region, pair, d0, active, acc, (early && bn < total) ? pn : -1);
+    // every wave is past the Zhat buffers (the transposes may reuse them),
+    // and the next pair's first chunk is visible
+    __syncthreads();
+    if (active) rot_epilogue<CTQ>(p, acc, pair, d0, tbl, sc, tid & 63);
+    if (bn >= total) break;
+    if (!early) {
+      __syncthreads();  // transposes done before buffer 0 is written again
+      fp16_first_chunk<CTQ>(p, region, pn);
+      __syncthreads();
+    }
+    b = bn;
+    pair = pn;
+    yb = ybn;
+  }
 }
 
 // ---- data scales ----------------------------------------------------------
@@ -186,6 +403,42 @@ size_t step3_fp16_lds_bytes(int Qa, int nwaves) {
   return sizeof(float2) * Qa + (k > e ? k : e);
 }
 
+size_t rot16_table_bytes(int Qa) {
+  const size_t QH = Qa / 2;
+  return (Qa % 64 == 0 && Qa <= 256) ? 2 * (QH / 16) * (QH / 32) * 1024 : 0;
+}
+
+// LDS of the MFMA-transform kernel: the tables, then the Zhat buffers and the
+// transpose rows, side by side where they fit (sep), else overlapping
+static size_t rot_lds(int Qa, int nwaves, bool sep) {
+  const size_t QH = Qa / 2;
+  const size_t k = sizeof(float) * 2 * QH * 36;
+  const size_t e = sizeof(uint32_t) * static_cast<size_t>(nwaves) * 16 * rot_row_words(static_cast<int>(QH));
+  return rot16_table_bytes(Qa) + (sep ? k + e : (k > e ? k : e));
+}
+constexpr size_t kRotLdsLimit = 160 * 1024;
+
+size_t step3_fp16_rot_lds_bytes(int Qa, int nwaves) {
+  const size_t sep = rot_lds(Qa, nwaves, true);
+  return sep <= kRotLdsLimit ? sep : rot_lds(Qa, nwaves, false);
+}
+
+namespace {
+
+int device_cus() {
+  static int cached[64] = {0};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+  if (cached[dev] <= 0) {
+    int n = 0;
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0) n = 256;
+    cached[dev] = n;
+  }
+  return cached[dev];
+}
+
+}  // namespace
+
 template <int CTQ, int MAXT>
 static hipError_t launch_step3_fp16_t(const Step3Args& a0, hipStream_t s) {
   Step3Args a = a0;
@@ -193,10 +446,26 @@ static hipError_t launch_step3_fp16_t(const Step3Args& a0, hipStream_t s) {
   a.nblk = (a.N + per_blk - 1) / per_blk;
   const size_t nwg = static_cast<size_t>(a.pairs) * a.nblk;
   if (nwg * 64 * a.nwaves > 0xffffffffull) return hipErrorInvalidConfiguration;
+  const int nf4 = 32 * CTQ * 8, nthr = 64 * a.nwaves;
+  const bool pref = (nf4 + nthr - 1) / nthr <= 2;
+  if constexpr (CTQ <= 4) {
+    if (a.rot16) {
+      // one workgroup per CU, looping over its pairs' shift blocks
+      const bool sep = rot_lds(a.Qa, a.nwaves, true) <= kRotLdsLimit;
+      const size_t lds = rot_lds(a.Qa, a.nwaves, sep);
+      auto kern = pref ? (sep ? step3_fp16_rot<CTQ, true, true> : step3_fp16_rot<CTQ, true, false>)
+                       : (sep ? step3_fp16_rot<CTQ, false, true> : step3_fp16_rot<CTQ, false, false>);
+      hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
+      if (e != hipSuccess) return e;
+      const unsigned grid = static_cast<unsigned>(std::min<size_t>(nwg, static_cast<size_t>(device_cus())));
+      hipLaunchKernelGGL(kern, dim3(grid), dim3(nthr), lds, s, a);
+      return hipGetLastError();
+    }
+  }
   const dim3 grid(static_cast<unsigned>(nwg));
   size_t lds = step3_fp16_lds_bytes(a.Qa, a.nwaves);
-  const int nf4 = 32 * CTQ * 8, nthr = 64 * a.nwaves;
-  auto kern = (nf4 + nthr - 1) / nthr <= 2 ? step3_fp16<CTQ, MAXT, true> : step3_fp16<CTQ, MAXT, false>;
+  auto kern = pref ? step3_fp16<CTQ, MAXT, true> : step3_fp16<CTQ, MAXT, false>;
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
   if (e != hipSuccess) return e;

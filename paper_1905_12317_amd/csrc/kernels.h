@@ -62,6 +62,7 @@ struct Step3Args {
   const float* xscale;   // device scalar multiplying the X outputs (FP16 form), or null
   unsigned long long* keys;  // [pairs]
   const float2* tw_qa;   // [Qa]
+  const void* rot16;     // FP16 form with Qa <= 256: the rotation transform tables (rot16_table_bytes), or null
   int pairs, Qa, H_pad, N, N_pad;
   int nwaves;            // waves per workgroup; each wave owns 16 shifts
   int nblk;              // workgroups per pair (shift blocks); 1-D grid of pairs * nblk
@@ -92,7 +93,17 @@ hipError_t launch_step3_bf16(const Step3Args& args, hipStream_t stream);
 // scales[0..1] = max |a|, max |b| (as float bits, reduced here), then
 // scales[2] = 1/s_a, scales[3] = 1/s_b, scales[4] = s_a s_b s_y, with s the
 // power of two at or above each maximum (1 for an all-zero input).
+// With Step3Args::rot16 set (Qa <= 256), the rotation transform runs on MFMA
+// from the fp16 tables T_E, T_O of the even and odd modes:
+//   T_E[r][2 m + c]: m = 0: 1 (c = 0), (-1)^r (c = 1);
+//                    m > 0: 2 cos(2 pi (2 m) r / Qa) (c = 0), 2 sin(...) (c = 1)
+//   T_O[r][2 m + c]: 2 cos(2 pi (2 m + 1) r / Qa) (c = 0), 2 sin(...) (c = 1)
+// for r, 2 m + c < Qa/2, stored as 1 KB MFMA fragments: value
+// T_p[16 t + l % 16][32 s + 8 (l / 16) + e] at half index
+// (((p Qa/32 + t) Qa/64 + s) 64 + l) 8 + e.
 size_t step3_fp16_lds_bytes(int Qa, int nwaves);
+size_t rot16_table_bytes(int Qa);  // 0 where the MFMA transform does not apply
+size_t step3_fp16_rot_lds_bytes(int Qa, int nwaves);
 hipError_t launch_step3_fp16(const Step3Args& args, hipStream_t stream);
 hipError_t launch_fp16_scales(const float* a, size_t a_count, const float* b, size_t b_count, float s_y,
                               float* scales, hipStream_t stream);

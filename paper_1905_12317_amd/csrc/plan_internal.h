@@ -102,14 +102,16 @@ struct ftk_plan {
   ftk_tuning_t tune{};
   // plan-owned device tables
   ftkint::DevBuf cz, ell, yt, yt_hi, yt_lo, tw_nf, tw_qa, deapod, ptbase, ptker;
+  ftkint::DevBuf rot16;  // FP16 form, Qa <= 256: rotation transform tables
   ftkint::Workspace own_ws;
   ftkint::Workspace* ws = &own_ws;
   size_t device_bytes() const {
     return cz.bytes + ell.bytes + yt.bytes + yt_hi.bytes + yt_lo.bytes + tw_nf.bytes + tw_qa.bytes +
-           deapod.bytes + ptbase.bytes + ptker.bytes + own_ws.bytes();
+           deapod.bytes + ptbase.bytes + ptker.bytes + rot16.bytes + own_ws.bytes();
   }
   void release_all() {
-    for (ftkint::DevBuf* b : {&cz, &ell, &yt, &yt_hi, &yt_lo, &tw_nf, &tw_qa, &deapod, &ptbase, &ptker}) b->release();
+    for (ftkint::DevBuf* b : {&cz, &ell, &yt, &yt_hi, &yt_lo, &tw_nf, &tw_qa, &deapod, &ptbase, &ptker, &rot16})
+      b->release();
     own_ws.release();
   }
 };
