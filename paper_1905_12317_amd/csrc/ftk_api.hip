@@ -337,10 +337,11 @@ int check_plan_args(int n, int K, int Q, double W, double eps, int precision) {
 
 namespace ftkint {
 
-ftk_tuning_t default_tuning() {
+ftk_tuning_t default_tuning(int precision) {
   ftk_tuning_t t;
   t.step3_waves = static_cast<int>(std::min<size_t>(16, env_mib("FTK_STEP3_WAVES", 16)));
-  t.step1_zblk = env_mib("FTK_STEP1_ZBLK", 128) == 64 ? 64 : 128;
+  // the FP16 form's Step 1 is faster with 64 SVD terms per workgroup
+  t.step1_zblk = env_mib("FTK_STEP1_ZBLK", precision == FTK_FP16 ? 64 : 128) == 64 ? 64 : 128;
   t.step1_wgs = static_cast<int>(std::min<size_t>(65536, std::max<size_t>(64, env_mib("FTK_STEP1_WGS", 4096))));
   t.stage_mib = static_cast<int>(std::min<size_t>(65536, std::max<size_t>(16, env_mib("FTK_STAGE_MB", 8192))));
   return t;
@@ -376,7 +377,7 @@ Needs plan_needs(const ftk_plan* p, int nA, int nB, bool from_pixels) {
   if (from_pixels) {
     const int cnt = std::max(nA, nB);
     const size_t per_img = (n * nf + nf * nf) * sizeof(float2);
-    const size_t budget = env_mib("FTK_TRANSFORM_SCRATCH_MB", 512) << 20;
+    const size_t budget = env_mib("FTK_TRANSFORM_SCRATCH_MB", 4096) << 20;
     d.transform_chunk = static_cast<int>(std::min<size_t>(std::max<size_t>(1, budget / per_img), std::max(cnt, 1)));
     d.tr_h = static_cast<size_t>(d.transform_chunk) * n * nf * sizeof(float2);
     d.tr_g = static_cast<size_t>(d.transform_chunk) * nf * nf * sizeof(float2);
@@ -472,7 +473,7 @@ int ftk_plan_create(ftk_plan** out, int n, int K, int Q, double W, double eps, i
     p->eps = eps;
     p->precision = precision;
     p->kmax = 0.5 * kPi * n;
-    p->tune = default_tuning();
+    p->tune = default_tuning(precision);
     build_tables(n, K, W, eps, p->t);
     p->H_pad = round_up(std::max(p->t.H, 1), 64);
     p->sk = ftkplan::spread_kernel(n, kNufftWidth);
@@ -619,7 +620,7 @@ int ftk_transform(ftk_plan* p, const float* imgs, int cnt, void* coeffs, void* s
   Workspace& ws = *p->ws;
   if (ws.tr_h.ensure(nd.tr_h) != hipSuccess || ws.tr_g.ensure(nd.tr_g) != hipSuccess)
     return fail(FTK_ENOMEM, "ftk_transform: scratch");
-  if (transform_lds_bytes(nf, p->Qa, 4) > kLdsLimit) return fail(FTK_EUNSUPPORTED, "ftk_transform: LDS");
+  if (transform_lds_bytes(nf, p->Qa, transform_waves()) > kLdsLimit) return fail(FTK_EUNSUPPORTED, "ftk_transform: LDS");
   hipError_t e;
   for (int c0 = 0; c0 < cnt; c0 += chunk) {
     const int c = std::min(chunk, cnt - c0);
@@ -817,7 +818,7 @@ int ftk_plan_set_tuning(ftk_plan* p, const ftk_tuning_t* t) {
     return fail(FTK_EINVAL, "step1_wgs must be 0 or in [64, 65536]");
   if (t->stage_mib != 0 && (t->stage_mib < 16 || t->stage_mib > 65536))
     return fail(FTK_EINVAL, "stage_mib must be 0 or in [16, 65536]");
-  const ftk_tuning_t d = default_tuning();
+  const ftk_tuning_t d = default_tuning(p->precision);
   p->tune.step3_waves = t->step3_waves ? t->step3_waves : d.step3_waves;
   p->tune.step1_zblk = t->step1_zblk ? t->step1_zblk : d.step1_zblk;
   p->tune.step1_wgs = t->step1_wgs ? t->step1_wgs : d.step1_wgs;

@@ -12,6 +12,8 @@
 //   3. a length-Qa DFT on each ring gives a(k_m; q) (eq. aqkcalc).
 // All scale factors (dx^2 h^2 / Qa and the kernel deconvolution) are folded
 // into the per-dimension deapodisation table.
+#include <cstdlib>
+
 #include "device_common.h"
 #include "kernels.h"
 
@@ -19,7 +21,7 @@ using namespace ftkdev;
 
 namespace {
 
-__global__ void __launch_bounds__(256) transform_kernel(TransformArgs p) {
+__global__ void __launch_bounds__(1024) transform_kernel(TransformArgs p) {
   extern __shared__ float2 lds[];
   const int img = blockIdx.x;
   const int n = p.n, nf = p.nf, Qa = p.Qa, M = p.M, w = p.w;
@@ -129,9 +131,19 @@ size_t transform_lds_bytes(int nf, int Qa, int nwaves) {
   return a > c ? a : c;
 }
 
+int transform_waves() {
+  static int w = 0;
+  if (w == 0) {
+    const char* v = std::getenv("FTK_TRANSFORM_WAVES");
+    const int x = v ? std::atoi(v) : 0;
+    w = (x >= 1 && x <= 16) ? x : 16;
+  }
+  return w;
+}
+
 hipError_t launch_transform(const TransformArgs& args, int cnt, hipStream_t stream) {
   if (cnt <= 0) return hipSuccess;
-  const int nwaves = 4;
+  const int nwaves = transform_waves();
   size_t lds = transform_lds_bytes(args.nf, args.Qa, nwaves);
   hipLaunchKernelGGL(transform_kernel, dim3(cnt), dim3(64 * nwaves), lds, stream, args);
   return hipGetLastError();

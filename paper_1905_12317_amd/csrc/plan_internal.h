@@ -118,7 +118,7 @@ struct ftk_plan {
 
 namespace ftkint {
 // Built-in launch shapes (environment overrides applied).
-ftk_tuning_t default_tuning();
+ftk_tuning_t default_tuning(int precision);
 Needs plan_needs(const ftk_plan* p, int nA, int nB, bool from_pixels);
 // alignment of nA images against K listed templates each
 Needs plan_needs_lists(const ftk_plan* p, int nA, int K);

@@ -105,7 +105,8 @@ def test_tuning_does_not_change_results(ftk):
         P.set_shifts(shifts)
         d = P.tuning()
         _say(f"[tuning {prec}] default {d}")
-        assert d == {"step3_waves": 16, "step1_zblk": 128, "step1_wgs": 4096, "stage_mib": 8192} or \
+        assert d == {"step3_waves": 16, "step1_zblk": 64 if prec == "fp16" else 128, "step1_wgs": 4096,
+                     "stage_mib": 8192} or \
             any(k in os.environ for k in ("FTK_STEP3_WAVES", "FTK_STEP1_ZBLK", "FTK_STEP1_WGS", "FTK_STAGE_MB"))
         imgs, tmps = _dev(s.images), _dev(s.templates)
         X0, b0 = P.align(imgs, tmps, want_X=True)
