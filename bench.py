@@ -1,6 +1,6 @@
 """Throughput of the FTK hot path on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--form fp32|bf16x3|fp16|all]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--form fp32|bf16x3|fp16|fp16+bf16x3|all]
 
 One step = one pass of the whole hot path over one batch of synthetic
 input already resident in HBM: transform of the 512 images and the 2048
@@ -8,6 +8,11 @@ templates (n = 128) to Fourier-Bessel coefficients, Step 1 (image x template
 contraction per mode), Step 3 (shift contraction, 197 shifts), the rotation
 FFT over all 256 rotations and the best pose of every pair.  Planning and
 the shift table are built once, outside the timed region.
+
+Forms: fp32, bf16x3 (split bf16, three products), fp16 (one product), and
+fp16+bf16x3 (the FP16 form over every pair, then the split form on each
+image's four best FP16 templates; its per-image best comes from the second
+pass).
 
 Prints one JSON line: the metric's value is whole-job pairs/s for the chosen
 form (the fastest whose per-image best poses agree with the FP32 form's on
@@ -41,12 +46,12 @@ PEAK_HBM = 8.0e12
 # the kernel sources they were taken on; a changed kernel reports null.
 # Source: profiles/step3_<form>_cryoem_n128.md.
 TRAFFIC = {
-    "bf16x3": {"bytes_per_launch": 9.401e+09, "sources": ["kern_align_bf16.hip", "step3_epilogue.h", "device_common.h", "kernels.h"],
-        "sha1": "1060e11ac2ef7e0995b98f4465867203aacebae7"},
-    "fp32": {"bytes_per_launch": 9.625e+09, "sources": ["kern_align.hip", "step3_epilogue.h", "device_common.h", "kernels.h"],
-        "sha1": "e24042023cf6d6fca59e78343d1179627d8d693b"},
-    "fp16": {"bytes_per_launch": 1.004e+10, "sources": ["kern_align_fp16.hip", "step3_epilogue.h", "device_common.h", "kernels.h"],
-        "sha1": "6ef83f6f362c4cd4b36d1f7a40f5f8c4972281af"},
+    "bf16x3": {"bytes_per_launch": 9.398e+09, "sources": ["kern_align_bf16.hip", "step3_epilogue.h", "device_common.h", "kernels.h"],
+        "sha1": "f887cf75e93d1c2dfb8f847b0430da34427e8cfd"},
+    "fp32": {"bytes_per_launch": 9.626e+09, "sources": ["kern_align.hip", "step3_epilogue.h", "device_common.h", "kernels.h"],
+        "sha1": "b9a7de8b2b72c7bc8842a0063ada3b676a0209e5"},
+    "fp16": {"bytes_per_launch": 8.673e+09, "sources": ["kern_align_fp16.hip", "step3_epilogue.h", "device_common.h", "kernels.h"],
+        "sha1": "7b4dfc706deb64dcea13df080dd4cfa45d2902ee"},
 }
 
 
@@ -466,7 +471,9 @@ def main():
                    "recall_true_template": recall(r["img_best"], inputs),
                    "best_pose_agreement_vs_fp32": agree[chosen],
                    "gflop_per_pair": (s1 + s3 + fft) / 1e9},
-        "roofline": {"kernel": "step3 (shift contraction on MFMA + rotation FFT + argmax)", "bound": "mfma",
+        "roofline": {"kernel": ("step3 FP16 (shift contraction and rotation transform on MFMA, argmax)"
+                                if chosen.startswith("fp16") else
+                                "step3 (shift contraction on MFMA + rotation FFT + argmax)"), "bound": "mfma",
                      "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
                      "frac": achieved / peak, "traffic": traffic,
                      "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
