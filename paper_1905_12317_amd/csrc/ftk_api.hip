@@ -620,7 +620,7 @@ int ftk_transform(ftk_plan* p, const float* imgs, int cnt, void* coeffs, void* s
   Workspace& ws = *p->ws;
   if (ws.tr_h.ensure(nd.tr_h) != hipSuccess || ws.tr_g.ensure(nd.tr_g) != hipSuccess)
     return fail(FTK_ENOMEM, "ftk_transform: scratch");
-  if (transform_lds_bytes(nf, p->Qa, transform_waves()) > kLdsLimit) return fail(FTK_EUNSUPPORTED, "ftk_transform: LDS");
+  if (transform_lds_bytes(nf, p->Qa, transform_waves(nf, p->Qa)) > kLdsLimit) return fail(FTK_EUNSUPPORTED, "ftk_transform: LDS");
   hipError_t e;
   for (int c0 = 0; c0 < cnt; c0 += chunk) {
     const int c = std::min(chunk, cnt - c0);

@@ -19,7 +19,8 @@ struct TransformArgs {
 };
 
 size_t transform_lds_bytes(int nf, int Qa, int nwaves);
-int transform_waves();  // waves per transform workgroup (FTK_TRANSFORM_WAVES, default 16)
+// waves per transform workgroup: FTK_TRANSFORM_WAVES (default 16), lowered until LDS fits
+int transform_waves(int nf, int Qa);
 hipError_t launch_transform(const TransformArgs& args, int cnt, hipStream_t stream);
 
 // Step 1 (eq. fbk3): Zhat of every pair of the call, into the staging below.

@@ -79,6 +79,28 @@ def test_transform_matches_oracle(ftk, n, M, Qa, kind):
     assert err < 2e-6
 
 
+@pytest.mark.parametrize("n,M,Qa", [(64, 32, 128), (96, 48, 192), (128, 64, 256), (192, 96, 384), (64, 32, 256)])
+def test_transform_repeatable(ftk, n, M, Qa):
+    """Regression: the first transform of a fresh plan (scratch never
+    written) equals later ones bitwise, in any image order, on the shapes of
+    the compile-time kernel (2n = Qa) and a generic one; the workgroups of one
+    image must not read its grid before every wave has written it."""
+    imgs = synth.white_noise_images(11, 96, n)
+    P = ftk.Plan(n, M, Qa, 2.0, 1e-3)
+    d = _dev(imgs)
+    first = P.transform(d).cpu().numpy()
+    again = P.transform(d).cpu().numpy()
+    rev = P.transform(torch.flip(d, dims=[0]).contiguous()).cpu().numpy()[::-1]
+    torch.cuda.synchronize()
+    _say(f"[transform repeat] n={n} Qa={Qa}: first vs again max {np.max(np.abs(first - again)):.3e}")
+    assert np.array_equal(first.view(np.uint32), again.view(np.uint32))
+    assert np.array_equal(first.view(np.uint32), rev.view(np.uint32))
+    if n <= 64:
+        plan = O.make_plan(n, M, Qa, 2.0, 1e-3)
+        ref = np.array([O.fb_coefficients(x, plan).T for x in imgs[:2]])
+        assert np.max(np.abs(first[:2] - ref)) / np.max(np.abs(ref)) < 2e-6
+
+
 # ------------------------------------------------------------------ alignment
 
 def test_align_from_oracle_coefficients_fp32(ftk):
