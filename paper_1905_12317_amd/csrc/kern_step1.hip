@@ -15,6 +15,8 @@
 // all template blocks.  Modes q = 0 .. Qa/2 are computed (Hermitian
 // symmetry of a real inner product); the result is staged as
 // zs[pair][q][c][zeta] with Qa/2 + 1 rows of q.
+#include <type_traits>
+
 #include "device_common.h"
 #include "kernels.h"
 
@@ -452,31 +454,41 @@ __device__ __forceinline__ void step1_bf16_tile(const Step1Args& p, float* smem,
     for (int i = 0; i < RT; ++i) {
       const int rt = rt0 + i;
       if (rt >= nRT) break;
-      const bool full = (rt + 1) * 16 <= p.nB;
+      // the lane's base address once per tile; each store adds scalar
+      // offsets (template row and chunk).  Tiles whose 16 templates all exist
+      // store without a row test.
+      const int nrows = p.nB - rt * 16 - 2 * r;
+      uint32_t* tb = zw + (static_cast<size_t>(rt) * 16 + 2 * r) * pair_words;
+      auto store_tile = [&](auto guarded) {
 #pragma unroll
-      for (int j = 0; j < CT; ++j) {
+        for (int j = 0; j < CT; ++j) {
 #pragma unroll
-        for (int v = 0; v < 16; ++v) {
-          const float x = acc[i][j][v];
-          // hi = bf16(x), lo = bf16(x - hi), packed (hi, lo) in one word
-          const float xh = static_cast<float>(static_cast<__bf16>(x));
-          const uint32_t w = __builtin_bit_cast(uint32_t, __builtin_convertvector(f32x2{x, x - xh}, bf16x2));
-          // even lane sends its lo half, odd lane its hi half; the even lane
-          // stores (hi, hi of the odd lane), the odd lane (lo of the even, lo)
-          const uint32_t got = static_cast<uint32_t>(
-              __builtin_amdgcn_mov_dpp(static_cast<int>(odd ? w : (w >> 16)), 0xB1, 0xF, 0xF, false));
-          const uint32_t word = odd ? ((got & 0xffffu) | (w & 0xffff0000u)) : ((w & 0xffffu) | (got << 16));
-          // accumulator row 8 (v / 4) + 4 r + v % 4: template rt 16 + kv + 2 r,
-          // part c = v % 2; k' = c H_pad + z0 + 32 j + c32 lies in chunk
-          // (c H_pad + z0) / 32 + j
-          const int kv = 4 * (v >> 2) + ((v & 3) >> 1);
-          const int B = rt * 16 + kv + 2 * r;
-          const int chunk = ((v & 1) * p.H_pad + z0) / 32 + j;
-          // streaming store: the staging is read back once, by Step 3
-          if (full || B < p.nB)
-            __builtin_nontemporal_store(word, zw + static_cast<size_t>(B) * pair_words + static_cast<size_t>(chunk) * QH * 32);
+          for (int v = 0; v < 16; ++v) {
+            const float x = acc[i][j][v];
+            // hi = bf16(x), lo = bf16(x - hi), packed (hi, lo) in one word
+            const float xh = static_cast<float>(static_cast<__bf16>(x));
+            const uint32_t w = __builtin_bit_cast(uint32_t, __builtin_convertvector(f32x2{x, x - xh}, bf16x2));
+            // even lane sends its lo half, odd lane its hi half; the even lane
+            // stores (hi, hi of the odd lane), the odd lane (lo of the even, lo)
+            const uint32_t got = static_cast<uint32_t>(
+                __builtin_amdgcn_mov_dpp(static_cast<int>(odd ? w : (w >> 16)), 0xB1, 0xF, 0xF, false));
+            const uint32_t word = odd ? ((got & 0xffffu) | (w & 0xffff0000u)) : ((w & 0xffffu) | (got << 16));
+            // accumulator row 8 (v / 4) + 4 r + v % 4: template rt 16 + kv + 2 r,
+            // part c = v % 2; k' = c H_pad + z0 + 32 j + c32 lies in chunk
+            // (c H_pad + z0) / 32 + j
+            const int kv = 4 * (v >> 2) + ((v & 3) >> 1);
+            const int chunk = ((v & 1) * p.H_pad + z0) / 32 + j;
+            // streaming store: the staging is read back once, by Step 3
+            if (!decltype(guarded)::value || kv < nrows)
+              __builtin_nontemporal_store(word, tb + static_cast<size_t>(kv) * pair_words +
+                                                    static_cast<size_t>(chunk) * QH * 32);
+          }
         }
-      }
+      };
+      if ((rt + 1) * 16 <= p.nB)
+        store_tile(std::false_type{});
+      else
+        store_tile(std::true_type{});
     }
   }
 }
@@ -579,32 +591,41 @@ __device__ __forceinline__ void step1_fp16_tile(const Step1Args& p, float* smem,
         }
       }
     }
-    // tiles whose 16 templates all exist store without a per-row test
+    // Accumulator row 8 (v / 4) + 4 r + v % 4 is template rt 16 + 4 (v / 4)
+    // + 2 r + (v % 4) / 2 (re|im in adjacent rows).  The lane's base address
+    // is formed once per tile; each store adds a scalar multiple of the pair
+    // stride.  Tiles whose 16 templates all exist store without a row test.
 #pragma unroll
     for (int i = 0; i < RT; ++i) {
       const int rt = rt0 + i;
       if (rt >= nRT) break;
-      const bool full = (rt + 1) * 16 <= p.nB;
+      const int nrows = p.nB - rt * 16 - 2 * r;  // rows of this lane's template pair that exist
+      uint32_t* tb = zw + (static_cast<size_t>(rt) * 16 + 2 * r) * pair_words;
+      auto store_tile = [&](auto guarded) {
 #pragma unroll
-      for (int j = 0; j < CT; ++j) {
-        // k' = c H_pad + z0 + 32 j + (c32 & ~1) for the pair this lane stores
-        const int kp = odd * p.H_pad + z0 + 32 * j + (c32 & ~1);
-        const size_t at = static_cast<size_t>(kp >> 6) * QH * 32 + ((kp & 63) >> 1);
+        for (int j = 0; j < CT; ++j) {
+          // k' = c H_pad + z0 + 32 j + (c32 & ~1) for the pair this lane stores
+          const int kp = odd * p.H_pad + z0 + 32 * j + (c32 & ~1);
+          uint32_t* tj = tb + static_cast<size_t>(kp >> 6) * QH * 32 + ((kp & 63) >> 1);
 #pragma unroll
-        for (int v = 0; v < 16; v += 2) {
-          const float xr = acc[i][j][v], xi = acc[i][j][v + 1];
-          // even lane sends its imaginary part, odd lane its real part
-          const float got = __builtin_bit_cast(
-              float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, odd ? xr : xi), 0xB1, 0xF, 0xF, false));
-          f16x2 w;
-          w[0] = static_cast<_Float16>(odd ? got : xr);
-          w[1] = static_cast<_Float16>(odd ? xi : got);
-          const int row = 8 * (v >> 2) + 4 * r + (v & 3);
-          const int B = rt * 16 + (row >> 1);
-          if (full || B < p.nB)
-            __builtin_nontemporal_store(__builtin_bit_cast(uint32_t, w), zw + static_cast<size_t>(B) * pair_words + at);
+          for (int v = 0; v < 16; v += 2) {
+            const float xr = acc[i][j][v], xi = acc[i][j][v + 1];
+            // even lane sends its imaginary part, odd lane its real part
+            const float got = __builtin_bit_cast(
+                float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, odd ? xr : xi), 0xB1, 0xF, 0xF, false));
+            f16x2 w;
+            w[0] = static_cast<_Float16>(odd ? got : xr);
+            w[1] = static_cast<_Float16>(odd ? xi : got);
+            const int brow = 4 * (v >> 2) + ((v & 3) >> 1);
+            if (!decltype(guarded)::value || brow < nrows)
+              __builtin_nontemporal_store(__builtin_bit_cast(uint32_t, w), tj + static_cast<size_t>(brow) * pair_words);
+          }
         }
-      }
+      };
+      if ((rt + 1) * 16 <= p.nB)
+        store_tile(std::false_type{});
+      else
+        store_tile(std::true_type{});
     }
   }
 }
