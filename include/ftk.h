@@ -220,7 +220,8 @@ int ftk_plan_stage_times(ftk_plan* plan, double* ms, int64_t* launches, int nsta
  *                 shifts; 1..16, lowered to what LDS allows (default 16)
  *   step1_zblk  : SVD terms per Step 1 workgroup, 64 or 128, lowered to 64
  *                 when H (padded to 64) is not a multiple of 128 or the
- *                 tile does not fit LDS (default 128; FTK_FP16: 64)
+ *                 tile does not fit LDS (default 128; FTK_FP16: 64;
+ *                 list alignments of up to 16 templates per image: 64)
  *   step1_wgs   : Step 1 splits its template sweep until the grid holds
  *                 about this many workgroups; 64..65536 (default 4096)
  *   stage_mib   : the Step 1 -> Step 3 staging buffer, MiB; images are

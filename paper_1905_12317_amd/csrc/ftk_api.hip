@@ -667,7 +667,9 @@ int align_impl(ftk_plan* p, const void* img_coeffs, int nA, const void* tmpl_coe
   if (ws.keys.ensure(nd.keys) != hipSuccess) return fail(FTK_ENOMEM, "ftk_align: key buffer");
   if (ws.tmpl.ensure(nd.tmpl) != hipSuccess) return fail(FTK_ENOMEM, "ftk_align: template operand buffer");
   if (ws.scales.ensure(nd.scales) != hipSuccess) return fail(FTK_ENOMEM, "ftk_align: scale buffer");
-  const int zblk = step1_zblk(p);
+  // short per-image lists fill one template tile per workgroup: the smaller
+  // SVD block gives twice the workgroups for the same operand work
+  const int zblk = (lists && K <= 16) ? 64 : step1_zblk(p);
   if (step1_v2_lds_bytes(p->M, zblk, prec) > kLdsLimit) return fail(FTK_EUNSUPPORTED, "ftk_align: step 1 tiles exceed LDS");
   unsigned long long* keys = ws.keys.as<unsigned long long>();
   hipError_t e;
