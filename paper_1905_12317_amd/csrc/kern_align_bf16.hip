@@ -14,6 +14,8 @@
 // and ends with the same rotation FFT and argmax.
 // MFMA: v_mfma_f32_32x32x16_bf16; lane l holds rows/cols l % 32 and the
 // 8 consecutive k = 8 (l / 32) .. +7 of each 16-wide K step.
+#include <algorithm>
+
 #include "device_common.h"
 #include "kernels.h"
 #include "step3_epilogue.h"
@@ -41,21 +43,23 @@ __device__ __forceinline__ f32x16 mfma3(bf16x8 ahi, bf16x8 alo, bf16x8 bhi, bf16
 
 // ---------------------------------------------------------------- Step 3
 
+// The K loop for one pair and one shift block: Zhat chunks staged through
+// LDS (two buffers of QH rows at `region`), three bf16 MFMAs per term.  The
+// first chunk is in buffer 0 and visible to the block on entry; ends after the
+// last chunk's MFMAs (no barrier).  With next_pair >= 0 (PREF only), the last
+// chunk's prefetch fetches the first chunk of next_pair instead and stores it
+// into buffer 0 after its MFMAs: visible after the caller's next barrier.
 // PREF: the block has enough threads to prefetch a whole chunk in MAXF4
 // float4 per thread (double buffering through registers); otherwise each
 // chunk is fetched after the MFMAs of the previous one.
-template <int CTQ, int MAXT, bool PREF>
-__global__ void __launch_bounds__(MAXT) step3_bf16x3(Step3Args p) {
-  extern __shared__ float smem[];
+template <int CTQ, bool PREF>
+__device__ __forceinline__ void bf16_kloop(const Step3Args& p, float* region, int pair, int d0, bool active,
+                                           f32x16 (&acc)[CTQ], int next_pair) {
   constexpr int QH = 32 * CTQ;
   constexpr int KC = 32;     // k' per staged chunk (2 MFMA K steps)
   constexpr int ROWW = 36;   // LDS words per q row: 16 hi, 16 lo, 4 pad
   const int tid = threadIdx.x;
   const int lane = tid & 63;
-  const int wave = tid >> 6;
-  int pair, yb;
-  step3_block(blockIdx.x, p.nblk, p.pairs, pair, yb);
-  const int d0 = (yb * p.nwaves + wave) * 16;
   const int r = lane >> 5;
   const int c32 = lane & 31;
   const int nk = 2 * p.H_pad;
@@ -63,11 +67,10 @@ __global__ void __launch_bounds__(MAXT) step3_bf16x3(Step3Args p) {
   // this pair's chunks of Zhat, already split: chunk c is QH rows of 128
   // bytes (16 words hi, 16 words lo), 8 float4 per row, contiguous
   const float4* zsp = static_cast<const float4*>(p.zs) + static_cast<size_t>(pair) * QH * (nk / 4);
-  float2* twl = reinterpret_cast<float2*>(smem);
-  float* region = smem + 4 * QH;
+  const float4* znext =
+      static_cast<const float4*>(p.zs) + static_cast<size_t>(next_pair < 0 ? pair : next_pair) * QH * (nk / 4);
   const int buf_words = QH * ROWW;
   const int nthr = blockDim.x;
-  for (int i = tid; i < 2 * QH; i += nthr) twl[i] = p.tw_qa[i];
   constexpr int MAXF4 = 2;
   const int nf4 = QH * (KC / 4);
   auto fetch = [&](int kc, int t) { return load_stream(zsp + static_cast<size_t>(kc / KC) * nf4 + t); };
@@ -75,12 +78,8 @@ __global__ void __launch_bounds__(MAXT) step3_bf16x3(Step3Args p) {
   auto put = [&](int buf, int t, float4 v) {
     *reinterpret_cast<float4*>(region + buf * buf_words + (t >> 3) * ROWW + (t & 7) * 4) = v;
   };
-  for (int t = tid; t < nf4; t += nthr) put(0, t, fetch(0, t));
-  __syncthreads();
-  f32x16 acc[CTQ];
 #pragma unroll
   for (int ct = 0; ct < CTQ; ++ct) acc[ct] = zero16();
-  const bool active = d0 < p.N;
   // shift panel in MFMA lane order: [row tile][K step][lane][8] for hi and lo
   const size_t tile = static_cast<size_t>(min(d0, p.N_pad - 16) / 16) * nks;
   const bf16x8* yhi = reinterpret_cast<const bf16x8*>(p.yt_hi) + tile * 64 + lane;
@@ -108,9 +107,14 @@ __global__ void __launch_bounds__(MAXT) step3_bf16x3(Step3Args p) {
     const bool more = kc + KC < nk;
     float4 nreg[MAXF4];
     if (PREF) {
-      const int kn = more ? kc + KC : kc;  // the last chunk re-reads itself
+      if (more || next_pair < 0) {
+        const int kn = more ? kc + KC : kc;  // the last chunk re-reads itself
 #pragma unroll
-      for (int k = 0; k < MAXF4; ++k) nreg[k] = fetch(kn, min(tid + k * nthr, nf4 - 1));
+        for (int k = 0; k < MAXF4; ++k) nreg[k] = fetch(kn, min(tid + k * nthr, nf4 - 1));
+      } else {
+#pragma unroll
+        for (int k = 0; k < MAXF4; ++k) nreg[k] = load_stream(znext + min(tid + k * nthr, nf4 - 1));
+      }
     }
     load_y(kc + KC, nh, nl);
     __builtin_amdgcn_sched_barrier(0);
@@ -138,6 +142,13 @@ __global__ void __launch_bounds__(MAXT) step3_bf16x3(Step3Args p) {
         for (int t = tid; t < nf4; t += nthr) put(cur ^ 1, t, fetch(kc + KC, t));
       }
       __syncthreads();
+    } else if (PREF && next_pair >= 0) {
+      // the last chunk is in buffer 1 (an even number of chunks): buffer 0 is free
+#pragma unroll
+      for (int k = 0; k < MAXF4; ++k) {
+        const int t = tid + k * nthr;
+        if (t < nf4) put(0, t, nreg[k]);
+      }
     }
   };
   bf16x8 yah[KC / 16], yal[KC / 16], ybh[KC / 16], ybl[KC / 16];
@@ -147,10 +158,85 @@ __global__ void __launch_bounds__(MAXT) step3_bf16x3(Step3Args p) {
     chunk(kc, yah, yal, ybh, ybl);
     chunk(kc + KC, ybh, ybl, yah, yal);
   }
+}
+
+// The first Zhat chunk of `pair` into LDS buffer 0.
+template <int CTQ>
+__device__ __forceinline__ void bf16_first_chunk(const Step3Args& p, float* region, int pair) {
+  constexpr int QH = 32 * CTQ;
+  const int nf4 = QH * 8;
+  const float4* zsp = static_cast<const float4*>(p.zs) + static_cast<size_t>(pair) * QH * (2 * p.H_pad / 4);
+  for (int t = threadIdx.x; t < nf4; t += blockDim.x)
+    *reinterpret_cast<float4*>(region + (t >> 3) * 36 + (t & 7) * 4) = load_stream(zsp + t);
+}
+
+template <int CTQ, int MAXT, bool PREF>
+__global__ void __launch_bounds__(MAXT) step3_bf16x3(Step3Args p) {
+  extern __shared__ float smem[];
+  constexpr int QH = 32 * CTQ;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  int pair, yb;
+  step3_block(blockIdx.x, p.nblk, p.pairs, pair, yb);
+  const int d0 = (yb * p.nwaves + wave) * 16;
+  float2* twl = reinterpret_cast<float2*>(smem);
+  float* region = smem + 4 * QH;
+  for (int i = tid; i < 2 * QH; i += blockDim.x) twl[i] = p.tw_qa[i];
+  const bool active = d0 < p.N;
+  bf16_first_chunk<CTQ>(p, region, pair);
+  __syncthreads();
+  f32x16 acc[CTQ];
+  bf16_kloop<CTQ, PREF>(p, region, pair, d0, active, acc, -1);
   __syncthreads();
   if (!active) return;
   float2* T = reinterpret_cast<float2*>(region) + wave * (epilogue_lds_bytes_per_wave() / sizeof(float2));
   step3_epilogue_reg<CTQ>(p, acc, pair, d0, T, twl, lane);
+}
+
+// Persistent form (one workgroup per CU, looping over its shift blocks) where
+// the FFT rows fit LDS beside the Zhat buffers: the next pair's first chunk is
+// stored during the last chunk of the current one, and a wave goes on to the
+// next pair's K loop as soon as its own FFT epilogue is done.
+template <int CTQ, bool PREF>
+__global__ void __launch_bounds__(1024) step3_bf16x3_p(Step3Args p) {
+  extern __shared__ float smem[];
+  constexpr int QH = 32 * CTQ;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  float2* twl = reinterpret_cast<float2*>(smem);
+  float* region = smem + 4 * QH;  // Zhat buffers
+  float2* T = reinterpret_cast<float2*>(region + 2 * QH * 36) +
+              wave * (epilogue_lds_bytes_per_wave() / sizeof(float2));
+  for (int i = tid; i < 2 * QH; i += blockDim.x) twl[i] = p.tw_qa[i];
+  const int total = p.pairs * p.nblk;
+  int b = blockIdx.x;
+  if (b >= total) return;
+  int pair, yb;
+  step3_block(b, p.nblk, p.pairs, pair, yb);
+  bf16_first_chunk<CTQ>(p, region, pair);
+  __syncthreads();
+  for (;;) {
+    const int d0 = (yb * p.nwaves + wave) * 16;
+    const bool active = d0 < p.N;
+    const int bn = b + gridDim.x;
+    int pn = 0, ybn = 0;
+    if (bn < total) step3_block(bn, p.nblk, p.pairs, pn, ybn);
+    f32x16 acc[CTQ];
+    bf16_kloop<CTQ, PREF>(p, region, pair, d0, active, acc, (PREF && bn < total) ? pn : -1);
+    __syncthreads();  // every wave is past the Zhat buffers; the next first chunk is visible
+    if (active) step3_epilogue_reg<CTQ>(p, acc, pair, d0, T, twl, lane);
+    if (bn >= total) break;
+    if (!PREF) {
+      __syncthreads();
+      bf16_first_chunk<CTQ>(p, region, pn);
+      __syncthreads();
+    }
+    b = bn;
+    pair = pn;
+    yb = ybn;
+  }
 }
 
 }  // namespace
@@ -162,6 +248,24 @@ size_t step3_bf16_lds_bytes(int Qa, int nwaves) {
   return sizeof(float2) * Qa + (k > e ? k : e);
 }
 
+// LDS of the persistent form: twiddles, Zhat buffers and FFT rows side by side
+static size_t bf16_persistent_lds(int Qa, int nwaves) {
+  const size_t QH = Qa / 2;
+  return sizeof(float2) * Qa + sizeof(float) * 2 * QH * 36 + static_cast<size_t>(nwaves) * epilogue_lds_bytes_per_wave();
+}
+
+static int bf16_device_cus() {
+  static int cached[64] = {0};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+  if (cached[dev] <= 0) {
+    int n = 0;
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0) n = 256;
+    cached[dev] = n;
+  }
+  return cached[dev];
+}
+
 template <int CTQ, int MAXT>
 static hipError_t launch_step3_bf16_t(const Step3Args& a0, hipStream_t s) {
   Step3Args a = a0;
@@ -169,10 +273,23 @@ static hipError_t launch_step3_bf16_t(const Step3Args& a0, hipStream_t s) {
   a.nblk = (a.N + per_blk - 1) / per_blk;
   const size_t nwg = static_cast<size_t>(a.pairs) * a.nblk;
   if (nwg * 64 * a.nwaves > 0xffffffffull) return hipErrorInvalidConfiguration;
+  const int nf4 = 32 * CTQ * 8, nthr = 64 * a.nwaves;
+  const bool pref = (nf4 + nthr - 1) / nthr <= 2;
+  if constexpr (MAXT == 1024) {
+    const size_t plds = bf16_persistent_lds(a.Qa, a.nwaves);
+    if (pref && plds <= 160 * 1024) {
+      auto kern = step3_bf16x3_p<CTQ, true>;
+      hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(plds));
+      if (e != hipSuccess) return e;
+      const unsigned grid = static_cast<unsigned>(std::min<size_t>(nwg, static_cast<size_t>(bf16_device_cus())));
+      hipLaunchKernelGGL(kern, dim3(grid), dim3(nthr), plds, s, a);
+      return hipGetLastError();
+    }
+  }
   const dim3 grid(static_cast<unsigned>(nwg));
   size_t lds = step3_bf16_lds_bytes(a.Qa, a.nwaves);
-  const int nf4 = 32 * CTQ * 8, nthr = 64 * a.nwaves;
-  auto kern = (nf4 + nthr - 1) / nthr <= 2 ? step3_bf16x3<CTQ, MAXT, true> : step3_bf16x3<CTQ, MAXT, false>;
+  auto kern = pref ? step3_bf16x3<CTQ, MAXT, true> : step3_bf16x3<CTQ, MAXT, false>;
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
   if (e != hipSuccess) return e;
