@@ -521,6 +521,12 @@ __global__ void __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(NW
 // are traded between adjacent lanes (adjacent zeta), so that the even lane
 // stores the real-part pair and the odd lane the imaginary-part pair, each as
 // one 32-bit word.
+// Store rows of one wave (FP16 form, plain slots): one template tile's
+// values as [template t][part c][zeta] fp16, rows of ZB / 2 words padded to
+// ZB / 2 + 4 (the two halves of a wave's rows then fall in different banks).
+__host__ __device__ constexpr int fp16_store_row_words(int zb) { return zb / 2 + 4; }
+__host__ __device__ constexpr int fp16_store_words(int zb) { return 32 * fp16_store_row_words(zb); }
+
 template <int RT, int CT, bool FOLD>
 __device__ __forceinline__ void step1_fp16_tile(const Step1Args& p, float* smem, int A, int q, int z0, int part) {
   const int tid = threadIdx.x;
@@ -592,9 +598,55 @@ __device__ __forceinline__ void step1_fp16_tile(const Step1Args& p, float* smem,
       }
     }
     // Accumulator row 8 (v / 4) + 4 r + v % 4 is template rt 16 + 4 (v / 4)
-    // + 2 r + (v % 4) / 2 (re|im in adjacent rows).  The lane's base address
-    // is formed once per tile; each store adds a scalar multiple of the pair
-    // stride.  Tiles whose 16 templates all exist store without a row test.
+    // + 2 r + (v % 4) / 2 (re|im in adjacent rows).
+    if constexpr (!FOLD) {
+      // Plain slots: each (template, part) holds ZB consecutive k' = c H_pad +
+      // z0 + zeta, whole 128-byte staging rows.  The tile goes through this
+      // wave's LDS rows so that 8 lanes store one row with 16-byte stores.
+      constexpr int SRW = fp16_store_row_words(ZB);
+      // after the image operand (the larger of a plain and a fold slot)
+      const int opw = max(p.zblk * (p.M + 4), 32 * (2 * p.M + 4));
+      uint32_t* st = reinterpret_cast<uint32_t*>(smem + opw) + wave * fp16_store_words(ZB);
+#pragma unroll
+      for (int i = 0; i < RT; ++i) {
+        const int rt = rt0 + i;
+        if (rt >= nRT) break;
+#pragma unroll
+        for (int j = 0; j < CT; ++j)
+#pragma unroll
+          for (int v = 0; v < 16; v += 2) {
+            const float xr = acc[i][j][v], xi = acc[i][j][v + 1];
+            // even lane: (re of zeta, re of zeta + 1); odd lane: (im of zeta - 1, im of zeta)
+            const float got = __builtin_bit_cast(
+                float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, odd ? xr : xi), 0xB1, 0xF, 0xF, false));
+            f16x2 w;
+            w[0] = static_cast<_Float16>(odd ? got : xr);
+            w[1] = static_cast<_Float16>(odd ? xi : got);
+            const int t = 4 * (v >> 2) + 2 * r + ((v & 3) >> 1);
+            st[(2 * t + odd) * SRW + 16 * j + (c32 >> 1)] = __builtin_bit_cast(uint32_t, w);
+          }
+        wave_sync();
+        // 16-byte units u: row (t, c) = u / (ZB / 8), segment u % (ZB / 8)
+        constexpr int SEGS = ZB / 8;
+#pragma unroll
+        for (int k = 0; k < (32 * SEGS) / 64; ++k) {
+          const int u = lane + 64 * k;
+          const int row = u / SEGS, seg = u - row * SEGS;
+          const int t = row >> 1, c = row & 1;
+          const int B = rt * 16 + t;
+          if (B < p.nB) {
+            const int kp = c * p.H_pad + z0 + 8 * seg;
+            const float4 val = *reinterpret_cast<const float4*>(st + row * SRW + 4 * seg);
+            typedef float v4f __attribute__((ext_vector_type(4)));
+            __builtin_nontemporal_store(v4f{val.x, val.y, val.z, val.w},
+                                        reinterpret_cast<v4f*>(zw + static_cast<size_t>(B) * pair_words +
+                                                               static_cast<size_t>(kp >> 6) * QH * 32 + ((kp & 63) >> 1)));
+          }
+        }
+        wave_sync();
+      }
+      continue;
+    }
 #pragma unroll
     for (int i = 0; i < RT; ++i) {
       const int rt = rt0 + i;
@@ -698,6 +750,8 @@ size_t step1_v2_lds_bytes(int M, int zb, int precision) {
   } else if (precision == 2) {
     plain = sizeof(float) * zb * (M + 4);
     fold = sizeof(float) * 32 * (2 * M + 4);
+    // plus the store rows of the 4 waves (fp16_store_words each)
+    return (plain > fold ? plain : fold) + sizeof(float) * 4 * fp16_store_words(zb);
   } else {
     plain = sizeof(float) * zb * (2 * M + 4);
     fold = sizeof(float) * 32 * (4 * M + 4);
