@@ -100,12 +100,11 @@ __device__ __forceinline__ void fp16_kloop(const Step3Args& p, float* region, in
 #pragma unroll
     for (int s = 0; s < KS; ++s) y[s] = yp[(kk / 16 + s) * 64];
   };
-  // One chunk: the MFMAs on LDS buffer (kc / KC) % 2 with the panel operands
-  // loaded one chunk earlier, then the next chunk is stored into the other
-  // buffer.  The loads are issued in the order they are consumed (next
-  // chunk's Zhat, then the panel operands of the chunk after it), so the
-  // waits before the MFMAs cover no load issued in this chunk.
-  auto chunk = [&](int kc, const f16x8 (&ay)[KS], f16x8 (&ny)[KS]) {
+  // One chunk: the MFMAs on LDS buffer (kc / KC) % 2, then the panel
+  // operands of the next chunk are loaded (one set of registers: the freed
+  // registers let all CTQ Zhat fragments of a K step be read before its
+  // MFMAs) and the next chunk is stored into the other buffer.
+  auto chunk = [&](int kc, f16x8 (&y)[KS]) {
     const int cur = (kc / KC) & 1;
     const bool more = kc + KC < nk;
     float4 nreg[MAXF4];
@@ -119,19 +118,19 @@ __device__ __forceinline__ void fp16_kloop(const Step3Args& p, float* region, in
         for (int k = 0; k < MAXF4; ++k) nreg[k] = load_stream(znext + min(tid + k * nthr, nf4 - 1));
       }
     }
-    load_y(kc + KC, ny);
     __builtin_amdgcn_sched_barrier(0);
     if (active) {
       const float* Zb = region + cur * buf_words + c32 * ROWW + 4 * r;
 #pragma unroll
       for (int s = 0; s < KS; ++s) {
+        f16x8 b[CTQ];
 #pragma unroll
-        for (int ct = 0; ct < CTQ; ++ct) {
-          const f16x8 b = *reinterpret_cast<const f16x8*>(Zb + ct * 32 * ROWW + 8 * s);
-          acc[ct] = __builtin_amdgcn_mfma_f32_32x32x16_f16(ay[s], b, acc[ct], 0, 0, 0);
-        }
+        for (int ct = 0; ct < CTQ; ++ct) b[ct] = *reinterpret_cast<const f16x8*>(Zb + ct * 32 * ROWW + 8 * s);
+#pragma unroll
+        for (int ct = 0; ct < CTQ; ++ct) acc[ct] = __builtin_amdgcn_mfma_f32_32x32x16_f16(y[s], b[ct], acc[ct], 0, 0, 0);
       }
     }
+    load_y(kc + KC, y);
     if (more) {
       if (PREF) {
 #pragma unroll
@@ -152,13 +151,10 @@ __device__ __forceinline__ void fp16_kloop(const Step3Args& p, float* region, in
       }
     }
   };
-  f16x8 y0[KS], y1[KS];
-  load_y(0, y0);
-  // nk / KC is even (H_pad is a multiple of 64)
-  for (int kc = 0; kc < nk; kc += 2 * KC) {
-    chunk(kc, y0, y1);
-    chunk(kc + KC, y1, y0);
-  }
+  f16x8 y[KS];
+  load_y(0, y);
+  // nk / KC is even (H_pad is a multiple of 64): the last chunk is in buffer 1
+  for (int kc = 0; kc < nk; kc += KC) chunk(kc, y);
 }
 
 template <int CTQ, int MAXT, bool PREF>
