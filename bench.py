@@ -400,8 +400,9 @@ def main():
         print(json.dumps({"copy_mib": args.calibrate_copy_mib, "bytes_read": n * 4, "bytes_written": n * 4}))
         return
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
-              "(the path would shard templates across GPUs, see the design notes)", file=sys.stderr)
+        print(f"bench.py: the FTK path runs on one GPU; --gpus {args.gpus} is not supported "
+              "(across GPUs the templates would be sharded, each GPU aligning every image against its share, "
+              "and the per-image best poses reduced)", file=sys.stderr)
         sys.exit(2)
     import torch
     if not torch.cuda.is_available():

@@ -17,7 +17,7 @@ pixels; a shift of d pixels is d*dx in the paper's units, so
 Kmax * |delta| = pi * |d|.  The maximum shift radius R (pixels) is 2W in the
 paper's wavelength units.
 
-Readings of the paper taken here (each listed in the design notes):
+Readings of the paper taken here (where it is silent, ambiguous or garbled):
   * pixel indices run 0..n-1 (Section 2.1 grid definition, not the 1..n of
     the trapezoid sum);
   * modes q run over -Qa/2..Qa/2-1 with Qa = 2Q angular samples
