@@ -168,8 +168,9 @@ int ftk_align(ftk_plan* plan, const float* images, int nA, const float* template
  * replace the coarse ones in best.  Each pose is the argmax over shifts and
  * rotations of the inner products of eq. fbk3, as in ftk_align_coeffs.  The
  * plans must come from the same ftk_plan_create arguments except the
- * precision, with the same shifts (FTK_EINVAL if n, K, Q, W, eps, N or H
- * differ); ftk_transform gives the same coefficients under either plan.
+ * precision (FTK_EINVAL if n, K, Q, W, eps or H differ), and the caller sets
+ * the same shifts on both (only their count N is checked); ftk_transform
+ * gives the same coefficients under either plan.
  *   best      : device ftk_pose [nA][nB], every pair
  *   best_t    : device int32 [nA]: per image, the template with the largest
  *               refined value (ties: lower template number), or NULL
