@@ -54,3 +54,25 @@ def test_more_than_one_gpu_is_refused():
                        text=True, timeout=120)
     assert r.returncode == 2
     assert "one GPU" in r.stderr
+
+
+def _sha1_of(names):
+    import hashlib
+    h = hashlib.sha1()
+    for name in names:
+        with open(os.path.join(ROOT, "paper_1905_12317_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def test_traffic_is_null_once_the_kernel_sources_change(monkeypatch):
+    """The recorded HBM bytes of a Step 3 kernel are reported only while the
+    sources they were measured on are unchanged (SHA-1 over the listed files)."""
+    fresh = dict(bench.TRAFFIC["fp16"])
+    fresh["sha1"] = _sha1_of(fresh["sources"])
+    monkeypatch.setitem(bench.TRAFFIC, "fp16", fresh)
+    assert bench.measured_traffic("fp16") == fresh["bytes_per_launch"]
+    stale = dict(bench.TRAFFIC["fp16"], sha1="0" * 40)
+    monkeypatch.setitem(bench.TRAFFIC, "fp16", stale)
+    assert bench.measured_traffic("fp16") is None
+    assert bench.measured_traffic("fp16+bf16x3") is None  # no entry of its own
