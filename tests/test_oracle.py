@@ -435,3 +435,86 @@ def test_lattice_counts_golden():
     g = _gold("lattice_counts.json")
     for R, cnt in g["counts"].items():
         assert len(synth.shift_lattice(float(R))) == cnt
+
+
+# ------------------------------------------ error scale and pose margin, exact
+
+def _scale_pin_devs(scale_fn, c):
+    """Relative deviations of a pair-scale function from what fixes it
+    exactly: s_AA = Re X_dir,AA(0, 0) (the direct polar inner product of
+    eq. Xdg at zero shift and rotation, with no Fourier-Bessel step),
+    s_AB^2 = X_AA(0, 0) X_BB(0, 0), and, for band-limited blobs, Parseval's
+    (2 pi)^2 dx^2 sum_ij A_ij^2 (eq. planch)."""
+    plan, n = c["plan"], c["n"]
+    a, b = O.ring_coefficients(c["Ah"]), O.ring_coefficients(c["Bh"])
+    zero = np.zeros((1, 2))
+    xaa = float(O.direct_X(c["Ah"], c["Ah"], plan.k, plan.w, zero, n)[0, 0].real)
+    xbb = float(O.direct_X(c["Bh"], c["Bh"], plan.k, plan.w, zero, n)[0, 0].real)
+    dx = 2.0 / n
+    pars = (2 * math.pi) ** 2 * dx * dx * float(np.sum(c["Ai"] ** 2))
+    return [abs(scale_fn(a, a, plan) - xaa) / xaa,
+            abs(scale_fn(b, b, plan) - xbb) / xbb,
+            abs(scale_fn(a, b, plan) ** 2 - xaa * xbb) / (xaa * xbb),
+            abs(scale_fn(a, a, plan) - pars) / pars]
+
+
+def test_pair_scale_exact(blob_case):
+    devs = _scale_pin_devs(O.pair_scale, blob_case)
+    assert max(devs[:3]) < 1e-12, devs
+    assert devs[3] < 1e-10, devs
+
+
+def test_pair_scale_planted_mistakes_fail():
+    # an extra 2 pi, a missing square root, a dropped radial weight: each must
+    # break the exact pins (an overestimate would loosen every parity bar)
+    n = 64
+    A, B, Ai, Bi = _blob_pair(3, n)
+    plan = O.make_plan(n, 32, 128, 2.0, 1e-8)
+    c = dict(n=n, plan=plan, Ai=Ai, Ah=O.polar_ft(Ai, plan.k, 128), Bh=O.polar_ft(Bi, plan.k, 128))
+    assert max(_scale_pin_devs(O.pair_scale, c)) < 1e-10
+    bad = [lambda a, b, p: 2 * math.pi * O.pair_scale(a, b, p),
+           lambda a, b, p: O.pair_scale(a, b, p) ** 2,
+           lambda a, b, p: O.pair_scale(a, b, _replaced(p, w=np.full_like(p.w, p.w.mean())))]
+    for f in bad:
+        assert max(_scale_pin_devs(f, c)) > 1e-2
+
+
+def _replaced(plan, **kw):
+    import copy
+    q = copy.copy(plan)
+    for k, v in kw.items():
+        setattr(q, k, v)
+    return q
+
+
+def _margin_pin(pose_fn):
+    """Distinct values with a known best, position and margin; a large
+    imaginary part that must not count (argmax of Re X)."""
+    rng = np.random.default_rng(31)
+    vals = rng.permutation(35).astype(np.float64) * 1.5 + 0.25  # 0.25, 1.75, ..., 51.25
+    X = vals.reshape(5, 7) + 1j * rng.uniform(-200, 200, (5, 7))
+    where = int(np.argmax(vals))
+    v, si, ri, margin = pose_fn(X)
+    return (v, si, ri, margin) == (51.25, where // 7, where % 7, 1.5)
+
+
+def test_best_pose_margin_exact():
+    assert _margin_pin(O.best_pose)
+    # a single pose has no second best: infinite margin
+    assert O.best_pose(np.array([[3.0]]))[3] == np.inf
+
+
+def test_best_pose_planted_mistakes_fail():
+    def second_equals_best(X):
+        v, si, ri, _ = O.best_pose(X)
+        return v, si, ri, 0.0
+
+    def magnitude(X):
+        return O.best_pose(np.abs(X))
+
+    def swapped_indices(X):
+        v, si, ri, m = O.best_pose(X)
+        return v, ri, si, m
+
+    for f in (second_equals_best, magnitude, swapped_indices):
+        assert not _margin_pin(f)
