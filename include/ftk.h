@@ -100,11 +100,17 @@ typedef struct ftk_plan_info_t {
  * current HIP device).
  *   n       : image side, 4 <= n <= 1024, even
  *   K       : radial quadrature nodes M, 1 <= K <= 512 (Gauss-Jacobi(0,1)
- *             rule for k dk on [0, pi n/2], Section 3.1)
- *   Q       : angular samples Qa = number of modes = number of rotations;
- *             even, of the form 2^a 3^b, 8 <= Q <= 4096 (eq. aqkcalc with
- *             Qa = 2Q of the paper)
+ *             rule for k dk on [0, pi n/2], Section 3.1); the reduced
+ *             precision forms (every form but FTK_FP32) need K to be a
+ *             multiple of 8 (FTK_EUNSUPPORTED otherwise)
+ *   Q       : angular samples Qa = number of modes = number of rotations
+ *             (eq. aqkcalc with Qa = 2Q of the paper).  The device kernels
+ *             take Q in {64, 128, 192, 256, 384} (a multiple of 64 of the
+ *             form 2^a 3^b, at most 384); any other Q is FTK_EUNSUPPORTED,
+ *             an odd Q or Q outside [8, 4096] FTK_EINVAL
  *   W       : maximum shift radius in pixels, 0 < W <= n/4
+ *   (n)     : besides, the transform's oversampled grid (the smallest
+ *             2^a 3^b >= 2n) must not exceed 4096 (FTK_EUNSUPPORTED)
  *   eps     : truncation level, every operator singular value > eps is
  *             kept (Section 4.5 and Theorem t:rank), 0 < eps < 1
  *   precision : ftk_precision

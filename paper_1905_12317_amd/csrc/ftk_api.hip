@@ -329,7 +329,8 @@ int check_plan_args(int n, int K, int Q, double W, double eps, int precision) {
     return fail(FTK_EUNSUPPORTED, "the bf16x3 and fp16 forms need K (radial nodes) to be a multiple of 8");
   if (!ftkplan::fft_supported(Q) || Q % 64 != 0 || Q > 384)
     return fail(FTK_EUNSUPPORTED, "Q must be a multiple of 64 of the form 2^a 3^b, at most 384");
-  if (ftkplan::fft_size(2 * n) > 4096) return fail(FTK_EUNSUPPORTED, "image too large for the transform");
+  const int nf = ftkplan::fft_size(2 * n);
+  if (nf <= 0 || nf > 4096) return fail(FTK_EUNSUPPORTED, "image too large for the transform");
   return FTK_OK;
 }
 

@@ -309,8 +309,9 @@ bool fft_supported(int L) {
 }
 
 int fft_size(int n) {
-  for (int L = std::max(n, 2);; ++L)
+  for (int L = std::max(n, 2); L <= 4096; ++L)
     if (fft_supported(L)) return L;
+  return 0;  // beyond the largest supported length
 }
 
 SpreadKernel spread_kernel(int n, int w) {

@@ -71,7 +71,8 @@ struct SpreadKernel {
 };
 SpreadKernel spread_kernel(int n, int w);
 
-// Smallest length >= n of the form 2^a 3^b that the device FFT supports.
+// Smallest length >= n of the form 2^a 3^b that the device FFT supports
+// (at most 4096); 0 when n > 4096.
 int fft_size(int n);
 bool fft_supported(int L);
 
