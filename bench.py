@@ -1,6 +1,6 @@
 """Throughput of the FTK hot path on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--form fp32|bf16x3|fp16|fp16+bf16x3|all]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--form fp32|bf16x3|fp16x3|fp16|fp16+bf16x3|all]
 
 One step = one pass of the whole hot path over one batch of synthetic
 input already resident in HBM: transform of the 512 images and the 2048
@@ -9,7 +9,8 @@ contraction per mode), Step 3 (shift contraction, 197 shifts), the rotation
 FFT over all 256 rotations and the best pose of every pair.  Planning and
 the shift table are built once, outside the timed region.
 
-Forms: fp32, bf16x3 (split bf16, three products), fp16 (one product), and
+Forms: fp32, bf16x3 (split bf16, three products), fp16x3 (split fp16 on
+power-of-two scaled operands, three products), fp16 (one product), and
 fp16+bf16x3 (the FP16 form over every pair, then the split form on each
 image's four best FP16 templates; its per-image best comes from the second
 pass).
@@ -382,7 +383,7 @@ def main():
                          "learned-proposal measurements, each printing its own JSON line")
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--form", default="all", choices=["fp32", "bf16x3", "fp16", "fp16+bf16x3", "all"])
+    ap.add_argument("--form", default="all", choices=["fp32", "bf16x3", "fp16x3", "fp16", "fp16+bf16x3", "all"])
     ap.add_argument("--lanes", type=int, default=4, help="ragged workload: concurrent lanes of the batch (1-4)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
@@ -419,7 +420,7 @@ def main():
     shifts = synth.shift_lattice(w["R"])
     log(f"inputs generated in {time.perf_counter() - t:.1f} s: {w['n_images']} x {w['n_templates']} "
         f"n={w['n']} N={len(shifts)}")
-    forms = ["fp32", "bf16x3", "fp16", "fp16+bf16x3"] if args.form == "all" else [args.form]
+    forms = ["fp32", "bf16x3", "fp16x3", "fp16", "fp16+bf16x3"] if args.form == "all" else [args.form]
     results = {}
     for f in forms:
         try:
@@ -454,7 +455,7 @@ def main():
         "metric": METRIC, "value": r["pairs_per_s"], "unit": "pairs/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": r["ms_per_step"], "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"fp32": "f32", "bf16x3": "bf16x3->f32", "fp16": "f16->f32",
+        "dtype": {"fp32": "f32", "bf16x3": "bf16x3->f32", "fp16x3": "f16x3->f32", "fp16": "f16->f32",
                   "fp16+bf16x3": "f16->f32, top-4 per image refined in bf16x3->f32"}[chosen],
         "data": "synthetic",
         "config": {"workload": f"{w['name']}: {w['n_images']} images x {w['n_templates']} templates, n={w['n']}, "
@@ -479,8 +480,9 @@ def main():
                      "frac": achieved / peak, "traffic": traffic,
                      "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                      "traffic_GBps": traffic / avg3 / 1e9 if traffic and avg3 > 0 else None,
-                     "products_per_mac": 3 if chosen == "bf16x3" else 1,
-                     "frac_of_form_ceiling": (achieved / (peak / 3) if chosen == "bf16x3" else achieved / peak),
+                     "products_per_mac": 3 if chosen in ("bf16x3", "fp16x3") else 1,
+                     "frac_of_form_ceiling": (achieved / (peak / 3) if chosen in ("bf16x3", "fp16x3")
+                                              else achieved / peak),
                      "algorithmic_flop_per_pair": s3, "pairs_per_launch": per_launch_pairs,
                      "avg_launch_ms": avg3 * 1e3,
                      "step1_achieved": (s1 * pairs * args.steps / max(n1, 1)) / (ms1 / max(n1, 1) / 1e3) / 1e12

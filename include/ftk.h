@@ -65,7 +65,11 @@ typedef enum ftk_precision {
                      (the 2 pi w G rows and the shift panel), Section 4.5 factors
                      kept in FP64 on the host.  About 11 significant bits per
                      operand: errors of a few 1e-4 of the pair scale, for
-                     eps >= 1e-3 */
+                     eps >= 1e-3 */,
+  FTK_FP16X3 = 3  /* split fp16 (hi + lo) with three products, FP32 accumulate,
+                     on the power-of-two scaled operands of FTK_FP16: about 22
+                     significant bits per product (errors of order 1e-6 of the
+                     pair scale), for eps down to 1e-5 */
 } ftk_precision;
 
 /* Best pose of one image-template pair: the largest Re X over the shift

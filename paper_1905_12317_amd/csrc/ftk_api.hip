@@ -130,6 +130,13 @@ uint16_t f16_rne(double x) {
   return sign | static_cast<uint16_t>((ef << 10) | m);
 }
 
+// value of finite IEEE binary16 bits: (1024 + m) 2^(e - 25), or m 2^-24 for e = 0
+double f16_value(uint16_t h) {
+  const int e = (h >> 10) & 31, m = h & 1023;
+  const double v = e == 0 ? std::ldexp(static_cast<double>(m), -24) : std::ldexp(static_cast<double>(1024 + m), e - 25);
+  return (h & 0x8000) ? -v : v;
+}
+
 double bf16_value(uint16_t h) {
   const uint32_t u = static_cast<uint32_t>(h) << 16;
   float f;
@@ -263,8 +270,8 @@ int upload_plan_tables(ftk_plan* p) {
   for (int z = 0; z < H; ++z) {
     ell[z] = p->t.ell[z];
     double sg = 1.0;
-    if (p->precision == FTK_FP16) {
-      // the FP16 form stores the row divided by the power of two at or above
+    if (p->precision == FTK_FP16 || p->precision == FTK_FP16X3) {
+      // the fp16 forms store the row divided by the power of two at or above
       // its largest entry; the shift panel carries that factor
       double mx = 0.0;
       for (int m = 0; m < M; ++m)
@@ -323,7 +330,7 @@ int check_plan_args(int n, int K, int Q, double W, double eps, int precision) {
   if (Q < 8 || Q > 4096 || (Q & 1)) return fail(FTK_EINVAL, "Q must be even and in [8, 4096]");
   if (!(W > 0.0) || W > n / 4.0) return fail(FTK_EINVAL, "W (shift radius, px) must be in (0, n/4]");
   if (!(eps > 0.0) || !(eps < 1.0)) return fail(FTK_EINVAL, "eps must be in (0, 1)");
-  if (precision != FTK_FP32 && precision != FTK_BF16X3 && precision != FTK_FP16)
+  if (precision != FTK_FP32 && precision != FTK_BF16X3 && precision != FTK_FP16 && precision != FTK_FP16X3)
     return fail(FTK_EINVAL, "unknown precision");
   if (precision != FTK_FP32 && K % 8 != 0)
     return fail(FTK_EUNSUPPORTED, "the bf16x3 and fp16 forms need K (radial nodes) to be a multiple of 8");
@@ -355,7 +362,7 @@ int step3_waves(const ftk_plan* p) {
   int maxw = std::max(1, std::min(p->tune.step3_waves, (p->Qa / 64 > 4) ? 8 : 16));
   const int prec = prec_code(p);
   auto lds = [&](int w) {
-    return prec == 1 ? step3_bf16_lds_bytes(p->Qa, w)
+    return (prec == 1 || prec == 3) ? step3_bf16_lds_bytes(p->Qa, w)
                      : (prec == 2 ? (p->rot16.ptr ? step3_fp16_rot_lds_bytes(p->Qa, w) : step3_fp16_lds_bytes(p->Qa, w))
                                   : step3_lds_bytes(p->Qa, w));
   };
@@ -392,7 +399,7 @@ Needs plan_needs(const ftk_plan* p, int nA, int nB, bool from_pixels) {
     d.stage = static_cast<size_t>(d.chunk_images) * nB * per_pair;
     d.keys = static_cast<size_t>(nA) * nB * sizeof(unsigned long long);
     d.tmpl = tmpl_prep_bytes(nB, p->M, p->Qa, prec_code(p));
-    d.scales = prec_code(p) == 2 ? 64 : 0;
+    d.scales = (prec_code(p) == 2 || prec_code(p) == 3) ? 64 : 0;
   }
   return d;
 }
@@ -406,7 +413,7 @@ Needs plan_needs_lists(const ftk_plan* p, int nA, int K) {
   d.stage = static_cast<size_t>(d.chunk_images) * K * per_pair;
   d.keys = static_cast<size_t>(nA) * K * sizeof(unsigned long long);
   d.tmpl = tmpl_prep_tile_bytes(static_cast<size_t>(d.chunk_images) * ((K + 15) / 16), p->M, p->Qa, prec_code(p));
-  d.scales = prec_code(p) == 2 ? 64 : 0;
+  d.scales = (prec_code(p) == 2 || prec_code(p) == 3) ? 64 : 0;
   return d;
 }
 
@@ -549,59 +556,58 @@ int ftk_set_shifts(ftk_plan* p, const double* shifts_px, int N) {
     }
   hipError_t e = upload(p->yt, yt);
   if (e != hipSuccess) return hip_fail(e, "ftk_set_shifts: upload");
+  // reduced-precision copies in MFMA lane order: [row tile][K step][lane][8],
+  // row tile = 32 embedded rows (16 shifts), K step = 16 embedded terms; lane
+  // l holds row l % 32 and k = 8 (l / 32) .. +7 of the step
+  const int nrt = 2 * Np / 32, nks = 2 * Hp / 16;
+  // the FP64 value of an embedded entry, times sg_zeta in the fp16 forms
+  auto entry = [&](int row, int k) {
+    const int d = row >> 1, z = k % Hp;
+    if (d >= N || z >= H) return 0.0;
+    const std::complex<double> y = Y[static_cast<size_t>(d) * H + z];
+    const int c = row & 1, cp = k / Hp;
+    return ((c == cp) ? y.real() : (c == 0 ? -y.imag() : y.imag())) * p->zeta_scale[z];
+  };
+  auto at = [&](int rt, int ks, int l, int e8) { return ((static_cast<size_t>(rt) * nks + ks) * 64 + l) * 8 + e8; };
   if (p->precision == FTK_BF16X3) {
-    // split hi/lo bf16 copies in MFMA lane order: [row tile][K step][lane][8],
-    // row tile = 32 embedded rows (16 shifts), K step = 16 embedded terms;
-    // lane l holds row l % 32 and k = 8 (l / 32) .. +7 of the step
-    const int nrt = 2 * Np / 32, nks = 2 * Hp / 16;
+    // split hi/lo bf16 copies
     std::vector<uint16_t> hi(static_cast<size_t>(nrt) * nks * 512), lo(hi.size());
     for (int rt = 0; rt < nrt; ++rt)
       for (int ks = 0; ks < nks; ++ks)
         for (int l = 0; l < 64; ++l)
           for (int e8 = 0; e8 < 8; ++e8) {
-            const int row = rt * 32 + (l & 31);
-            const int k = ks * 16 + 8 * (l >> 5) + e8;
-            // the FP64 value of the embedded entry
-            double v = 0.0;
-            const int d = row >> 1, z = k % Hp;
-            if (d < N && z < H) {
-              const std::complex<double> y = Y[static_cast<size_t>(d) * H + z];
-              const int c = row & 1, cp = k / Hp;
-              v = (c == cp) ? y.real() : (c == 0 ? -y.imag() : y.imag());
-            }
-            const size_t at = ((static_cast<size_t>(rt) * nks + ks) * 64 + l) * 8 + e8;
-            hi[at] = bf16_rne(static_cast<float>(v));
-            lo[at] = bf16_rne(static_cast<float>(v - bf16_value(hi[at])));
+            const double v = entry(rt * 32 + (l & 31), ks * 16 + 8 * (l >> 5) + e8);
+            const size_t i = at(rt, ks, l, e8);
+            hi[i] = bf16_rne(static_cast<float>(v));
+            lo[i] = bf16_rne(static_cast<float>(v - bf16_value(hi[i])));
           }
     if ((e = upload(p->yt_hi, hi)) != hipSuccess) return hip_fail(e, "ftk_set_shifts: upload");
     if ((e = upload(p->yt_lo, lo)) != hipSuccess) return hip_fail(e, "ftk_set_shifts: upload");
   }
-  if (p->precision == FTK_FP16) {
-    // fp16 panel in MFMA lane order (as the split form's hi part), column
-    // zeta multiplied by sg_zeta and the whole panel divided by the power of
-    // two s_y at or above its largest entry
-    const int nrt = 2 * Np / 32, nks = 2 * Hp / 16;
-    auto entry = [&](int row, int k) {
-      const int d = row >> 1, z = k % Hp;
-      if (d >= N || z >= H) return 0.0;
-      const std::complex<double> y = Y[static_cast<size_t>(d) * H + z];
-      const int c = row & 1, cp = k / Hp;
-      return ((c == cp) ? y.real() : (c == 0 ? -y.imag() : y.imag())) * p->zeta_scale[z];
-    };
+  if (p->precision == FTK_FP16 || p->precision == FTK_FP16X3) {
+    // fp16 panel, column zeta multiplied by sg_zeta and the whole panel
+    // divided by the power of two s_y at or above its largest entry; the
+    // split fp16 form also keeps lo = fp16(v - hi), rounded from FP64
     double mx = 0.0;
     for (int row = 0; row < 2 * N; ++row)
       for (int k = 0; k < 2 * Hp; ++k) mx = std::max(mx, std::fabs(entry(row, k)));
     const double sy = pow2_at_or_above(mx);
-    std::vector<uint16_t> h16(static_cast<size_t>(nrt) * nks * 512);
+    const bool split = p->precision == FTK_FP16X3;
+    // the split form lifts the panel to the top of the fp16 range (its lo
+    // parts then stay normal numbers down to 2^-18 of the largest entry)
+    const double ysc = split ? std::ldexp(1.0, split_f16_exps(p->M).data) : 1.0;
+    std::vector<uint16_t> h16(static_cast<size_t>(nrt) * nks * 512), l16(split ? h16.size() : 0);
     for (int rt = 0; rt < nrt; ++rt)
       for (int ks = 0; ks < nks; ++ks)
         for (int l = 0; l < 64; ++l)
           for (int e8 = 0; e8 < 8; ++e8) {
-            const int row = rt * 32 + (l & 31);
-            const int k = ks * 16 + 8 * (l >> 5) + e8;
-            h16[((static_cast<size_t>(rt) * nks + ks) * 64 + l) * 8 + e8] = f16_rne(entry(row, k) / sy);
+            const double v = entry(rt * 32 + (l & 31), ks * 16 + 8 * (l >> 5) + e8) / sy * ysc;
+            const size_t i = at(rt, ks, l, e8);
+            h16[i] = f16_rne(v);
+            if (split) l16[i] = f16_rne(v - f16_value(h16[i]));
           }
     if ((e = upload(p->yt_hi, h16)) != hipSuccess) return hip_fail(e, "ftk_set_shifts: upload");
+    if (split && (e = upload(p->yt_lo, l16)) != hipSuccess) return hip_fail(e, "ftk_set_shifts: upload");
     p->y_scale = static_cast<float>(sy);
   }
   p->N = N;
@@ -678,13 +684,16 @@ int align_impl(ftk_plan* p, const void* img_coeffs, int nA, const void* tmpl_coe
   if ((e = launch_keys_init(keys, pairs, s)) != hipSuccess) return hip_fail(e, "ftk_align: keys init");
   p->timer.end(ev, s, 3);
   const float2* bco = static_cast<const float2*>(tmpl_coeffs);
-  // FP16 form: the per-call data scales, [max|a|, max|b|, 1/s_a, 1/s_b, s_a s_b s_y]
-  float* scales = prec == 2 ? ws.scales.as<float>() : nullptr;
+  // fp16 forms: the per-call data scales, [max|a|, max|b|, 2^e/s_a, 2^e/s_b,
+  // s_a s_b s_y 2^e_x, 2^e_z] (exponents 0 in the FP16 form, split_f16_exps
+  // in the split-fp16 form)
+  float* scales = (prec == 2 || prec == 3) ? ws.scales.as<float>() : nullptr;
   if (scales) {
     ev = p->timer.begin(s);
     const size_t per = static_cast<size_t>(2) * p->Qa * p->M;
+    const SplitF16Exps x = prec == 3 ? split_f16_exps(p->M) : SplitF16Exps{0, 0, 0};
     if ((e = launch_fp16_scales(static_cast<const float*>(img_coeffs), per * nA, reinterpret_cast<const float*>(bco),
-                                per * nB, p->y_scale, scales, s)) != hipSuccess)
+                                per * nB, p->y_scale, scales, x.data, x.x, x.z, s)) != hipSuccess)
       return hip_fail(e, "ftk_align: fp16 scales");
     p->timer.end(ev, s, 4);
   }
@@ -753,7 +762,8 @@ int align_impl(ftk_plan* p, const void* img_coeffs, int nA, const void* tmpl_coe
     a3.keys = keys + static_cast<size_t>(A0) * nBe;
     a3.X = X ? X + static_cast<size_t>(A0) * nBe * p->N * p->Qa : nullptr;
     ev = p->timer.begin(s);
-    e = prec == 1 ? launch_step3_bf16(a3, s) : (prec == 2 ? launch_step3_fp16(a3, s) : launch_step3(a3, p->precision, s));
+    e = (prec == 1 || prec == 3) ? launch_step3_bf16(a3, prec == 3, s)
+                                 : (prec == 2 ? launch_step3_fp16(a3, s) : launch_step3(a3, p->precision, s));
     if (e != hipSuccess) return hip_fail(e, "ftk_align: step 3");
     p->timer.end(ev, s, 2);
   }

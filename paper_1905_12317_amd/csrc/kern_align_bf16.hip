@@ -1,19 +1,24 @@
-// Step 3 of the FTK in split-bf16 form on gfx950 MFMA.
+// Step 3 of the FTK in split form on gfx950 MFMA: split bf16 (FTK_BF16X3) and
+// split fp16 (FTK_FP16X3).
 //
 // Every operand x of the two contractions is written as x = hi + lo with
-// hi = bf16(x) and lo = bf16(x - hi) (round to nearest even), and each
-// product uses three bf16 MFMAs with FP32 accumulation:
-//     A B ~ A_hi B_hi + A_hi B_lo + A_lo B_hi,
-// which keeps about 16 significant bits per product (the dropped A_lo B_lo
-// and the rounding of lo are O(2^-16) relative).  The quadrature weights and
-// the operator SVD stay FP64 on the host; only their FP32 products enter.
+// hi = T(x) and lo = T(x - hi) (round to nearest even, T = bf16 or fp16),
+// and each product uses three MFMAs with FP32 accumulation:
+//     A B ~ A_hi B_hi + A_hi B_lo + A_lo B_hi.
+// With bf16 (8 significant bits) this keeps about 16 bits per product; with
+// fp16 (11 bits) about 22, but fp16 has a narrow exponent range, so the fp16
+// form runs on operands scaled by powers of two (per call for the data, per
+// SVD term for the tables, as the FP16 form: Zhat / (s_a s_b sg_zeta) is
+// bounded by 2M, the scaled shift panel by 1) and multiplies X back when it
+// is stored.  The quadrature weights and the operator SVD stay FP64 on the
+// host; only their FP32 products enter.
 //
 // Data flow is that of the FP32 form (kern_align.hip): Step 1
 // (kern_step1.hip) writes Zhat, already split into hi + lo and in chunks of
 // 32 k' laid out as Step 3 stages them, Step 3 copies the chunks into LDS
 // and ends with the same rotation FFT and argmax.
-// MFMA: v_mfma_f32_32x32x16_bf16; lane l holds rows/cols l % 32 and the
-// 8 consecutive k = 8 (l / 32) .. +7 of each 16-wide K step.
+// MFMA: v_mfma_f32_32x32x16_bf16 / _f16; lane l holds rows/cols l % 32 and
+// the 8 consecutive k = 8 (l / 32) .. +7 of each 16-wide K step.
 #include <algorithm>
 
 #include "device_common.h"
@@ -24,6 +29,7 @@ using namespace ftkdev;
 
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 
 namespace {
 
@@ -34,10 +40,29 @@ __device__ __forceinline__ f32x16 zero16() {
   return z;
 }
 
-__device__ __forceinline__ f32x16 mfma3(bf16x8 ahi, bf16x8 alo, bf16x8 bhi, bf16x8 blo, f32x16 c) {
-  c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ahi, bhi, c, 0, 0, 0);
-  c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ahi, blo, c, 0, 0, 0);
-  c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(alo, bhi, c, 0, 0, 0);
+// element type of a split form: its 8-wide MFMA operand and the 32x32x16 MFMA
+template <class T>
+struct Split;
+template <>
+struct Split<__bf16> {
+  typedef bf16x8 v8;
+  static __device__ __forceinline__ f32x16 mma(v8 a, v8 b, f32x16 c) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+  }
+};
+template <>
+struct Split<_Float16> {
+  typedef f16x8 v8;
+  static __device__ __forceinline__ f32x16 mma(v8 a, v8 b, f32x16 c) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, c, 0, 0, 0);
+  }
+};
+
+template <class T, class V>
+__device__ __forceinline__ f32x16 mfma3(V ahi, V alo, V bhi, V blo, f32x16 c) {
+  c = Split<T>::mma(ahi, bhi, c);
+  c = Split<T>::mma(ahi, blo, c);
+  c = Split<T>::mma(alo, bhi, c);
   return c;
 }
 
@@ -52,8 +77,8 @@ __device__ __forceinline__ f32x16 mfma3(bf16x8 ahi, bf16x8 alo, bf16x8 bhi, bf16
 // PREF: the block has enough threads to prefetch a whole chunk in MAXF4
 // float4 per thread (double buffering through registers); otherwise each
 // chunk is fetched after the MFMAs of the previous one.
-template <int CTQ, bool PREF>
-__device__ __forceinline__ void bf16_kloop(const Step3Args& p, float* region, int pair, int d0, bool active,
+template <class T, int CTQ, bool PREF>
+__device__ __forceinline__ void split_kloop(const Step3Args& p, float* region, int pair, int d0, bool active,
                                            f32x16 (&acc)[CTQ], int next_pair) {
   constexpr int QH = 32 * CTQ;
   constexpr int KC = 32;     // k' per staged chunk (2 MFMA K steps)
@@ -71,6 +96,7 @@ __device__ __forceinline__ void bf16_kloop(const Step3Args& p, float* region, in
       static_cast<const float4*>(p.zs) + static_cast<size_t>(next_pair < 0 ? pair : next_pair) * QH * (nk / 4);
   const int buf_words = QH * ROWW;
   const int nthr = blockDim.x;
+  typedef typename Split<T>::v8 V;
   constexpr int MAXF4 = 2;
   const int nf4 = QH * (KC / 4);
   auto fetch = [&](int kc, int t) { return load_stream(zsp + static_cast<size_t>(kc / KC) * nf4 + t); };
@@ -82,11 +108,11 @@ __device__ __forceinline__ void bf16_kloop(const Step3Args& p, float* region, in
   for (int ct = 0; ct < CTQ; ++ct) acc[ct] = zero16();
   // shift panel in MFMA lane order: [row tile][K step][lane][8] for hi and lo
   const size_t tile = static_cast<size_t>(min(d0, p.N_pad - 16) / 16) * nks;
-  const bf16x8* yhi = reinterpret_cast<const bf16x8*>(p.yt_hi) + tile * 64 + lane;
-  const bf16x8* ylo = reinterpret_cast<const bf16x8*>(p.yt_lo) + tile * 64 + lane;
+  const V* yhi = reinterpret_cast<const V*>(p.yt_hi) + tile * 64 + lane;
+  const V* ylo = reinterpret_cast<const V*>(p.yt_lo) + tile * 64 + lane;
   // shift-panel operands of the chunk at kc (past the end: the last chunk
   // again, so the loads need no condition)
-  auto load_y = [&](int kc, bf16x8 (&yh)[KC / 16], bf16x8 (&yl)[KC / 16]) {
+  auto load_y = [&](int kc, V (&yh)[KC / 16], V (&yl)[KC / 16]) {
     const int kk = min(kc, nk - KC);
 #pragma unroll
     for (int s = 0; s < KC / 16; ++s) {
@@ -101,8 +127,8 @@ __device__ __forceinline__ void bf16_kloop(const Step3Args& p, float* region, in
   // chunk after it) and the waits before the MFMAs cover no load issued in
   // this chunk.  Every wave issues the same unconditional loads (clamped to
   // valid addresses), so the wait counts are exact.
-  auto chunk = [&](int kc, const bf16x8 (&ah)[KC / 16], const bf16x8 (&al)[KC / 16], bf16x8 (&nh)[KC / 16],
-                   bf16x8 (&nl)[KC / 16]) {
+  auto chunk = [&](int kc, const V (&ah)[KC / 16], const V (&al)[KC / 16], V (&nh)[KC / 16],
+                   V (&nl)[KC / 16]) {
     const int cur = (kc / KC) & 1;
     const bool more = kc + KC < nk;
     float4 nreg[MAXF4];
@@ -125,9 +151,9 @@ __device__ __forceinline__ void bf16_kloop(const Step3Args& p, float* region, in
 #pragma unroll
         for (int ct = 0; ct < CTQ; ++ct) {
           const float* row = Zb + ct * 32 * ROWW + 8 * s;
-          const bf16x8 bhi = *reinterpret_cast<const bf16x8*>(row);
-          const bf16x8 blo = *reinterpret_cast<const bf16x8*>(row + 16);
-          acc[ct] = mfma3(ah[s], al[s], bhi, blo, acc[ct]);
+          const V bhi = *reinterpret_cast<const V*>(row);
+          const V blo = *reinterpret_cast<const V*>(row + 16);
+          acc[ct] = mfma3<T>(ah[s], al[s], bhi, blo, acc[ct]);
         }
       }
     }
@@ -151,7 +177,7 @@ __device__ __forceinline__ void bf16_kloop(const Step3Args& p, float* region, in
       }
     }
   };
-  bf16x8 yah[KC / 16], yal[KC / 16], ybh[KC / 16], ybl[KC / 16];
+  V yah[KC / 16], yal[KC / 16], ybh[KC / 16], ybl[KC / 16];
   load_y(0, yah, yal);
   // nk / KC is even (H_pad is a multiple of 64)
   for (int kc = 0; kc < nk; kc += 2 * KC) {
@@ -162,7 +188,7 @@ __device__ __forceinline__ void bf16_kloop(const Step3Args& p, float* region, in
 
 // The first Zhat chunk of `pair` into LDS buffer 0.
 template <int CTQ>
-__device__ __forceinline__ void bf16_first_chunk(const Step3Args& p, float* region, int pair) {
+__device__ __forceinline__ void split_first_chunk(const Step3Args& p, float* region, int pair) {
   constexpr int QH = 32 * CTQ;
   const int nf4 = QH * 8;
   const float4* zsp = static_cast<const float4*>(p.zs) + static_cast<size_t>(pair) * QH * (2 * p.H_pad / 4);
@@ -170,8 +196,8 @@ __device__ __forceinline__ void bf16_first_chunk(const Step3Args& p, float* regi
     *reinterpret_cast<float4*>(region + (t >> 3) * 36 + (t & 7) * 4) = load_stream(zsp + t);
 }
 
-template <int CTQ, int MAXT, bool PREF>
-__global__ void __launch_bounds__(MAXT) step3_bf16x3(Step3Args p) {
+template <class T, int CTQ, int MAXT, bool PREF>
+__global__ void __launch_bounds__(MAXT) step3_split(Step3Args p) {
   extern __shared__ float smem[];
   constexpr int QH = 32 * CTQ;
   const int tid = threadIdx.x;
@@ -184,22 +210,22 @@ __global__ void __launch_bounds__(MAXT) step3_bf16x3(Step3Args p) {
   float* region = smem + 4 * QH;
   for (int i = tid; i < 2 * QH; i += blockDim.x) twl[i] = p.tw_qa[i];
   const bool active = d0 < p.N;
-  bf16_first_chunk<CTQ>(p, region, pair);
+  split_first_chunk<CTQ>(p, region, pair);
   __syncthreads();
   f32x16 acc[CTQ];
-  bf16_kloop<CTQ, PREF>(p, region, pair, d0, active, acc, -1);
+  split_kloop<T, CTQ, PREF>(p, region, pair, d0, active, acc, -1);
   __syncthreads();
   if (!active) return;
-  float2* T = reinterpret_cast<float2*>(region) + wave * (epilogue_lds_bytes_per_wave() / sizeof(float2));
-  step3_epilogue_reg<CTQ>(p, acc, pair, d0, T, twl, lane);
+  float2* rows = reinterpret_cast<float2*>(region) + wave * (epilogue_lds_bytes_per_wave() / sizeof(float2));
+  step3_epilogue_reg<CTQ>(p, acc, pair, d0, rows, twl, lane);
 }
 
 // Persistent form (one workgroup per CU, looping over its shift blocks) where
 // the FFT rows fit LDS beside the Zhat buffers: the next pair's first chunk is
 // stored during the last chunk of the current one, and a wave goes on to the
 // next pair's K loop as soon as its own FFT epilogue is done.
-template <int CTQ, bool PREF>
-__global__ void __launch_bounds__(1024) step3_bf16x3_p(Step3Args p) {
+template <class T, int CTQ, bool PREF>
+__global__ void __launch_bounds__(1024) step3_split_p(Step3Args p) {
   extern __shared__ float smem[];
   constexpr int QH = 32 * CTQ;
   const int tid = threadIdx.x;
@@ -207,15 +233,15 @@ __global__ void __launch_bounds__(1024) step3_bf16x3_p(Step3Args p) {
   const int wave = tid >> 6;
   float2* twl = reinterpret_cast<float2*>(smem);
   float* region = smem + 4 * QH;  // Zhat buffers
-  float2* T = reinterpret_cast<float2*>(region + 2 * QH * 36) +
-              wave * (epilogue_lds_bytes_per_wave() / sizeof(float2));
+  float2* rows = reinterpret_cast<float2*>(region + 2 * QH * 36) +
+                 wave * (epilogue_lds_bytes_per_wave() / sizeof(float2));
   for (int i = tid; i < 2 * QH; i += blockDim.x) twl[i] = p.tw_qa[i];
   const int total = p.pairs * p.nblk;
   int b = blockIdx.x;
   if (b >= total) return;
   int pair, yb;
   step3_block(b, p.nblk, p.pairs, pair, yb);
-  bf16_first_chunk<CTQ>(p, region, pair);
+  split_first_chunk<CTQ>(p, region, pair);
   __syncthreads();
   for (;;) {
     const int d0 = (yb * p.nwaves + wave) * 16;
@@ -224,13 +250,13 @@ __global__ void __launch_bounds__(1024) step3_bf16x3_p(Step3Args p) {
     int pn = 0, ybn = 0;
     if (bn < total) step3_block(bn, p.nblk, p.pairs, pn, ybn);
     f32x16 acc[CTQ];
-    bf16_kloop<CTQ, PREF>(p, region, pair, d0, active, acc, (PREF && bn < total) ? pn : -1);
+    split_kloop<T, CTQ, PREF>(p, region, pair, d0, active, acc, (PREF && bn < total) ? pn : -1);
     __syncthreads();  // every wave is past the Zhat buffers; the next first chunk is visible
-    if (active) step3_epilogue_reg<CTQ>(p, acc, pair, d0, T, twl, lane);
+    if (active) step3_epilogue_reg<CTQ>(p, acc, pair, d0, rows, twl, lane);
     if (bn >= total) break;
     if (!PREF) {
       __syncthreads();
-      bf16_first_chunk<CTQ>(p, region, pn);
+      split_first_chunk<CTQ>(p, region, pn);
       __syncthreads();
     }
     b = bn;
@@ -266,8 +292,8 @@ static int bf16_device_cus() {
   return cached[dev];
 }
 
-template <int CTQ, int MAXT>
-static hipError_t launch_step3_bf16_t(const Step3Args& a0, hipStream_t s) {
+template <class T, int CTQ, int MAXT>
+static hipError_t launch_step3_split_t(const Step3Args& a0, hipStream_t s) {
   Step3Args a = a0;
   const int per_blk = 16 * a.nwaves;
   a.nblk = (a.N + per_blk - 1) / per_blk;
@@ -278,7 +304,7 @@ static hipError_t launch_step3_bf16_t(const Step3Args& a0, hipStream_t s) {
   if constexpr (MAXT == 1024) {
     const size_t plds = bf16_persistent_lds(a.Qa, a.nwaves);
     if (pref && plds <= 160 * 1024) {
-      auto kern = step3_bf16x3_p<CTQ, true>;
+      auto kern = step3_split_p<T, CTQ, true>;
       hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                          hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(plds));
       if (e != hipSuccess) return e;
@@ -289,7 +315,7 @@ static hipError_t launch_step3_bf16_t(const Step3Args& a0, hipStream_t s) {
   }
   const dim3 grid(static_cast<unsigned>(nwg));
   size_t lds = step3_bf16_lds_bytes(a.Qa, a.nwaves);
-  auto kern = pref ? step3_bf16x3<CTQ, MAXT, true> : step3_bf16x3<CTQ, MAXT, false>;
+  auto kern = pref ? step3_split<T, CTQ, MAXT, true> : step3_split<T, CTQ, MAXT, false>;
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
   if (e != hipSuccess) return e;
@@ -297,14 +323,20 @@ static hipError_t launch_step3_bf16_t(const Step3Args& a0, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_step3_bf16(const Step3Args& a, hipStream_t s) {
-  if (a.pairs <= 0) return hipSuccess;
+template <class T>
+static hipError_t launch_step3_split_q(const Step3Args& a, hipStream_t s) {
   switch (a.Qa / 64) {
-    case 1: return launch_step3_bf16_t<1, 1024>(a, s);
-    case 2: return launch_step3_bf16_t<2, 1024>(a, s);
-    case 3: return launch_step3_bf16_t<3, 1024>(a, s);
-    case 4: return launch_step3_bf16_t<4, 1024>(a, s);
-    case 6: return launch_step3_bf16_t<6, 512>(a, s);
+    case 1: return launch_step3_split_t<T, 1, 1024>(a, s);
+    case 2: return launch_step3_split_t<T, 2, 1024>(a, s);
+    case 3: return launch_step3_split_t<T, 3, 1024>(a, s);
+    case 4: return launch_step3_split_t<T, 4, 1024>(a, s);
+    case 6: return launch_step3_split_t<T, 6, 512>(a, s);
     default: return hipErrorInvalidValue;
   }
+}
+
+hipError_t launch_step3_bf16(const Step3Args& a, bool fp16, hipStream_t s) {
+  if (a.pairs <= 0) return hipSuccess;
+  if (fp16 && !a.xscale) return hipErrorInvalidValue;
+  return fp16 ? launch_step3_split_q<_Float16>(a, s) : launch_step3_split_q<__bf16>(a, s);
 }

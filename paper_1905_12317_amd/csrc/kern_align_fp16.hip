@@ -381,13 +381,16 @@ __device__ __forceinline__ float pow2_at_or_above(float m) {
   return ldexpf(1.f, f == 0.5f ? e - 1 : e);
 }
 
-__global__ void scales_finalize(float* s, float s_y) {
+// s[2], s[3] = 2^e_data / s_a, 2^e_data / s_b; s[4] = s_a s_b s_y 2^e_x;
+// s[5] = 2^e_z (all exact powers of two)
+__global__ void scales_finalize(float* s, float s_y, int e_data, int e_x, int e_z) {
   if (threadIdx.x != 0) return;
   const float sa = pow2_at_or_above(__uint_as_float(reinterpret_cast<unsigned*>(s)[0]));
   const float sb = pow2_at_or_above(__uint_as_float(reinterpret_cast<unsigned*>(s)[1]));
-  s[2] = 1.f / sa;
-  s[3] = 1.f / sb;
-  s[4] = sa * sb * s_y;
+  s[2] = ldexpf(1.f / sa, e_data);
+  s[3] = ldexpf(1.f / sb, e_data);
+  s[4] = ldexpf(sa * sb * s_y, e_x);
+  s[5] = ldexpf(1.f, e_z);
 }
 
 }  // namespace
@@ -482,13 +485,13 @@ hipError_t launch_step3_fp16(const Step3Args& a, hipStream_t s) {
 }
 
 hipError_t launch_fp16_scales(const float* a, size_t a_count, const float* b, size_t b_count, float s_y,
-                              float* scales, hipStream_t s) {
+                              float* scales, int e_data, int e_x, int e_z, hipStream_t s) {
   unsigned* u = reinterpret_cast<unsigned*>(scales);
   hipLaunchKernelGGL(scales_init, dim3(1), dim3(64), 0, s, u);
   const int ga = static_cast<int>(std::min<size_t>((a_count + 255) / 256, 2048));
   const int gb = static_cast<int>(std::min<size_t>((b_count + 255) / 256, 2048));
   if (a_count) hipLaunchKernelGGL(absmax_kernel, dim3(ga), dim3(256), 0, s, a, a_count, u);
   if (b_count) hipLaunchKernelGGL(absmax_kernel, dim3(gb), dim3(256), 0, s, b, b_count, u + 1);
-  hipLaunchKernelGGL(scales_finalize, dim3(1), dim3(64), 0, s, scales, s_y);
+  hipLaunchKernelGGL(scales_finalize, dim3(1), dim3(64), 0, s, scales, s_y, e_data, e_x, e_z);
   return hipGetLastError();
 }

@@ -1,4 +1,5 @@
-// Step 1 of the FTK (eq. fbk3) on gfx950 MFMA, FP32 and split-bf16 forms.
+// Step 1 of the FTK (eq. fbk3) on gfx950 MFMA: FP32, split (bf16 or fp16,
+// three products) and FP16 forms.
 //
 //     Zhat_B[zeta](q) = sum_m conj b_B(k_m; q) P_zeta(m; q),
 //     P_zeta(m; q)   = 2 pi w_m G_zeta(k_m) a(k_m; q - l_zeta mod Qa),
@@ -24,11 +25,9 @@ using namespace ftkdev;
 
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 typedef _Float16 f16x4 __attribute__((ext_vector_type(4)));
 typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
-typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 typedef float f32x2 __attribute__((ext_vector_type(2)));
 
 namespace {
@@ -85,10 +84,15 @@ __global__ void tmpl_prep_fp32(const float2* __restrict__ b, float* __restrict__
   }
 }
 
-// Split form, 32x32x16 MFMA: one K step is 8 m (k' = 16 ks + 8 (l/32) + e).
-// Layout [q][row tile][ks][lane][8 hi, 8 lo] bf16.
-__global__ void tmpl_prep_bf16(const float2* __restrict__ b, __bf16* __restrict__ out, int nB, int nRT, int M,
-                               int Qa, int NQ, const int* __restrict__ lists, int K, int nRTk, int a0) {
+// Split forms, 32x32x16 MFMA: one K step is 8 m (k' = 16 ks + 8 (l/32) + e).
+// Layout [q][row tile][ks][lane][8 hi, 8 lo] of T (bf16, or fp16 with b
+// scaled by dscale[1] = 2^e / s_b).
+template <class T>
+__global__ void tmpl_prep_split(const float2* __restrict__ b, T* __restrict__ out, int nB, int nRT, int M, int Qa,
+                                int NQ, const int* __restrict__ lists, int K, int nRTk, int a0,
+                                const float* __restrict__ dscale) {
+  typedef T v8 __attribute__((ext_vector_type(8)));
+  const float sb = dscale ? dscale[1] : 1.f;
   const int nks = M / 8;
   const size_t total = static_cast<size_t>(NQ) * nRT * nks * 64;
   for (size_t t = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x; t < total;
@@ -102,17 +106,17 @@ __global__ void tmpl_prep_bf16(const float2* __restrict__ b, __bf16* __restrict_
     const int row = lane & 31;
     const int B = tile_template(rt, row >> 1, nB, lists, K, nRTk, a0);
     const int c = row & 1;
-    bf16x8 hi, lo;
+    v8 hi, lo;
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
       const int kp = ks * 16 + 8 * (lane >> 5) + e;
       float v = 0.f;
-      if (B >= 0) v = embed(b[(static_cast<size_t>(B) * Qa + q) * M + (kp >> 1)], c, kp & 1);
-      const __bf16 h = static_cast<__bf16>(v);
+      if (B >= 0) v = embed(b[(static_cast<size_t>(B) * Qa + q) * M + (kp >> 1)], c, kp & 1) * sb;
+      const T h = static_cast<T>(v);
       hi[e] = h;
-      lo[e] = static_cast<__bf16>(v - static_cast<float>(h));
+      lo[e] = static_cast<T>(v - static_cast<float>(h));
     }
-    bf16x8* o = reinterpret_cast<bf16x8*>(out) + t * 2;
+    v8* o = reinterpret_cast<v8*>(out) + t * 2;
     o[0] = hi;
     o[1] = lo;
   }
@@ -343,23 +347,41 @@ __global__ void __launch_bounds__(256) step1_fp32_v2(Step1Args p) {
     step1_fp32_tile<RT, CT, false>(p, smem, A, y - CT + 1, zb, part);
 }
 
-// ---- Step 1, split-bf16 form -------------------------------------------
+// ---- Step 1, split forms (bf16 or fp16, three products) -----------------
 
-__device__ __forceinline__ f32x16 mfma3(bf16x8 ahi, bf16x8 alo, bf16x8 bhi, bf16x8 blo, f32x16 c) {
-  c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ahi, bhi, c, 0, 0, 0);
-  c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ahi, blo, c, 0, 0, 0);
-  c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(alo, bhi, c, 0, 0, 0);
+__device__ __forceinline__ f32x16 mma16(bf16x8 a, bf16x8 b, f32x16 c) {
+  return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ f32x16 mma16(f16x8 a, f16x8 b, f32x16 c) {
+  return __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, c, 0, 0, 0);
+}
+template <class V>
+__device__ __forceinline__ f32x16 mfma3(V ahi, V alo, V bhi, V blo, f32x16 c) {
+  c = mma16(ahi, bhi, c);
+  c = mma16(ahi, blo, c);
+  c = mma16(alo, bhi, c);
   return c;
 }
 
 // Same work split and Nyquist fold as the FP32 form.  LDS: image operand per
-// zeta row: [2 MK bf16 hi][2 MK bf16 lo] + 4 words pad (MK = M, or 2M when
-// folding).  The result is split into bf16 hi + lo and written in Step 3's
-// chunk layout [pair][k' / 32][q][32 hi][32 lo]: lanes j and j + 1 (adjacent
-// zeta) trade halves so that the even lane stores the hi pair and the odd
-// lane the lo pair as 32-bit words.
-template <int RT, int CT, bool FOLD>
-__device__ __forceinline__ void step1_bf16_tile(const Step1Args& p, float* smem, int A, int q, int z0, int part) {
+// zeta row: [2 MK hi][2 MK lo] of T + 4 words pad (MK = M, or 2M when
+// folding).  The result is split into hi + lo and written in Step 3's chunk
+// layout [pair][k' / 32][q][32 hi][32 lo]: lanes j and j + 1 (adjacent zeta)
+// trade halves so that the even lane stores the hi pair and the odd lane the
+// lo pair as 32-bit words.  T = fp16: the image operand is 2^e P / (s_a
+// sg_zeta) (dscale[0] = 2^e / s_a; the 2 pi w G table of the plan is stored
+// divided by sg_zeta), the template operand 2^e b / s_b, and the FP32 result
+// is multiplied by dscale[3] = 2^e_z before the split (the exponents keep
+// every hi and lo a normal fp16 number over the useful range; the scales are
+// powers of two, so no rounding is added).
+template <class T, int RT, int CT, bool FOLD>
+__device__ __forceinline__ void step1_split_tile(const Step1Args& p, float* smem, int A, int q, int z0, int part) {
+  typedef T v8 __attribute__((ext_vector_type(8)));
+  typedef T v4 __attribute__((ext_vector_type(4)));
+  typedef T v2 __attribute__((ext_vector_type(2)));
+  constexpr bool kScaled = std::is_same<T, _Float16>::value;
+  const float sa = kScaled ? p.dscale[0] : 1.f;
+  const float zsc = kScaled ? p.dscale[3] : 1.f;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -378,17 +400,17 @@ __device__ __forceinline__ void step1_bf16_tile(const Step1Args& p, float* smem,
         const int z = i / (MK / 2);
         const int m2 = i - z * (MK / 2);
         float x[4];
-        fill_value(d, FOLD && 2 * m2 >= M, 1.f, x);
-        bf16x4 hi, lo;
+        fill_value(d, FOLD && 2 * m2 >= M, sa, x);
+        v4 hi, lo;
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-          const __bf16 h = static_cast<__bf16>(x[e]);
+          const T h = static_cast<T>(x[e]);
           hi[e] = h;
-          lo[e] = static_cast<__bf16>(x[e] - static_cast<float>(h));
+          lo[e] = static_cast<T>(x[e] - static_cast<float>(h));
         }
         float* dst = smem + z * RW + 2 * m2;
-        *reinterpret_cast<bf16x4*>(dst) = hi;
-        *reinterpret_cast<bf16x4*>(dst + MK) = lo;
+        *reinterpret_cast<v4*>(dst) = hi;
+        *reinterpret_cast<v4*>(dst + MK) = lo;
       });
   __syncthreads();
   const int r = lane >> 5;
@@ -413,12 +435,12 @@ __device__ __forceinline__ void step1_bf16_tile(const Step1Args& p, float* smem,
 #pragma unroll
     for (int pass = 0; pass < NP; ++pass) {
       const int qt = pass ? QH : q;
-      const bf16x8* rq = reinterpret_cast<const bf16x8*>(p.r16) +
+      const v8* rq = reinterpret_cast<const v8*>(p.r16) +
                          ((static_cast<size_t>(qt) * p.tiles_per_q + img_off) * nks * 64 + lane) * 2;
-      const bf16x8* ra[RT];
+      const v8* ra[RT];
 #pragma unroll
       for (int i = 0; i < RT; ++i) ra[i] = rq + static_cast<size_t>(min(rt0 + i, nRT - 1)) * nks * 128;
-      bf16x8 nhi[RT], nlo[RT];
+      v8 nhi[RT], nlo[RT];
 #pragma unroll
       for (int i = 0; i < RT; ++i) {
         nhi[i] = ra[i][0];
@@ -426,7 +448,7 @@ __device__ __forceinline__ void step1_bf16_tile(const Step1Args& p, float* smem,
       }
       const float* Pp = Pb + pass * M;  // the Nyquist half starts at k' = 2M (M words)
       for (int ks = 0; ks < nks; ++ks) {
-        bf16x8 ahi[RT], alo[RT];
+        v8 ahi[RT], alo[RT];
 #pragma unroll
         for (int i = 0; i < RT; ++i) {
           ahi[i] = nhi[i];
@@ -442,8 +464,8 @@ __device__ __forceinline__ void step1_bf16_tile(const Step1Args& p, float* smem,
 #pragma unroll
         for (int j = 0; j < CT; ++j) {
           const float* prow = Pp + j * 32 * RW + 8 * ks;
-          const bf16x8 bhi = *reinterpret_cast<const bf16x8*>(prow);
-          const bf16x8 blo = *reinterpret_cast<const bf16x8*>(prow + MK);
+          const v8 bhi = *reinterpret_cast<const v8*>(prow);
+          const v8 blo = *reinterpret_cast<const v8*>(prow + MK);
 #pragma unroll
           for (int i = 0; i < RT; ++i) acc[i][j] = mfma3(ahi[i], alo[i], bhi, blo, acc[i][j]);
         }
@@ -464,10 +486,10 @@ __device__ __forceinline__ void step1_bf16_tile(const Step1Args& p, float* smem,
         for (int j = 0; j < CT; ++j) {
 #pragma unroll
           for (int v = 0; v < 16; ++v) {
-            const float x = acc[i][j][v];
-            // hi = bf16(x), lo = bf16(x - hi), packed (hi, lo) in one word
-            const float xh = static_cast<float>(static_cast<__bf16>(x));
-            const uint32_t w = __builtin_bit_cast(uint32_t, __builtin_convertvector(f32x2{x, x - xh}, bf16x2));
+            const float x = kScaled ? acc[i][j][v] * zsc : acc[i][j][v];
+            // hi = T(x), lo = T(x - hi), packed (hi, lo) in one word
+            const float xh = static_cast<float>(static_cast<T>(x));
+            const uint32_t w = __builtin_bit_cast(uint32_t, __builtin_convertvector(f32x2{x, x - xh}, v2));
             // even lane sends its lo half, odd lane its hi half; the even lane
             // stores (hi, hi of the odd lane), the odd lane (lo of the even, lo)
             const uint32_t got = static_cast<uint32_t>(
@@ -496,17 +518,17 @@ __device__ __forceinline__ void step1_bf16_tile(const Step1Args& p, float* smem,
 // At least 2 waves per SIMD: left free, the compiler keeps the accumulators
 // in AGPRs and copies them all to VGPRs for the split at the end (about 300
 // registers, 1 wave per SIMD).
-template <int RT, int CT, int NW>
-__global__ void __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(NW == 8 ? 4 : 2))) step1_bf16_v2(Step1Args p) {
+template <class T, int RT, int CT, int NW>
+__global__ void __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(NW == 8 ? 4 : 2))) step1_split_v2(Step1Args p) {
   extern __shared__ float smem[];
   int A, y, zp;
   if (!step1_block(blockIdx.x, p, CT, A, y, zp)) return;
   const int zb = (zp / p.tparts) * (32 * CT);
   const int part = zp % p.tparts;
   if (y < CT)
-    step1_bf16_tile<RT, 1, true>(p, smem, A, 0, zb + 32 * y, part);
+    step1_split_tile<T, RT, 1, true>(p, smem, A, 0, zb + 32 * y, part);
   else
-    step1_bf16_tile<RT, CT, false>(p, smem, A, y - CT + 1, zb, part);
+    step1_split_tile<T, RT, CT, false>(p, smem, A, y - CT + 1, zb, part);
 }
 
 // ---- Step 1, FP16 form --------------------------------------------------
@@ -722,7 +744,7 @@ hipError_t launch_tmpl_prep(const float2* b, void* out, int nB, int M, int Qa, i
 hipError_t launch_tmpl_prep_lists(const float2* b, void* out, int nB, int M, int Qa, int precision,
                                   const float* dscale, const int* lists, int K, int na, int a0, hipStream_t s) {
   if (nB <= 0 || (lists && (K <= 0 || na <= 0))) return hipSuccess;
-  if (precision == 2 && !dscale) return hipErrorInvalidValue;
+  if ((precision == 2 || precision == 3) && !dscale) return hipErrorInvalidValue;
   const int nRTk = lists ? (K + 15) / 16 : 0;
   const int nRT = lists ? na * nRTk : (nB + 15) / 16;
   const int NQ = Qa / 2 + 1;
@@ -734,9 +756,12 @@ hipError_t launch_tmpl_prep_lists(const float2* b, void* out, int nB, int M, int
   else if (precision == 2)
     hipLaunchKernelGGL(tmpl_prep_fp16, dim3(blocks), dim3(256), 0, s, b, static_cast<_Float16*>(out), nB, nRT, M,
                        Qa, NQ, lists, K, nRTk, a0, dscale);
+  else if (precision == 3)
+    hipLaunchKernelGGL(tmpl_prep_split<_Float16>, dim3(blocks), dim3(256), 0, s, b, static_cast<_Float16*>(out), nB,
+                       nRT, M, Qa, NQ, lists, K, nRTk, a0, dscale);
   else
-    hipLaunchKernelGGL(tmpl_prep_bf16, dim3(blocks), dim3(256), 0, s, b, static_cast<__bf16*>(out), nB, nRT, M,
-                       Qa, NQ, lists, K, nRTk, a0);
+    hipLaunchKernelGGL(tmpl_prep_split<__bf16>, dim3(blocks), dim3(256), 0, s, b, static_cast<__bf16*>(out), nB,
+                       nRT, M, Qa, NQ, lists, K, nRTk, a0, nullptr);
   return hipGetLastError();
 }
 
@@ -803,10 +828,25 @@ hipError_t launch_step1_v2(const Step1Args& a, int precision, hipStream_t s) {
       default: return hipErrorInvalidValue;
     }
 #undef FTK_S1
+  } else if (precision == 3) {
+    if (!a.dscale) return hipErrorInvalidValue;
+#define FTK_S1(ct)                                                        \
+  case ct: {                                                               \
+    auto k = step1_split_v2<_Float16, kBf16RT, ct, kBf16NW>;              \
+    if ((e = set_lds(k, lds)) != hipSuccess) return e;                    \
+    hipLaunchKernelGGL(k, grid, dim3(64 * kBf16NW), lds, s, a);           \
+    break;                                                                 \
+  }
+    switch (CT) {
+      FTK_S1(2)
+      FTK_S1(4)
+      default: return hipErrorInvalidValue;
+    }
+#undef FTK_S1
   } else {
 #define FTK_S1(ct)                                                        \
   case ct: {                                                               \
-    auto k = step1_bf16_v2<kBf16RT, ct, kBf16NW>;                         \
+    auto k = step1_split_v2<__bf16, kBf16RT, ct, kBf16NW>;                \
     if ((e = set_lds(k, lds)) != hipSuccess) return e;                    \
     hipLaunchKernelGGL(k, grid, dim3(64 * kBf16NW), lds, s, a);           \
     break;                                                                 \

@@ -49,7 +49,8 @@ struct Step1Args {
 // K index k' = c H_pad + zeta (c = 0 real, 1 imaginary part).  4 Qa H_pad
 // bytes per pair in the FP32 and split forms, half that in the FP16 form:
 //   FP32:       [pair][q][k'] float
-//   split-bf16: [pair][k' / 32][q][32 bf16 hi of k' % 32][32 bf16 lo]
+//   split:      [pair][k' / 32][q][32 hi of k' % 32][32 lo], bf16 (split
+//               bf16) or fp16 (split fp16, scaled by 1 / (s_a s_b sg_zeta))
 //               (one 128-byte row per q and chunk of 32 k': Step 3 copies
 //               whole chunks into LDS without converting them)
 //   FP16:       [pair][k' / 64][q][64 fp16 of k' % 64] (the same 128-byte
@@ -58,10 +59,10 @@ struct Step1Args {
 struct Step3Args {
   const void* zs;        // Zhat staging (above)
   const float* yt;       // [2 H_pad][2 N_pad] real embedding of Y, transposed
-  const uint16_t* yt_hi; // split-precision copies (bf16), same layout
+  const uint16_t* yt_hi; // reduced-precision copies (bf16 or fp16 in MFMA lane order)
   const uint16_t* yt_lo;
   float* X;              // [pairs][N][Qa] or nullptr
-  const float* xscale;   // device scalar multiplying the X outputs (FP16 form), or null
+  const float* xscale;   // device scalar multiplying the X outputs (FP16 and split-fp16 forms), or null
   unsigned long long* keys;  // [pairs]
   const float2* tw_qa;   // [Qa]
   const void* rot16;     // FP16 form with Qa <= 256: the rotation transform tables (rot16_table_bytes), or null
@@ -77,7 +78,8 @@ hipError_t launch_step3(const Step3Args& args, int precision, hipStream_t stream
 // covers q = 0 .. Qa/2 (Qa/2 + 1 slices).
 size_t tmpl_prep_bytes(int nB, int M, int Qa, int precision);
 size_t tmpl_prep_tile_bytes(size_t tiles, int M, int Qa, int precision);
-// precision: 0 FP32, 1 split-bf16, 2 FP16 (then dscale[1] = 1/s_b scales b)
+// precision: 0 FP32, 1 split-bf16, 2 FP16, 3 split-fp16 (2 and 3: dscale[1]
+// scales b)
 hipError_t launch_tmpl_prep(const float2* b, void* out, int nB, int M, int Qa, int precision, const float* dscale,
                             hipStream_t stream);
 // per-image template lists [.][K] for images a0 .. a0 + na - 1 of the call
@@ -86,15 +88,20 @@ hipError_t launch_tmpl_prep_lists(const float2* b, void* out, int nB, int M, int
 size_t step1_v2_lds_bytes(int M, int zb, int precision);
 hipError_t launch_step1_v2(const Step1Args& args, int precision, hipStream_t stream);
 
-// split-bf16 forms of the two contractions (kern_align_bf16.hip)
+// Step 3 of the split forms (kern_align_bf16.hip): split bf16, or split fp16
+// (fp16 = true; then args.xscale must be set)
 size_t step3_bf16_lds_bytes(int Qa, int nwaves);
-hipError_t launch_step3_bf16(const Step3Args& args, hipStream_t stream);
+hipError_t launch_step3_bf16(const Step3Args& args, bool fp16, hipStream_t stream);
 
 // FP16 form (kern_align_fp16.hip): Step 3 with one FP16 product per term
-// (same LDS footprint as the split form), and the per-call data scales:
-// scales[0..1] = max |a|, max |b| (as float bits, reduced here), then
-// scales[2] = 1/s_a, scales[3] = 1/s_b, scales[4] = s_a s_b s_y, with s the
-// power of two at or above each maximum (1 for an all-zero input).
+// (same LDS footprint as the split form), and the per-call data scales of the
+// FP16 and split-fp16 forms: scales[0..1] = max |a|, max |b| (as float bits,
+// reduced here), then scales[2] = 2^e_data / s_a, scales[3] = 2^e_data / s_b,
+// scales[4] = s_a s_b s_y 2^e_x, scales[5] = 2^e_z, with s the power of two
+// at or above each maximum (1 for an all-zero input).  The FP16 form uses
+// e_data = e_x = e_z = 0; the split-fp16 form lifts its operands to the top
+// of the fp16 range (kernels of kern_step1.hip multiply Step 1's FP32 result
+// by 2^e_z before splitting it, and X is multiplied back by scales[4]).
 // With Step3Args::rot16 set (Qa <= 256), the rotation transform runs on MFMA
 // from the fp16 tables T_E, T_O of the even and odd modes:
 //   T_E[r][2 m + c]: m = 0: 1 (c = 0), (-1)^r (c = 1);
@@ -108,9 +115,9 @@ size_t rot16_table_bytes(int Qa);  // 0 where the MFMA transform does not apply
 size_t step3_fp16_rot_lds_bytes(int Qa, int nwaves);
 hipError_t launch_step3_fp16(const Step3Args& args, hipStream_t stream);
 hipError_t launch_fp16_scales(const float* a, size_t a_count, const float* b, size_t b_count, float s_y,
-                              float* scales, hipStream_t stream);
+                              float* scales, int e_data, int e_x, int e_z, hipStream_t stream);
 
 hipError_t launch_keys_init(unsigned long long* keys, size_t count, hipStream_t stream);
-// vscale: device scalar multiplying the pose values (FP16 form), or null
+// vscale: device scalar multiplying the pose values (FP16 and split-fp16 forms), or null
 hipError_t launch_keys_to_poses(const unsigned long long* keys, void* poses, size_t count, int Qa,
                                 const float* vscale, hipStream_t stream);

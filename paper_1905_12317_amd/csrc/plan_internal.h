@@ -122,9 +122,31 @@ ftk_tuning_t default_tuning(int precision);
 Needs plan_needs(const ftk_plan* p, int nA, int nB, bool from_pixels);
 // alignment of nA images against K listed templates each
 Needs plan_needs_lists(const ftk_plan* p, int nA, int K);
-// kernel precision code of a plan: 0 FP32, 1 split-bf16, 2 FP16
+// kernel precision code of a plan: 0 FP32, 1 split-bf16, 2 FP16, 3 split-fp16
 inline int prec_code(const ftk_plan* p) {
-  return p->precision == FTK_BF16X3 ? 1 : (p->precision == FTK_FP16 ? 2 : 0);
+  switch (p->precision) {
+    case FTK_BF16X3: return 1;
+    case FTK_FP16: return 2;
+    case FTK_FP16X3: return 3;
+    default: return 0;
+  }
+}
+// Power-of-two exponents of the split-fp16 form.  Its lo parts lose
+// precision where they fall below the smallest normal fp16 (2^-14), so every
+// operand is lifted to the top of the fp16 range: a / s_a, b / s_b and the
+// scaled shift panel (all at most 1) are multiplied by 2^data; Step 1's FP32
+// result, at most 4M 2^(2 data) in magnitude (K = 4M terms in the Nyquist
+// fold), is multiplied by 2^z = 2^-(data + ceil(log2 4M)) before it is split,
+// which leaves it at most 2^data; X is multiplied back by s_a s_b s_y 2^x
+// with x = ceil(log2 4M) - 2 data.
+struct SplitF16Exps {
+  int data, x, z;
+};
+inline SplitF16Exps split_f16_exps(int M) {
+  constexpr int kData = 15;  // fp16 holds values up to 65504 < 2^16
+  int c = 0;
+  while ((1 << c) < 4 * M) ++c;
+  return SplitF16Exps{kData, c - 2 * kData, -(kData + c)};
 }
 // Step 3 waves per workgroup and Step 1 zeta block actually used by a plan.
 int step3_waves(const ftk_plan* p);

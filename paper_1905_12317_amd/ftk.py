@@ -20,7 +20,8 @@ FTK_OK = 0
 FTK_FP32 = 0
 FTK_BF16X3 = 1
 FTK_FP16 = 2
-PRECISIONS = {"fp32": FTK_FP32, "bf16x3": FTK_BF16X3, "fp16": FTK_FP16}
+FTK_FP16X3 = 3
+PRECISIONS = {"fp32": FTK_FP32, "bf16x3": FTK_BF16X3, "fp16": FTK_FP16, "fp16x3": FTK_FP16X3}
 
 
 class FTKError(RuntimeError):

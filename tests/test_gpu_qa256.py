@@ -31,7 +31,8 @@ N_IMG, N_TMP = 3, 100
 # persistent loop (pair p is taken by workgroup p mod 256), 256, 257, 298, 299
 # to the second
 PAIRS = [(0, 0), (0, 1), (1, 37), (2, 55), (2, 56), (2, 57), (2, 98), (2, 99)]
-BARS = {"fp32": 1e-5, "bf16x3": 1e-3, "fp16": 1e-3}
+# the split-fp16 form is held to 1e-5 here, the bar it claims for any eps
+BARS = {"fp32": 1e-5, "bf16x3": 1e-3, "fp16": 1e-3, "fp16x3": 1e-5}
 
 
 def _say(*a):
@@ -69,7 +70,7 @@ def _align(ftk, s, shifts, form, stage_mib=0):
     return X.cpu().numpy(), ftk.poses_numpy(best)
 
 
-@pytest.mark.parametrize("form", ["fp32", "bf16x3", "fp16"])
+@pytest.mark.parametrize("form", ["fp32", "bf16x3", "fp16", "fp16x3"])
 def test_benchmark_instances_elementwise(case, form):
     ftk, s, shifts, ref = case
     bar = BARS[form]
