@@ -163,6 +163,28 @@ int ftk_transform(ftk_plan* plan, const float* imgs, int cnt, void* coeffs, void
 int ftk_align_coeffs(ftk_plan* plan, const void* img_coeffs, int nA, const void* tmpl_coeffs,
                      int nB, float* X, ftk_pose* best, void* stream);
 
+/* Size of the fixed device scratch of ftk_align_coeffs_noalloc (256 MiB).
+ * The library holds it on every GPU it runs on until the process ends. */
+#define FTK_NOALLOC_SCRATCH_BYTES (256u * 1024u * 1024u)
+
+/* ftk_align_coeffs for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same kernels and results, with every buffer the call
+ * needs (pose keys, 8 nA nB bytes; the Step 1 template operand; the data
+ * scales of the fp16 forms; and the Zhat staging of at least one image
+ * against all nB templates) carved from one fixed device array of
+ * FTK_NOALLOC_SCRATCH_BYTES per GPU.  It calls no hipMalloc, hipFree or
+ * allocating library routine and records no stage timing.  Arguments,
+ * layouts and ownership as ftk_align_coeffs.
+ * The scratch keeps the last call's contents; every call initialises what
+ * it reads.  Calls that overlap on one GPU (different streams or host
+ * threads) share the array and race: the caller serialises them.
+ * Errors: FTK_EUNSUPPORTED when the call needs more than the scratch (the
+ * message states the sizes), otherwise as ftk_align_coeffs (never
+ * FTK_ENOMEM). */
+int ftk_align_coeffs_noalloc(ftk_plan* plan, const void* img_coeffs, int nA, const void* tmpl_coeffs,
+                             int nB, float* X, ftk_pose* best, void* stream);
+
 /* Alignment from pixels: ftk_transform of images and templates into
  * plan-owned coefficient buffers, then ftk_align_coeffs.
  *   images    : device float32 [nA][n][n]

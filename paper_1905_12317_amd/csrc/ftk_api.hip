@@ -393,7 +393,7 @@ Needs plan_needs(const ftk_plan* p, int nA, int nB, bool from_pixels) {
     d.coef_b = cb * nB;
   }
   if (nA > 0 && nB > 0) {
-    const size_t per_pair = static_cast<size_t>(p->Qa / 2) * 2 * p->H_pad * (prec_code(p) == 2 ? 2 : 4);
+    const size_t per_pair = stage_bytes_per_pair(p);
     const size_t budget = static_cast<size_t>(p->tune.stage_mib) << 20;
     d.chunk_images = static_cast<int>(std::min<size_t>(nA, std::max<size_t>(1, budget / (per_pair * nB))));
     d.stage = static_cast<size_t>(d.chunk_images) * nB * per_pair;
@@ -407,7 +407,7 @@ Needs plan_needs(const ftk_plan* p, int nA, int nB, bool from_pixels) {
 Needs plan_needs_lists(const ftk_plan* p, int nA, int K) {
   Needs d;
   if (nA <= 0 || K <= 0) return d;
-  const size_t per_pair = static_cast<size_t>(p->Qa / 2) * 2 * p->H_pad * (prec_code(p) == 2 ? 2 : 4);
+  const size_t per_pair = stage_bytes_per_pair(p);
   const size_t budget = static_cast<size_t>(p->tune.stage_mib) << 20;
   d.chunk_images = static_cast<int>(std::min<size_t>(nA, std::max<size_t>(1, budget / (per_pair * K))));
   d.stage = static_cast<size_t>(d.chunk_images) * K * per_pair;
@@ -655,64 +655,68 @@ int ftk_transform(ftk_plan* p, const float* imgs, int cnt, void* coeffs, void* s
 
 }  // extern "C"
 
-namespace {
+namespace ftkint {
 
 // Steps 1-3 + argmax for nA images against nB templates (lists == NULL) or
 // against K templates of their own (lists [nA][K]); results per pair
-// (image, template or list slot) in X [.][N][Qa] and best.
-int align_impl(ftk_plan* p, const void* img_coeffs, int nA, const void* tmpl_coeffs, int nB, const int32_t* lists,
-               int K, float* X, ftk_pose* best, void* stream) {
+// (image, template or list slot) in X [.][N][Qa] and best.  The buffers
+// are the caller's (sized by plan_needs / plan_needs_lists, or carved from
+// the no-allocation scratch); tm (null: no timing) records the launches.
+int align_run(ftk_plan* p, const void* img_coeffs, int nA, const void* tmpl_coeffs, int nB, const int32_t* lists,
+              int K, float* X, ftk_pose* best, const AlignBufs& buf, StageTimer* tm, void* stream) {
   hipStream_t s = static_cast<hipStream_t>(stream);
   const int QH = p->Qa / 2;
   const int nBe = lists ? K : nB;  // templates per image
   const size_t pairs = static_cast<size_t>(nA) * nBe;
   const int prec = prec_code(p);
-  const Needs nd = lists ? plan_needs_lists(p, nA, K) : plan_needs(p, nA, nB, false);
-  const int chunkA = nd.chunk_images;
-  Workspace& ws = *p->ws;
-  if (ws.stage.ensure(nd.stage) != hipSuccess) return fail(FTK_ENOMEM, "ftk_align: staging buffer");
-  if (ws.keys.ensure(nd.keys) != hipSuccess) return fail(FTK_ENOMEM, "ftk_align: key buffer");
-  if (ws.tmpl.ensure(nd.tmpl) != hipSuccess) return fail(FTK_ENOMEM, "ftk_align: template operand buffer");
-  if (ws.scales.ensure(nd.scales) != hipSuccess) return fail(FTK_ENOMEM, "ftk_align: scale buffer");
+  const int chunkA = buf.chunk_images;
+  if (chunkA < 1) return fail(FTK_EINVAL, "ftk_align: no staging for one image");
+  struct NoTimer {
+    StageTimer* t;
+    hipEvent_t begin(hipStream_t st) { return t ? t->begin(st) : nullptr; }
+    void end(hipEvent_t a, hipStream_t st, int stage) {
+      if (t) t->end(a, st, stage);
+    }
+  } timer{tm};
   // short per-image lists fill one template tile per workgroup: the smaller
   // SVD block gives twice the workgroups for the same operand work
   const int zblk = (lists && K <= 16) ? 64 : step1_zblk(p);
   if (step1_v2_lds_bytes(p->M, zblk, prec) > kLdsLimit) return fail(FTK_EUNSUPPORTED, "ftk_align: step 1 tiles exceed LDS");
-  unsigned long long* keys = ws.keys.as<unsigned long long>();
+  unsigned long long* keys = buf.keys;
   hipError_t e;
-  hipEvent_t ev = p->timer.begin(s);
+  hipEvent_t ev = timer.begin(s);
   if ((e = launch_keys_init(keys, pairs, s)) != hipSuccess) return hip_fail(e, "ftk_align: keys init");
-  p->timer.end(ev, s, 3);
+  timer.end(ev, s, 3);
   const float2* bco = static_cast<const float2*>(tmpl_coeffs);
   // fp16 forms: the per-call data scales, [max|a|, max|b|, 2^e/s_a, 2^e/s_b,
   // s_a s_b s_y 2^e_x, 2^e_z] (exponents 0 in the FP16 form, split_f16_exps
   // in the split-fp16 form)
-  float* scales = (prec == 2 || prec == 3) ? ws.scales.as<float>() : nullptr;
+  float* scales = (prec == 2 || prec == 3) ? buf.scales : nullptr;
   if (scales) {
-    ev = p->timer.begin(s);
+    ev = timer.begin(s);
     const size_t per = static_cast<size_t>(2) * p->Qa * p->M;
     const SplitF16Exps x = prec == 3 ? split_f16_exps(p->M) : SplitF16Exps{0, 0, 0};
     if ((e = launch_fp16_scales(static_cast<const float*>(img_coeffs), per * nA, reinterpret_cast<const float*>(bco),
                                 per * nB, p->y_scale, scales, x.data, x.x, x.z, s)) != hipSuccess)
       return hip_fail(e, "ftk_align: fp16 scales");
-    p->timer.end(ev, s, 4);
+    timer.end(ev, s, 4);
   }
   if (!lists) {
     // template operand of Step 1: embedded (and split or scaled) once per call
-    ev = p->timer.begin(s);
-    if ((e = launch_tmpl_prep(bco, ws.tmpl.ptr, nB, p->M, p->Qa, prec, scales ? scales + 2 : nullptr, s)) !=
+    ev = timer.begin(s);
+    if ((e = launch_tmpl_prep(bco, buf.tmpl, nB, p->M, p->Qa, prec, scales ? scales + 2 : nullptr, s)) !=
         hipSuccess)
       return hip_fail(e, "ftk_align: template operand");
-    p->timer.end(ev, s, 4);
+    timer.end(ev, s, 4);
   }
 
   Step1Args a1{};
   a1.cz = p->cz.as<float>();
   a1.ell = p->ell.as<int>();
-  a1.zs = ws.stage.ptr;
+  a1.zs = buf.stage;
   a1.b = bco;
-  a1.r32 = ws.tmpl.as<float>();
-  a1.r16 = ws.tmpl.ptr;
+  a1.r32 = static_cast<float*>(buf.tmpl);
+  a1.r16 = buf.tmpl;
   a1.dscale = scales ? scales + 2 : nullptr;
   a1.nB = nBe;
   a1.img_tiles = lists ? (K + 15) / 16 : 0;
@@ -741,11 +745,11 @@ int align_impl(ftk_plan* p, const void* img_coeffs, int nA, const void* tmpl_coe
     if (lists) {
       // this chunk's own template operand, gathered through the lists
       a1.tiles_per_q = na * a1.img_tiles;
-      ev = p->timer.begin(s);
-      if ((e = launch_tmpl_prep_lists(bco, ws.tmpl.ptr, nB, p->M, p->Qa, prec, scales ? scales + 2 : nullptr, lists,
+      ev = timer.begin(s);
+      if ((e = launch_tmpl_prep_lists(bco, buf.tmpl, nB, p->M, p->Qa, prec, scales ? scales + 2 : nullptr, lists,
                                       K, na, A0, s)) != hipSuccess)
         return hip_fail(e, "ftk_align_lists: template operand");
-      p->timer.end(ev, s, 4);
+      timer.end(ev, s, 4);
     }
     {
       // split the template sweep until the grid holds about step1_wgs workgroups
@@ -753,27 +757,44 @@ int align_impl(ftk_plan* p, const void* img_coeffs, int nA, const void* tmpl_coe
       const int max_parts = std::max(1, ((nBe + 15) / 16 + 7) / 8);
       a1.tparts = std::min(max_parts, std::max(1, (p->tune.step1_wgs + base - 1) / base));
     }
-    ev = p->timer.begin(s);
+    ev = timer.begin(s);
     e = launch_step1_v2(a1, prec, s);
     if (e != hipSuccess) return hip_fail(e, "ftk_align: step 1");
-    p->timer.end(ev, s, 1);
-    a3.zs = ws.stage.ptr;
+    timer.end(ev, s, 1);
+    a3.zs = buf.stage;
     a3.pairs = na * nBe;
     a3.keys = keys + static_cast<size_t>(A0) * nBe;
     a3.X = X ? X + static_cast<size_t>(A0) * nBe * p->N * p->Qa : nullptr;
-    ev = p->timer.begin(s);
+    ev = timer.begin(s);
     e = (prec == 1 || prec == 3) ? launch_step3_bf16(a3, prec == 3, s)
                                  : (prec == 2 ? launch_step3_fp16(a3, s) : launch_step3(a3, p->precision, s));
     if (e != hipSuccess) return hip_fail(e, "ftk_align: step 3");
-    p->timer.end(ev, s, 2);
+    timer.end(ev, s, 2);
   }
   if (best) {
-    ev = p->timer.begin(s);
+    ev = timer.begin(s);
     if ((e = launch_keys_to_poses(keys, best, pairs, p->Qa, scales ? scales + 4 : nullptr, s)) != hipSuccess)
       return hip_fail(e, "ftk_align: poses");
-    p->timer.end(ev, s, 3);
+    timer.end(ev, s, 3);
   }
   return FTK_OK;
+}
+
+}  // namespace ftkint
+
+namespace {
+
+int align_impl(ftk_plan* p, const void* img_coeffs, int nA, const void* tmpl_coeffs, int nB, const int32_t* lists,
+               int K, float* X, ftk_pose* best, void* stream) {
+  const Needs nd = lists ? plan_needs_lists(p, nA, K) : plan_needs(p, nA, nB, false);
+  Workspace& ws = *p->ws;
+  if (ws.stage.ensure(nd.stage) != hipSuccess) return fail(FTK_ENOMEM, "ftk_align: staging buffer");
+  if (ws.keys.ensure(nd.keys) != hipSuccess) return fail(FTK_ENOMEM, "ftk_align: key buffer");
+  if (ws.tmpl.ensure(nd.tmpl) != hipSuccess) return fail(FTK_ENOMEM, "ftk_align: template operand buffer");
+  if (ws.scales.ensure(nd.scales) != hipSuccess) return fail(FTK_ENOMEM, "ftk_align: scale buffer");
+  const AlignBufs buf{ws.stage.ptr, ws.keys.as<unsigned long long>(), ws.tmpl.ptr, ws.scales.as<float>(),
+                      nd.chunk_images};
+  return align_run(p, img_coeffs, nA, tmpl_coeffs, nB, lists, K, X, best, buf, &p->timer, stream);
 }
 
 }  // namespace

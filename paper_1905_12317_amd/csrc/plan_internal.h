@@ -131,6 +131,25 @@ inline int prec_code(const ftk_plan* p) {
     default: return 0;
   }
 }
+// Buffers of one alignment call: Zhat staging for chunk_images images, the
+// pose keys of every pair, the Step 1 template operand and the data scales
+// of the fp16 forms.
+struct AlignBufs {
+  void* stage;
+  unsigned long long* keys;
+  void* tmpl;
+  float* scales;
+  int chunk_images;
+};
+// Steps 1-3 and the argmax on caller-provided buffers (ftk_api.hip); tm may
+// be null (no stage timing).
+int align_run(ftk_plan* p, const void* img_coeffs, int nA, const void* tmpl_coeffs, int nB, const int32_t* lists,
+              int K, float* X, ftk_pose* best, const AlignBufs& buf, StageTimer* tm, void* stream);
+// Zhat staging bytes of one image-template pair: Qa/2 rows of 2 H_pad values,
+// 2 bytes each in the FP16 form, 4 otherwise (FP32, or hi + lo).
+inline size_t stage_bytes_per_pair(const ftk_plan* p) {
+  return static_cast<size_t>(p->Qa / 2) * 2 * p->H_pad * (prec_code(p) == 2 ? 2 : 4);
+}
 // Power-of-two exponents of the split-fp16 form.  Its lo parts lose
 // precision where they fall below the smallest normal fp16 (2^-14), so every
 // operand is lifted to the top of the fp16 range: a / s_a, b / s_b and the

@@ -72,7 +72,7 @@ POSE_DTYPE = np.dtype([("value", np.float32), ("shift", np.int32), ("rot", np.in
 
 #: every symbol include/ftk.h declares
 EXPORTS = ["ftk_plan_create", "ftk_plan_destroy", "ftk_plan_info", "ftk_set_shifts", "ftk_transform",
-           "ftk_align_coeffs", "ftk_align", "ftk_plan_tables", "ftk_plan_profile", "ftk_plan_stage_times",
+           "ftk_align_coeffs", "ftk_align_coeffs_noalloc", "ftk_align", "ftk_plan_tables", "ftk_plan_profile", "ftk_plan_stage_times",
            "ftk_plan_set_tuning", "ftk_plan_get_tuning", "ftk_batch_create", "ftk_batch_run", "ftk_batch_info",
            "ftk_batch_destroy", "ftk_strerror", "ftk_last_error_message",
            # include/ftk_mlp.h
@@ -115,6 +115,7 @@ def lib() -> ctypes.CDLL:
     L.ftk_set_shifts.argtypes = [vp, vp, i]
     L.ftk_transform.argtypes = [vp, vp, i, vp, vp]
     L.ftk_align_coeffs.argtypes = [vp, vp, i, vp, i, vp, vp, vp]
+    L.ftk_align_coeffs_noalloc.argtypes = [vp, vp, i, vp, i, vp, vp, vp]
     L.ftk_align.argtypes = [vp, vp, i, vp, i, vp, vp, vp]
     L.ftk_plan_tables.argtypes = [i, i, d, d, vp, i, ctypes.POINTER(i), vp, vp, vp, vp, vp, vp,
                                   ctypes.POINTER(d)]
@@ -291,6 +292,16 @@ class Plan:
         X, best = self._outputs(a.shape[0], b.shape[0], want_X, a.device, X, best)
         _check(lib().ftk_align_coeffs(self._h, _ptr(a), a.shape[0], _ptr(b), b.shape[0], _ptr(X), _ptr(best),
                                       _stream(stream)), "ftk_align_coeffs")
+        return X, best
+
+    def align_coeffs_noalloc(self, a, b, X=None, best=None, stream=None):
+        """ftk_align_coeffs_noalloc: the caller passes the outputs (X and/or
+        best, device tensors); the library allocates nothing."""
+        import torch
+        _require_cuda(a, torch.complex64, "img_coeffs")
+        _require_cuda(b, torch.complex64, "tmpl_coeffs")
+        _check(lib().ftk_align_coeffs_noalloc(self._h, _ptr(a), a.shape[0], _ptr(b), b.shape[0], _ptr(X), _ptr(best),
+                                              _stream(stream)), "ftk_align_coeffs_noalloc")
         return X, best
 
     def align(self, images, templates, want_X=False, X=None, best=None, stream=None):
