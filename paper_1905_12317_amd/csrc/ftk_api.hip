@@ -236,8 +236,12 @@ double pow2_at_or_above(double x) {
 }
 
 // The FP16 form's rotation transform tables T_E, T_O (the real map from the
-// packed modes to the Qa rotations, split by the parity of the mode), fp16,
-// in the fragment order the Step 3 kernel reads (kernels.h).
+// packed modes to the rotations r < Qa/2, split by the parity of the mode),
+// fp16, as the A-operand fragments of the 16x16x32 MFMA in the K order of the
+// two-tile Step 3 (kernels.h): fragment (parity, row tile t, K step s), lane
+// l, element e holds the entry of rotation r = 16 t + l % 16 and mode q =
+// 32 s + 8 (e / 2) + 4 (g / 2) + 2 (e % 2) + parity, part c = g % 2
+// (g = l / 16).
 std::vector<uint16_t> rotation_tables_f16(int Qa) {
   const int QH = Qa / 2, NT = QH / 16, NS = QH / 32;
   std::vector<uint16_t> out(static_cast<size_t>(2) * NT * NS * 64 * 8);
@@ -247,8 +251,8 @@ std::vector<uint16_t> rotation_tables_f16(int Qa) {
         for (int l = 0; l < 64; ++l)
           for (int e = 0; e < 8; ++e) {
             const int r = 16 * t + l % 16;
-            const int kk = 32 * s + 8 * (l / 16) + e;
-            const int m = kk / 2, c = kk % 2, q = 2 * m + par;
+            const int g = l / 16, c = g % 2;
+            const int q = 32 * s + 8 * (e / 2) + 4 * (g / 2) + 2 * (e % 2) + par;
             double v;
             if (q == 0) {
               v = c == 0 ? 1.0 : ((r & 1) ? -1.0 : 1.0);
@@ -593,6 +597,10 @@ int ftk_set_shifts(ftk_plan* p, const double* shifts_px, int N) {
       for (int k = 0; k < 2 * Hp; ++k) mx = std::max(mx, std::fabs(entry(row, k)));
     const double sy = pow2_at_or_above(mx);
     const bool split = p->precision == FTK_FP16X3;
+    // the FP16 form's two-tile Step 3 (Qa <= 256) takes the panel as the B
+    // operand of its transposed contraction: column rho = 16 c + dl of a
+    // shift tile instead of row 2 dl + c
+    const bool jcol = !split && rot16_table_bytes(p->Qa) > 0;
     // the split form lifts the panel to the top of the fp16 range (its lo
     // parts then stay normal numbers down to 2^-18 of the largest entry)
     const double ysc = split ? std::ldexp(1.0, split_f16_exps(p->M).data) : 1.0;
@@ -601,7 +609,9 @@ int ftk_set_shifts(ftk_plan* p, const double* shifts_px, int N) {
       for (int ks = 0; ks < nks; ++ks)
         for (int l = 0; l < 64; ++l)
           for (int e8 = 0; e8 < 8; ++e8) {
-            const double v = entry(rt * 32 + (l & 31), ks * 16 + 8 * (l >> 5) + e8) / sy * ysc;
+            const int rho = l & 31;
+            const int row = jcol ? 2 * (rt * 16 + (rho & 15)) + (rho >> 4) : rt * 32 + rho;
+            const double v = entry(row, ks * 16 + 8 * (l >> 5) + e8) / sy * ysc;
             const size_t i = at(rt, ks, l, e8);
             h16[i] = f16_rne(v);
             if (split) l16[i] = f16_rne(v - f16_value(h16[i]));

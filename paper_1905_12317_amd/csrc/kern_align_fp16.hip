@@ -181,7 +181,7 @@ __global__ void __launch_bounds__(MAXT) step3_fp16(Step3Args p) {
   step3_epilogue_reg<CTQ>(p, acc, pair, d0, T, twl, lane);
 }
 
-// ---- rotation transform on MFMA (Qa <= 256) --------------------------------
+// ---- shift contraction and rotation transform on MFMA (Qa <= 256) -------
 //
 // The Qa real outputs of a shift are a real linear map of the packed modes
 // P(q) = Xhat(q), q = 0 .. QH - 1 (P(0) = Xhat(0) + i Xhat(QH)):
@@ -189,170 +189,414 @@ __global__ void __launch_bounds__(MAXT) step3_fp16(Step3Args p) {
 //          + sum_{q >= 1} 2 (Re P(q) cos(2 pi q r / Qa) + Im P(q) sin(2 pi q r / Qa)).
 // Split by the parity of q, X(r) = E(r) + O(r) and X(r + QH) = E(r) - O(r)
 // for r < QH (the odd-q terms change sign under r -> r + QH, the even ones
-// and the Nyquist term do not).  E and O are two real products
-//   E[r][dl] = sum_k T_E[r][k] V_E[k][dl],  O likewise,
-// with k = 2 m + c over the modes q = 2 m (E) or 2 m + 1 (O), c = 0 real and
-// 1 imaginary part: each is a (QH x QH) by (QH x 16 shifts) product, done
-// with v_mfma_f32_16x16x32_f16 (fp16 operands, FP32 accumulation).  The
-// tables T_E and T_O (fp16, built on the host, laid out as the MFMA's
-// A-operand fragments: [E/O][row tile t][K step s][lane][8]) stay in LDS for
-// the whole kernel, which loops over its pairs (one workgroup per CU).
+// and the Nyquist term do not).  E and O are two real products with the
+// fp16 tables T_E, T_O (QH rotations by QH (mode, re|im) entries each),
+// v_mfma_f32_16x16x32_f16, FP32 accumulation.
+//
+// The shift contraction runs transposed, D[q][j] = sum_k' Zhat[q][k'] Y[k'][j]
+// (v_mfma_f32_32x32x16_f16, the staged Zhat fragment as A, the shift panel
+// as B), with column j = 16 c + dl of a tile of 16 shifts (c = 0 real, 1
+// imaginary part).  Lane l then holds column l % 32 and, in register v of
+// column tile ct, the mode q = 32 ct + 8 (v / 4) + 4 (l / 32) + v % 4.  That
+// is the B operand of the 16x16x32 MFMA (lane l holds column n = l % 16 =
+// dl and k = 8 (l / 16) + e, e = 0 .. 7) once the rotation's K index of lane
+// group g = l / 16 is read as c = g % 2 and q = 32 ct + 8 (e / 2) +
+// 4 (g / 2) + 2 (e % 2) + parity, i.e. register v = 2 e + parity: the
+// tables are built in that K order (host), and the contraction's results
+// feed the rotation MFMAs with no lane exchange and no LDS transpose.
+//
+// Each wave owns two tiles of 16 shifts: every Zhat fragment read from LDS
+// feeds two contraction MFMAs and every table fragment two rotation MFMAs.
+// One workgroup of 8 waves per CU loops over its (pair, shift block) units;
+// the tables stay in LDS for the whole kernel, and the next pair's first
+// Zhat chunk is stored during the last chunk of the current one.
 //
 // 16x16x32 operand layouts: A lane l holds A[l % 16][8 (l / 16) + e],
-// B lane l holds B[8 (l / 16) + e][l % 16], e = 0 .. 7; the result lane l
-// holds D[4 (l / 16) + v][l % 16], v = 0 .. 3.
+// B lane l holds B[8 (l / 16) + e][l % 16]; the result lane l holds
+// D[4 (l / 16) + v][l % 16], v = 0 .. 3.
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-__host__ __device__ constexpr int rot_row_words(int QH) { return QH / 2 + 4; }  // transpose row: QH/2 words + pad
+constexpr int kMtWaves = 8;        // waves per workgroup of the two-tile kernel
+constexpr int kMtCompute = 7;      // waves 0..6 compute; wave 7 stages Zhat
+constexpr int kMtTiles = 2;        // shift tiles (16 shifts each) per compute wave
+constexpr int kMtBlockShifts = 16 * kMtCompute * kMtTiles;  // shifts of one shift block
+
+// Zhat staging of the two-tile kernel.  The workgroup walks a stream of
+// chunks: for each of its (pair, shift block) units in turn, the pair's Zhat
+// in chunks of 64 k' (QH rows of 128 bytes, 4 MFMA K steps).  Wave 7 (the
+// stager) loads the stream from HBM into registers three chunks ahead and
+// stores chunk g into LDS buffer g % kMtRing as soon as every compute wave
+// has finished chunk g - kMtRing; it then publishes ready[g % kMtRing] =
+// g + 1.  A compute wave waits for that value before it reads chunk g and
+// publishes prog[wave] = g + 1 once its reads of chunk g are done.  There is
+// no workgroup barrier in the loop: the stager runs ahead of the compute
+// waves by up to kMtRing chunks, the compute waves drift freely (one wave's
+// rotation epilogue overlaps another's contraction on the same SIMD), and the
+// compute waves issue no Zhat loads, so their shift-panel loads never wait
+// behind an HBM load.
+constexpr int kMtRing = 5;
 
 template <int CTQ>
-__device__ __forceinline__ void rot_epilogue(const Step3Args& p, f32x16 (&acc)[CTQ], int pair, int d0,
-                                             const float4* __restrict__ tbl, uint32_t* sc, int lane) {
+struct MtStage {
+  static constexpr int QH = 32 * CTQ;
+  static constexpr int ROWW = 36;       // LDS words per q row: 32 data, 4 pad
+  static constexpr int BUF = QH * ROWW;  // words of one buffer
+  static constexpr int NF4 = QH * 8;     // float4 of one chunk
+  static constexpr int PER = NF4 / 64;   // float4 per stager lane
+  static __device__ __forceinline__ float* at(float* region, int buf, int t) {
+    return region + buf * BUF + (t >> 3) * ROWW + (t & 7) * 4;
+  }
+  // flags after the ring: ready[kMtRing], prog[kMtCompute], abort
+  static __device__ __forceinline__ int* flags(float* region) {
+    return reinterpret_cast<int*>(region + kMtRing * BUF);
+  }
+};
+constexpr int kMtFlagWords = kMtRing + kMtCompute + 1;
+
+// Wait (workgroup-scope acquire) until *addr >= want.  Bounded: after about
+// 2^20 polls the wait gives up and sets *abort, which ends every later wait
+// at once (the results are then wrong, but no wave can hang).
+__device__ __forceinline__ void mt_wait_ge(int* addr, int want, int* abort) {
+  for (int it = 0; it < (1 << 20); ++it) {
+    if (__hip_atomic_load(addr, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) >= want) return;
+    if (__hip_atomic_load(abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) != 0) return;
+    __builtin_amdgcn_s_sleep(1);
+  }
+  __hip_atomic_store(abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// Workgroup-scope release store of v (one lane), after this wave's LDS
+// accesses so far.
+__device__ __forceinline__ void mt_publish(int* addr, int v) {
+  if ((threadIdx.x & 63) == 0) __hip_atomic_store(addr, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// Stream position g -> the Zhat chunk it stages (float4 pointer).
+__device__ __forceinline__ const float4* mt_chunk_src(const Step3Args& p, int g, int nch, int QH) {
+  const int unit = blockIdx.x + (g / nch) * gridDim.x;
+  int pair, yb;
+  step3_block(unit, p.nblk, p.pairs, pair, yb);
+  return static_cast<const float4*>(p.zs) + (static_cast<size_t>(pair) * (2 * p.H_pad / 64) + g % nch) * QH * 8;
+}
+
+// The stager: T chunks in the stream, three register sets of PER float4.
+template <int CTQ>
+__device__ __forceinline__ void mt_stager(const Step3Args& p, float* region, int T, int nch) {
+  using S = MtStage<CTQ>;
+  const int lane = threadIdx.x & 63;
+  int* ready = S::flags(region);
+  int* prog = ready + kMtRing;
+  int* abort = prog + kMtCompute;
+  float4 r0[S::PER], r1[S::PER], r2[S::PER];
+  auto issue = [&](float4 (&r)[S::PER], int g) {
+    const float4* src = mt_chunk_src(p, min(g, T - 1), nch, S::QH) + lane;  // past the end: reloads the last
+#pragma unroll
+    for (int k = 0; k < S::PER; ++k) r[k] = load_stream(src + 64 * k);
+  };
+  auto step = [&](float4 (&r)[S::PER], int g) {
+    // buffer g % kMtRing is free once every compute wave has finished chunk g - kMtRing
+    if (g >= kMtRing) {
+      for (int w = 0; w < kMtCompute; ++w) mt_wait_ge(prog + w, g - kMtRing + 1, abort);
+    }
+    const int buf = g % kMtRing;
+#pragma unroll
+    for (int k = 0; k < S::PER; ++k) *reinterpret_cast<float4*>(S::at(region, buf, lane + 64 * k)) = r[k];
+    mt_publish(ready + buf, g + 1);
+    issue(r, g + 3);
+  };
+  issue(r0, 0);
+  issue(r1, 1);
+  issue(r2, 2);
+  for (int g = 0; g < T; g += 3) {
+    step(r0, g);
+    if (g + 1 >= T) break;
+    step(r1, g + 1);
+    if (g + 2 >= T) break;
+    step(r2, g + 2);
+  }
+}
+
+// One chunk of the transposed contraction for a compute wave: K steps
+// 4 c .. 4 c + 3 from LDS buffer `buf`, both tiles; the shift panel operands
+// come from a ring of four register slots, each refilled after use with the
+// K step four ahead (wrapping into the next unit's tiles at the end of the
+// pair: yn0, yn1).
+template <int CTQ>
+__device__ __forceinline__ void mt_chunk(const float* region, int buf, int c, int nks, f32x16 (&acc)[kMtTiles][CTQ],
+                                         f16x8 (&y0)[4], f16x8 (&y1)[4], const f16x8* y0p, const f16x8* y1p,
+                                         const f16x8* yn0, const f16x8* yn1, int lane) {
+  using S = MtStage<CTQ>;
+  const float* Zb = region + buf * S::BUF + (lane & 31) * S::ROWW + 4 * (lane >> 5);
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    f16x8 a[CTQ];
+#pragma unroll
+    for (int ct = 0; ct < CTQ; ++ct) a[ct] = *reinterpret_cast<const f16x8*>(Zb + ct * 32 * S::ROWW + 8 * s);
+#pragma unroll
+    for (int ct = 0; ct < CTQ; ++ct)
+      acc[0][ct] = __builtin_amdgcn_mfma_f32_32x32x16_f16(a[ct], y0[s], acc[0][ct], 0, 0, 0);
+    // a missing second tile multiplies the first one's panel (its results
+    // are never used): no branch in the loop
+#pragma unroll
+    for (int ct = 0; ct < CTQ; ++ct)
+      acc[1][ct] = __builtin_amdgcn_mfma_f32_32x32x16_f16(a[ct], y1[s], acc[1][ct], 0, 0, 0);
+    const int kn = 4 * c + s + 4;
+    const bool wrap = kn >= nks;
+    const int ko = (wrap ? kn - nks : kn) * 64;
+    y0[s] = (wrap ? yn0 : y0p)[ko];
+    y1[s] = (wrap ? yn1 : y1p)[ko];
+  }
+}
+
+// Rotation transform, argmax and (WX) X stores of the wave's two tiles
+// (shifts past N, e.g. of a missing second tile, take no part in the argmax
+// and are not stored).  Software-pipelined over the row tiles t of 16
+// rotations: the table fragments of t + 1 are read, the MFMAs of t issued
+// and the vector work of t - 1 done, so both overlap the matrix cores.
+//
+// Argmax.  Lane l holds, per tile and half of the rotations, the quads
+// r = 16 t + 4 (l / 16) + v, v = 0..3 (and r + QH).  With X stored (WX) every
+// element is compared and stored.  Without, a lane keeps per tile and half
+// only the largest quad maximum and the first t that reached it (5 vector
+// operations per quad instead of 12); the wave then takes the best
+// (value, quad index) over its lanes, which is the best (value, index) over
+// the wave at quad granularity: quads of different lanes are disjoint index
+// ranges, and within a lane the first t and the first half win ties.  The
+// winning lane's quad is recomputed (one row tile of products, the same
+// inputs and order, so bitwise the same values) and its lowest element equal
+// to the maximum completes the index.
+template <int CTQ, bool WX>
+__device__ __forceinline__ void mt_epilogue(const Step3Args& p, f32x16 (&acc)[kMtTiles][CTQ], int pair, int t0,
+                                            const float4* __restrict__ tbl, int lane) {
   constexpr int QH = 32 * CTQ;
   constexpr int Qa = 2 * QH;
-  constexpr int NT = QH / 16;  // row tiles (16 rotations each)
-  constexpr int NS = QH / 32;  // K steps of 32
-  constexpr int RS = rot_row_words(QH);
-  const int jj = lane & 31;
-  const int hh = lane >> 5;
-  // (1) fp16 (re, im) pairs: acc rows 2 dl + c, register v = 2 g + c holds
-  // shift dl = 4 (g / 2) + 2 hh + g % 2 of column q = 32 ct + jj
-  uint32_t h2[CTQ][8];
+  constexpr int NT = QH / 16;  // row tiles of 16 rotations
+  constexpr int NTL = kMtTiles;
+  typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
+  typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+  // B operands: the even-q (E) and odd-q (O) registers of each column tile
+  f16x8 BE[NTL][CTQ], BO[NTL][CTQ];
 #pragma unroll
-  for (int ct = 0; ct < CTQ; ++ct)
+  for (int st = 0; st < NTL; ++st)
 #pragma unroll
-    for (int g = 0; g < 8; ++g) {
-      typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
-      const f16x2 v = __builtin_convertvector((float2_v{acc[ct][2 * g], acc[ct][2 * g + 1]}), f16x2);
-      h2[ct][g] = __builtin_bit_cast(uint32_t, v);
+    for (int ct = 0; ct < CTQ; ++ct) {
+      u32x4 e4, o4;
+#pragma unroll
+      for (int w = 0; w < 4; ++w) {
+        e4[w] = __builtin_bit_cast(uint32_t, __builtin_convertvector(
+                                                  (float2_v{acc[st][ct][4 * w], acc[st][ct][4 * w + 2]}), f16x2));
+        o4[w] = __builtin_bit_cast(uint32_t, __builtin_convertvector(
+                                                  (float2_v{acc[st][ct][4 * w + 1], acc[st][ct][4 * w + 3]}), f16x2));
+      }
+      BE[st][ct] = __builtin_bit_cast(f16x8, e4);
+      BO[st][ct] = __builtin_bit_cast(f16x8, o4);
     }
-  // (2) transpose through this wave's LDS rows: row dl holds words m =
-  // 0 .. QH/2 - 1, the (re, im) of mode 2 m + parity; even columns first
-  f16x8 BE[NS], BO[NS];
-  uint32_t* const wbase = sc + 2 * hh * RS + (jj >> 1);            // + compile-time offsets
-  const uint32_t* const rbase = sc + (lane & 15) * RS + 4 * (lane >> 4);
-#pragma unroll
-  for (int par = 0; par < 2; ++par) {
-    if ((jj & 1) == par) {
-#pragma unroll
-      for (int ct = 0; ct < CTQ; ++ct)
-#pragma unroll
-        for (int g = 0; g < 8; ++g) wbase[(4 * (g >> 1) + (g & 1)) * RS + 16 * ct] = h2[ct][g];
-    }
-    wave_sync();
-#pragma unroll
-    for (int s = 0; s < NS; ++s) {
-      const f16x8 v = *reinterpret_cast<const f16x8*>(rbase + 16 * s);
-      if (par == 0)
-        BE[s] = v;
-      else
-        BO[s] = v;
-    }
-    wave_sync();
-  }
-  // (3) 16 rotations per tile: E and O products, X(r) = E + O and
-  // X(r + QH) = E - O; per lane one shift, rotations r = 16 t + 4 (l / 16) + v
   const int dl = lane & 15;
-  const int delta = d0 + dl;
-  const bool valid = delta < p.N;
   const int r4 = 4 * (lane >> 4);
-  float* xr = (p.X && valid) ? p.X + (static_cast<size_t>(pair) * p.N + delta) * Qa + r4 : nullptr;
-  const float xs = (xr && p.xscale) ? *p.xscale : 1.f;
+  float xs = 1.f;
+  float* xr[NTL];
+  bool valid[NTL];
+  float bv0[NTL], bv1[NTL];
+  int bs0[NTL], bs1[NTL];  // WX: step 4 t + v of the best in each half; else the first t of the best quad
+#pragma unroll
+  for (int st = 0; st < NTL; ++st) {
+    const int delta = 16 * (t0 + st) + dl;
+    valid[st] = delta < p.N;
+    xr[st] = WX ? p.X + (static_cast<size_t>(pair) * p.N + (valid[st] ? delta : 0)) * Qa + r4 : nullptr;
+    bv0[st] = bv1[st] = -__builtin_inff();
+    bs0[st] = bs1[st] = -1;
+  }
+  if (WX && p.xscale) xs = *p.xscale;
   const f16x8* tb = reinterpret_cast<const f16x8*>(tbl) + lane;
-  float bv0 = -__builtin_inff(), bv1 = -__builtin_inff();
-  int bs0 = -1, bs1 = -1;  // step 4 t + v of the best in each half
+  f16x8 tE[2][CTQ], tO[2][CTQ];  // table fragments of t (slot t % 2)
+  f32x4 dE[2][NTL], dO[2][NTL];  // products of t (slot t % 2)
+  auto load_tables = [&](int t, int slot) {
+#pragma unroll
+    for (int s = 0; s < CTQ; ++s) {
+      tE[slot][s] = tb[64 * (t * CTQ + s)];
+      tO[slot][s] = tb[64 * ((NT + t) * CTQ + s)];
+    }
+  };
+  auto products = [&](int slot) {
+#pragma unroll
+    for (int st = 0; st < NTL; ++st) {
+      dE[slot][st] = f32x4{0.f, 0.f, 0.f, 0.f};
+      dO[slot][st] = f32x4{0.f, 0.f, 0.f, 0.f};
+    }
+#pragma unroll
+    for (int s = 0; s < CTQ; ++s)
+#pragma unroll
+      for (int st = 0; st < NTL; ++st) {
+        dE[slot][st] = __builtin_amdgcn_mfma_f32_16x16x32_f16(tE[slot][s], BE[st][s], dE[slot][st], 0, 0, 0);
+        dO[slot][st] = __builtin_amdgcn_mfma_f32_16x16x32_f16(tO[slot][s], BO[st][s], dO[slot][st], 0, 0, 0);
+      }
+  };
+  // sums and compares (increasing r within each half: a later equal value
+  // never replaces, so the lowest index wins ties; NaN never compares
+  // greater) and (WX) stores of the rotations of row tile t
+  auto finish = [&](int t, int slot) {
+#pragma unroll
+    for (int st = 0; st < NTL; ++st) {
+      f32x4 x0, x1;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        x0[v] = dE[slot][st][v] + dO[slot][st][v];
+        x1[v] = dE[slot][st][v] - dO[slot][st][v];
+      }
+      if (WX) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const bool g0 = x0[v] > bv0[st], g1 = x1[v] > bv1[st];
+          bv0[st] = g0 ? x0[v] : bv0[st];
+          bs0[st] = g0 ? 4 * t + v : bs0[st];
+          bv1[st] = g1 ? x1[v] : bv1[st];
+          bs1[st] = g1 ? 4 * t + v : bs1[st];
+        }
+        if (valid[st]) {
+          *reinterpret_cast<float4*>(xr[st] + 16 * t) = make_float4(x0[0] * xs, x0[1] * xs, x0[2] * xs, x0[3] * xs);
+          *reinterpret_cast<float4*>(xr[st] + QH + 16 * t) =
+              make_float4(x1[0] * xs, x1[1] * xs, x1[2] * xs, x1[3] * xs);
+        }
+      } else {
+        // quad maxima (fmaxf skips NaN), then the first t of the largest
+        const float m0 = fmaxf(fmaxf(fmaxf(x0[0], x0[1]), x0[2]), x0[3]);
+        const float m1 = fmaxf(fmaxf(fmaxf(x1[0], x1[1]), x1[2]), x1[3]);
+        const bool g0 = m0 > bv0[st], g1 = m1 > bv1[st];
+        bv0[st] = g0 ? m0 : bv0[st];
+        bs0[st] = g0 ? t : bs0[st];
+        bv1[st] = g1 ? m1 : bv1[st];
+        bs1[st] = g1 ? t : bs1[st];
+      }
+    }
+  };
+  load_tables(0, 0);
 #pragma unroll
   for (int t = 0; t < NT; ++t) {
-    f32x4 dE = {0.f, 0.f, 0.f, 0.f}, dO = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-    for (int s = 0; s < NS; ++s) {
-      dE = __builtin_amdgcn_mfma_f32_16x16x32_f16(tb[64 * (t * NS + s)], BE[s], dE, 0, 0, 0);
-      dO = __builtin_amdgcn_mfma_f32_16x16x32_f16(tb[64 * ((NT + t) * NS + s)], BO[s], dO, 0, 0, 0);
-    }
-    f32x4 x0, x1;
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      x0[v] = dE[v] + dO[v];
-      x1[v] = dE[v] - dO[v];
-      // increasing r within each half: a later equal value never replaces
-      // (the lowest index wins ties); NaN never compares greater
-      if (x0[v] > bv0) {
-        bv0 = x0[v];
-        bs0 = 4 * t + v;
-      }
-      if (x1[v] > bv1) {
-        bv1 = x1[v];
-        bs1 = 4 * t + v;
-      }
-    }
-    if (xr) {
-      *reinterpret_cast<float4*>(xr + 16 * t) = make_float4(x0[0] * xs, x0[1] * xs, x0[2] * xs, x0[3] * xs);
-      *reinterpret_cast<float4*>(xr + QH + 16 * t) = make_float4(x1[0] * xs, x1[1] * xs, x1[2] * xs, x1[3] * xs);
-    }
+    if (t + 1 < NT) load_tables(t + 1, (t + 1) & 1);
+    products(t & 1);
+    if (t > 0) finish(t - 1, (t - 1) & 1);
   }
-  // the lane's best: the first half wins ties (lower index)
-  const bool take1 = bs1 >= 0 && (bs0 < 0 || bv1 > bv0);
-  const int bs = take1 ? bs1 : bs0;
-  float bv = take1 ? bv1 : bv0;
+  finish(NT - 1, (NT - 1) & 1);
+  // the lane's best over its shifts (the first half of the rotations wins
+  // ties: lower index), then over the wave; without X the index is that of
+  // the quad (its element v = 0)
+  float bv = -__builtin_inff();
   uint32_t bi = 0xffffffffu;
-  if (valid && bs >= 0)
-    bi = static_cast<uint32_t>(delta) * Qa + (take1 ? QH : 0) + 16 * (bs >> 2) + r4 + (bs & 3);
-  else
-    bv = -__builtin_inff();
+#pragma unroll
+  for (int st = 0; st < NTL; ++st) {
+    const bool take1 = bs1[st] >= 0 && (bs0[st] < 0 || bv1[st] > bv0[st]);
+    const int bs = take1 ? bs1[st] : bs0[st];
+    const bool ok = valid[st] && bs >= 0;
+    const uint32_t r = WX ? 16 * (bs >> 2) + r4 + (bs & 3) : 16 * bs + r4;
+    const uint32_t i = static_cast<uint32_t>(16 * (t0 + st) + dl) * Qa + (take1 ? QH : 0) + r;
+    ep_better(bv, bi, ok ? (take1 ? bv1[st] : bv0[st]) : -__builtin_inff(), ok ? i : 0xffffffffu);
+  }
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) {
     const float ov = __shfl_xor(bv, off);
     const uint32_t oi = static_cast<uint32_t>(__shfl_xor(static_cast<int>(bi), off));
     ep_better(bv, bi, ov, oi);
   }
-  if (lane == 0 && bi != 0xffffffffu) atomicMax(p.keys + pair, pose_key(bv, bi));
+  if (bi == 0xffffffffu) return;  // no valid shift (wave-uniform)
+  if (!WX) {
+    // the winning quad: shift delta = bi / Qa (tile st, lane dl + 16 (r4 / 4)),
+    // rotation r = bi % Qa = half QH + 16 t + r4
+    const uint32_t delta = bi / Qa, rr = bi - delta * Qa;
+    const int half = rr >= static_cast<uint32_t>(QH);
+    const int rq = static_cast<int>(rr) - (half ? QH : 0);
+    const int t = __builtin_amdgcn_readfirstlane(rq >> 4);
+    const int st = __builtin_amdgcn_readfirstlane(static_cast<int>(delta >> 4) - t0);
+    const int win = static_cast<int>(delta & 15) + 4 * (rq & 15);
+    load_tables(t, 0);
+    f32x4 e = {0.f, 0.f, 0.f, 0.f}, o = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int s = 0; s < CTQ; ++s) {
+      e = __builtin_amdgcn_mfma_f32_16x16x32_f16(tE[0][s], st ? BE[1][s] : BE[0][s], e, 0, 0, 0);
+      o = __builtin_amdgcn_mfma_f32_16x16x32_f16(tO[0][s], st ? BO[1][s] : BO[0][s], o, 0, 0, 0);
+    }
+    int v = 3;
+#pragma unroll
+    for (int k = 3; k >= 0; --k) v = ((half ? e[k] - o[k] : e[k] + o[k]) == bv) ? k : v;
+    bi += static_cast<uint32_t>(__shfl(v, win));
+  }
+  if (lane == 0) atomicMax(p.keys + pair, pose_key(bv, bi));
 }
 
-// SEP: the transpose rows have LDS of their own after the Zhat buffers (the
-// next pair's first chunk is then stored during the last chunk of the
-// current one); otherwise they reuse the Zhat buffers.
-template <int CTQ, bool PREF, bool SEP>
-__global__ void __launch_bounds__(1024) step3_fp16_rot(Step3Args p) {
+// One workgroup of kMtWaves waves per CU, looping over (pair, shift block)
+// units; a shift block is kMtCompute * kMtTiles tiles of 16 shifts.
+template <int CTQ, bool WX>
+__global__ void __launch_bounds__(64 * kMtWaves) step3_fp16_mt(Step3Args p) {
   extern __shared__ float smem[];
+  using S = MtStage<CTQ>;
   constexpr int QH = 32 * CTQ;
-  constexpr int NFRAG = 2 * (QH / 16) * (QH / 32);  // 1 KB each
-  constexpr int RS = rot_row_words(QH);
+  constexpr int NFRAG = 2 * (QH / 16) * CTQ;  // 1 KB each
   const int tid = threadIdx.x;
-  const int wave = tid >> 6;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   float4* tbl = reinterpret_cast<float4*>(smem);
   const float4* tsrc = static_cast<const float4*>(p.rot16);
   for (int i = tid; i < NFRAG * 64; i += blockDim.x) tbl[i] = tsrc[i];
   float* region = smem + NFRAG * 256;
-  uint32_t* sc = reinterpret_cast<uint32_t*>(region + (SEP ? 2 * QH * 36 : 0)) + wave * 16 * RS;
+  int* ready = S::flags(region);
+  int* prog = ready + kMtRing;
+  int* abort = prog + kMtCompute;
+  if (tid < kMtFlagWords) ready[tid] = 0;
   const int total = p.pairs * p.nblk;
+  if (static_cast<int>(blockIdx.x) >= total) return;
+  __syncthreads();  // tables and flags set (the only workgroup barrier)
+  const int units = (total - 1 - static_cast<int>(blockIdx.x)) / static_cast<int>(gridDim.x) + 1;
+  const int nks = p.H_pad / 8;   // K steps of 16 k' (2 H_pad k')
+  const int nch = p.H_pad / 32;  // chunks of 64 k'
+  if (wave == kMtCompute) {
+    mt_stager<CTQ>(p, region, units * nch, nch);
+    return;
+  }
+  const int lane = tid & 63;
+  const int ntiles = (p.N + 15) / 16;
+  const int ntile_pad = p.N_pad / 16;
+  // shift panel fragments [tile][K step][lane][8] fp16 (column j = 16 c + dl)
+  // of the wave's two tiles in shift block yb (a missing tile reads the last)
+  auto panel = [&](int yb, int st) {
+    const int t = min((yb * kMtCompute + wave) * kMtTiles + st, ntile_pad - 1);
+    return reinterpret_cast<const f16x8*>(p.yt_hi) + static_cast<size_t>(t) * nks * 64 + lane;
+  };
   int b = blockIdx.x;
-  if (b >= total) return;
   int pair, yb;
   step3_block(b, p.nblk, p.pairs, pair, yb);
-  fp16_first_chunk<CTQ>(p, region, pair);
-  __syncthreads();
+  const f16x8* y0p = panel(yb, 0);
+  const f16x8* y1p = panel(yb, 1);
+  f16x8 y0[4], y1[4];
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    y0[s] = y0p[min(s, nks - 1) * 64];
+    y1[s] = y1p[min(s, nks - 1) * 64];
+  }
+  int g = 0;  // stream position
   for (;;) {
-    const int d0 = (yb * p.nwaves + wave) * 16;
-    const bool active = d0 < p.N;
+    const int t0 = (yb * kMtCompute + wave) * kMtTiles;
+    const int nt = max(0, min(kMtTiles, ntiles - t0));
     const int bn = b + gridDim.x;
-    int pn = 0, ybn = 0;
+    int pn = pair, ybn = yb;
     if (bn < total) step3_block(bn, p.nblk, p.pairs, pn, ybn);
-    constexpr bool early = SEP && PREF;  // next first chunk stored inside the K loop
-    f32x16 acc[CTQ];
-    fp16_kloop<CTQ, PREF>(p, region, pair, d0, active, acc, (early && bn < total) ? pn : -1);
-    // every wave is past the Zhat buffers (the transposes may reuse them),
-    // and the next pair's first chunk is visible
-    __syncthreads();
-    if (active) rot_epilogue<CTQ>(p, acc, pair, d0, tbl, sc, tid & 63);
-    if (bn >= total) break;
-    if (!early) {
-      __syncthreads();  // transposes done before buffer 0 is written again
-      fp16_first_chunk<CTQ>(p, region, pn);
-      __syncthreads();
+    const f16x8* yn0 = panel(ybn, 0);
+    const f16x8* yn1 = panel(ybn, 1);
+    f32x16 acc[kMtTiles][CTQ];
+#pragma unroll
+    for (int st = 0; st < kMtTiles; ++st)
+#pragma unroll
+      for (int ct = 0; ct < CTQ; ++ct) acc[st][ct] = zero16();
+    for (int c = 0; c < nch; ++c, ++g) {
+      const int buf = g % kMtRing;
+      mt_wait_ge(ready + buf, g + 1, abort);  // chunk g is in buffer g % kMtRing
+      if (nt > 0) mt_chunk<CTQ>(region, buf, c, nks, acc, y0, y1, y0p, y1p, yn0, yn1, lane);
+      mt_publish(prog + wave, g + 1);  // done reading chunk g
     }
+    if (nt > 0) mt_epilogue<CTQ, WX>(p, acc, pair, t0, tbl, lane);
+    if (bn >= total) break;
     b = bn;
     pair = pn;
     yb = ybn;
+    y0p = yn0;
+    y1p = yn1;
   }
 }
 
@@ -407,19 +651,11 @@ size_t rot16_table_bytes(int Qa) {
   return (Qa % 64 == 0 && Qa <= 256) ? 2 * (QH / 16) * (QH / 32) * 1024 : 0;
 }
 
-// LDS of the MFMA-transform kernel: the tables, then the Zhat buffers and the
-// transpose rows, side by side where they fit (sep), else overlapping
-static size_t rot_lds(int Qa, int nwaves, bool sep) {
+// LDS of the two-tile kernel: the tables, the ring of Zhat buffers of 64 k',
+// the flags
+size_t step3_fp16_rot_lds_bytes(int Qa, int) {
   const size_t QH = Qa / 2;
-  const size_t k = sizeof(float) * 2 * QH * 36;
-  const size_t e = sizeof(uint32_t) * static_cast<size_t>(nwaves) * 16 * rot_row_words(static_cast<int>(QH));
-  return rot16_table_bytes(Qa) + (sep ? k + e : (k > e ? k : e));
-}
-constexpr size_t kRotLdsLimit = 160 * 1024;
-
-size_t step3_fp16_rot_lds_bytes(int Qa, int nwaves) {
-  const size_t sep = rot_lds(Qa, nwaves, true);
-  return sep <= kRotLdsLimit ? sep : rot_lds(Qa, nwaves, false);
+  return rot16_table_bytes(Qa) + sizeof(float) * kMtRing * QH * 36 + sizeof(int) * kMtFlagWords;
 }
 
 namespace {
@@ -449,16 +685,20 @@ static hipError_t launch_step3_fp16_t(const Step3Args& a0, hipStream_t s) {
   const bool pref = (nf4 + nthr - 1) / nthr <= 2;
   if constexpr (CTQ <= 4) {
     if (a.rot16) {
-      // one workgroup per CU, looping over its pairs' shift blocks
-      const bool sep = rot_lds(a.Qa, a.nwaves, true) <= kRotLdsLimit;
-      const size_t lds = rot_lds(a.Qa, a.nwaves, sep);
-      auto kern = pref ? (sep ? step3_fp16_rot<CTQ, true, true> : step3_fp16_rot<CTQ, true, false>)
-                       : (sep ? step3_fp16_rot<CTQ, false, true> : step3_fp16_rot<CTQ, false, false>);
+      // one workgroup of kMtWaves waves per CU; a shift block is
+      // kMtCompute * kMtTiles tiles of 16 shifts
+      Step3Args m = a0;
+      m.nwaves = kMtWaves;
+      m.nblk = (m.N + kMtBlockShifts - 1) / kMtBlockShifts;
+      const size_t units = static_cast<size_t>(m.pairs) * m.nblk;
+      if (units > 0x7fffffffull) return hipErrorInvalidConfiguration;
+      const size_t lds = step3_fp16_rot_lds_bytes(m.Qa, kMtWaves);
+      auto kern = m.X ? step3_fp16_mt<CTQ, true> : step3_fp16_mt<CTQ, false>;
       hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                          hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
       if (e != hipSuccess) return e;
-      const unsigned grid = static_cast<unsigned>(std::min<size_t>(nwg, static_cast<size_t>(device_cus())));
-      hipLaunchKernelGGL(kern, dim3(grid), dim3(nthr), lds, s, a);
+      const unsigned grid = static_cast<unsigned>(std::min<size_t>(units, static_cast<size_t>(device_cus())));
+      hipLaunchKernelGGL(kern, dim3(grid), dim3(64 * kMtWaves), lds, s, m);
       return hipGetLastError();
     }
   }

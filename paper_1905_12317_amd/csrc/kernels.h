@@ -102,14 +102,17 @@ hipError_t launch_step3_bf16(const Step3Args& args, bool fp16, hipStream_t strea
 // e_data = e_x = e_z = 0; the split-fp16 form lifts its operands to the top
 // of the fp16 range (kernels of kern_step1.hip multiply Step 1's FP32 result
 // by 2^e_z before splitting it, and X is multiplied back by scales[4]).
-// With Step3Args::rot16 set (Qa <= 256), the rotation transform runs on MFMA
-// from the fp16 tables T_E, T_O of the even and odd modes:
-//   T_E[r][2 m + c]: m = 0: 1 (c = 0), (-1)^r (c = 1);
-//                    m > 0: 2 cos(2 pi (2 m) r / Qa) (c = 0), 2 sin(...) (c = 1)
-//   T_O[r][2 m + c]: 2 cos(2 pi (2 m + 1) r / Qa) (c = 0), 2 sin(...) (c = 1)
-// for r, 2 m + c < Qa/2, stored as 1 KB MFMA fragments: value
-// T_p[16 t + l % 16][32 s + 8 (l / 16) + e] at half index
-// (((p Qa/32 + t) Qa/64 + s) 64 + l) 8 + e.
+// With Step3Args::rot16 set (Qa <= 256), Step 3 runs the two-tile kernel:
+// the shift contraction transposed (Zhat as the A operand; the fp16 shift
+// panel then has, per tile of 16 shifts, column 16 c + dl in place of row
+// 2 dl + c) and the rotation transform on MFMA from the fp16 tables T_E, T_O
+// of the even and odd modes, rows r < Qa/2:
+//   T[r][q, c]: q = 0: 1 (c = 0), (-1)^r (c = 1);
+//               q > 0: 2 cos(2 pi q r / Qa) (c = 0), 2 sin(...) (c = 1)
+// stored as 1 KB fragments (parity p, row tile t, K step s) of the
+// 16x16x32 MFMA's A operand: lane l, element e holds r = 16 t + l % 16,
+// c = (l / 16) % 2, q = 32 s + 8 (e / 2) + 4 (l / 32) + 2 (e % 2) + p, at
+// half index (((p Qa/32 + t) Qa/64 + s) 64 + l) 8 + e.
 size_t step3_fp16_lds_bytes(int Qa, int nwaves);
 size_t rot16_table_bytes(int Qa);  // 0 where the MFMA transform does not apply
 size_t step3_fp16_rot_lds_bytes(int Qa, int nwaves);

@@ -145,3 +145,30 @@ def test_align_fp16_input_scale(ftk):
     rel = np.max(np.abs(X2 - 1e4 * X0), axis=(2, 3)) / (1e4 * S)
     _say(f"  x 1e4: max rel difference {rel.max():.3e}")
     assert rel.max() <= eps
+
+
+@pytest.mark.parametrize("n,M,Qa,R,nshift", [(32, 16, 64, 2.0, 49), (64, 32, 128, 3.0, 0), (128, 64, 256, 4.0, 0),
+                                             (128, 64, 256, 8.0, 0), (32, 16, 128, 2.5, 30)])
+def test_poses_without_X_equal_poses_with_X(ftk, n, M, Qa, R, nshift):
+    """The best-pose-only kernel (argmax per quad of rotations, the winning
+    quad recomputed) gives bitwise the poses of the kernel that writes every
+    X and compares every element: same values, same (shift, rotation), ties
+    to the lowest index.  Blob pairs, white noise against itself and against
+    its copy rotated by 90 degrees; 797 shifts (several shift blocks per pair)
+    and 30 off-lattice shifts (a partial tile) included."""
+    rng = np.random.default_rng(7 + n + Qa)
+    shifts = (np.array([synth.area_uniform_disk(rng, R) for _ in range(nshift)]) if nshift
+              else synth.shift_lattice(R))
+    st = synth.make_alignment_set(9, n, 37, 5, 20, min(R, 2.0), 0.1)
+    noise = synth.white_noise_images(33, 3, n)
+    images = np.concatenate([st.images, noise, np.rot90(noise, 1, axes=(1, 2))])
+    templates = np.concatenate([st.templates, noise])
+    P = ftk.Plan(n, M, Qa, R, 1e-3, precision="fp16")
+    P.set_shifts(shifts)
+    _say(f"[fp16 poses] n={n} Qa={Qa} N={len(shifts)} nA={len(images)} nB={len(templates)}")
+    X, b1 = P.align(_dev(images), _dev(templates), want_X=True)
+    _, b2 = P.align(_dev(images), _dev(templates))
+    torch.cuda.synchronize()
+    p1, p2 = ftk.poses_numpy(b1), ftk.poses_numpy(b2)
+    for k in ("value", "shift", "rot"):
+        assert np.array_equal(p1[k], p2[k]), k
