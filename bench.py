@@ -182,9 +182,12 @@ def recall(best, inputs):
     return float(np.mean(best[0] == inputs.true_template))
 
 
-def cpu_baseline(inputs, w, shifts, n_img=8, n_tmp=48):
-    """The FP64 oracle as it stands (direct NUDFT transform + FP64 FTK) on a
-    bounded sample of the same workload, timed on the host."""
+def cpu_baseline(inputs, w, shifts, n_img=8, n_tmp=48, n_dir=(2, 4)):
+    """The FP64 oracle as it stands, timed on the host on bounded samples of
+    the same workload: the FP64 FTK (direct NUDFT transform + eq. fbk3 +
+    argmax) on n_img x n_tmp pairs, and the direct inner product on the polar
+    quadrature (eq. Xdg discretised, no SVD; polar samples by direct sum +
+    argmax) on n_dir[0] x n_dir[1] pairs."""
     from oracle import ftk as O
     try:
         from threadpoolctl import threadpool_info
@@ -200,10 +203,19 @@ def cpu_baseline(inputs, w, shifts, n_img=8, n_tmp=48):
             X = O.ftk_X(ai, bj, plan)
             O.best_pose(X)
     dt = time.perf_counter() - t
+    t = time.perf_counter()
+    ah = [O.polar_ft(x, plan.k, plan.Qa) for x in inputs.images[:n_dir[0]]]
+    bh = [O.polar_ft(x, plan.k, plan.Qa) for x in inputs.templates[:n_dir[1]]]
+    for ai in ah:
+        for bj in bh:
+            O.best_pose(np.real(O.direct_X(ai, bj, plan.k, plan.w, shifts, w["n"])))
+    dt_dir = time.perf_counter() - t
+    n_d = n_dir[0] * n_dir[1]
     return {"value": n_img * n_tmp / dt, "unit": "pairs/s", "cores": int(threads), "kind": "oracle",
-            "sample": f"first {n_img} images x {n_tmp} templates ({n_img * n_tmp} pairs) of the same workload: "
-                      f"direct FP64 NUDFT transform of the {n_img + n_tmp} images + FP64 FTK + argmax, "
-                      f"{dt:.1f} s"}
+            "sample": f"FP64 FTK: first {n_img} images x {n_tmp} templates ({n_img * n_tmp} pairs) of the same "
+                      f"workload, direct FP64 NUDFT transform of the {n_img + n_tmp} images + FP64 FTK + argmax, "
+                      f"{dt:.1f} s; direct inner product (no SVD): first {n_dir[0]} x {n_dir[1]} pairs, {dt_dir:.1f} s",
+            "direct_X_pairs_per_s": n_d / dt_dir}
 
 
 RAGGED = dict(name="ragged_c4", stacks=64, seed=4, scale=0.25, nblob=60, snr=0.05, eps=1e-3)
