@@ -98,6 +98,7 @@ typedef struct ftk_plan_info_t {
   double kmax;        /* pi n / 2 */
   size_t coeff_bytes_per_image; /* 8 * M * Qa */
   size_t device_bytes;          /* device memory held by the plan now */
+  int weighted;                 /* 1: operator SVD with a k-side weight */
 } ftk_plan_info_t;
 
 /* Build a plan (host FP64 planning, then upload of the device tables on the
@@ -121,6 +122,19 @@ typedef struct ftk_plan_info_t {
  * On success *out owns the plan; release it with ftk_plan_destroy.
  * Errors: FTK_EINVAL, FTK_EUNSUPPORTED, FTK_ENOMEM, FTK_EDEVICE. */
 int ftk_plan_create(ftk_plan** out, int n, int K, int Q, double W, double eps, int precision);
+
+/* ftk_plan_create with a k-side weight in the operator SVD (Section 4.5,
+ * the remark on alternative weight functions): the SVD of each J_l(delta k)
+ * is taken with the measure p(k) k dk on [0, Kmax] in place of k dk,
+ *   p(k) = c sum_{j < nterms} alpha[j] exp(-beta[j] (k / Kmax)^2),
+ * alpha[j] >= 0 (not all 0), beta[j] >= 0, finite, host arrays copied by
+ * the call, c set so that p has mean 1 over the disk of radius Kmax.  Every
+ * Sigma > eps is kept as before, now in the p-weighted norm: with p shaped
+ * like the power spectrum of the templates, fewer terms reach a given
+ * accuracy of the inner products (the remark's purpose).  nterms = 0 is
+ * ftk_plan_create.  Errors: as ftk_plan_create; FTK_EINVAL for bad terms. */
+int ftk_plan_create_weighted(ftk_plan** out, int n, int K, int Q, double W, double eps, int precision,
+                             const double* alpha, const double* beta, int nterms);
 
 /* Release the plan and all device memory it holds.  NULL is allowed.  The
  * caller must make sure no work that uses the plan is still in flight. */
@@ -199,10 +213,11 @@ int ftk_align(ftk_plan* plan, const float* images, int nA, const float* template
  * again by `fine` (for example an FTK_BF16X3 plan), and those k poses
  * replace the coarse ones in best.  Each pose is the argmax over shifts and
  * rotations of the inner products of eq. fbk3, as in ftk_align_coeffs.  The
- * plans must come from the same ftk_plan_create arguments except the
- * precision (FTK_EINVAL if n, K, Q, W, eps or H differ), and the caller sets
- * the same shifts on both (only their count N is checked); ftk_transform
- * gives the same coefficients under either plan.
+ * plans must share n, K, Q and W (FTK_EINVAL otherwise); their precision,
+ * eps and k-side weight (hence H) may differ, so the coarse pass may use a
+ * cheaper factorisation than the fine one.  The caller sets the same shifts
+ * on both (only their count N is checked); ftk_transform gives the same
+ * coefficients under either plan.
  *   best      : device ftk_pose [nA][nB], every pair
  *   best_t    : device int32 [nA]: per image, the template with the largest
  *               refined value (ties: lower template number), or NULL
@@ -227,6 +242,11 @@ int ftk_align_refined(ftk_plan* coarse, ftk_plan* fine, const void* img_coeffs, 
 int ftk_plan_tables(int n, int K, double W, double eps, const double* shifts_px, int N,
                     int* H_out, int32_t* ell, double* sigma, double* G, double* k, double* w,
                     double* Y, double* sigma_next);
+/* ftk_plan_tables with the k-side weight of ftk_plan_create_weighted
+ * (alpha, beta, nterms as there; nterms = 0: ftk_plan_tables). */
+int ftk_plan_tables_weighted(int n, int K, double W, double eps, const double* alpha, const double* beta,
+                             int nterms, const double* shifts_px, int N, int* H_out, int32_t* ell, double* sigma,
+                             double* G, double* k, double* w, double* Y, double* sigma_next);
 
 /* Stage timing.  While enabled, the plan records a pair of HIP events on the
  * caller's stream around every kernel launch it makes, tagged with a stage:

@@ -78,7 +78,7 @@ class ModalSVD:
     xn: np.ndarray
     xw: np.ndarray
     yn: np.ndarray
-    yw: np.ndarray
+    yw: np.ndarray  # y-side quadrature weights times the weight function p(y_j)
 
     def sigma_v(self, eta: int, y) -> np.ndarray:
         """Sigma_eta * v_eta(y) at any y in [0,1] (Nystrom, no division)."""
@@ -87,7 +87,8 @@ class ModalSVD:
         return J @ (np.sqrt(self.xw) * self.Umat[:, eta])
 
     def u(self, eta: int, x) -> np.ndarray:
-        """u_eta(x) at any x in [0, X] (Nystrom through the y side)."""
+        """u_eta(x) at any x in [0, X] (Nystrom through the y side; the y-side
+        measure p(y) y dy is in yw)."""
         x = np.asarray(x, dtype=np.float64)
         J = jv(self.ell, np.multiply.outer(x, self.yn))  # (..., P)
         return (J @ (np.sqrt(self.yw) * self.Vt[eta, :])) / self.sigma[eta]
@@ -98,17 +99,48 @@ def svd_nodes(X: float) -> int:
     return int(math.ceil(2.0 * X)) + 48
 
 
-def modal_svd(ell: int, X: float, P: int | None = None) -> ModalSVD:
+def weight_function(alpha, beta=None):
+    """The k-side weight p(y), y = k / Kmax in [0, 1], of the remark on
+    alternative weight functions (Section 4.5): a sum of Gaussians
+    p(y) = c sum_j alpha_j exp(-beta_j y^2) (alpha_j >= 0 and not all zero,
+    beta_j >= 0), with c such that its mean over the unit disk is 1,
+    int_0^1 p(y) y dy = 1/2 (each term integrates to
+    alpha (1 - exp(-beta)) / (2 beta), alpha / 2 at beta = 0).  alpha None:
+    p = 1, the paper's weight (the L2 norm over the disk).  With this scaling
+    the sum of every Sigma^2 stays pi^2 W^2 for any weight."""
+    if alpha is None:
+        return None
+    a = np.asarray(alpha, dtype=np.float64).ravel()
+    b = np.asarray(beta, dtype=np.float64).ravel()
+    if a.size < 1 or a.size != b.size or not (np.all(np.isfinite(a)) and np.all(np.isfinite(b))):
+        raise ValueError("weight: alpha and beta of equal length, finite")
+    if np.any(a < 0) or np.any(b < 0) or not np.any(a > 0):
+        raise ValueError("weight: alpha >= 0 (not all 0), beta >= 0")
+    total = float(sum(aj * ((1.0 - math.exp(-bj)) / (2.0 * bj) if bj > 0 else 0.5) for aj, bj in zip(a, b)))
+    c = 0.5 / total
+    def p(y):
+        y = np.asarray(y, dtype=np.float64)
+        t = a[:, None] * np.exp(-np.multiply.outer(b, y.ravel() ** 2))
+        return c * np.sum(t, axis=0).reshape(y.shape)
+
+    return p
+
+
+def modal_svd(ell: int, X: float, P: int | None = None, weight=None) -> ModalSVD:
+    """weight: None (p = 1) or a function p(y) from weight_function.  The SVD
+    is that of J_l(x y) on x in [0, X] (x dx), y in [0, 1] (p(y) y dy)."""
     P = svd_nodes(X) if P is None else P
     xn, xw = radial_quadrature(P, X)
     yn, yw = radial_quadrature(P, 1.0)
+    if weight is not None:
+        yw = yw * weight(yn)
     K = np.sqrt(xw)[:, None] * jv(ell, np.multiply.outer(xn, yn)) * np.sqrt(yw)[None, :]
     U, s, Vt = np.linalg.svd(K)
     return ModalSVD(ell, X, s, U, Vt, xn, xw, yn, yw)
 
 
-def singular_values(ell: int, X: float, P: int | None = None) -> np.ndarray:
-    return modal_svd(ell, X, P).sigma
+def singular_values(ell: int, X: float, P: int | None = None, weight=None) -> np.ndarray:
+    return modal_svd(ell, X, P, weight).sigma
 
 
 @dataclasses.dataclass
@@ -129,6 +161,7 @@ class Plan:
     g: np.ndarray  # (H, M) Sigma_zeta v_zeta(k_m / kmax)
     svds: dict  # ell -> ModalSVD
     sigma_next: float  # largest discarded singular value
+    weight: object = None  # the k-side weight function p(y), or None (p = 1)
     shifts: np.ndarray | None = None  # (N, 2) px
     Y: np.ndarray | None = None  # (N, H) complex
 
@@ -137,11 +170,12 @@ class Plan:
         return int(self.ell.size)
 
 
-def truncation(R: float, eps: float, lmax: int | None = None, P: int | None = None):
+def truncation(R: float, eps: float, lmax: int | None = None, P: int | None = None, weight=None):
     """(l, eta, sigma) of every kept term, the svds, and the first dropped value.
 
     Keeps Sigma_eta(l) > eps for l = 0, +-1, +-2, ... until Sigma_1(l) <= eps
-    (or |l| > lmax when a cap is given).
+    (or |l| > lmax when a cap is given).  weight: the k-side weight function
+    (weight_function), or None.
     """
     X = math.pi * R
     svds, keep = {}, []
@@ -150,29 +184,32 @@ def truncation(R: float, eps: float, lmax: int | None = None, P: int | None = No
     while True:
         if lmax is not None and ell > lmax:
             break
-        sv = modal_svd(ell, X, P)
+        sv = modal_svd(ell, X, P, weight)
         if sv.sigma[0] <= eps:
             dropped = max(dropped, sv.sigma[0])
             break
         signs = [ell] if ell == 0 else [ell, -ell]
         for l in signs:
-            s = sv if l == ell else modal_svd(l, X, P)
+            s = sv if l == ell else modal_svd(l, X, P, weight)
             svds[l] = s
             h = int(np.sum(s.sigma > eps))
             keep += [(l, e, s.sigma[e]) for e in range(h)]
             dropped = max(dropped, s.sigma[h] if h < s.sigma.size else 0.0)
         ell += 1
     if lmax is not None:
-        sv = modal_svd(lmax + 1, X, P)
+        sv = modal_svd(lmax + 1, X, P, weight)
         dropped = max(dropped, sv.sigma[0])
     return keep, svds, dropped
 
 
 def make_plan(n: int, M: int, Qa: int, R: float, eps: float,
-              lmax: int | None = None, P: int | None = None) -> Plan:
+              lmax: int | None = None, P: int | None = None, weight=None) -> Plan:
+    """weight: None (the paper's weight), or (alpha, beta) of the k-side
+    weight sum_j alpha_j exp(-beta_j (k / Kmax)^2) (see weight_function)."""
     kmax = 0.5 * math.pi * n
     k, w = radial_quadrature(M, kmax)
-    keep, svds, dropped = truncation(R, eps, lmax, P)
+    weight = None if weight is None else weight_function(*weight)
+    keep, svds, dropped = truncation(R, eps, lmax, P, weight)
     keep.sort(key=lambda t: (t[0], t[1]))
     ell = np.array([t[0] for t in keep], dtype=np.int64)
     eta = np.array([t[1] for t in keep], dtype=np.int64)
@@ -181,7 +218,7 @@ def make_plan(n: int, M: int, Qa: int, R: float, eps: float,
     g = np.zeros((ell.size, M))
     for z, (l, e) in enumerate(zip(ell, eta)):
         g[z] = svds[int(l)].sigma_v(int(e), y)
-    return Plan(n, M, Qa, R, eps, kmax, k, w, ell, eta, sig, g, svds, dropped)
+    return Plan(n, M, Qa, R, eps, kmax, k, w, ell, eta, sig, g, svds, dropped, weight)
 
 
 def set_shifts(plan: Plan, shifts_px: np.ndarray) -> Plan:

@@ -144,10 +144,10 @@ double bf16_value(uint16_t h) {
   return f;
 }
 
-int build_tables(int n, int M, double W, double eps, HostTables& t) {
+int build_tables(int n, int M, double W, double eps, HostTables& t, const ftkplan::Weight& weight) {
   const double kmax = 0.5 * kPi * n;
   ftkplan::radial_rule(M, kmax, t.k, t.w);
-  t.tr = ftkplan::truncate(kPi * W, eps);
+  t.tr = ftkplan::truncate(kPi * W, eps, weight);
   t.L = t.tr.L;
   t.sigma_next = t.tr.sigma_next;
   t.H = static_cast<int>(t.tr.terms.size());
@@ -440,13 +440,15 @@ const char* ftk_strerror(int status) {
 
 const char* ftk_last_error_message(void) { return g_last_error.c_str(); }
 
-int ftk_plan_tables(int n, int K, double W, double eps, const double* shifts_px, int N, int* H_out, int32_t* ell,
-                    double* sigma, double* G, double* k, double* w, double* Y, double* sigma_next) {
-  if (n < 4 || K < 1 || K > 512 || !(W > 0) || !(eps > 0) || !(eps < 1) || N < 0 || (N > 0 && !shifts_px))
+int ftk_plan_tables_weighted(int n, int K, double W, double eps, const double* alpha, const double* beta,
+                             int nterms, const double* shifts_px, int N, int* H_out, int32_t* ell, double* sigma,
+                             double* G, double* k, double* w, double* Y, double* sigma_next) {
+  if (n < 4 || K < 1 || K > 512 || !(W > 0) || !(eps > 0) || !(eps < 1) || N < 0 || (N > 0 && !shifts_px) ||
+      nterms < 0 || nterms > 4096)
     return fail(FTK_EINVAL, "ftk_plan_tables: invalid argument");
   try {
     HostTables t;
-    build_tables(n, K, W, eps, t);
+    build_tables(n, K, W, eps, t, ftkplan::make_weight(alpha, beta, nterms));
     if (H_out) *H_out = t.H;
     if (sigma_next) *sigma_next = t.sigma_next;
     for (int z = 0; z < t.H; ++z) {
@@ -470,11 +472,24 @@ int ftk_plan_tables(int n, int K, double W, double eps, const double* shifts_px,
   return FTK_OK;
 }
 
+int ftk_plan_tables(int n, int K, double W, double eps, const double* shifts_px, int N, int* H_out, int32_t* ell,
+                    double* sigma, double* G, double* k, double* w, double* Y, double* sigma_next) {
+  return ftk_plan_tables_weighted(n, K, W, eps, nullptr, nullptr, 0, shifts_px, N, H_out, ell, sigma, G, k, w, Y,
+                                  sigma_next);
+}
+
 int ftk_plan_create(ftk_plan** out, int n, int K, int Q, double W, double eps, int precision) {
+  return ftk_plan_create_weighted(out, n, K, Q, W, eps, precision, nullptr, nullptr, 0);
+}
+
+int ftk_plan_create_weighted(ftk_plan** out, int n, int K, int Q, double W, double eps, int precision,
+                             const double* alpha, const double* beta, int nterms) {
   if (!out) return fail(FTK_EINVAL, "ftk_plan_create: out is NULL");
   *out = nullptr;
   int rc = check_plan_args(n, K, Q, W, eps, precision);
   if (rc != FTK_OK) return rc;
+  if (nterms < 0 || nterms > 4096 || (nterms > 0 && (!alpha || !beta)))
+    return fail(FTK_EINVAL, "ftk_plan_create_weighted: nterms must be in [0, 4096] with alpha and beta given");
   ftk_plan* p = nullptr;
   try {
     p = new ftk_plan();
@@ -486,7 +501,8 @@ int ftk_plan_create(ftk_plan** out, int n, int K, int Q, double W, double eps, i
     p->precision = precision;
     p->kmax = 0.5 * kPi * n;
     p->tune = default_tuning(precision);
-    build_tables(n, K, W, eps, p->t);
+    p->weighted = nterms > 0;
+    build_tables(n, K, W, eps, p->t, ftkplan::make_weight(alpha, beta, nterms));
     p->H_pad = round_up(std::max(p->t.H, 1), 64);
     p->sk = ftkplan::spread_kernel(n, kNufftWidth);
   } catch (const std::bad_alloc&) {
@@ -530,6 +546,7 @@ int ftk_plan_info(const ftk_plan* p, ftk_plan_info_t* o) {
   o->kmax = p->kmax;
   o->coeff_bytes_per_image = static_cast<size_t>(8) * p->M * p->Qa;
   o->device_bytes = p->device_bytes();
+  o->weighted = p->weighted ? 1 : 0;
   return FTK_OK;
 }
 

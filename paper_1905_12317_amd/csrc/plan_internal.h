@@ -91,6 +91,7 @@ struct Needs {
 struct ftk_plan {
   ftkint::StageTimer timer;
   int n = 0, M = 0, Qa = 0, precision = 0;
+  bool weighted = false;  // operator SVD with a k-side weight (Section 4.5 remark)
   double W = 0, eps = 0, kmax = 0;
   ftkint::HostTables t;
   int H_pad = 0, N = 0, N_pad = 0;

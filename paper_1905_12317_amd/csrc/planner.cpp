@@ -246,7 +246,34 @@ double ModalSVD::u(int eta, double x) const {
   return s / sigma[eta];
 }
 
-ModalSVD modal_svd(int ell, double X) {
+double Weight::operator()(double y) const {
+  if (alpha.empty()) return 1.0;
+  double s = 0.0;
+  for (size_t j = 0; j < alpha.size(); ++j) s += alpha[j] * std::exp(-beta[j] * y * y);
+  return c * s;
+}
+
+Weight make_weight(const double* alpha, const double* beta, int nterms) {
+  Weight w;
+  if (nterms <= 0) return w;
+  if (!alpha || !beta) throw std::invalid_argument("weight: NULL terms");
+  double total = 0.0, amax = 0.0;
+  for (int j = 0; j < nterms; ++j) {
+    const double a = alpha[j], b = beta[j];
+    if (!std::isfinite(a) || !std::isfinite(b) || a < 0.0 || b < 0.0)
+      throw std::invalid_argument("weight: alpha and beta must be finite and >= 0");
+    // int_0^1 a exp(-b y^2) y dy
+    total += b > 0.0 ? a * (-std::expm1(-b)) / (2.0 * b) : 0.5 * a;
+    amax = std::max(amax, a);
+    w.alpha.push_back(a);
+    w.beta.push_back(b);
+  }
+  if (!(amax > 0.0) || !(total > 0.0)) throw std::invalid_argument("weight: every alpha is 0");
+  w.c = 0.5 / total;
+  return w;
+}
+
+ModalSVD modal_svd(int ell, double X, const Weight& weight) {
   if (ell < 0) throw std::invalid_argument("modal_svd: ell >= 0 expected");
   ModalSVD r;
   r.ell = ell;
@@ -255,6 +282,8 @@ ModalSVD modal_svd(int ell, double X) {
   const int P = r.P;
   radial_rule(P, X, r.xn, r.xw);
   radial_rule(P, 1.0, r.yn, r.yw);
+  if (!weight.empty())
+    for (int j = 0; j < P; ++j) r.yw[j] *= weight(r.yn[j]);
   std::vector<double> K(static_cast<size_t>(P) * P);
   std::vector<double> J(ell + 1);
   for (int i = 0; i < P; ++i)
@@ -266,11 +295,11 @@ ModalSVD modal_svd(int ell, double X) {
   return r;
 }
 
-Truncation truncate(double X, double eps) {
+Truncation truncate(double X, double eps, const Weight& weight) {
   Truncation tr;
   std::vector<int> keep_count;
   for (int ell = 0; ell < 4096; ++ell) {
-    ModalSVD s = modal_svd(ell, X);
+    ModalSVD s = modal_svd(ell, X, weight);
     if (s.sigma[0] <= eps) {
       tr.sigma_next = std::max(tr.sigma_next, s.sigma[0]);
       break;

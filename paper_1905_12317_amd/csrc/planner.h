@@ -21,7 +21,20 @@ void bessel_orders(int lmax, double z, double* out);
 // J_l(z) = (1/2 pi) int exp(i (z sin a - l a)) da; used as a self-check.
 double bessel_integral(int l, double z);
 
-// Modal SVD of J_l(x y) on x in [0, X] (x dx) and y in [0, 1] (y dy).
+// k-side weight of the operator SVD (Section 4.5, the remark on alternative
+// weight functions): p(y) = c sum_j alpha_j exp(-beta_j y^2), y = k / Kmax,
+// alpha_j >= 0 (not all 0), beta_j >= 0, with c such that its mean over the
+// unit disk is 1 (int_0^1 p(y) y dy = 1/2).  Empty: p = 1, the paper's weight.
+struct Weight {
+  std::vector<double> alpha, beta;
+  double c = 1.0;
+  bool empty() const { return alpha.empty(); }
+  double operator()(double y) const;
+};
+// Checks the terms and sets c; throws std::invalid_argument on bad terms.
+Weight make_weight(const double* alpha, const double* beta, int nterms);
+
+// Modal SVD of J_l(x y) on x in [0, X] (x dx) and y in [0, 1] (p(y) y dy).
 struct ModalSVD {
   int ell = 0;
   int P = 0;
@@ -29,14 +42,14 @@ struct ModalSVD {
   std::vector<double> sigma;  // P, descending
   std::vector<double> U;      // P x P, column eta = left vector (x side), U[i*P + eta]
   std::vector<double> V;      // P x P, column eta = right vector (y side), V[j*P + eta]
-  std::vector<double> xn, xw, yn, yw;
+  std::vector<double> xn, xw, yn, yw;  // yw: quadrature weights times p(y_j)
   // Sigma_eta v_eta(y), Nystrom through the x side (no division by Sigma).
   double sigma_v(int eta, double y) const;
   // u_eta(x), Nystrom through the y side.
   double u(int eta, double x) const;
 };
 
-ModalSVD modal_svd(int ell, double X);
+ModalSVD modal_svd(int ell, double X, const Weight& weight = Weight());
 
 struct Term {
   int ell;
@@ -52,7 +65,7 @@ struct Truncation {
 };
 
 // Keep every Sigma_eta(l) > eps; scan |l| = 0, 1, ... until Sigma_1(l) <= eps.
-Truncation truncate(double X, double eps);
+Truncation truncate(double X, double eps, const Weight& weight = Weight());
 
 // One-sided Jacobi SVD of a dense m x n (m >= n) row-major matrix A.
 // On exit: sigma (n, descending), U (m x n, row-major), V (n x n, row-major).

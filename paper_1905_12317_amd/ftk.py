@@ -36,7 +36,8 @@ class PlanInfo(ctypes.Structure):
                 ("nufft_width", ctypes.c_int), ("nufft_grid", ctypes.c_int),
                 ("shift_radius_px", ctypes.c_double), ("eps", ctypes.c_double),
                 ("sigma_next", ctypes.c_double), ("kmax", ctypes.c_double),
-                ("coeff_bytes_per_image", ctypes.c_size_t), ("device_bytes", ctypes.c_size_t)]
+                ("coeff_bytes_per_image", ctypes.c_size_t), ("device_bytes", ctypes.c_size_t),
+                ("weighted", ctypes.c_int)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -72,7 +73,8 @@ POSE_DTYPE = np.dtype([("value", np.float32), ("shift", np.int32), ("rot", np.in
 
 #: every symbol include/ftk.h declares
 EXPORTS = ["ftk_plan_create", "ftk_plan_destroy", "ftk_plan_info", "ftk_set_shifts", "ftk_transform",
-           "ftk_align_coeffs", "ftk_align_coeffs_noalloc", "ftk_align", "ftk_plan_tables", "ftk_plan_profile", "ftk_plan_stage_times",
+           "ftk_align_coeffs", "ftk_align_coeffs_noalloc", "ftk_align", "ftk_plan_tables", "ftk_plan_create_weighted",
+           "ftk_plan_tables_weighted", "ftk_plan_profile", "ftk_plan_stage_times",
            "ftk_plan_set_tuning", "ftk_plan_get_tuning", "ftk_batch_create", "ftk_batch_run", "ftk_batch_info",
            "ftk_batch_destroy", "ftk_strerror", "ftk_last_error_message",
            # include/ftk_mlp.h
@@ -109,6 +111,9 @@ def lib() -> ctypes.CDLL:
     L = ctypes.CDLL(LIB_PATH)
     vp, i, d = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
     L.ftk_plan_create.argtypes = [ctypes.POINTER(vp), i, i, i, d, d, i]
+    L.ftk_plan_create_weighted.argtypes = [ctypes.POINTER(vp), i, i, i, d, d, i, vp, vp, i]
+    L.ftk_plan_tables_weighted.argtypes = [i, i, d, d, vp, vp, i, vp, i, ctypes.POINTER(i), vp, vp, vp, vp, vp, vp,
+                                           ctypes.POINTER(d)]
     L.ftk_plan_destroy.argtypes = [vp]
     L.ftk_plan_destroy.restype = None
     L.ftk_plan_info.argtypes = [vp, ctypes.POINTER(PlanInfo)]
@@ -185,13 +190,26 @@ def _require_cuda(t, dtype, name):
         raise ValueError(f"{name} must be contiguous")
 
 
-def ftk_plan_tables(n: int, K: int, W: float, eps: float, shifts_px=None):
-    """Host-only FP64 tables of the planner (no device work)."""
+def _weight_arrays(weight):
+    if weight is None:
+        return None, None, 0
+    a = np.ascontiguousarray(weight[0], dtype=np.float64).ravel()
+    b = np.ascontiguousarray(weight[1], dtype=np.float64).ravel()
+    if a.size != b.size:
+        raise ValueError("weight: alpha and beta differ in length")
+    return a, b, a.size
+
+
+def ftk_plan_tables(n: int, K: int, W: float, eps: float, shifts_px=None, weight=None):
+    """Host-only FP64 tables of the planner (no device work); weight =
+    (alpha, beta) of the k-side weight, or None."""
     L = lib()
     H = ctypes.c_int(0)
     sn = ctypes.c_double(0)
-    _check(L.ftk_plan_tables(n, K, W, eps, None, 0, ctypes.byref(H), None, None, None, None, None, None,
-                             ctypes.byref(sn)), "ftk_plan_tables")
+    a, b, nt = _weight_arrays(weight)
+    ap, bp = (a.ctypes.data, b.ctypes.data) if nt else (None, None)
+    _check(L.ftk_plan_tables_weighted(n, K, W, eps, ap, bp, nt, None, 0, ctypes.byref(H), None, None, None, None,
+                                      None, None, ctypes.byref(sn)), "ftk_plan_tables")
     H = H.value
     ell = np.zeros(H, np.int32)
     sig = np.zeros(H)
@@ -206,20 +224,25 @@ def ftk_plan_tables(n: int, K: int, W: float, eps: float, shifts_px=None):
         N = sh.shape[0]
         Y = np.zeros((N, H), np.complex128)
     Hc = ctypes.c_int(0)
-    _check(L.ftk_plan_tables(n, K, W, eps, sh.ctypes.data if sh is not None else None, N, ctypes.byref(Hc),
-                             ell.ctypes.data, sig.ctypes.data, G.ctypes.data, k.ctypes.data, w.ctypes.data,
-                             Y.ctypes.data if Y is not None else None, ctypes.byref(sn)), "ftk_plan_tables")
+    _check(L.ftk_plan_tables_weighted(n, K, W, eps, ap, bp, nt, sh.ctypes.data if sh is not None else None, N,
+                                      ctypes.byref(Hc), ell.ctypes.data, sig.ctypes.data, G.ctypes.data, k.ctypes.data,
+                                      w.ctypes.data, Y.ctypes.data if Y is not None else None, ctypes.byref(sn)),
+           "ftk_plan_tables")
     return dict(H=H, ell=ell, sigma=sig, G=G, k=k, w=w, Y=Y, sigma_next=sn.value)
 
 
 class Plan:
     """Owns an ftk_plan (ftk_plan_create / ftk_plan_destroy)."""
 
-    def __init__(self, n: int, K: int, Q: int, W: float, eps: float, precision="fp32"):
+    def __init__(self, n: int, K: int, Q: int, W: float, eps: float, precision="fp32", weight=None):
+        """weight: None, or (alpha, beta) of the k-side weight of the operator
+        SVD (ftk_plan_create_weighted)."""
         L = lib()
         prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
         h = ctypes.c_void_p()
-        _check(L.ftk_plan_create(ctypes.byref(h), n, K, Q, W, eps, prec), "ftk_plan_create")
+        a, b, nt = _weight_arrays(weight)
+        _check(L.ftk_plan_create_weighted(ctypes.byref(h), n, K, Q, W, eps, prec, a.ctypes.data if nt else None,
+                                          b.ctypes.data if nt else None, nt), "ftk_plan_create")
         self._h = h
         self.n, self.M, self.Qa = n, K, Q
         self.N = 0

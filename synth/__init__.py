@@ -231,3 +231,20 @@ def gaussian_noise(seed: int, sigmas, n: int, device="cuda"):
     sig = torch.as_tensor(np.asarray(sigmas, dtype=np.float32), device=device)
     z = torch.randn((sig.shape[0], n, n), generator=g, device=device, dtype=torch.float32)
     return z * sig[:, None, None]
+
+
+def blob_power_spectrum(nterms: int = 16, sigma_lo_px: float = 1.0, sigma_hi_px: float = 3.0):
+    """Expected radial power spectrum of the blob templates as a sum of
+    Gaussians in y = k / Kmax (Kmax = pi n / 2): returns (alpha, beta) with
+    P(y) = sum_j alpha_j exp(-beta_j y^2).
+
+    A Gaussian blob of width s pixels (s dx in the image's units, dx = 2/n)
+    has power exp(-k^2 s^2 dx^2) = exp(-pi^2 y^2 s^2) at radius k; blob
+    centres are independent, so the cross terms average out and the power is
+    the mean of that over s ~ U[sigma_lo, sigma_hi], here by the
+    nterms-point Gauss-Legendre rule in s.  It does not depend on n.  A
+    description of the input distribution, passed to the planner as a
+    k-side weight."""
+    x, wx = np.polynomial.legendre.leggauss(nterms)
+    s = sigma_lo_px + (x + 1.0) * 0.5 * (sigma_hi_px - sigma_lo_px)
+    return 0.5 * wx, (math.pi ** 2) * s ** 2

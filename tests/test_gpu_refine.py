@@ -84,8 +84,46 @@ def test_refined_rejects_mismatched_plans(ftk):
         P.set_shifts(synth.shift_lattice(2.0))
     a = torch.zeros((2, 64, 16), dtype=torch.complex64, device="cuda")
     with pytest.raises(ftk.FTKError):
-        ftk.align_refined(A, B, a, a, 1)
+        ftk.align_refined(A, B, a, a, 1)  # Q differs
+    D = ftk.Plan(32, 16, 64, 2.0, 1e-3, precision="bf16x3")
+    D.set_shifts(synth.shift_lattice(1.5))
+    with pytest.raises(ftk.FTKError):
+        ftk.align_refined(A, D, a, a, 1)  # the shift lists differ in length
     C = ftk.Plan(32, 16, 64, 2.0, 1e-3, precision="bf16x3")
     C.set_shifts(synth.shift_lattice(2.0))
     with pytest.raises(ftk.FTKError):
         ftk.align_refined(A, C, a, a, 3)  # k > nB
+
+
+def test_refined_weighted_coarse_pass(ftk):
+    """Coarse pass on a plan with a power-spectrum weighted SVD and a looser
+    eps (fewer terms), refinement on the paper's weight: the plans differ in
+    H, which the two-pass call allows; the refined pairs still equal the fine
+    plan's own poses bitwise and the others the coarse plan's."""
+    n, M, Qa, R, k = 64, 32, 128, 2.0, 4
+    s = synth.make_alignment_set(23, n, 40, 4, 20, R, 0.05)
+    shifts = synth.shift_lattice(R)
+    Pc = ftk.Plan(n, M, Qa, R, 5e-3, precision="fp16", weight=synth.blob_power_spectrum())
+    Pf = ftk.Plan(n, M, Qa, R, 1e-3, precision="bf16x3")
+    for P in (Pc, Pf):
+        P.set_shifts(shifts)
+    assert Pc.info()["H"] < Pf.info()["H"]
+    a = Pf.transform(torch.as_tensor(s.images, dtype=torch.float32, device="cuda"))
+    b = Pf.transform(torch.as_tensor(s.templates, dtype=torch.float32, device="cuda"))
+    _, coarse = Pc.align_coeffs(a, b)
+    _, fine = Pf.align_coeffs(a, b)
+    best, bt, bp = ftk.align_refined(Pc, Pf, a, b, k)
+    torch.cuda.synchronize()
+    C, Fn, B = (ftk.poses_numpy(x) for x in (coarse, fine, best))
+    bt = bt.cpu().numpy()
+    L = _topk_host(C["value"], k)
+    for i in range(4):
+        listed = set(L[i].tolist())
+        for j in range(40):
+            ref = Fn[i, j] if j in listed else C[i, j]
+            assert (B[i, j]["value"], B[i, j]["shift"], B[i, j]["rot"]) == \
+                (ref["value"], ref["shift"], ref["rot"]), (i, j, j in listed)
+        assert bt[i] == min(L[i], key=lambda j: (-float(Fn[i, j]["value"]), j))
+    _say(f"[refine weighted] H coarse {Pc.info()['H']} fine {Pf.info()['H']}: "
+         f"per-image best equal to the full split search on "
+         f"{sum(int(bt[i] == int(np.argmax(Fn[i]['value']))) for i in range(4))}/4 images")

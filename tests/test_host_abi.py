@@ -98,3 +98,24 @@ def test_binding_has_no_fallback(monkeypatch):
     monkeypatch.setattr(ftk, "LIB_PATH", "/nonexistent/libftk.so")
     with pytest.raises(ImportError):
         ftk.lib()
+
+
+@pytest.mark.parametrize("n,M,R,eps", [(32, 16, 2.0, 1e-3), (128, 64, 4.0, 1e-3), (64, 32, 4.0, 1e-5)])
+def test_weighted_planner_matches_oracle(n, M, R, eps):
+    """The k-side weighted operator SVD (Section 4.5 remark): the planner's
+    tables equal the oracle's, and the weight lowers H."""
+    wt = synth.blob_power_spectrum()
+    sh = synth.shift_lattice(R)
+    T = ftk.ftk_plan_tables(n, M, R, eps, sh, weight=wt)
+    P = O.set_shifts(O.make_plan(n, M, 2 * n, R, eps, weight=wt), sh)
+    assert T["H"] == P.H < ftk.ftk_plan_tables(n, M, R, eps)["H"]
+    assert sorted(T["ell"].tolist()) == sorted(P.ell.tolist())
+    assert np.max(np.abs(np.sort(T["sigma"]) - np.sort(P.sigma))) < 1e-11 * P.sigma.max()
+    assert abs(T["sigma_next"] - P.sigma_next) < 1e-11 * P.sigma.max()
+    for l in set(P.ell.tolist()):
+        a = T["Y"][:, T["ell"] == l] @ T["G"][T["ell"] == l]
+        b = P.Y[:, P.ell == l] @ P.g[P.ell == l]
+        assert np.max(np.abs(a - b)) < 1e-10 * max(1.0, np.max(np.abs(b)))
+    # bad terms are refused
+    with pytest.raises(ftk.FTKError):
+        ftk.ftk_plan_tables(n, M, R, eps, weight=([1.0, -1.0], [0.0, 1.0]))
