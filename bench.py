@@ -95,13 +95,16 @@ WEIGHTED_EPS = 5e-3  # eps of the weighted-SVD plan: the paper plan's accuracy a
 def run_form(form, inputs, w, steps, warmup, shifts, eps=None, weight=None):
     """One form over the workload.  "fp16+bf16x3" is the two-pass form: the
     FP16 form over every pair, then the split form on each image's REFINE_K
-    best FP16 templates (ftk_align_refined).  eps / weight: a plan other than
+    best FP16 templates (ftk_align_refined).  "bft": brute-force
+    translations (ftk_bft_align, FP32), the paper's comparison method.  eps / weight: a plan other than
     the workload's (the k-side weighted operator SVD)."""
     import torch
     from paper_1905_12317_amd import ftk
     dev = torch.device("cuda:0")
     two = form == "fp16+bf16x3"
-    P = ftk.Plan(w["n"], w["M"], w["Qa"], w["R"], eps or w["eps"], precision="fp16" if two else form, weight=weight)
+    bft = form == "bft"
+    prec = "fp16" if two else ("fp32" if bft else form)
+    P = ftk.Plan(w["n"], w["M"], w["Qa"], w["R"], eps or w["eps"], precision=prec, weight=weight)
     P.set_shifts(shifts)
     Pf = None
     if two:
@@ -125,6 +128,8 @@ def run_form(form, inputs, w, steps, warmup, shifts, eps=None, weight=None):
             P.transform(templates, cb, stream=stream)
             _, per_image["t"], per_image["pose"] = ftk.align_refined(P, Pf, ca, cb, REFINE_K, best=best,
                                                                       stream=stream)
+        elif bft:
+            P.bft_align(images, templates, best=best, stream=stream)
         else:
             P.align(images, templates, best=best, stream=stream)
 
@@ -401,6 +406,7 @@ def main():
     ap.add_argument("--lanes", type=int, default=4, help="ragged workload: concurrent lanes of the batch (1-4)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-weighted", action="store_true", help="skip the weighted-SVD measurement")
+    ap.add_argument("--no-bft", action="store_true", help="skip the brute-force-translation measurement")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="only run a plain device-to-device copy of this many MiB (3 times) and exit; "
                          "used to scale the FETCH_SIZE / WRITE_SIZE counters")
@@ -531,6 +537,21 @@ def main():
                 "speedup_vs_paper_weight_two_pass": r2["pairs_per_s"] / results["fp16+bf16x3"]["pairs_per_s"],
                 "best_pose_agreement_vs_fp32": agreement(r2["img_best"], results["fp32"]["img_best"])
                 if "fp32" in results else None}
+    if not args.no_bft:
+        # brute-force translations (Section 6.2) on the same workload, grids
+        # and shifts: the paper's FTK-versus-BFT axis on this GPU
+        rb = run_form("bft", inputs, w, args.steps, args.warmup, shifts)
+        log(f"[bft] {rb['ms_per_step']:.2f} ms/step, {rb['pairs_per_s']:.4g} pairs/s, stages {rb['stages']}")
+        qh = Qa // 2 + 1
+        out["config"]["bft"] = {
+            "pairs_per_s": rb["pairs_per_s"], "ms_per_step": rb["ms_per_step"],
+            "stage_ms_per_step": {k: v[0] / args.steps for k, v in rb["stages"].items()},
+            "contraction_gflop_per_pair": 8.0 * N * M * qh / 1e9,
+            "ftk_contraction_gflop_per_pair": (s1 + s3) / 1e9,
+            "ftk_speedup_over_bft": {k: v["pairs_per_s"] / rb["pairs_per_s"] for k, v in results.items()},
+            "best_pose_agreement_vs_ftk_fp32": agreement(rb["img_best"], results["fp32"]["img_best"])
+            if "fp32" in results else None,
+            "recall_true_template": recall(rb["img_best"], inputs)}
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(inputs, w, shifts)
     print(json.dumps(out), flush=True)

@@ -227,6 +227,27 @@ int ftk_align(ftk_plan* plan, const float* images, int nA, const float* template
 int ftk_align_refined(ftk_plan* coarse, ftk_plan* fine, const void* img_coeffs, int nA, const void* tmpl_coeffs,
                       int nB, int k, ftk_pose* best, int32_t* best_t, ftk_pose* best_pose, void* stream);
 
+/* Brute-force translations (BFT, Section 6.2 of the paper), the method the
+ * paper compares FTK with, on the plan's grids and shifts: for every image
+ * and shift, the translated Fourier-Bessel coefficients T_delta a(k_m; q)
+ * (the ring samples times the translation phase exp(-i k . delta) of eq. Fdk,
+ * then the ring DFT of eq. aqkcalc); for every pair and shift, eq. fbk2
+ * with l_max = 0, Xhat(delta, q) = 2 pi sum_m w_m T_delta a conj b; then
+ * the rotation FFT of eq. 1dfft and the argmax.  Its X equals the direct
+ * inner product on the polar quadrature (no SVD, no truncation) up to FP32
+ * rounding.  FP32 throughout, whatever the plan's precision form; the SVD
+ * tables are not used.  Arguments, layouts, ownership and results as
+ * ftk_align (pixels in, X [nA][nB][N][Q] optional, best [nA][nB]).  The
+ * plan's workspace grows by the translated coefficients of one chunk of
+ * images ((Q/2 + 1) N' K complex, N' = N rounded up to 32 or 64, per image)
+ * and an Xhat staging of Q/2 x 2 N' floats per pair; images are chunked to
+ * the staging size of ftk_plan_set_tuning.  Stage timing: the translation
+ * is stage 5, the contraction stage 1, the rotation FFT stage 2.
+ * Errors: FTK_EINVAL, FTK_ESTATE (no shifts), FTK_ENOMEM, FTK_EUNSUPPORTED,
+ * FTK_EDEVICE. */
+int ftk_bft_align(ftk_plan* plan, const float* images, int nA, const float* templates, int nB, float* X,
+                  ftk_pose* best, void* stream);
+
 /* FP64 planning tables, host only (no device work, usable without a GPU):
  * the same truncation and factor tables a plan with these arguments uses.
  * Pass NULL for any output not wanted; sizes come from *H_out (call once
@@ -256,6 +277,7 @@ int ftk_plan_tables_weighted(int n, int K, double W, double eps, const double* a
  *   3 bookkeeping (pose key init / conversion)
  *   4 operand preparation (templates embedded, and split for bf16x3,
  *     into Step 1's lane order, once per call)
+ *   5 translated coefficients of ftk_bft_align
  * ftk_plan_profile(plan, 1) enables (and clears), 0 disables.
  * ftk_plan_stage_times waits for the recorded events, writes per-stage sums
  * of elapsed milliseconds and launch counts into ms[nstages] and

@@ -373,6 +373,37 @@ def bft_X(a: np.ndarray, b: np.ndarray, plan: Plan, lmax: int) -> np.ndarray:
     return out
 
 
+def bft_translated_coefficients(Ahat: np.ndarray, plan: Plan) -> np.ndarray:
+    """Brute-force translations, precomputation (Section 6.2): for every
+    shift, the Fourier-Bessel coefficients of the translated image, T_delta
+    a(k_m; q) = (1/Qa) sum_p Ahat(k_m, psi_p) exp(-i k_m . delta)
+    exp(-i q psi_p): the ring samples times the translation phase (eq. Fdk)
+    before the ring DFT of eq. aqkcalc.  Returns (N, M, Qa), q in
+    signed_modes() order."""
+    M, Qa = Ahat.shape
+    dx = 2.0 / plan.n
+    psi = polar_angles(Qa)
+    q = signed_modes(Qa)
+    D = np.exp(-1j * np.multiply.outer(psi, q)) / Qa  # (p, q)
+    out = np.zeros((plan.shifts.shape[0], M, Qa), dtype=np.complex128)
+    for s, (sx, sy) in enumerate(plan.shifts):
+        kd = np.multiply.outer(plan.k, sx * dx * np.cos(psi) + sy * dx * np.sin(psi))  # (M, p)
+        out[s] = (Ahat * np.exp(-1j * kd)) @ D
+    return out
+
+
+def bft_translations_X(Ahat: np.ndarray, b: np.ndarray, plan: Plan) -> np.ndarray:
+    """Brute-force translations (Section 6.2): eq. fbk2 with l_max = 0 on
+    the translated coefficients of each shift, then the rotation sum of
+    eq. 1dfft: X(delta, r) = sum_q e^{-i q gamma_r} 2 pi sum_m w_m
+    T_delta a(k_m; q) conj b(k_m; q).  Returns (N, Qa)."""
+    Ta = bft_translated_coefficients(Ahat, plan)
+    Qa = b.shape[1]
+    E = np.exp(-1j * np.multiply.outer(signed_modes(Qa), polar_angles(Qa)))  # (q, r)
+    Xh = TWO_PI * np.einsum("m,dmq,mq->dq", plan.w, Ta, np.conj(b))
+    return Xh @ E
+
+
 # ---------------------------------------------------------------------------
 # Poses and error scale
 # ---------------------------------------------------------------------------

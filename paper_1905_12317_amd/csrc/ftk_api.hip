@@ -317,6 +317,12 @@ int upload_plan_tables(ftk_plan* p) {
   hipError_t e;
   if ((e = upload(p->cz, cz)) != hipSuccess) return hip_fail(e, "upload cz");
   if ((e = upload(p->ell, ell)) != hipSuccess) return hip_fail(e, "upload ell");
+  {
+    // brute-force translations: 2 pi w_m
+    std::vector<float> bcz(M);
+    for (int m = 0; m < M; ++m) bcz[m] = static_cast<float>(2.0 * kPi * p->t.w[m]);
+    if ((e = upload(p->bft_cz, bcz)) != hipSuccess) return hip_fail(e, "upload bft_cz");
+  }
   if ((e = upload(p->tw_nf, twiddles(nf))) != hipSuccess) return hip_fail(e, "upload tw_nf");
   if ((e = upload(p->tw_qa, twiddles(Qa))) != hipSuccess) return hip_fail(e, "upload tw_qa");
   if ((e = upload(p->deapod, dea)) != hipSuccess) return hip_fail(e, "upload deapod");
@@ -637,6 +643,18 @@ int ftk_set_shifts(ftk_plan* p, const double* shifts_px, int N) {
     if (split && (e = upload(p->yt_lo, l16)) != hipSuccess) return hip_fail(e, "ftk_set_shifts: upload");
     p->y_scale = static_cast<float>(sy);
   }
+  {
+    // brute-force translations: (k_m dx, k_m dy), the shift in image units
+    const int M = p->M;
+    const double px = 2.0 / p->n;
+    std::vector<float> kd(static_cast<size_t>(2) * N * M);
+    for (int d = 0; d < N; ++d)
+      for (int m = 0; m < M; ++m) {
+        kd[2 * (static_cast<size_t>(d) * M + m) + 0] = static_cast<float>(p->t.k[m] * shifts_px[2 * d] * px);
+        kd[2 * (static_cast<size_t>(d) * M + m) + 1] = static_cast<float>(p->t.k[m] * shifts_px[2 * d + 1] * px);
+      }
+    if ((e = upload(p->bft_kd, kd)) != hipSuccess) return hip_fail(e, "ftk_set_shifts: upload");
+  }
   p->N = N;
   p->N_pad = Np;
   return FTK_OK;
@@ -647,6 +665,14 @@ int ftk_transform(ftk_plan* p, const float* imgs, int cnt, void* coeffs, void* s
   if (cnt < 0) return fail(FTK_EINVAL, "ftk_transform: cnt < 0");
   if (cnt == 0) return FTK_OK;
   if (!imgs || !coeffs) return fail(FTK_EINVAL, "ftk_transform: NULL buffer");
+  return transform_run(p, imgs, cnt, static_cast<float2*>(coeffs), nullptr, stream);
+}
+
+}  // extern "C"
+
+namespace ftkint {
+
+int transform_run(ftk_plan* p, const float* imgs, int cnt, float2* coeffs, float2* polar, void* stream) {
   hipStream_t s = static_cast<hipStream_t>(stream);
   const int n = p->n, nf = p->sk.nf;
   const Needs nd = plan_needs(p, cnt, 0, true);
@@ -660,7 +686,8 @@ int ftk_transform(ftk_plan* p, const float* imgs, int cnt, void* coeffs, void* s
     const int c = std::min(chunk, cnt - c0);
     TransformArgs a;
     a.imgs = imgs + static_cast<size_t>(c0) * n * n;
-    a.coeffs = static_cast<float2*>(coeffs) + static_cast<size_t>(c0) * p->Qa * p->M;
+    a.coeffs = coeffs + static_cast<size_t>(c0) * p->Qa * p->M;
+    a.polar = polar ? polar + static_cast<size_t>(c0) * p->Qa * p->M : nullptr;
     a.scratchH = ws.tr_h.as<float2>();
     a.scratchG = ws.tr_g.as<float2>();
     a.deapod = p->deapod.as<float>();
@@ -679,10 +706,6 @@ int ftk_transform(ftk_plan* p, const float* imgs, int cnt, void* coeffs, void* s
   }
   return FTK_OK;
 }
-
-}  // extern "C"
-
-namespace ftkint {
 
 // Steps 1-3 + argmax for nA images against nB templates (lists == NULL) or
 // against K templates of their own (lists [nA][K]); results per pair

@@ -240,7 +240,11 @@ __device__ __forceinline__ bool step1_block(int b, const Step1Args& p, int CT, i
 // the template operand that of mode Qa/2).  Slots y >= CT are the modes
 // q = y - CT + 1 .. Qa/2 - 1 over the whole block.
 // LDS: image operand P[k'][zeta] (k' = 2m + c', zeta contiguous, stride PS).
-template <int RT, int CT, bool FOLD>
+// BFT: the brute-force-translation contraction instead (zeta is a shift
+// delta, H_pad the padded shift count): P_delta(m; q) = 2 pi w_m Ta(k_m; q)
+// from the translated coefficients p.ta [image][q = 0 .. Qa/2][delta][m],
+// with p.cz[m] = 2 pi w_m and no mode offset.
+template <int RT, int CT, bool FOLD, bool BFT>
 __device__ __forceinline__ void step1_fp32_tile(const Step1Args& p, float* smem, int A, int q, int z0, int part) {
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -250,31 +254,46 @@ __device__ __forceinline__ void step1_fp32_tile(const Step1Args& p, float* smem,
   constexpr int PS = (ZB % 64 == 0) ? ZB + 32 : ZB;  // row stride == 32 mod 64 words
   constexpr int NP = FOLD ? 2 : 1;
   const int MK = NP * M;
-  const float2* arow = p.a + static_cast<size_t>(A) * Qa * M;
   struct D {
     float2 av;
     float cm;
   };
-  batched_fill<8>(
-      ZB * MK, [&](int i) { return p.ell[z0 + i / MK]; },
-      [&](int ell, int i) {
-        const int z = i / MK;
-        const int mm = i - z * MK;
-        const bool ny = FOLD && mm >= M;
-        const int m = ny ? mm - M : mm;
-        int row = (ny ? QH : q) - ell;
-        row %= Qa;
-        row += (row < 0) ? Qa : 0;
-        return D{arow[static_cast<size_t>(row) * M + m], p.cz[static_cast<size_t>(z0 + z) * M + m]};
-      },
-      [&](const D& d, int i) {
-        const int z = i / MK;
-        const int mm = i - z * MK;
-        const bool ny = FOLD && mm >= M;
-        // i (x + i y) = -y + i x for the Nyquist half
-        smem[(2 * mm) * PS + z] = ny ? -d.cm * d.av.y : d.cm * d.av.x;
-        smem[(2 * mm + 1) * PS + z] = ny ? d.cm * d.av.x : d.cm * d.av.y;
-      });
+  auto store = [&](const D& d, int i) {
+    const int z = i / MK;
+    const int mm = i - z * MK;
+    const bool ny = FOLD && mm >= M;
+    // i (x + i y) = -y + i x for the Nyquist half
+    smem[(2 * mm) * PS + z] = ny ? -d.cm * d.av.y : d.cm * d.av.x;
+    smem[(2 * mm + 1) * PS + z] = ny ? d.cm * d.av.x : d.cm * d.av.y;
+  };
+  if constexpr (BFT) {
+    const float2* tq = p.ta + static_cast<size_t>(A) * (QH + 1) * p.H_pad * M;
+    batched_fill<8>(
+        ZB * MK, [&](int) { return 0; },
+        [&](int, int i) {
+          const int z = i / MK;
+          const int mm = i - z * MK;
+          const bool ny = FOLD && mm >= M;
+          const int m = ny ? mm - M : mm;
+          return D{tq[(static_cast<size_t>(ny ? QH : q) * p.H_pad + z0 + z) * M + m], p.cz[m]};
+        },
+        store);
+  } else {
+    const float2* arow = p.a + static_cast<size_t>(A) * Qa * M;
+    batched_fill<8>(
+        ZB * MK, [&](int i) { return p.ell[z0 + i / MK]; },
+        [&](int ell, int i) {
+          const int z = i / MK;
+          const int mm = i - z * MK;
+          const bool ny = FOLD && mm >= M;
+          const int m = ny ? mm - M : mm;
+          int row = (ny ? QH : q) - ell;
+          row %= Qa;
+          row += (row < 0) ? Qa : 0;
+          return D{arow[static_cast<size_t>(row) * M + m], p.cz[static_cast<size_t>(z0 + z) * M + m]};
+        },
+        store);
+  }
   __syncthreads();
   const int r = lane >> 5;
   const int c32 = lane & 31;
@@ -334,7 +353,7 @@ __device__ __forceinline__ void step1_fp32_tile(const Step1Args& p, float* smem,
   }
 }
 
-template <int RT, int CT>
+template <int RT, int CT, bool BFT>
 __global__ void __launch_bounds__(256) step1_fp32_v2(Step1Args p) {
   extern __shared__ float smem[];
   int A, y, zp;
@@ -342,9 +361,9 @@ __global__ void __launch_bounds__(256) step1_fp32_v2(Step1Args p) {
   const int zb = (zp / p.tparts) * (32 * CT);
   const int part = zp % p.tparts;
   if (y < CT)
-    step1_fp32_tile<RT, 1, true>(p, smem, A, 0, zb + 32 * y, part);
+    step1_fp32_tile<RT, 1, true, BFT>(p, smem, A, 0, zb + 32 * y, part);
   else
-    step1_fp32_tile<RT, CT, false>(p, smem, A, y - CT + 1, zb, part);
+    step1_fp32_tile<RT, CT, false, BFT>(p, smem, A, y - CT + 1, zb, part);
 }
 
 // ---- Step 1, split forms (bf16 or fp16, three products) -----------------
@@ -802,7 +821,7 @@ hipError_t launch_step1_v2(const Step1Args& a, int precision, hipStream_t s) {
   if (precision == 0) {
 #define FTK_S1(ct)                                              \
   case ct: {                                                     \
-    auto k = step1_fp32_v2<2, ct>;                              \
+    auto k = step1_fp32_v2<2, ct, false>;                       \
     if ((e = set_lds(k, lds)) != hipSuccess) return e;          \
     hipLaunchKernelGGL(k, grid, dim3(256), lds, s, a);          \
     break;                                                       \
@@ -858,5 +877,33 @@ hipError_t launch_step1_v2(const Step1Args& a, int precision, hipStream_t s) {
     }
 #undef FTK_S1
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_step1_bft(const Step1Args& a, hipStream_t s) {
+  if (a.nA <= 0 || a.nB <= 0) return hipSuccess;
+  if (!a.ta) return hipErrorInvalidValue;
+  const int CT = a.zblk / 32;
+  const int QH = a.Qa / 2;
+  const size_t groups = static_cast<size_t>(QH - 1 + CT) * (a.H_pad / a.zblk) * a.tparts;
+  const size_t nwg = 8 * static_cast<size_t>(a.nA) * ((groups + 7) / 8);
+  if (nwg > 0x7fffffffull) return hipErrorInvalidConfiguration;
+  const dim3 grid(static_cast<unsigned>(nwg));
+  const size_t lds = step1_v2_lds_bytes(a.M, a.zblk, 0);
+  hipError_t e;
+#define FTK_S1(ct)                                              \
+  case ct: {                                                     \
+    auto k = step1_fp32_v2<2, ct, true>;                        \
+    if ((e = set_lds(k, lds)) != hipSuccess) return e;          \
+    hipLaunchKernelGGL(k, grid, dim3(256), lds, s, a);          \
+    break;                                                       \
+  }
+  switch (CT) {
+    FTK_S1(1)
+    FTK_S1(2)
+    FTK_S1(4)
+    default: return hipErrorInvalidValue;
+  }
+#undef FTK_S1
   return hipGetLastError();
 }

@@ -222,6 +222,11 @@ __global__ void __launch_bounds__(1024) transform_kernel(TransformArgs p) {
         }
         ba[pp] = acc;
         ba[pp + half] = cconj(acc);
+        if (p.polar) {
+          float2* pr = p.polar + (static_cast<size_t>(img) * M + m) * Qa;
+          pr[pp] = acc;
+          pr[pp + half] = cconj(acc);
+        }
       }
       wave_sync();
       float2* r = fft_qa(ba, bb, lane);

@@ -8,6 +8,7 @@
 struct TransformArgs {
   const float* imgs;     // [cnt][n][n]
   float2* coeffs;        // [cnt][Qa][M]
+  float2* polar;         // [cnt][M][Qa] ring samples Ahat(k_m, psi_p) / Qa, or null
   float2* scratchH;      // [cnt][n][nf]
   float2* scratchG;      // [cnt][nf][nf] (transposed: [l2][l1])
   const float* deapod;   // [n] per-dimension deconvolution and scale
@@ -29,6 +30,7 @@ struct Step1Args {
   const float2* b;       // template coefficients [nB][Qa][M]
   const float* cz;       // [H_pad][M]: 2 pi w_m Sigma v(k_m), 0 on padding
   const int* ell;        // [H_pad]: l_zeta, 0 on padding
+  const float2* ta;      // brute-force translations only: translated coefficients (launch_step1_bft)
   void* zs;              // Zhat staging, layout by form (below)
   const float* r32;      // embedded template operand, FP32 lane order (tmpl_prep)
   const void* r16;       // embedded template operand, bf16 hi/lo or fp16 lane order (tmpl_prep)
@@ -124,3 +126,29 @@ hipError_t launch_keys_init(unsigned long long* keys, size_t count, hipStream_t 
 // vscale: device scalar multiplying the pose values (FP16 and split-fp16 forms), or null
 hipError_t launch_keys_to_poses(const unsigned long long* keys, void* poses, size_t count, int Qa,
                                 const float* vscale, hipStream_t stream);
+
+// Brute-force translations (Section 6.2 of the paper), kern_bft.hip and
+// launch_step1_bft.  Per image A and shift delta the translated coefficients
+//   Ta[A][q][delta][m] = sum_p Ahat(k_m, psi_p) / Qa e^{-i k_m (dx cos psi_p + dy sin psi_p)} e^{-2 pi i q p / Qa}
+// for q = 0 .. Qa/2 (Hermitian symmetry of a real image), zero for the
+// padded shifts delta >= N; then Step 1 with zeta = delta, no mode offset
+// and P_delta(m; q) = 2 pi w_m Ta gives Xhat(delta, q) directly in the
+// FTK staging layout (H_pad = the padded shift count), and the rotation
+// epilogue of Step 3 runs on it without a shift contraction.
+struct BftTranslateArgs {
+  const float2* polar;   // [nA][M][Qa] (TransformArgs::polar)
+  float2* ta;            // [nA][Qa/2 + 1][N_pad][M]
+  const float2* kd;      // [N][M]: (k_m dx, k_m dy) of shift delta, image units
+  const float2* tw_qa;   // [Qa] exp(-2 pi i k / Qa)
+  int nA, M, Qa, N, N_pad;
+};
+size_t bft_translate_lds_bytes(int Qa);
+hipError_t launch_bft_translate(const BftTranslateArgs& args, hipStream_t stream);
+// Step 1 on the translated coefficients (Step1Args::ta set, H_pad = N_pad,
+// cz = [M] 2 pi w_m, zblk = 32, 64 or 128)
+hipError_t launch_step1_bft(const Step1Args& args, hipStream_t stream);
+// rotation FFT + argmax of Xhat read from the staging (Step3Args: zs, X,
+// keys, tw_qa, pairs, Qa, H_pad = N_pad of the staging, N); one wave per
+// 16 shifts of a pair, nwaves waves per workgroup
+size_t bft_rotate_lds_bytes(int Qa, int nwaves);
+hipError_t launch_bft_rotate(const Step3Args& args, hipStream_t stream);

@@ -68,13 +68,15 @@ struct HostTables {
 // lends a shared one to each of its plans while it runs them.
 struct Workspace {
   DevBuf tr_h, tr_g, coef_a, coef_b, stage, keys, tmpl, scales;
-  DevBuf refine;  // lists and poses of the two-pass alignment
+  DevBuf refine;     // lists and poses of the two-pass alignment
+  DevBuf polar, ta;  // brute-force translations: ring samples, translated coefficients
   size_t bytes() const {
     return tr_h.bytes + tr_g.bytes + coef_a.bytes + coef_b.bytes + stage.bytes + keys.bytes + tmpl.bytes +
-           scales.bytes + refine.bytes;
+           scales.bytes + refine.bytes + polar.bytes + ta.bytes;
   }
   void release() {
-    for (DevBuf* b : {&tr_h, &tr_g, &coef_a, &coef_b, &stage, &keys, &tmpl, &scales, &refine}) b->release();
+    for (DevBuf* b : {&tr_h, &tr_g, &coef_a, &coef_b, &stage, &keys, &tmpl, &scales, &refine, &polar, &ta})
+      b->release();
   }
 };
 
@@ -104,14 +106,18 @@ struct ftk_plan {
   // plan-owned device tables
   ftkint::DevBuf cz, ell, yt, yt_hi, yt_lo, tw_nf, tw_qa, deapod, ptbase, ptker;
   ftkint::DevBuf rot16;  // FP16 form, Qa <= 256: rotation transform tables
+  // brute-force translations: [M] 2 pi w_m, and [N][M] (k_m dx, k_m dy) of
+  // each shift in image units
+  ftkint::DevBuf bft_cz, bft_kd;
   ftkint::Workspace own_ws;
   ftkint::Workspace* ws = &own_ws;
   size_t device_bytes() const {
     return cz.bytes + ell.bytes + yt.bytes + yt_hi.bytes + yt_lo.bytes + tw_nf.bytes + tw_qa.bytes +
-           deapod.bytes + ptbase.bytes + ptker.bytes + rot16.bytes + own_ws.bytes();
+           deapod.bytes + ptbase.bytes + ptker.bytes + rot16.bytes + bft_cz.bytes + bft_kd.bytes + own_ws.bytes();
   }
   void release_all() {
-    for (ftkint::DevBuf* b : {&cz, &ell, &yt, &yt_hi, &yt_lo, &tw_nf, &tw_qa, &deapod, &ptbase, &ptker, &rot16})
+    for (ftkint::DevBuf* b :
+         {&cz, &ell, &yt, &yt_hi, &yt_lo, &tw_nf, &tw_qa, &deapod, &ptbase, &ptker, &rot16, &bft_cz, &bft_kd})
       b->release();
     own_ws.release();
   }
@@ -168,6 +174,9 @@ inline SplitF16Exps split_f16_exps(int M) {
   while ((1 << c) < 4 * M) ++c;
   return SplitF16Exps{kData, c - 2 * kData, -(kData + c)};
 }
+// ftk_transform's body; polar (optional) receives the ring samples
+// [cnt][M][Qa] that the ring DFT transforms (TransformArgs::polar).
+int transform_run(ftk_plan* p, const float* imgs, int cnt, float2* coeffs, float2* polar, void* stream);
 // Step 3 waves per workgroup and Step 1 zeta block actually used by a plan.
 int step3_waves(const ftk_plan* p);
 int step1_zblk(const ftk_plan* p);
