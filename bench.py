@@ -89,10 +89,11 @@ def flops_per_pair(H, M, N, Qa):
 
 
 REFINE_K = 4  # templates per image re-aligned by the split form in the two-pass form
+UPSAMPLE = 5  # rotation upsampling factor of the upsampled measurement (5 x 256 = 1280 rotations)
 WEIGHTED_EPS = 5e-3  # eps of the weighted-SVD plan: the paper plan's accuracy at eps = 1e-3 (see main)
 
 
-def run_form(form, inputs, w, steps, warmup, shifts, eps=None, weight=None):
+def run_form(form, inputs, w, steps, warmup, shifts, eps=None, weight=None, up=1):
     """One form over the workload.  "fp16+bf16x3" is the two-pass form: the
     FP16 form over every pair, then the split form on each image's REFINE_K
     best FP16 templates (ftk_align_refined).  "bft": brute-force
@@ -106,6 +107,8 @@ def run_form(form, inputs, w, steps, warmup, shifts, eps=None, weight=None):
     prec = "fp16" if two else ("fp32" if bft else form)
     P = ftk.Plan(w["n"], w["M"], w["Qa"], w["R"], eps or w["eps"], precision=prec, weight=weight)
     P.set_shifts(shifts)
+    if up > 1:
+        P.set_rotations(up)
     Pf = None
     if two:
         Pf = ftk.Plan(w["n"], w["M"], w["Qa"], w["R"], w["eps"], precision="bf16x3")
@@ -407,6 +410,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-weighted", action="store_true", help="skip the weighted-SVD measurement")
     ap.add_argument("--no-bft", action="store_true", help="skip the brute-force-translation measurement")
+    ap.add_argument("--no-upsample", action="store_true", help="skip the rotation-upsampling measurement")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="only run a plain device-to-device copy of this many MiB (3 times) and exit; "
                          "used to scale the FETCH_SIZE / WRITE_SIZE counters")
@@ -552,6 +556,18 @@ def main():
             "best_pose_agreement_vs_ftk_fp32": agreement(rb["img_best"], results["fp32"]["img_best"])
             if "fp32" in results else None,
             "recall_true_template": recall(rb["img_best"], inputs)}
+    if not args.no_upsample:
+        # rotation upsampling (remark after eq. 1dfft) to 5 Qa = 1280 rotations,
+        # about the paper's n pi^2 rotation grid, for the split-fp16 form and BFT
+        ups = {}
+        for f in ("fp16x3", "bft"):
+            ru = run_form(f, inputs, w, args.steps, args.warmup, shifts, up=UPSAMPLE)
+            log(f"[{f} x{UPSAMPLE} rotations] {ru['ms_per_step']:.2f} ms/step, {ru['pairs_per_s']:.4g} pairs/s")
+            ups[f] = {"pairs_per_s": ru["pairs_per_s"], "ms_per_step": ru["ms_per_step"],
+                      "stage_ms_per_step": {k: v[0] / args.steps for k, v in ru["stages"].items()}}
+        ups["rotations"] = UPSAMPLE * Qa
+        ups["ftk_fp16x3_speedup_over_bft"] = ups["fp16x3"]["pairs_per_s"] / ups["bft"]["pairs_per_s"]
+        out["config"]["upsampled_rotations"] = ups
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(inputs, w, shifts)
     print(json.dumps(out), flush=True)

@@ -99,6 +99,7 @@ typedef struct ftk_plan_info_t {
   size_t coeff_bytes_per_image; /* 8 * M * Qa */
   size_t device_bytes;          /* device memory held by the plan now */
   int weighted;                 /* 1: operator SVD with a k-side weight */
+  int rotations;                /* rotations per pose search: U Qa (ftk_plan_set_rotations) */
 } ftk_plan_info_t;
 
 /* Build a plan (host FP64 planning, then upload of the device tables on the
@@ -226,6 +227,23 @@ int ftk_align(ftk_plan* plan, const float* images, int nA, const float* template
  * Errors: FTK_EINVAL, FTK_ESTATE, FTK_ENOMEM, FTK_EDEVICE. */
 int ftk_align_refined(ftk_plan* coarse, ftk_plan* fine, const void* img_coeffs, int nA, const void* tmpl_coeffs,
                       int nB, int k, ftk_pose* best, int32_t* best_t, ftk_pose* best_pose, void* stream);
+
+/* Rotation upsampling (the remark after eq. 1dfft: zero-padding the angular
+ * sum samples more rotations at little cost).  With upsample = U > 1 the
+ * alignments of this plan evaluate X on U Q rotations gamma_r = 2 pi r / (U Q),
+ * r = 0 .. U Q - 1: X = Re sum_q e^{-i q gamma} Xhat(delta, q) over the Q
+ * modes (the Nyquist mode as its cosine), which at every U-th rotation equals
+ * the Q-rotation result.  X then has rows of U Q values ([nA][nB][N][U Q])
+ * and ftk_pose.rot runs over [0, U Q).  Implemented as U passes of the
+ * Q-point rotation FFT on Xhat(q) e^{-i q 2 pi u / (U Q)}, u = 0 .. U - 1,
+ * Step 3 handing Xhat over through device memory (Q/2 x 2 N' floats per pair,
+ * N' = N rounded up to 16, counted against the staging size).  Applies to
+ * ftk_align, ftk_align_coeffs, ftk_align_lists, ftk_bft_align, batches and
+ * ftk_align_refined (both plans with the same U); not to the FP16 form
+ * (FTK_EUNSUPPORTED at alignment) nor to ftk_align_coeffs_noalloc.
+ * upsample = 1 (the default) restores Q rotations.
+ * Errors: FTK_EINVAL (upsample outside [1, 16]). */
+int ftk_plan_set_rotations(ftk_plan* plan, int upsample);
 
 /* Brute-force translations (BFT, Section 6.2 of the paper), the method the
  * paper compares FTK with, on the plan's grids and shifts: for every image

@@ -351,6 +351,38 @@ def ftk_X(a: np.ndarray, b: np.ndarray, plan: Plan) -> np.ndarray:
     return Xh @ E
 
 
+def ftk_xhat(a: np.ndarray, b: np.ndarray, plan: Plan) -> np.ndarray:
+    """Xhat(delta, q) of eq. fbk3 (Step 1, then Step 3): (N, Qa), q in
+    signed_modes() order."""
+    return plan.Y @ ftk_zhat(a, b, plan)
+
+
+def rotation_sum_upsampled(Xh: np.ndarray, U: int) -> np.ndarray:
+    """Step 2 (eq. 1dfft) on a U times finer rotation grid, gamma_r =
+    2 pi r / (U Qa), r = 0 .. U Qa - 1: the zero-padded angular sum of the
+    remark after eq. 1dfft.  The Nyquist mode -Qa/2 enters as its cosine (half
+    of it at each of +-Qa/2), so X stays real and, at every U-th angle, equals
+    the sum on the Qa-point grid.  Xh: (N, Qa) in signed_modes() order."""
+    N, Qa = Xh.shape
+    q = signed_modes(Qa)
+    gam = TWO_PI * np.arange(U * Qa) / (U * Qa)
+    inner = q != -(Qa // 2)
+    E = np.exp(-1j * np.multiply.outer(q[inner], gam))
+    return Xh[:, inner] @ E + Xh[:, ~inner] * np.cos(0.5 * Qa * gam)[None, :]
+
+
+def ftk_X_upsampled(a: np.ndarray, b: np.ndarray, plan: Plan, U: int) -> np.ndarray:
+    """FP64 FTK with U Qa rotations: (N, U Qa) complex."""
+    return rotation_sum_upsampled(ftk_xhat(a, b, plan), U)
+
+
+def bft_X_upsampled(Ahat: np.ndarray, b: np.ndarray, plan: Plan, U: int) -> np.ndarray:
+    """Brute-force translations with U Qa rotations: (N, U Qa) complex."""
+    Ta = bft_translated_coefficients(Ahat, plan)
+    Xh = TWO_PI * np.einsum("m,dmq,mq->dq", plan.w, Ta, np.conj(b))
+    return rotation_sum_upsampled(Xh, U)
+
+
 def bft_X(a: np.ndarray, b: np.ndarray, plan: Plan, lmax: int) -> np.ndarray:
     """FTK Steps 1-2 with the exact Bessel kernel (eq. fastrots), one shift at a
     time: the untruncated reference of the same cyclic discretisation."""

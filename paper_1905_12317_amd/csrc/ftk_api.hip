@@ -403,10 +403,11 @@ Needs plan_needs(const ftk_plan* p, int nA, int nB, bool from_pixels) {
     d.coef_b = cb * nB;
   }
   if (nA > 0 && nB > 0) {
-    const size_t per_pair = stage_bytes_per_pair(p);
+    const size_t per_pair = stage_bytes_per_pair(p) + xhat_bytes_per_pair(p);
     const size_t budget = static_cast<size_t>(p->tune.stage_mib) << 20;
     d.chunk_images = static_cast<int>(std::min<size_t>(nA, std::max<size_t>(1, budget / (per_pair * nB))));
-    d.stage = static_cast<size_t>(d.chunk_images) * nB * per_pair;
+    d.stage = static_cast<size_t>(d.chunk_images) * nB * stage_bytes_per_pair(p);
+    d.xhat = static_cast<size_t>(d.chunk_images) * nB * xhat_bytes_per_pair(p);
     d.keys = static_cast<size_t>(nA) * nB * sizeof(unsigned long long);
     d.tmpl = tmpl_prep_bytes(nB, p->M, p->Qa, prec_code(p));
     d.scales = (prec_code(p) == 2 || prec_code(p) == 3) ? 64 : 0;
@@ -417,10 +418,11 @@ Needs plan_needs(const ftk_plan* p, int nA, int nB, bool from_pixels) {
 Needs plan_needs_lists(const ftk_plan* p, int nA, int K) {
   Needs d;
   if (nA <= 0 || K <= 0) return d;
-  const size_t per_pair = stage_bytes_per_pair(p);
+  const size_t per_pair = stage_bytes_per_pair(p) + xhat_bytes_per_pair(p);
   const size_t budget = static_cast<size_t>(p->tune.stage_mib) << 20;
   d.chunk_images = static_cast<int>(std::min<size_t>(nA, std::max<size_t>(1, budget / (per_pair * K))));
-  d.stage = static_cast<size_t>(d.chunk_images) * K * per_pair;
+  d.stage = static_cast<size_t>(d.chunk_images) * K * stage_bytes_per_pair(p);
+  d.xhat = static_cast<size_t>(d.chunk_images) * K * xhat_bytes_per_pair(p);
   d.keys = static_cast<size_t>(nA) * K * sizeof(unsigned long long);
   d.tmpl = tmpl_prep_tile_bytes(static_cast<size_t>(d.chunk_images) * ((K + 15) / 16), p->M, p->Qa, prec_code(p));
   d.scales = (prec_code(p) == 2 || prec_code(p) == 3) ? 64 : 0;
@@ -553,6 +555,14 @@ int ftk_plan_info(const ftk_plan* p, ftk_plan_info_t* o) {
   o->coeff_bytes_per_image = static_cast<size_t>(8) * p->M * p->Qa;
   o->device_bytes = p->device_bytes();
   o->weighted = p->weighted ? 1 : 0;
+  o->rotations = p->Qa * p->up;
+  return FTK_OK;
+}
+
+int ftk_plan_set_rotations(ftk_plan* p, int upsample) {
+  if (!p) return fail(FTK_EINVAL, "ftk_plan_set_rotations: NULL plan");
+  if (upsample < 1 || upsample > 16) return fail(FTK_EINVAL, "ftk_plan_set_rotations: upsample must be in [1, 16]");
+  p->up = upsample;
   return FTK_OK;
 }
 
@@ -721,6 +731,10 @@ int align_run(ftk_plan* p, const void* img_coeffs, int nA, const void* tmpl_coef
   const int prec = prec_code(p);
   const int chunkA = buf.chunk_images;
   if (chunkA < 1) return fail(FTK_EINVAL, "ftk_align: no staging for one image");
+  const int U = p->up;
+  if (U > 1 && prec == 2)
+    return fail(FTK_EUNSUPPORTED, "ftk_align: rotation upsampling is not available in the FP16 form");
+  if (U > 1 && !buf.xhat) return fail(FTK_EUNSUPPORTED, "ftk_align: rotation upsampling needs an Xhat buffer");
   struct NoTimer {
     StageTimer* t;
     hipEvent_t begin(hipStream_t st) { return t ? t->begin(st) : nullptr; }
@@ -814,16 +828,27 @@ int align_run(ftk_plan* p, const void* img_coeffs, int nA, const void* tmpl_coef
     a3.zs = buf.stage;
     a3.pairs = na * nBe;
     a3.keys = keys + static_cast<size_t>(A0) * nBe;
-    a3.X = X ? X + static_cast<size_t>(A0) * nBe * p->N * p->Qa : nullptr;
+    a3.X = X ? X + static_cast<size_t>(A0) * nBe * p->N * p->Qa * U : nullptr;
+    a3.xhat = U > 1 ? buf.xhat : nullptr;
     ev = timer.begin(s);
     e = (prec == 1 || prec == 3) ? launch_step3_bf16(a3, prec == 3, s)
                                  : (prec == 2 ? launch_step3_fp16(a3, s) : launch_step3(a3, p->precision, s));
     if (e != hipSuccess) return hip_fail(e, "ftk_align: step 3");
+    if (U > 1) {
+      // the rotation sum on the U-fold grid, from the Xhat Step 3 stored
+      Step3Args ar = a3;
+      ar.zs = buf.xhat;
+      ar.xhat = nullptr;
+      ar.H_pad = p->N_pad;
+      ar.nwaves = 4;
+      ar.up = U;
+      if ((e = launch_xhat_rotate(ar, s)) != hipSuccess) return hip_fail(e, "ftk_align: upsampled rotation");
+    }
     timer.end(ev, s, 2);
   }
   if (best) {
     ev = timer.begin(s);
-    if ((e = launch_keys_to_poses(keys, best, pairs, p->Qa, scales ? scales + 4 : nullptr, s)) != hipSuccess)
+    if ((e = launch_keys_to_poses(keys, best, pairs, p->Qa * U, scales ? scales + 4 : nullptr, s)) != hipSuccess)
       return hip_fail(e, "ftk_align: poses");
     timer.end(ev, s, 3);
   }
@@ -842,8 +867,9 @@ int align_impl(ftk_plan* p, const void* img_coeffs, int nA, const void* tmpl_coe
   if (ws.keys.ensure(nd.keys) != hipSuccess) return fail(FTK_ENOMEM, "ftk_align: key buffer");
   if (ws.tmpl.ensure(nd.tmpl) != hipSuccess) return fail(FTK_ENOMEM, "ftk_align: template operand buffer");
   if (ws.scales.ensure(nd.scales) != hipSuccess) return fail(FTK_ENOMEM, "ftk_align: scale buffer");
+  if (ws.xhat.ensure(nd.xhat) != hipSuccess) return fail(FTK_ENOMEM, "ftk_align: Xhat buffer");
   const AlignBufs buf{ws.stage.ptr, ws.keys.as<unsigned long long>(), ws.tmpl.ptr, ws.scales.as<float>(),
-                      nd.chunk_images};
+                      nd.chunk_images, ws.xhat.as<float>()};
   return align_run(p, img_coeffs, nA, tmpl_coeffs, nB, lists, K, X, best, buf, &p->timer, stream);
 }
 

@@ -44,6 +44,7 @@ void needs_max(Needs& a, const Needs& b) {
   a.keys = std::max(a.keys, b.keys);
   a.tmpl = std::max(a.tmpl, b.tmpl);
   a.scales = std::max(a.scales, b.scales);
+  a.xhat = std::max(a.xhat, b.xhat);
 }
 
 hipError_t ensure_all(Workspace& w, const Needs& d) {
@@ -55,6 +56,7 @@ hipError_t ensure_all(Workspace& w, const Needs& d) {
   if ((e = w.stage.ensure(d.stage)) != hipSuccess) return e;
   if ((e = w.keys.ensure(d.keys)) != hipSuccess) return e;
   if ((e = w.tmpl.ensure(d.tmpl)) != hipSuccess) return e;
+  if ((e = w.xhat.ensure(d.xhat)) != hipSuccess) return e;
   return w.scales.ensure(d.scales);
 }
 

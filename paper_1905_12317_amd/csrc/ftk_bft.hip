@@ -112,6 +112,7 @@ int ftk_bft_align(ftk_plan* p, const float* images, int nA, const float* templat
   a3.N = N;
   a3.N_pad = Np;
   a3.nwaves = 4;
+  a3.up = p->up;
   for (int A0 = 0; A0 < nA; A0 += chunk) {
     const int na = std::min(chunk, nA - A0);
     rc = transform_run(p, images + static_cast<size_t>(A0) * p->n * p->n, na, ws.coef_a.as<float2>(),
@@ -132,14 +133,14 @@ int ftk_bft_align(ftk_plan* p, const float* images, int nA, const float* templat
     tm.end(ev, s, 1);
     a3.pairs = na * nB;
     a3.keys = keys + static_cast<size_t>(A0) * nB;
-    a3.X = X ? X + static_cast<size_t>(A0) * nB * N * Qa : nullptr;
+    a3.X = X ? X + static_cast<size_t>(A0) * nB * N * Qa * p->up : nullptr;
     ev = tm.begin(s);
-    if ((e = launch_bft_rotate(a3, s)) != hipSuccess) return hip_fail(e, "ftk_bft_align: rotation");
+    if ((e = launch_xhat_rotate(a3, s)) != hipSuccess) return hip_fail(e, "ftk_bft_align: rotation");
     tm.end(ev, s, 2);
   }
   if (best) {
     ev = tm.begin(s);
-    if ((e = launch_keys_to_poses(keys, best, pairs, Qa, nullptr, s)) != hipSuccess)
+    if ((e = launch_keys_to_poses(keys, best, pairs, Qa * p->up, nullptr, s)) != hipSuccess)
       return hip_fail(e, "ftk_bft_align: poses");
     tm.end(ev, s, 3);
   }

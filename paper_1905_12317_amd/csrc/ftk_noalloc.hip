@@ -55,6 +55,7 @@ int ftk_align_coeffs_noalloc(ftk_plan* p, const void* img_coeffs, int nA, const 
   if (nA == 0 || nB == 0) return FTK_OK;
   if (!X && !best) return fail(FTK_EINVAL, "ftk_align_coeffs_noalloc: X and best are both NULL");
   if (!img_coeffs || !tmpl_coeffs) return fail(FTK_EINVAL, "ftk_align_coeffs_noalloc: NULL coefficients");
+  if (p->up > 1) return fail(FTK_EUNSUPPORTED, "ftk_align_coeffs_noalloc: rotation upsampling is not available");
   // layout of the scratch: pose keys, template operand, data scales, staging
   const int prec = prec_code(p);
   const size_t keys = align256(static_cast<size_t>(nA) * nB * sizeof(unsigned long long));
@@ -74,7 +75,7 @@ int ftk_align_coeffs_noalloc(ftk_plan* p, const void* img_coeffs, int nA, const 
   const size_t room = FTK_NOALLOC_SCRATCH_BYTES - fixed;
   const AlignBufs buf{b + fixed, reinterpret_cast<unsigned long long*>(b), b + keys,
                       scl ? reinterpret_cast<float*>(b + keys + tmpl) : nullptr,
-                      static_cast<int>(std::min<size_t>(static_cast<size_t>(nA), room / per_image))};
+                      static_cast<int>(std::min<size_t>(static_cast<size_t>(nA), room / per_image)), nullptr};
   return align_run(p, img_coeffs, nA, tmpl_coeffs, nB, nullptr, 0, X, best, buf, nullptr, stream);
 }
 

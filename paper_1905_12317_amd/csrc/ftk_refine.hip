@@ -88,7 +88,7 @@ __global__ void scatter_poses_kernel(const PoseR* __restrict__ refined, const in
 // (eps, k-side weight, hence H) may differ: the coarse pass may use a cheaper
 // one, the fine pass gives the refined values.
 bool same_shape(const ftk_plan* a, const ftk_plan* b) {
-  return a->n == b->n && a->M == b->M && a->Qa == b->Qa && a->W == b->W && a->N == b->N;
+  return a->n == b->n && a->M == b->M && a->Qa == b->Qa && a->up == b->up && a->W == b->W && a->N == b->N;
 }
 
 }  // namespace
@@ -100,7 +100,7 @@ int ftk_align_refined(ftk_plan* coarse, ftk_plan* fine, const void* img_coeffs, 
   if (!coarse || !fine) return fail(FTK_EINVAL, "ftk_align_refined: NULL plan");
   if (nA < 0 || nB < 0) return fail(FTK_EINVAL, "ftk_align_refined: negative count");
   if (coarse->N <= 0 || fine->N <= 0) return fail(FTK_ESTATE, "ftk_align_refined: call ftk_set_shifts first");
-  if (!same_shape(coarse, fine)) return fail(FTK_EINVAL, "ftk_align_refined: the plans differ in n, K, Q, W or N");
+  if (!same_shape(coarse, fine)) return fail(FTK_EINVAL, "ftk_align_refined: the plans differ in n, K, Q, rotations, W or N");
   if (nA == 0 || nB == 0) return FTK_OK;
   if (k < 1 || k > 64 || k > nB) return fail(FTK_EINVAL, "ftk_align_refined: k must be in [1, min(nB, 64)]");
   if (!img_coeffs || !tmpl_coeffs || !best) return fail(FTK_EINVAL, "ftk_align_refined: NULL buffer");

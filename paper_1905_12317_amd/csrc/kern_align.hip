@@ -27,7 +27,7 @@ __device__ __forceinline__ f32x16 zero16() {
 // PREF: enough threads to prefetch a whole chunk in MAXF4 float4 per thread
 // (double buffering through registers); otherwise each chunk is fetched after
 // the MFMAs of the previous one.
-template <int CTQ, int MAXT, bool PREF>
+template <int CTQ, int MAXT, bool PREF, int EPI>
 __global__ void __launch_bounds__(MAXT) step3_fp32(Step3Args p) {
   extern __shared__ float smem[];
   constexpr int QH = 32 * CTQ;
@@ -116,7 +116,7 @@ __global__ void __launch_bounds__(MAXT) step3_fp32(Step3Args p) {
   __syncthreads();
   if (!active) return;
   float2* T = reinterpret_cast<float2*>(region) + wave * (epilogue_lds_bytes_per_wave() / sizeof(float2));
-  step3_epilogue_reg<CTQ>(p, acc, pair, d0, T, twl, lane);
+  step3_epilogue_reg<CTQ, EPI>(p, acc, pair, d0, T, twl, lane);
 }
 
 __global__ void keys_init_kernel(unsigned long long* keys, size_t count) {
@@ -169,7 +169,9 @@ static hipError_t launch_step3_t(const Step3Args& a0, hipStream_t s) {
   const dim3 grid(static_cast<unsigned>(nwg));
   size_t lds = step3_lds_bytes(a.Qa, a.nwaves);
   const int nf4 = 32 * CTQ * 8, nthr = 64 * a.nwaves;
-  auto kern = (nf4 + nthr - 1) / nthr <= 2 ? step3_fp32<CTQ, MAXT, true> : step3_fp32<CTQ, MAXT, false>;
+  const bool pref = (nf4 + nthr - 1) / nthr <= 2;
+  auto kern = a.xhat ? (pref ? step3_fp32<CTQ, MAXT, true, kEpiStore> : step3_fp32<CTQ, MAXT, false, kEpiStore>)
+                     : (pref ? step3_fp32<CTQ, MAXT, true, kEpiRotate> : step3_fp32<CTQ, MAXT, false, kEpiRotate>);
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
   if (e != hipSuccess) return e;

@@ -196,7 +196,7 @@ __device__ __forceinline__ void split_first_chunk(const Step3Args& p, float* reg
     *reinterpret_cast<float4*>(region + (t >> 3) * 36 + (t & 7) * 4) = load_stream(zsp + t);
 }
 
-template <class T, int CTQ, int MAXT, bool PREF>
+template <class T, int CTQ, int MAXT, bool PREF, int EPI>
 __global__ void __launch_bounds__(MAXT) step3_split(Step3Args p) {
   extern __shared__ float smem[];
   constexpr int QH = 32 * CTQ;
@@ -217,7 +217,7 @@ __global__ void __launch_bounds__(MAXT) step3_split(Step3Args p) {
   __syncthreads();
   if (!active) return;
   float2* rows = reinterpret_cast<float2*>(region) + wave * (epilogue_lds_bytes_per_wave() / sizeof(float2));
-  step3_epilogue_reg<CTQ>(p, acc, pair, d0, rows, twl, lane);
+  step3_epilogue_reg<CTQ, EPI>(p, acc, pair, d0, rows, twl, lane);
 }
 
 // Persistent form (one workgroup per CU, looping over its shift blocks) where
@@ -303,7 +303,7 @@ static hipError_t launch_step3_split_t(const Step3Args& a0, hipStream_t s) {
   const bool pref = (nf4 + nthr - 1) / nthr <= 2;
   if constexpr (MAXT == 1024) {
     const size_t plds = bf16_persistent_lds(a.Qa, a.nwaves);
-    if (pref && plds <= 160 * 1024) {
+    if (pref && plds <= 160 * 1024 && !a.xhat) {
       auto kern = step3_split_p<T, CTQ, true>;
       hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                          hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(plds));
@@ -315,7 +315,10 @@ static hipError_t launch_step3_split_t(const Step3Args& a0, hipStream_t s) {
   }
   const dim3 grid(static_cast<unsigned>(nwg));
   size_t lds = step3_bf16_lds_bytes(a.Qa, a.nwaves);
-  auto kern = pref ? step3_split<T, CTQ, MAXT, true> : step3_split<T, CTQ, MAXT, false>;
+  // Xhat out (rotation upsampling): the plain form with the storing epilogue
+  auto kern = a.xhat ? (pref ? step3_split<T, CTQ, MAXT, true, kEpiStore> : step3_split<T, CTQ, MAXT, false, kEpiStore>)
+                     : (pref ? step3_split<T, CTQ, MAXT, true, kEpiRotate>
+                             : step3_split<T, CTQ, MAXT, false, kEpiRotate>);
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
   if (e != hipSuccess) return e;

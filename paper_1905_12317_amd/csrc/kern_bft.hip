@@ -13,9 +13,10 @@
 //      kern_step1.hip): the sum of eq. fbk3 with l_max = 0,
 //      Xhat(delta, q) = 2 pi sum_m w_m T_delta a(k_m; q) conj b(k_m; q),
 //      as the same MFMA GEMM over the templates, staged as Zhat would be.
-//   3. bft_rotate: each wave reads the Xhat of 16 shifts of a pair straight
-//      into the register layout of the Step 3 epilogue (rotation FFT of
-//      eq. 1dfft and the argmax) and runs it.
+//   3. xhat_rotate: each wave reads the Xhat of 16 shifts of a pair into the
+//      register layout of the Step 3 epilogue (rotation FFT of eq. 1dfft and
+//      the argmax) and runs it, U times over for U-fold rotation upsampling.
+//      FTK's Step 3 hands its Xhat to the same kernel when upsampling.
 #include "device_common.h"
 #include "kernels.h"
 #include "step3_epilogue.h"
@@ -27,6 +28,7 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 namespace {
 
+constexpr float kPiF = 3.14159265358979f;
 constexpr int kBftDB = 8;       // shifts per translate workgroup
 constexpr int kBftWaves = 16;   // waves per translate workgroup
 
@@ -95,25 +97,32 @@ __global__ void __launch_bounds__(64 * kBftWaves) bft_translate_kernel(BftTransl
   }
 }
 
-// One wave per (pair, 16 shifts).  The staging row of mode q holds
+// One wave per (pair, 16 shifts).  The Xhat row of mode q holds
 // [c][delta] (c = 0 real, 1 imaginary part; H_pad = the padded shift count),
 // so the wave's Xhat is 2 QH runs of 16 floats (64 bytes).  They are read
 // with 16-byte loads, four lanes per run, into LDS rows [c][q][16] (stride
 // kRotRow), then into the epilogue's register layout: lane (h, j), register
 // v = 4 g + r of tile ct holds mode 32 ct + j, shift d0 + 4 g + 2 h + r / 2,
 // part r % 2 (one LDS float2 read gives two neighbouring shifts of a part).
-// The epilogue's transpose rows reuse the same LDS once the registers hold
-// Xhat.
+// Without upsampling the epilogue's transpose rows reuse the same LDS once
+// the registers hold Xhat.  With U > 1 (UP) the rows stay, and pass u reads
+// them multiplied by e^{-i q phi_u}, phi_u = 2 pi u / (U Qa): the Qa-point
+// transform of that sequence is X at the rotations gamma_r + phi_u (the
+// zero-padded sum of the remark after eq. 1dfft, sampled U times finer).
+// The Nyquist mode (imaginary part of the q = 0 column) contributes
+// Xhat_N cos(Qa gamma / 2), i.e. Xhat_N (-1)^r cos(pi u / U) on pass u.
 constexpr int kRotRow = 18;  // floats per LDS row: 16 shifts + 2 (row starts spread over the banks)
 
-__host__ __device__ constexpr size_t rot_wave_floats(int QH) {
-  return static_cast<size_t>(2) * QH * kRotRow > epilogue_lds_bytes_per_wave() / sizeof(float)
-             ? static_cast<size_t>(2) * QH * kRotRow
-             : epilogue_lds_bytes_per_wave() / sizeof(float);
+__host__ __device__ constexpr size_t rot_rows_floats(int QH) { return static_cast<size_t>(2) * QH * kRotRow; }
+__host__ __device__ constexpr size_t rot_wave_floats(int QH, bool up) {
+  return up ? rot_rows_floats(QH) + epilogue_lds_bytes_per_wave() / sizeof(float)
+            : (rot_rows_floats(QH) > epilogue_lds_bytes_per_wave() / sizeof(float)
+                   ? rot_rows_floats(QH)
+                   : epilogue_lds_bytes_per_wave() / sizeof(float));
 }
 
-template <int CTQ>
-__global__ void __launch_bounds__(256) bft_rotate_kernel(Step3Args p) {
+template <int CTQ, bool UP>
+__global__ void __launch_bounds__(256) xhat_rotate_kernel(Step3Args p) {
   extern __shared__ float smem[];
   constexpr int QH = 32 * CTQ;
   constexpr int Qa = 2 * QH;
@@ -130,7 +139,7 @@ __global__ void __launch_bounds__(256) bft_rotate_kernel(Step3Args p) {
   const int d0 = static_cast<int>(unit - static_cast<size_t>(pair) * tiles) * 16;
   const int h = lane >> 5;
   const int j = lane & 31;
-  float* S = smem + 2 * Qa + wave * rot_wave_floats(QH);
+  float* S = smem + 2 * Qa + wave * rot_wave_floats(QH, UP);
   {
     // run s = 16 k + lane / 4 is (q, c) = (s / 2, s % 2); quarter lane % 4
     const float* zp = static_cast<const float*>(p.zs) + static_cast<size_t>(pair) * QH * 2 * p.H_pad + d0 +
@@ -155,18 +164,51 @@ __global__ void __launch_bounds__(256) bft_rotate_kernel(Step3Args p) {
   }
   wave_sync();
   f32x16 acc[CTQ];
+  if constexpr (!UP) {
 #pragma unroll
-  for (int ct = 0; ct < CTQ; ++ct)
+    for (int ct = 0; ct < CTQ; ++ct)
 #pragma unroll
-    for (int g = 0; g < 4; ++g)
+      for (int g = 0; g < 4; ++g)
 #pragma unroll
-      for (int c = 0; c < 2; ++c) {
-        const float2 x = *reinterpret_cast<const float2*>(S + (c * QH + 32 * ct + j) * kRotRow + 4 * g + 2 * h);
-        acc[ct][4 * g + c] = x.x;
-        acc[ct][4 * g + 2 + c] = x.y;
+        for (int c = 0; c < 2; ++c) {
+          const float2 x = *reinterpret_cast<const float2*>(S + (c * QH + 32 * ct + j) * kRotRow + 4 * g + 2 * h);
+          acc[ct][4 * g + c] = x.x;
+          acc[ct][4 * g + 2 + c] = x.y;
+        }
+    wave_sync();
+    step3_epilogue_reg<CTQ>(p, acc, pair, d0, reinterpret_cast<float2*>(S), twl, lane);
+  } else {
+    const int U = p.up;
+    const int Qr = U * Qa;
+    float2* T = reinterpret_cast<float2*>(S + rot_rows_floats(QH));
+    for (int u = 0; u < U; ++u) {
+      const float nyq = cosf(static_cast<float>(kPiF * u) / static_cast<float>(U));
+#pragma unroll
+      for (int ct = 0; ct < CTQ; ++ct) {
+        const int q = 32 * ct + j;
+        // e^{-i q phi_u} from the exact angle index (q u mod U Qa)
+        float sn, cn;
+        sincosf(2.f * kPiF * static_cast<float>((q * u) % Qr) / static_cast<float>(Qr), &sn, &cn);
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+          const float2 re = *reinterpret_cast<const float2*>(S + (32 * ct + j) * kRotRow + 4 * g + 2 * h);
+          const float2 im = *reinterpret_cast<const float2*>(S + (QH + 32 * ct + j) * kRotRow + 4 * g + 2 * h);
+          if (q == 0) {
+            acc[ct][4 * g + 0] = re.x;
+            acc[ct][4 * g + 1] = im.x * nyq;
+            acc[ct][4 * g + 2] = re.y;
+            acc[ct][4 * g + 3] = im.y * nyq;
+          } else {
+            acc[ct][4 * g + 0] = re.x * cn + im.x * sn;
+            acc[ct][4 * g + 1] = im.x * cn - re.x * sn;
+            acc[ct][4 * g + 2] = re.y * cn + im.y * sn;
+            acc[ct][4 * g + 3] = im.y * cn - re.y * sn;
+          }
+        }
       }
-  wave_sync();
-  step3_epilogue_reg<CTQ>(p, acc, pair, d0, reinterpret_cast<float2*>(S), twl, lane);
+      step3_epilogue_reg<CTQ, kEpiUpsample>(p, acc, pair, d0, T, twl, lane, U, u);
+    }
+  }
 }
 
 template <class K>
@@ -202,24 +244,25 @@ hipError_t launch_bft_translate(const BftTranslateArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
-size_t bft_rotate_lds_bytes(int Qa, int nwaves) {
-  return sizeof(float2) * static_cast<size_t>(Qa) + sizeof(float) * static_cast<size_t>(nwaves) * rot_wave_floats(Qa / 2);
+size_t xhat_rotate_lds_bytes(int Qa, int nwaves, int up) {
+  return sizeof(float2) * static_cast<size_t>(Qa) +
+         sizeof(float) * static_cast<size_t>(nwaves) * rot_wave_floats(Qa / 2, up > 1);
 }
 
-hipError_t launch_bft_rotate(const Step3Args& a, hipStream_t s) {
+hipError_t launch_xhat_rotate(const Step3Args& a, hipStream_t s) {
   if (a.pairs <= 0) return hipSuccess;
-  if (a.nwaves < 1 || a.nwaves > 4) return hipErrorInvalidValue;
+  if (a.nwaves < 1 || a.nwaves > 4 || a.up < 1) return hipErrorInvalidValue;
   const size_t units = static_cast<size_t>(a.pairs) * ((a.N + 15) / 16);
   const size_t nwg = (units + a.nwaves - 1) / a.nwaves;
   if (nwg > 0x7fffffffull) return hipErrorInvalidConfiguration;
-  const size_t lds = bft_rotate_lds_bytes(a.Qa, a.nwaves);
+  const size_t lds = xhat_rotate_lds_bytes(a.Qa, a.nwaves, a.up);
   hipError_t e;
-#define FTK_BR(ct)                                                          \
-  case ct: {                                                                 \
-    auto k = bft_rotate_kernel<ct>;                                          \
-    if ((e = set_lds(k, lds)) != hipSuccess) return e;                       \
-    hipLaunchKernelGGL(k, dim3(static_cast<unsigned>(nwg)), dim3(64 * a.nwaves), lds, s, a); \
-    break;                                                                   \
+#define FTK_BR(ct)                                                                                  \
+  case ct: {                                                                                         \
+    auto k = a.up > 1 ? xhat_rotate_kernel<ct, true> : xhat_rotate_kernel<ct, false>;                \
+    if ((e = set_lds(k, lds)) != hipSuccess) return e;                                               \
+    hipLaunchKernelGGL(k, dim3(static_cast<unsigned>(nwg)), dim3(64 * a.nwaves), lds, s, a);          \
+    break;                                                                                           \
   }
   switch (a.Qa / 64) {
     FTK_BR(1)

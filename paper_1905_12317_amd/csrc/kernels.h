@@ -68,6 +68,8 @@ struct Step3Args {
   unsigned long long* keys;  // [pairs]
   const float2* tw_qa;   // [Qa]
   const void* rot16;     // FP16 form with Qa <= 256: the rotation transform tables (rot16_table_bytes), or null
+  float* xhat;           // or: Xhat out [pairs][Qa/2][2][N_pad] instead of the rotation sum (upsampling)
+  int up;                // rotation upsampling factor of launch_xhat_rotate (1: none)
   int pairs, Qa, H_pad, N, N_pad;
   int nwaves;            // waves per workgroup; each wave owns 16 shifts
   int nblk;              // workgroups per pair (shift blocks); 1-D grid of pairs * nblk
@@ -147,8 +149,10 @@ hipError_t launch_bft_translate(const BftTranslateArgs& args, hipStream_t stream
 // Step 1 on the translated coefficients (Step1Args::ta set, H_pad = N_pad,
 // cz = [M] 2 pi w_m, zblk = 32, 64 or 128)
 hipError_t launch_step1_bft(const Step1Args& args, hipStream_t stream);
-// rotation FFT + argmax of Xhat read from the staging (Step3Args: zs, X,
-// keys, tw_qa, pairs, Qa, H_pad = N_pad of the staging, N); one wave per
-// 16 shifts of a pair, nwaves waves per workgroup
-size_t bft_rotate_lds_bytes(int Qa, int nwaves);
-hipError_t launch_bft_rotate(const Step3Args& args, hipStream_t stream);
+// rotation FFT + argmax of Xhat read from HBM (Step3Args: zs = Xhat rows
+// [pair][Qa/2][2][H_pad], X, xscale, keys, tw_qa, pairs, Qa, H_pad, N, up);
+// one wave per 16 shifts of a pair, nwaves (<= 4) waves per workgroup.
+// up = U > 1: U Qa rotations (X rows of U Qa values, pose index delta U Qa +
+// rotation), as U passes of the Qa-point transform on phase-shifted Xhat.
+size_t xhat_rotate_lds_bytes(int Qa, int nwaves, int up);
+hipError_t launch_xhat_rotate(const Step3Args& args, hipStream_t stream);

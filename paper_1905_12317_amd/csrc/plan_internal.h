@@ -70,12 +70,13 @@ struct Workspace {
   DevBuf tr_h, tr_g, coef_a, coef_b, stage, keys, tmpl, scales;
   DevBuf refine;     // lists and poses of the two-pass alignment
   DevBuf polar, ta;  // brute-force translations: ring samples, translated coefficients
+  DevBuf xhat;       // rotation upsampling: Xhat of a chunk of pairs
   size_t bytes() const {
     return tr_h.bytes + tr_g.bytes + coef_a.bytes + coef_b.bytes + stage.bytes + keys.bytes + tmpl.bytes +
-           scales.bytes + refine.bytes + polar.bytes + ta.bytes;
+           scales.bytes + refine.bytes + polar.bytes + ta.bytes + xhat.bytes;
   }
   void release() {
-    for (DevBuf* b : {&tr_h, &tr_g, &coef_a, &coef_b, &stage, &keys, &tmpl, &scales, &refine, &polar, &ta})
+    for (DevBuf* b : {&tr_h, &tr_g, &coef_a, &coef_b, &stage, &keys, &tmpl, &scales, &refine, &polar, &ta, &xhat})
       b->release();
   }
 };
@@ -84,6 +85,7 @@ struct Workspace {
 struct Needs {
   size_t tr_h = 0, tr_g = 0, coef_a = 0, coef_b = 0, stage = 0, keys = 0, tmpl = 0;
   size_t scales = 0;        // FP16 form: the per-call data scales
+  size_t xhat = 0;          // rotation upsampling: Xhat of a chunk
   int chunk_images = 0;     // images per Step 1 / Step 3 chunk
   int transform_chunk = 0;  // images per transform launch
 };
@@ -93,6 +95,7 @@ struct Needs {
 struct ftk_plan {
   ftkint::StageTimer timer;
   int n = 0, M = 0, Qa = 0, precision = 0;
+  int up = 1;  // rotation upsampling: U Qa rotations (remark after eq. 1dfft)
   bool weighted = false;  // operator SVD with a k-side weight (Section 4.5 remark)
   double W = 0, eps = 0, kmax = 0;
   ftkint::HostTables t;
@@ -147,6 +150,7 @@ struct AlignBufs {
   void* tmpl;
   float* scales;
   int chunk_images;
+  float* xhat;  // rotation upsampling (plan up > 1): Xhat of chunk_images images
 };
 // Steps 1-3 and the argmax on caller-provided buffers (ftk_api.hip); tm may
 // be null (no stage timing).
@@ -156,6 +160,11 @@ int align_run(ftk_plan* p, const void* img_coeffs, int nA, const void* tmpl_coef
 // 2 bytes each in the FP16 form, 4 otherwise (FP32, or hi + lo).
 inline size_t stage_bytes_per_pair(const ftk_plan* p) {
   return static_cast<size_t>(p->Qa / 2) * 2 * p->H_pad * (prec_code(p) == 2 ? 2 : 4);
+}
+// Xhat bytes of one pair when the plan upsamples the rotations (else 0):
+// Qa/2 rows of 2 N_pad floats.
+inline size_t xhat_bytes_per_pair(const ftk_plan* p) {
+  return p->up > 1 ? static_cast<size_t>(p->Qa / 2) * 2 * p->N_pad * sizeof(float) : 0;
 }
 // Power-of-two exponents of the split-fp16 form.  Its lo parts lose
 // precision where they fall below the smallest normal fp16 (2^-14), so every

@@ -93,13 +93,40 @@ __device__ __forceinline__ float ep_bperm(float v, int addr) {
 constexpr int kQuadXor1 = 0xB1;  // quad_perm [1, 0, 3, 2]
 constexpr int kQuadXor2 = 0x4E;  // quad_perm [2, 3, 0, 1]
 
-template <int CTQ, class Acc>
+// Modes of the epilogue (compile time, so the plain form keeps its registers):
+//   kEpiRotate:  the rotation sum and argmax as described above;
+//   kEpiStore:   no rotation sum; the wave stores its Xhat into p.xhat, rows
+//                [pair][q][c][delta] (c = 0 real, 1 imaginary part, N_pad
+//                shifts), for the upsampled rotation kernel;
+//   kEpiUpsample: pass u of U of the rotation upsampling: acc holds
+//                Xhat(q) e^{-i q 2 pi u / (U Qa)} and output r of this pass is
+//                rotation U r + u of the U Qa-point grid (X rows of U Qa
+//                values, pose index delta U Qa + U r + u).
+constexpr int kEpiRotate = 0, kEpiStore = 1, kEpiUpsample = 2;
+
+template <int CTQ, int MODE = kEpiRotate, class Acc>
 __device__ __forceinline__ void step3_epilogue_reg(const Step3Args& p, Acc (&acc)[CTQ], int pair, int d0, float2* T,
-                                                   const float2* __restrict__ tw, int lane) {
+                                                   const float2* __restrict__ tw, int lane, int Ur = 1, int ur = 0) {
   constexpr int QH = 32 * CTQ;
   constexpr int Qa = 2 * QH;
+  constexpr bool UP = MODE == kEpiUpsample;
   const int h = lane >> 5;
   const int j = lane & 31;
+  const int U = UP ? Ur : 1;
+  const int u = UP ? ur : 0;
+  if constexpr (MODE == kEpiStore) {
+    float* xb = p.xhat + static_cast<size_t>(pair) * QH * 2 * p.N_pad + d0 + 2 * h;
+#pragma unroll
+    for (int ct = 0; ct < CTQ; ++ct) {
+      float* row = xb + static_cast<size_t>(32 * ct + j) * 2 * p.N_pad;
+#pragma unroll
+      for (int g = 0; g < 4; ++g)
+#pragma unroll
+        for (int c = 0; c < 2; ++c)
+          *reinterpret_cast<float2*>(row + c * p.N_pad + 4 * g) = make_float2(acc[ct][4 * g + c], acc[ct][4 * g + 2 + c]);
+    }
+    return;
+  } else {
   const int src4 = ((h << 5) | ((32 - j) & 31)) << 2;  // byte address of the lane of column QH - k (j > 0)
   // W^{32 ct + j}, and the powers w^{j s1} (w = exp(-2 pi i / QH)), from the
   // table: the same for every shift of the lane
@@ -199,7 +226,8 @@ __device__ __forceinline__ void step3_epilogue_reg(const Step3Args& p, Acc (&acc
   // those rounds are dead before the FFT temporaries are needed.
   float bv = -__builtin_inff();
   uint32_t bi = 0xffffffffu;
-  float* Xp = p.X ? p.X + static_cast<size_t>(pair) * p.N * Qa : nullptr;
+  const int Qo = U * Qa;  // X row length and pose index stride
+  float* Xp = p.X ? p.X + static_cast<size_t>(pair) * p.N * Qo : nullptr;
   // scale of the stored X values (the FP16 form computes X / (s_a s_b s_y));
   // the argmax does not depend on it
   const float xs = (Xp && p.xscale) ? *p.xscale : 1.f;
@@ -275,13 +303,24 @@ __device__ __forceinline__ void step3_epilogue_reg(const Step3Args& p, Acc (&acc
 #pragma unroll
       for (int k = 15; k >= 0; --k) rk = (((k & 1) ? Y[k >> 1].y : Y[k >> 1].x) == rv) ? k : rk;
       const bool ok = valid && rk >= 0;
-      const uint32_t ridx = static_cast<uint32_t>(delta) * Qa + 2 * (s1 + CTQ * (8 * (a1 + 2 * a0) + (rk >> 1))) + (rk & 1);
+      const uint32_t ridx = static_cast<uint32_t>(delta) * Qo +
+                            U * (2 * (s1 + CTQ * (8 * (a1 + 2 * a0) + (rk >> 1))) + (rk & 1)) + u;
       ep_better(bv, bi, ok ? rv : -__builtin_inff(), ok ? ridx : 0xffffffffu);
       if (Xp && valid) {
-        float2* xr = reinterpret_cast<float2*>(Xp + static_cast<size_t>(delta) * Qa);
+        if (!UP) {
+          float2* xr = reinterpret_cast<float2*>(Xp + static_cast<size_t>(delta) * Qa);
 #pragma unroll
-        for (int sp = 0; sp < 8; ++sp)
-          xr[s1 + CTQ * (sp + 8 * (a1 + 2 * a0))] = make_float2(Y[sp].x * xs, Y[sp].y * xs);
+          for (int sp = 0; sp < 8; ++sp)
+            xr[s1 + CTQ * (sp + 8 * (a1 + 2 * a0))] = make_float2(Y[sp].x * xs, Y[sp].y * xs);
+        } else {
+          float* xr = Xp + static_cast<size_t>(delta) * Qo + u;
+#pragma unroll
+          for (int sp = 0; sp < 8; ++sp) {
+            const int t2 = 2 * (s1 + CTQ * (sp + 8 * (a1 + 2 * a0)));
+            xr[U * t2] = Y[sp].x * xs;
+            xr[U * (t2 + 1)] = Y[sp].y * xs;
+          }
+        }
       }
       __builtin_amdgcn_sched_barrier(0);
     }
@@ -294,6 +333,7 @@ __device__ __forceinline__ void step3_epilogue_reg(const Step3Args& p, Acc (&acc
     ep_better(bv, bi, ov, oi);
   }
   if (lane == 0 && bi != 0xffffffffu) atomicMax(p.keys + pair, pose_key(bv, bi));
+  }
 }
 
 }  // namespace ftkdev

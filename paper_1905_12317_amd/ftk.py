@@ -37,7 +37,7 @@ class PlanInfo(ctypes.Structure):
                 ("shift_radius_px", ctypes.c_double), ("eps", ctypes.c_double),
                 ("sigma_next", ctypes.c_double), ("kmax", ctypes.c_double),
                 ("coeff_bytes_per_image", ctypes.c_size_t), ("device_bytes", ctypes.c_size_t),
-                ("weighted", ctypes.c_int)]
+                ("weighted", ctypes.c_int), ("rotations", ctypes.c_int)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -73,7 +73,7 @@ POSE_DTYPE = np.dtype([("value", np.float32), ("shift", np.int32), ("rot", np.in
 
 #: every symbol include/ftk.h declares
 EXPORTS = ["ftk_plan_create", "ftk_plan_destroy", "ftk_plan_info", "ftk_set_shifts", "ftk_transform",
-           "ftk_align_coeffs", "ftk_align_coeffs_noalloc", "ftk_align", "ftk_bft_align", "ftk_plan_tables", "ftk_plan_create_weighted",
+           "ftk_align_coeffs", "ftk_align_coeffs_noalloc", "ftk_align", "ftk_bft_align", "ftk_plan_set_rotations", "ftk_plan_tables", "ftk_plan_create_weighted",
            "ftk_plan_tables_weighted", "ftk_plan_profile", "ftk_plan_stage_times",
            "ftk_plan_set_tuning", "ftk_plan_get_tuning", "ftk_batch_create", "ftk_batch_run", "ftk_batch_info",
            "ftk_batch_destroy", "ftk_strerror", "ftk_last_error_message",
@@ -123,6 +123,7 @@ def lib() -> ctypes.CDLL:
     L.ftk_align_coeffs_noalloc.argtypes = [vp, vp, i, vp, i, vp, vp, vp]
     L.ftk_align.argtypes = [vp, vp, i, vp, i, vp, vp, vp]
     L.ftk_bft_align.argtypes = [vp, vp, i, vp, i, vp, vp, vp]
+    L.ftk_plan_set_rotations.argtypes = [vp, i]
     L.ftk_plan_tables.argtypes = [i, i, d, d, vp, i, ctypes.POINTER(i), vp, vp, vp, vp, vp, vp,
                                   ctypes.POINTER(d)]
     L.ftk_plan_profile.argtypes = [vp, i]
@@ -247,6 +248,7 @@ class Plan:
         self._h = h
         self.n, self.M, self.Qa = n, K, Q
         self.N = 0
+        self.up = 1
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
@@ -286,6 +288,11 @@ class Plan:
         t = Tuning(step3_waves, step1_zblk, step1_wgs, stage_mib)
         _check(lib().ftk_plan_set_tuning(self._h, ctypes.byref(t)), "ftk_plan_set_tuning")
 
+    def set_rotations(self, upsample: int):
+        """ftk_plan_set_rotations: U * Qa rotations (rotation upsampling)."""
+        _check(lib().ftk_plan_set_rotations(self._h, int(upsample)), "ftk_plan_set_rotations")
+        self.up = int(upsample)
+
     def set_shifts(self, shifts_px):
         sh = np.ascontiguousarray(shifts_px, dtype=np.float64).reshape(-1, 2)
         _check(lib().ftk_set_shifts(self._h, sh.ctypes.data, sh.shape[0]), "ftk_set_shifts")
@@ -304,7 +311,7 @@ class Plan:
     def _outputs(self, nA, nB, want_X, device, X, best):
         import torch
         if want_X and X is None:
-            X = torch.empty((nA, nB, self.N, self.Qa), dtype=torch.float32, device=device)
+            X = torch.empty((nA, nB, self.N, self.Qa * self.up), dtype=torch.float32, device=device)
         if best is None:
             best = torch.empty((nA, nB, 3), dtype=torch.int32, device=device)
         return X, best
