@@ -89,11 +89,16 @@ def flops_per_pair(H, M, N, Qa):
 
 
 REFINE_K = 4  # templates per image re-aligned by the split form in the two-pass form
+# joint translation-CTF measurement: 300 kV, Cs 2.7 mm, 7 % amplitude contrast,
+# 2 A pixels, a 14000-16000 A defocus window searched at 5 values
+CTF_PARAMS = dict(wavelength_A=0.019687, cs_mm=2.7, amplitude_contrast=0.07, pixel_A=2.0,
+                  defocus_min_A=14000.0, defocus_max_A=16000.0)
+CTF_DEFOCI = [14000.0, 14500.0, 15000.0, 15500.0, 16000.0]
 UPSAMPLE = 5  # rotation upsampling factor of the upsampled measurement (5 x 256 = 1280 rotations)
 WEIGHTED_EPS = 5e-3  # eps of the weighted-SVD plan: the paper plan's accuracy at eps = 1e-3 (see main)
 
 
-def run_form(form, inputs, w, steps, warmup, shifts, eps=None, weight=None, up=1):
+def run_form(form, inputs, w, steps, warmup, shifts, eps=None, weight=None, up=1, ctf=None, defoci=None):
     """One form over the workload.  "fp16+bf16x3" is the two-pass form: the
     FP16 form over every pair, then the split form on each image's REFINE_K
     best FP16 templates (ftk_align_refined).  "bft": brute-force
@@ -105,8 +110,12 @@ def run_form(form, inputs, w, steps, warmup, shifts, eps=None, weight=None, up=1
     two = form == "fp16+bf16x3"
     bft = form == "bft"
     prec = "fp16" if two else ("fp32" if bft else form)
-    P = ftk.Plan(w["n"], w["M"], w["Qa"], w["R"], eps or w["eps"], precision=prec, weight=weight)
-    P.set_shifts(shifts)
+    P = ftk.Plan(w["n"], w["M"], w["Qa"], w["R"], eps or w["eps"], precision=prec, weight=weight, ctf=ctf)
+    if ctf is not None:
+        # poses: every shift at every defocus value
+        P.set_poses(np.repeat(shifts, len(defoci), axis=0), np.tile(np.asarray(defoci, float), len(shifts)))
+    else:
+        P.set_shifts(shifts)
     if up > 1:
         P.set_rotations(up)
     Pf = None
@@ -411,6 +420,7 @@ def main():
     ap.add_argument("--no-weighted", action="store_true", help="skip the weighted-SVD measurement")
     ap.add_argument("--no-bft", action="store_true", help="skip the brute-force-translation measurement")
     ap.add_argument("--no-upsample", action="store_true", help="skip the rotation-upsampling measurement")
+    ap.add_argument("--no-ctf", action="store_true", help="skip the joint translation-CTF measurement")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="only run a plain device-to-device copy of this many MiB (3 times) and exit; "
                          "used to scale the FETCH_SIZE / WRITE_SIZE counters")
@@ -568,6 +578,18 @@ def main():
         ups["rotations"] = UPSAMPLE * Qa
         ups["ftk_fp16x3_speedup_over_bft"] = ups["fp16x3"]["pairs_per_s"] / ups["bft"]["pairs_per_s"]
         out["config"]["upsampled_rotations"] = ups
+    if not args.no_ctf and "fp16" in results:
+        # joint translation-CTF factorisation (Section 7.1): shifts x 5 defocus
+        # values in one alignment, against 5 plain alignments (one per defocus,
+        # each the cost of the plain plan) as the alternative
+        rc = run_form("fp16", inputs, w, args.steps, args.warmup, shifts, ctf=CTF_PARAMS, defoci=CTF_DEFOCI)
+        log(f"[fp16 ctf] {rc['ms_per_step']:.2f} ms/step, {rc['pairs_per_s']:.4g} pairs/s, H={rc['info']['H']}")
+        out["config"]["ctf"] = {
+            "form": "fp16", "ctf": CTF_PARAMS, "defocus_A": CTF_DEFOCI, "poses": len(shifts) * len(CTF_DEFOCI),
+            "H": rc["info"]["H"], "H_plain": H, "pairs_per_s": rc["pairs_per_s"], "ms_per_step": rc["ms_per_step"],
+            "time_vs_one_plain_alignment_per_defocus": rc["ms_per_step"] / (len(CTF_DEFOCI) *
+                                                                            results["fp16"]["ms_per_step"]),
+            "stage_ms_per_step": {k: v[0] / args.steps for k, v in rc["stages"].items()}}
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(inputs, w, shifts)
     print(json.dumps(out), flush=True)

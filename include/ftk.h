@@ -100,7 +100,22 @@ typedef struct ftk_plan_info_t {
   size_t device_bytes;          /* device memory held by the plan now */
   int weighted;                 /* 1: operator SVD with a k-side weight */
   int rotations;                /* rotations per pose search: U Qa (ftk_plan_set_rotations) */
+  int ctf;                      /* 1: joint translation-CTF factorisation (ftk_plan_create_ctf) */
 } ftk_plan_info_t;
+
+/* Contrast transfer function of ftk_plan_create_ctf: the isotropic
+ * weak-phase model C(s; tau) = -(sqrt(1 - A^2) sin chi + A cos chi),
+ * chi = pi lambda tau s^2 - (pi/2) Cs lambda^3 s^4, s the spatial frequency
+ * in 1/Angstrom (s = 1 / (2 pixel) at k = Kmax), tau the defocus (Angstrom,
+ * underfocus positive).  No envelope, no astigmatism. */
+typedef struct ftk_ctf_t {
+  double wavelength_A;        /* electron wavelength, [0, 1] (0.019687 at 300 kV) */
+  double cs_mm;               /* spherical aberration, [0, 100] */
+  double amplitude_contrast;  /* A, [0, 1] */
+  double pixel_A;             /* pixel size, (0, 100] */
+  double defocus_min_A;       /* planned defocus range tmin < tmax, |tau| <= 1e6 */
+  double defocus_max_A;
+} ftk_ctf_t;
 
 /* Build a plan (host FP64 planning, then upload of the device tables on the
  * current HIP device).
@@ -228,6 +243,28 @@ int ftk_align(ftk_plan* plan, const float* images, int nA, const float* template
 int ftk_align_refined(ftk_plan* coarse, ftk_plan* fine, const void* img_coeffs, int nA, const void* tmpl_coeffs,
                       int nB, int k, ftk_pose* best, int32_t* best_t, ftk_pose* best_pose, void* stream);
 
+/* Joint translation and CTF factorisation (Section 7.1, other 2D kernels):
+ * a plan whose SVD terms factorise F(delta, k) C(|k|; tau) into
+ * Y_zeta(delta, tau) G_zeta(k), so that one alignment searches shifts,
+ * defocus values and rotations: X(delta, tau, gamma) = <R_gamma T_delta C_tau
+ * A, B> (equal to aligning A with the CTF-filtered template C_tau B).  Per
+ * angular mode l the SVD is that of J_l(x y) C(y; tau) from L2(y dy) on
+ * [0, 1] to L2(x dx dtau) on [0, pi W] x [tmin, tmax] (defocus measure of
+ * mass 1), kept above eps as in ftk_plan_create.  The kernels are those of
+ * every plan; only the tables (and H, which grows with the defocus range)
+ * differ.  Poses are set with ftk_set_poses (one defocus per shift);
+ * ftk_set_shifts and ftk_bft_align refuse such plans.  Other arguments and
+ * errors as ftk_plan_create (FTK_EINVAL for CTF parameters out of range). */
+int ftk_plan_create_ctf(ftk_plan** out, int n, int K, int Q, double W, double eps, int precision,
+                        const ftk_ctf_t* ctf);
+
+/* Poses (shift_i, defocus_i), i < N, of a plan with a CTF: shifts_px as in
+ * ftk_set_shifts, defocus_A [N] within the planned range (FTK_ERANGE
+ * otherwise).  The pose index plays the part of the shift index in X and in
+ * ftk_pose.shift.  On a plan without a CTF, defocus_A must be NULL and the
+ * call is ftk_set_shifts.  Errors as ftk_set_shifts. */
+int ftk_set_poses(ftk_plan* plan, const double* shifts_px, const double* defocus_A, int N);
+
 /* Rotation upsampling (the remark after eq. 1dfft: zero-padding the angular
  * sum samples more rotations at little cost).  With upsample = U > 1 the
  * alignments of this plan evaluate X on U Q rotations gamma_r = 2 pi r / (U Q),
@@ -286,6 +323,12 @@ int ftk_plan_tables(int n, int K, double W, double eps, const double* shifts_px,
 int ftk_plan_tables_weighted(int n, int K, double W, double eps, const double* alpha, const double* beta,
                              int nterms, const double* shifts_px, int N, int* H_out, int32_t* ell, double* sigma,
                              double* G, double* k, double* w, double* Y, double* sigma_next);
+
+/* ftk_plan_tables for a plan with a CTF: Y [N][H][2] for the poses
+ * (shifts_px [N][2], defocus_A [N]); other outputs as ftk_plan_tables. */
+int ftk_plan_tables_ctf(int n, int K, double W, double eps, const ftk_ctf_t* ctf, const double* shifts_px,
+                        const double* defocus_A, int N, int* H_out, int32_t* ell, double* sigma, double* G,
+                        double* k, double* w, double* Y, double* sigma_next);
 
 /* Stage timing.  While enabled, the plan records a pair of HIP events on the
  * caller's stream around every kernel launch it makes, tagged with a stage:

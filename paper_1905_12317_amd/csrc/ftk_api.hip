@@ -144,10 +144,11 @@ double bf16_value(uint16_t h) {
   return f;
 }
 
-int build_tables(int n, int M, double W, double eps, HostTables& t, const ftkplan::Weight& weight) {
+int build_tables(int n, int M, double W, double eps, HostTables& t, const ftkplan::Weight& weight,
+                 const ftkplan::Ctf& ctf) {
   const double kmax = 0.5 * kPi * n;
   ftkplan::radial_rule(M, kmax, t.k, t.w);
-  t.tr = ftkplan::truncate(kPi * W, eps, weight);
+  t.tr = ftkplan::truncate(kPi * W, eps, weight, ctf);
   t.L = t.tr.L;
   t.sigma_next = t.tr.sigma_next;
   t.H = static_cast<int>(t.tr.terms.size());
@@ -156,23 +157,29 @@ int build_tables(int n, int M, double W, double eps, HostTables& t, const ftkpla
     t.eta.push_back(term.eta);
     t.sigma.push_back(term.sigma);
   }
-  // G[zeta][m] = Sigma v(y_m) = sum_i sqrt(xw_i) J_l(x_i y_m) U[i][eta]
+  // G[zeta][m] = Sigma v(y_m) = sum_{i,t} sqrt(xw_i tw_t) J_l(x_i y_m) C(y_m; tau_t) U[(i, t)][eta]
+  // (one tau node and C = 1 without a CTF); every mode shares the nodes
   t.G.assign(static_cast<size_t>(t.H) * M, 0.0);
   const ftkplan::ModalSVD& s0 = t.tr.svds[0];
-  const int P = s0.P;
+  const int P = s0.P, Pt = s0.Pt, Py = s0.Py;
   std::vector<double> J(static_cast<size_t>(t.L + 1) * P);
-  std::vector<double> tmp(t.L + 1);
+  std::vector<double> tmp(t.L + 1), c(Pt, 1.0);
   for (int m = 0; m < M; ++m) {
     const double y = t.k[m] / kmax;
     for (int i = 0; i < P; ++i) {
       ftkplan::bessel_orders(t.L, s0.xn[i] * y, tmp.data());
       for (int l = 0; l <= t.L; ++l) J[static_cast<size_t>(l) * P + i] = tmp[l];
     }
+    if (s0.ctf.on)
+      for (int q = 0; q < Pt; ++q) c[q] = s0.ctf(y, s0.tn[q]) * std::sqrt(s0.tw[q]);
     for (int z = 0; z < t.H; ++z) {
       const int la = std::abs(t.ell[z]);
       const ftkplan::ModalSVD& s = t.tr.svds[la];
       double acc = 0.0;
-      for (int i = 0; i < P; ++i) acc += std::sqrt(s.xw[i]) * J[static_cast<size_t>(la) * P + i] * s.U[i * P + t.eta[z]];
+      for (int i = 0; i < P; ++i)
+        for (int q = 0; q < Pt; ++q)
+          acc += std::sqrt(s.xw[i]) * c[q] * J[static_cast<size_t>(la) * P + i] *
+                 s.U[static_cast<size_t>(i * Pt + q) * Py + t.eta[z]];
       if (t.ell[z] < 0 && (la & 1)) acc = -acc;
       t.G[static_cast<size_t>(z) * M + m] = acc;
     }
@@ -180,28 +187,40 @@ int build_tables(int n, int M, double W, double eps, HostTables& t, const ftkpla
   return FTK_OK;
 }
 
-// Y[delta][zeta] = u_zeta(pi |d|) exp(-i l (omega + pi/2)), d in pixels.
-int build_Y(const HostTables& t, const double* shifts, int N, double W, std::vector<std::complex<double>>& Y) {
+// Y[delta][zeta] = u_zeta(pi |d|, tau) exp(-i l (omega + pi/2)), d in
+// pixels, tau the pose's defocus (defocus NULL: plans without a CTF).
+int build_Y(const HostTables& t, const double* shifts, const double* defocus, int N, double W,
+            std::vector<std::complex<double>>& Y) {
   const ftkplan::ModalSVD& s0 = t.tr.svds[0];
-  const int P = s0.P;
+  const int Py = s0.Py;
+  if (s0.ctf.on && !defocus) return fail(FTK_ESTATE, "ftk_set_poses: a plan with a CTF needs a defocus per pose");
+  if (!s0.ctf.on && defocus) return fail(FTK_EINVAL, "ftk_set_poses: defocus given to a plan without a CTF");
   Y.assign(static_cast<size_t>(N) * t.H, 0.0);
-  std::vector<double> J(static_cast<size_t>(t.L + 1) * P), tmp(t.L + 1);
+  std::vector<double> J(static_cast<size_t>(t.L + 1) * Py), tmp(t.L + 1), cy(Py, 1.0);
   for (int d = 0; d < N; ++d) {
     const double dx = shifts[2 * d], dy = shifts[2 * d + 1];
     if (!std::isfinite(dx) || !std::isfinite(dy)) return fail(FTK_EINVAL, "ftk_set_shifts: non-finite shift");
     const double rad = std::hypot(dx, dy);
     if (rad > W * (1.0 + 1e-9)) return fail(FTK_ERANGE, "ftk_set_shifts: shift outside the planned disk");
+    if (defocus) {
+      const double tau = defocus[d];
+      const double span = s0.ctf.tmax - s0.ctf.tmin;
+      if (!std::isfinite(tau) || tau < s0.ctf.tmin - 1e-9 * span || tau > s0.ctf.tmax + 1e-9 * span)
+        return fail(FTK_ERANGE, "ftk_set_poses: defocus outside the planned range");
+      for (int j = 0; j < Py; ++j) cy[j] = s0.ctf(s0.yn[j], tau);
+    }
     const double om = std::atan2(dy, dx);
     const double x = kPi * rad;
-    for (int j = 0; j < P; ++j) {
+    for (int j = 0; j < Py; ++j) {
       ftkplan::bessel_orders(t.L, x * s0.yn[j], tmp.data());
-      for (int l = 0; l <= t.L; ++l) J[static_cast<size_t>(l) * P + j] = tmp[l];
+      for (int l = 0; l <= t.L; ++l) J[static_cast<size_t>(l) * Py + j] = tmp[l];
     }
     for (int z = 0; z < t.H; ++z) {
       const int la = std::abs(t.ell[z]);
       const ftkplan::ModalSVD& s = t.tr.svds[la];
       double acc = 0.0;
-      for (int j = 0; j < P; ++j) acc += std::sqrt(s.yw[j]) * J[static_cast<size_t>(la) * P + j] * s.V[j * P + t.eta[z]];
+      for (int j = 0; j < Py; ++j)
+        acc += std::sqrt(s.yw[j]) * J[static_cast<size_t>(la) * Py + j] * cy[j] * s.V[static_cast<size_t>(j) * Py + t.eta[z]];
       const double u = acc / s.sigma[t.eta[z]];
       const double ph = -t.ell[z] * (om + 0.5 * kPi);
       Y[static_cast<size_t>(d) * t.H + z] = std::complex<double>(u * std::cos(ph), u * std::sin(ph));
@@ -448,15 +467,25 @@ const char* ftk_strerror(int status) {
 
 const char* ftk_last_error_message(void) { return g_last_error.c_str(); }
 
-int ftk_plan_tables_weighted(int n, int K, double W, double eps, const double* alpha, const double* beta,
-                             int nterms, const double* shifts_px, int N, int* H_out, int32_t* ell, double* sigma,
-                             double* G, double* k, double* w, double* Y, double* sigma_next) {
+}  // extern "C"
+
+namespace {
+
+ftkplan::Ctf ctf_of(const ftk_ctf_t* c) {
+  if (!c) return ftkplan::Ctf();
+  return ftkplan::make_ctf(c->wavelength_A, c->cs_mm, c->amplitude_contrast, c->pixel_A, c->defocus_min_A,
+                           c->defocus_max_A);
+}
+
+int plan_tables_impl(int n, int K, double W, double eps, const double* alpha, const double* beta, int nterms,
+                     const ftk_ctf_t* ctf, const double* shifts_px, const double* defocus, int N, int* H_out,
+                     int32_t* ell, double* sigma, double* G, double* k, double* w, double* Y, double* sigma_next) {
   if (n < 4 || K < 1 || K > 512 || !(W > 0) || !(eps > 0) || !(eps < 1) || N < 0 || (N > 0 && !shifts_px) ||
-      nterms < 0 || nterms > 4096)
+      nterms < 0 || nterms > 4096 || (ctf && nterms > 0))
     return fail(FTK_EINVAL, "ftk_plan_tables: invalid argument");
   try {
     HostTables t;
-    build_tables(n, K, W, eps, t, ftkplan::make_weight(alpha, beta, nterms));
+    build_tables(n, K, W, eps, t, ftkplan::make_weight(alpha, beta, nterms), ctf_of(ctf));
     if (H_out) *H_out = t.H;
     if (sigma_next) *sigma_next = t.sigma_next;
     for (int z = 0; z < t.H; ++z) {
@@ -468,7 +497,7 @@ int ftk_plan_tables_weighted(int n, int K, double W, double eps, const double* a
     if (w) std::memcpy(w, t.w.data(), K * sizeof(double));
     if (Y && N > 0) {
       std::vector<std::complex<double>> Yc;
-      int rc = build_Y(t, shifts_px, N, W, Yc);
+      int rc = build_Y(t, shifts_px, defocus, N, W, Yc);
       if (rc != FTK_OK) return rc;
       std::memcpy(Y, Yc.data(), Yc.size() * sizeof(std::complex<double>));
     }
@@ -480,24 +509,15 @@ int ftk_plan_tables_weighted(int n, int K, double W, double eps, const double* a
   return FTK_OK;
 }
 
-int ftk_plan_tables(int n, int K, double W, double eps, const double* shifts_px, int N, int* H_out, int32_t* ell,
-                    double* sigma, double* G, double* k, double* w, double* Y, double* sigma_next) {
-  return ftk_plan_tables_weighted(n, K, W, eps, nullptr, nullptr, 0, shifts_px, N, H_out, ell, sigma, G, k, w, Y,
-                                  sigma_next);
-}
-
-int ftk_plan_create(ftk_plan** out, int n, int K, int Q, double W, double eps, int precision) {
-  return ftk_plan_create_weighted(out, n, K, Q, W, eps, precision, nullptr, nullptr, 0);
-}
-
-int ftk_plan_create_weighted(ftk_plan** out, int n, int K, int Q, double W, double eps, int precision,
-                             const double* alpha, const double* beta, int nterms) {
+int plan_create_impl(ftk_plan** out, int n, int K, int Q, double W, double eps, int precision, const double* alpha,
+                     const double* beta, int nterms, const ftk_ctf_t* ctf) {
   if (!out) return fail(FTK_EINVAL, "ftk_plan_create: out is NULL");
   *out = nullptr;
   int rc = check_plan_args(n, K, Q, W, eps, precision);
   if (rc != FTK_OK) return rc;
   if (nterms < 0 || nterms > 4096 || (nterms > 0 && (!alpha || !beta)))
     return fail(FTK_EINVAL, "ftk_plan_create_weighted: nterms must be in [0, 4096] with alpha and beta given");
+  if (ctf && nterms > 0) return fail(FTK_EINVAL, "ftk_plan_create: a k-side weight and a CTF together");
   ftk_plan* p = nullptr;
   try {
     p = new ftk_plan();
@@ -510,7 +530,8 @@ int ftk_plan_create_weighted(ftk_plan** out, int n, int K, int Q, double W, doub
     p->kmax = 0.5 * kPi * n;
     p->tune = default_tuning(precision);
     p->weighted = nterms > 0;
-    build_tables(n, K, W, eps, p->t, ftkplan::make_weight(alpha, beta, nterms));
+    p->has_ctf = ctf != nullptr;
+    build_tables(n, K, W, eps, p->t, ftkplan::make_weight(alpha, beta, nterms), ctf_of(ctf));
     p->H_pad = round_up(std::max(p->t.H, 1), 64);
     p->sk = ftkplan::spread_kernel(n, kNufftWidth);
   } catch (const std::bad_alloc&) {
@@ -528,6 +549,49 @@ int ftk_plan_create_weighted(ftk_plan** out, int n, int K, int Q, double W, doub
   }
   *out = p;
   return FTK_OK;
+}
+
+int set_poses_impl(ftk_plan* p, const double* shifts_px, const double* defocus, int N);
+
+}  // namespace
+
+extern "C" {
+
+int ftk_plan_tables_weighted(int n, int K, double W, double eps, const double* alpha, const double* beta,
+                             int nterms, const double* shifts_px, int N, int* H_out, int32_t* ell, double* sigma,
+                             double* G, double* k, double* w, double* Y, double* sigma_next) {
+  return plan_tables_impl(n, K, W, eps, alpha, beta, nterms, nullptr, shifts_px, nullptr, N, H_out, ell, sigma, G,
+                          k, w, Y, sigma_next);
+}
+
+int ftk_plan_tables_ctf(int n, int K, double W, double eps, const ftk_ctf_t* ctf, const double* shifts_px,
+                        const double* defocus_A, int N, int* H_out, int32_t* ell, double* sigma, double* G, double* k,
+                        double* w, double* Y, double* sigma_next) {
+  if (!ctf) return fail(FTK_EINVAL, "ftk_plan_tables_ctf: NULL ctf");
+  if (N > 0 && !defocus_A) return fail(FTK_EINVAL, "ftk_plan_tables_ctf: NULL defocus");
+  return plan_tables_impl(n, K, W, eps, nullptr, nullptr, 0, ctf, shifts_px, defocus_A, N, H_out, ell, sigma, G, k,
+                          w, Y, sigma_next);
+}
+
+int ftk_plan_tables(int n, int K, double W, double eps, const double* shifts_px, int N, int* H_out, int32_t* ell,
+                    double* sigma, double* G, double* k, double* w, double* Y, double* sigma_next) {
+  return ftk_plan_tables_weighted(n, K, W, eps, nullptr, nullptr, 0, shifts_px, N, H_out, ell, sigma, G, k, w, Y,
+                                  sigma_next);
+}
+
+int ftk_plan_create(ftk_plan** out, int n, int K, int Q, double W, double eps, int precision) {
+  return ftk_plan_create_weighted(out, n, K, Q, W, eps, precision, nullptr, nullptr, 0);
+}
+
+int ftk_plan_create_weighted(ftk_plan** out, int n, int K, int Q, double W, double eps, int precision,
+                             const double* alpha, const double* beta, int nterms) {
+  return plan_create_impl(out, n, K, Q, W, eps, precision, alpha, beta, nterms, nullptr);
+}
+
+int ftk_plan_create_ctf(ftk_plan** out, int n, int K, int Q, double W, double eps, int precision,
+                        const ftk_ctf_t* ctf) {
+  if (!ctf) return fail(FTK_EINVAL, "ftk_plan_create_ctf: NULL ctf");
+  return plan_create_impl(out, n, K, Q, W, eps, precision, nullptr, nullptr, 0, ctf);
 }
 
 void ftk_plan_destroy(ftk_plan* p) {
@@ -556,6 +620,7 @@ int ftk_plan_info(const ftk_plan* p, ftk_plan_info_t* o) {
   o->device_bytes = p->device_bytes();
   o->weighted = p->weighted ? 1 : 0;
   o->rotations = p->Qa * p->up;
+  o->ctf = p->has_ctf ? 1 : 0;
   return FTK_OK;
 }
 
@@ -568,10 +633,27 @@ int ftk_plan_set_rotations(ftk_plan* p, int upsample) {
 
 int ftk_set_shifts(ftk_plan* p, const double* shifts_px, int N) {
   if (!p || !shifts_px) return fail(FTK_EINVAL, "ftk_set_shifts: NULL argument");
+  if (p->has_ctf) return fail(FTK_ESTATE, "ftk_set_shifts: the plan has a CTF; use ftk_set_poses");
+  return set_poses_impl(p, shifts_px, nullptr, N);
+}
+
+int ftk_set_poses(ftk_plan* p, const double* shifts_px, const double* defocus_A, int N) {
+  if (!p || !shifts_px) return fail(FTK_EINVAL, "ftk_set_poses: NULL argument");
+  if (p->has_ctf != (defocus_A != nullptr))
+    return fail(FTK_EINVAL, p->has_ctf ? "ftk_set_poses: a plan with a CTF needs a defocus per pose"
+                           : "ftk_set_poses: defocus given to a plan without a CTF");
+  return set_poses_impl(p, shifts_px, defocus_A, N);
+}
+
+}  // extern "C"
+
+namespace {
+
+int set_poses_impl(ftk_plan* p, const double* shifts_px, const double* defocus, int N) {
   if (N < 1 || N > 65536) return fail(FTK_EINVAL, "ftk_set_shifts: N must be in [1, 65536]");
   std::vector<std::complex<double>> Y;
   try {
-    int rc = build_Y(p->t, shifts_px, N, p->W, Y);
+    int rc = build_Y(p->t, shifts_px, defocus, N, p->W, Y);
     if (rc != FTK_OK) return rc;
   } catch (const std::bad_alloc&) {
     return fail(FTK_ENOMEM, "ftk_set_shifts: host allocation failed");
@@ -669,6 +751,10 @@ int ftk_set_shifts(ftk_plan* p, const double* shifts_px, int N) {
   p->N_pad = Np;
   return FTK_OK;
 }
+
+}  // namespace
+
+extern "C" {
 
 int ftk_transform(ftk_plan* p, const float* imgs, int cnt, void* coeffs, void* stream) {
   if (!p) return fail(FTK_EINVAL, "ftk_transform: NULL plan");

@@ -46,6 +46,7 @@ int ftk_bft_align(ftk_plan* p, const float* images, int nA, const float* templat
   if (!p) return fail(FTK_EINVAL, "ftk_bft_align: NULL plan");
   if (nA < 0 || nB < 0) return fail(FTK_EINVAL, "ftk_bft_align: negative count");
   if (p->N <= 0) return fail(FTK_ESTATE, "ftk_bft_align: call ftk_set_shifts first");
+  if (p->has_ctf) return fail(FTK_EUNSUPPORTED, "ftk_bft_align: plans with a CTF are not supported");
   if (nA == 0 || nB == 0) return FTK_OK;
   if (!X && !best) return fail(FTK_EINVAL, "ftk_bft_align: X and best are both NULL");
   if (!images || !templates) return fail(FTK_EINVAL, "ftk_bft_align: NULL images");

@@ -97,6 +97,7 @@ struct ftk_plan {
   int n = 0, M = 0, Qa = 0, precision = 0;
   int up = 1;  // rotation upsampling: U Qa rotations (remark after eq. 1dfft)
   bool weighted = false;  // operator SVD with a k-side weight (Section 4.5 remark)
+  bool has_ctf = false;   // joint translation-CTF factorisation (Section 7.1); poses carry a defocus
   double W = 0, eps = 0, kmax = 0;
   ftkint::HostTables t;
   int H_pad = 0, N = 0, N_pad = 0;

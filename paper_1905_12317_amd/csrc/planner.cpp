@@ -5,6 +5,8 @@
 #include <cmath>
 #include <numeric>
 #include <stdexcept>
+#include <string>
+#include <thread>
 
 namespace ftkplan {
 
@@ -226,22 +228,120 @@ void jacobi_svd(int m, int n, std::vector<double> A, std::vector<double>& sigma,
   }
 }
 
+void qr_jacobi_svd(int m, int n, const std::vector<double>& A, std::vector<double>& sigma, std::vector<double>& U,
+                   std::vector<double>& V) {
+  // column-major copy; Householder vectors kept below the diagonal
+  std::vector<double> Cm(static_cast<size_t>(m) * n);
+  for (int i = 0; i < m; ++i)
+    for (int j = 0; j < n; ++j) Cm[static_cast<size_t>(j) * m + i] = A[static_cast<size_t>(i) * n + j];
+  std::vector<double> beta(n, 0.0), diag(n, 0.0);
+  for (int k = 0; k < n; ++k) {
+    double* ck = &Cm[static_cast<size_t>(k) * m];
+    double nrm2 = 0.0;
+    for (int i = k; i < m; ++i) nrm2 += ck[i] * ck[i];
+    const double nrm = std::sqrt(nrm2);
+    if (nrm == 0.0) {
+      diag[k] = 0.0;
+      continue;
+    }
+    const double alpha = ck[k] > 0 ? -nrm : nrm;
+    ck[k] -= alpha;  // v = x - alpha e_k, stored in place
+    double vv = 0.0;
+    for (int i = k; i < m; ++i) vv += ck[i] * ck[i];
+    beta[k] = vv > 0.0 ? 2.0 / vv : 0.0;
+    for (int j = k + 1; j < n; ++j) {
+      double* cj = &Cm[static_cast<size_t>(j) * m];
+      double d = 0.0;
+      for (int i = k; i < m; ++i) d += ck[i] * cj[i];
+      d *= beta[k];
+      for (int i = k; i < m; ++i) cj[i] -= d * ck[i];
+    }
+    diag[k] = alpha;
+  }
+  std::vector<double> R(static_cast<size_t>(n) * n, 0.0);
+  for (int i = 0; i < n; ++i) {
+    R[static_cast<size_t>(i) * n + i] = diag[i];
+    for (int j = i + 1; j < n; ++j) R[static_cast<size_t>(i) * n + j] = Cm[static_cast<size_t>(j) * m + i];
+  }
+  std::vector<double> UR;
+  jacobi_svd(n, n, std::move(R), sigma, UR, V);
+  // U = H_0 ... H_{n-1} [U_R; 0], column by column
+  U.assign(static_cast<size_t>(m) * n, 0.0);
+  std::vector<double> w(m);
+  for (int c = 0; c < n; ++c) {
+    std::fill(w.begin(), w.end(), 0.0);
+    for (int i = 0; i < n; ++i) w[i] = UR[static_cast<size_t>(i) * n + c];
+    for (int k = n - 1; k >= 0; --k) {
+      if (beta[k] == 0.0) continue;
+      const double* vk = &Cm[static_cast<size_t>(k) * m];
+      double d = 0.0;
+      for (int i = k; i < m; ++i) d += vk[i] * w[i];
+      d *= beta[k];
+      for (int i = k; i < m; ++i) w[i] -= d * vk[i];
+    }
+    for (int i = 0; i < m; ++i) U[static_cast<size_t>(i) * n + c] = w[i];
+  }
+}
+
+double Ctf::chi(double y, double tau) const {
+  const double s = y / (2.0 * pixel);
+  const double s2 = s * s;
+  return kPi * lambda * tau * s2 - 0.5 * kPi * cs * lambda * lambda * lambda * s2 * s2;
+}
+
+double Ctf::operator()(double y, double tau) const {
+  if (!on) return 1.0;
+  const double c = chi(y, tau);
+  return -(std::sqrt(1.0 - amp * amp) * std::sin(c) + amp * std::cos(c));
+}
+
+Ctf make_ctf(double wavelength_A, double cs_mm, double amplitude_contrast, double pixel_A, double tmin_A,
+             double tmax_A) {
+  for (double v : {wavelength_A, cs_mm, amplitude_contrast, pixel_A, tmin_A, tmax_A})
+    if (!std::isfinite(v)) throw std::invalid_argument("ctf: non-finite parameter");
+  if (wavelength_A < 0.0 || wavelength_A > 1.0) throw std::invalid_argument("ctf: wavelength must be in [0, 1] A");
+  if (cs_mm < 0.0 || cs_mm > 100.0) throw std::invalid_argument("ctf: Cs must be in [0, 100] mm");
+  if (amplitude_contrast < 0.0 || amplitude_contrast > 1.0)
+    throw std::invalid_argument("ctf: amplitude contrast must be in [0, 1]");
+  if (!(pixel_A > 0.0) || pixel_A > 100.0) throw std::invalid_argument("ctf: pixel size must be in (0, 100] A");
+  if (!(tmax_A > tmin_A) || std::fabs(tmin_A) > 1e6 || std::fabs(tmax_A) > 1e6)
+    throw std::invalid_argument("ctf: defocus range must satisfy tmin < tmax, |tau| <= 1e6 A");
+  Ctf c;
+  c.on = true;
+  c.lambda = wavelength_A;
+  c.cs = cs_mm * 1e7;
+  c.amp = amplitude_contrast;
+  c.pixel = pixel_A;
+  c.tmin = tmin_A;
+  c.tmax = tmax_A;
+  return c;
+}
+
+double ModalSVD::kernel(double x, double y, double tau) const {
+  std::vector<double> J(ell + 1);
+  bessel_orders(ell, x * y, J.data());
+  return J[ell] * ctf(y, tau);
+}
+
 double ModalSVD::sigma_v(int eta, double y) const {
   std::vector<double> J(ell + 1);
+  std::vector<double> c(Pt, 1.0);
+  if (ctf.on)
+    for (int t = 0; t < Pt; ++t) c[t] = ctf(y, tn[t]) * std::sqrt(tw[t]);
   double s = 0.0;
   for (int i = 0; i < P; ++i) {
     bessel_orders(ell, xn[i] * y, J.data());
-    s += std::sqrt(xw[i]) * J[ell] * U[i * P + eta];
+    for (int t = 0; t < Pt; ++t) s += std::sqrt(xw[i]) * c[t] * J[ell] * U[static_cast<size_t>(i * Pt + t) * Py + eta];
   }
   return s;
 }
 
-double ModalSVD::u(int eta, double x) const {
+double ModalSVD::u(int eta, double x, double tau) const {
   std::vector<double> J(ell + 1);
   double s = 0.0;
-  for (int j = 0; j < P; ++j) {
+  for (int j = 0; j < Py; ++j) {
     bessel_orders(ell, x * yn[j], J.data());
-    s += std::sqrt(yw[j]) * J[ell] * V[j * P + eta];
+    s += std::sqrt(yw[j]) * J[ell] * ctf(yn[j], tau) * V[static_cast<size_t>(j) * Py + eta];
   }
   return s / sigma[eta];
 }
@@ -279,6 +379,7 @@ ModalSVD modal_svd(int ell, double X, const Weight& weight) {
   r.ell = ell;
   r.X = X;
   r.P = static_cast<int>(std::ceil(X)) + 32;
+  r.Py = r.P;
   const int P = r.P;
   radial_rule(P, X, r.xn, r.xw);
   radial_rule(P, 1.0, r.yn, r.yw);
@@ -295,20 +396,82 @@ ModalSVD modal_svd(int ell, double X, const Weight& weight) {
   return r;
 }
 
-Truncation truncate(double X, double eps, const Weight& weight) {
+ModalSVD ctf_modal_svd(int ell, double X, const Ctf& ctf) {
+  if (ell < 0) throw std::invalid_argument("ctf_modal_svd: ell >= 0 expected");
+  ModalSVD r;
+  r.ell = ell;
+  r.X = X;
+  r.ctf = ctf;
+  // x nodes as the translation SVD; tau nodes for the phase range of chi at
+  // Nyquist over the defocus range; y nodes for the oscillation of C in y
+  double chimax = 0.0;
+  for (int i = 0; i <= 256; ++i)
+    for (double t : {ctf.tmin, ctf.tmax}) chimax = std::max(chimax, std::fabs(ctf.chi(i / 256.0, t)));
+  const double dchi = kPi * ctf.lambda * (ctf.tmax - ctf.tmin) / (4.0 * ctf.pixel * ctf.pixel);
+  r.P = static_cast<int>(std::ceil(X)) + 32;
+  r.Pt = static_cast<int>(std::ceil(dchi)) + 12;
+  r.Py = r.P + static_cast<int>(std::ceil(2.0 * chimax)) + 24;
+  const int P = r.P, Pt = r.Pt, Py = r.Py;
+  radial_rule(P, X, r.xn, r.xw);
+  radial_rule(Py, 1.0, r.yn, r.yw);
+  legendre_rule01(Pt, r.tn, r.tw);  // weights of mass 1
+  for (int t = 0; t < Pt; ++t) r.tn[t] = ctf.tmin + r.tn[t] * (ctf.tmax - ctf.tmin);
+  if (P * Pt < Py) throw std::invalid_argument("ctf_modal_svd: fewer shift-side than k-side nodes");
+  std::vector<double> C(static_cast<size_t>(Pt) * Py);
+  for (int t = 0; t < Pt; ++t)
+    for (int j = 0; j < Py; ++j) C[static_cast<size_t>(t) * Py + j] = ctf(r.yn[j], r.tn[t]);
+  std::vector<double> A(static_cast<size_t>(P) * Pt * Py);
+  std::vector<double> J(ell + 1);
+  for (int i = 0; i < P; ++i)
+    for (int j = 0; j < Py; ++j) {
+      bessel_orders(ell, r.xn[i] * r.yn[j], J.data());
+      for (int t = 0; t < Pt; ++t)
+        A[static_cast<size_t>(i * Pt + t) * Py + j] =
+            std::sqrt(r.xw[i] * r.tw[t]) * J[ell] * C[static_cast<size_t>(t) * Py + j] * std::sqrt(r.yw[j]);
+    }
+  qr_jacobi_svd(P * Pt, Py, A, r.sigma, r.U, r.V);
+  return r;
+}
+
+Truncation truncate(double X, double eps, const Weight& weight, const Ctf& ctf) {
   Truncation tr;
   std::vector<int> keep_count;
-  for (int ell = 0; ell < 4096; ++ell) {
-    ModalSVD s = modal_svd(ell, X, weight);
-    if (s.sigma[0] <= eps) {
-      tr.sigma_next = std::max(tr.sigma_next, s.sigma[0]);
-      break;
+  // modes in batches, one thread each (the CTF kernel's SVDs are the costly ones)
+  const int batch = ctf.on ? std::max(1u, std::min(16u, std::thread::hardware_concurrency())) : 1;
+  bool done = false;
+  for (int ell0 = 0; ell0 < 4096 && !done; ell0 += batch) {
+    std::vector<ModalSVD> got(batch);
+    if (batch == 1) {
+      got[0] = modal_svd(ell0, X, weight);
+    } else {
+      std::vector<std::thread> th;
+      std::vector<std::string> err(batch);
+      for (int b = 0; b < batch; ++b)
+        th.emplace_back([&, b] {
+          try {
+            got[b] = ctf_modal_svd(ell0 + b, X, ctf);
+          } catch (const std::exception& ex) {
+            err[b] = ex.what();
+          }
+        });
+      for (auto& t : th) t.join();
+      for (const auto& e : err)
+        if (!e.empty()) throw std::invalid_argument(e);
     }
-    int h = 0;
-    while (h < s.P && s.sigma[h] > eps) ++h;
-    if (h < s.P) tr.sigma_next = std::max(tr.sigma_next, s.sigma[h]);
-    keep_count.push_back(h);
-    tr.svds.push_back(std::move(s));
+    for (int b = 0; b < batch; ++b) {
+      ModalSVD& s = got[b];
+      if (s.sigma[0] <= eps) {
+        tr.sigma_next = std::max(tr.sigma_next, s.sigma[0]);
+        done = true;
+        break;
+      }
+      int h = 0;
+      const int ns = static_cast<int>(s.sigma.size());
+      while (h < ns && s.sigma[h] > eps) ++h;
+      if (h < ns) tr.sigma_next = std::max(tr.sigma_next, s.sigma[h]);
+      keep_count.push_back(h);
+      tr.svds.push_back(std::move(s));
+    }
   }
   tr.L = static_cast<int>(keep_count.size()) - 1;
   for (int ell = -tr.L; ell <= tr.L; ++ell) {

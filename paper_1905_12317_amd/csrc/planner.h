@@ -34,22 +34,45 @@ struct Weight {
 // Checks the terms and sets c; throws std::invalid_argument on bad terms.
 Weight make_weight(const double* alpha, const double* beta, int nterms);
 
-// Modal SVD of J_l(x y) on x in [0, X] (x dx) and y in [0, 1] (p(y) y dy).
+// Contrast transfer function for the joint translation-CTF factorisation
+// (Section 7.1, other 2D kernels): the isotropic weak-phase model
+//   C(y; tau) = -(sqrt(1 - A^2) sin chi + A cos chi),
+//   chi = pi lambda tau s^2 - (pi / 2) Cs lambda^3 s^4,  s = y / (2 pixel),
+// y = k / Kmax, s in 1/Angstrom, lambda, Cs, tau and the pixel in Angstrom;
+// tau (defocus) ranges over [tmin, tmax] with the uniform measure of mass 1.
+struct Ctf {
+  bool on = false;
+  double lambda = 0, cs = 0, amp = 0, pixel = 1, tmin = 0, tmax = 0;
+  double chi(double y, double tau) const;
+  double operator()(double y, double tau) const;
+};
+// Checks the parameters (throws std::invalid_argument); cs in millimetres.
+Ctf make_ctf(double wavelength_A, double cs_mm, double amplitude_contrast, double pixel_A, double tmin_A,
+             double tmax_A);
+
+// Modal SVD of the kernel K_l(x, tau; y) = J_l(x y) C(y; tau) from L2(p(y) y dy)
+// on [0, 1] to L2(x dx dtau) on [0, X] x [tmin, tmax] (without a CTF: C = 1
+// and no tau, the translation kernel of Section 4.5).
 struct ModalSVD {
   int ell = 0;
-  int P = 0;
+  int P = 0;   // x nodes
+  int Pt = 1;  // tau nodes (1 without a CTF)
+  int Py = 0;  // y nodes (P without a CTF)
   double X = 0;
-  std::vector<double> sigma;  // P, descending
-  std::vector<double> U;      // P x P, column eta = left vector (x side), U[i*P + eta]
-  std::vector<double> V;      // P x P, column eta = right vector (y side), V[j*P + eta]
-  std::vector<double> xn, xw, yn, yw;  // yw: quadrature weights times p(y_j)
+  Ctf ctf;
+  std::vector<double> sigma;  // Py, descending
+  std::vector<double> U;      // (P Pt) x Py: row i Pt + t (x_i, tau_t), column eta = left vector
+  std::vector<double> V;      // Py x Py, column eta = right vector (y side), V[j*Py + eta]
+  std::vector<double> xn, xw, tn, tw, yn, yw;  // yw: quadrature weights times p(y_j)
+  double kernel(double x, double y, double tau) const;
   // Sigma_eta v_eta(y), Nystrom through the x side (no division by Sigma).
   double sigma_v(int eta, double y) const;
-  // u_eta(x), Nystrom through the y side.
-  double u(int eta, double x) const;
+  // u_eta(x, tau), Nystrom through the y side.
+  double u(int eta, double x, double tau = 0.0) const;
 };
 
 ModalSVD modal_svd(int ell, double X, const Weight& weight = Weight());
+ModalSVD ctf_modal_svd(int ell, double X, const Ctf& ctf);
 
 struct Term {
   int ell;
@@ -65,12 +88,18 @@ struct Truncation {
 };
 
 // Keep every Sigma_eta(l) > eps; scan |l| = 0, 1, ... until Sigma_1(l) <= eps.
-Truncation truncate(double X, double eps, const Weight& weight = Weight());
+// With ctf.on the modal SVDs are those of the joint kernel (the weight is
+// then not used).
+Truncation truncate(double X, double eps, const Weight& weight = Weight(), const Ctf& ctf = Ctf());
 
 // One-sided Jacobi SVD of a dense m x n (m >= n) row-major matrix A.
 // On exit: sigma (n, descending), U (m x n, row-major), V (n x n, row-major).
 void jacobi_svd(int m, int n, std::vector<double> A, std::vector<double>& sigma,
                 std::vector<double>& U, std::vector<double>& V);
+// The same for m much larger than n: Householder QR first, one-sided Jacobi
+// on the n x n triangle, U = Q U_R.
+void qr_jacobi_svd(int m, int n, const std::vector<double>& A, std::vector<double>& sigma,
+                   std::vector<double>& U, std::vector<double>& V);
 
 // NUFFT (type 2) spreading kernel: phi(z) = exp(beta (sqrt(1 - z^2) - 1)),
 // |z| < 1.  Phi(s) = int psi(t) e^{i s t} dt with psi(t) = phi(t / alpha).

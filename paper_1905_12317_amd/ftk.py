@@ -37,7 +37,7 @@ class PlanInfo(ctypes.Structure):
                 ("shift_radius_px", ctypes.c_double), ("eps", ctypes.c_double),
                 ("sigma_next", ctypes.c_double), ("kmax", ctypes.c_double),
                 ("coeff_bytes_per_image", ctypes.c_size_t), ("device_bytes", ctypes.c_size_t),
-                ("weighted", ctypes.c_int), ("rotations", ctypes.c_int)]
+                ("weighted", ctypes.c_int), ("rotations", ctypes.c_int), ("ctf", ctypes.c_int)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -73,7 +73,8 @@ POSE_DTYPE = np.dtype([("value", np.float32), ("shift", np.int32), ("rot", np.in
 
 #: every symbol include/ftk.h declares
 EXPORTS = ["ftk_plan_create", "ftk_plan_destroy", "ftk_plan_info", "ftk_set_shifts", "ftk_transform",
-           "ftk_align_coeffs", "ftk_align_coeffs_noalloc", "ftk_align", "ftk_bft_align", "ftk_plan_set_rotations", "ftk_plan_tables", "ftk_plan_create_weighted",
+           "ftk_align_coeffs", "ftk_align_coeffs_noalloc", "ftk_align", "ftk_bft_align", "ftk_plan_set_rotations", "ftk_plan_create_ctf", "ftk_set_poses",
+           "ftk_plan_tables_ctf", "ftk_plan_tables", "ftk_plan_create_weighted",
            "ftk_plan_tables_weighted", "ftk_plan_profile", "ftk_plan_stage_times",
            "ftk_plan_set_tuning", "ftk_plan_get_tuning", "ftk_batch_create", "ftk_batch_run", "ftk_batch_info",
            "ftk_batch_destroy", "ftk_strerror", "ftk_last_error_message",
@@ -86,6 +87,13 @@ EXPORTS = ["ftk_plan_create", "ftk_plan_destroy", "ftk_plan_info", "ftk_set_shif
 FTK_MLP_FP32 = 0
 FTK_MLP_BF16 = 1
 MLP_PRECISIONS = {"fp32": FTK_MLP_FP32, "bf16": FTK_MLP_BF16}
+
+
+class Ctf(ctypes.Structure):
+    """ftk_ctf_t: weak-phase CTF of ftk_plan_create_ctf."""
+    _fields_ = [("wavelength_A", ctypes.c_double), ("cs_mm", ctypes.c_double),
+                ("amplitude_contrast", ctypes.c_double), ("pixel_A", ctypes.c_double),
+                ("defocus_min_A", ctypes.c_double), ("defocus_max_A", ctypes.c_double)]
 
 
 class MLPInfo(ctypes.Structure):
@@ -124,6 +132,10 @@ def lib() -> ctypes.CDLL:
     L.ftk_align.argtypes = [vp, vp, i, vp, i, vp, vp, vp]
     L.ftk_bft_align.argtypes = [vp, vp, i, vp, i, vp, vp, vp]
     L.ftk_plan_set_rotations.argtypes = [vp, i]
+    L.ftk_plan_create_ctf.argtypes = [ctypes.POINTER(vp), i, i, i, d, d, i, ctypes.POINTER(Ctf)]
+    L.ftk_set_poses.argtypes = [vp, vp, vp, i]
+    L.ftk_plan_tables_ctf.argtypes = [i, i, d, d, ctypes.POINTER(Ctf), vp, vp, i, ctypes.POINTER(i), vp, vp, vp, vp,
+                                      vp, vp, ctypes.POINTER(d)]
     L.ftk_plan_tables.argtypes = [i, i, d, d, vp, i, ctypes.POINTER(i), vp, vp, vp, vp, vp, vp,
                                   ctypes.POINTER(d)]
     L.ftk_plan_profile.argtypes = [vp, i]
@@ -233,18 +245,52 @@ def ftk_plan_tables(n: int, K: int, W: float, eps: float, shifts_px=None, weight
     return dict(H=H, ell=ell, sigma=sig, G=G, k=k, w=w, Y=Y, sigma_next=sn.value)
 
 
+def _ctf(c) -> "Ctf":
+    """Ctf from a dict with the ftk_ctf_t field names (or a Ctf)."""
+    return c if isinstance(c, Ctf) else Ctf(**c)
+
+
+def ftk_plan_tables_ctf(n: int, K: int, W: float, eps: float, ctf, shifts_px=None, defocus_A=None):
+    """Host-only FP64 tables of a plan with a CTF (ftk_plan_tables_ctf)."""
+    L = lib()
+    c = _ctf(ctf)
+    H = ctypes.c_int(0)
+    sn = ctypes.c_double(0)
+    _check(L.ftk_plan_tables_ctf(n, K, W, eps, ctypes.byref(c), None, None, 0, ctypes.byref(H), None, None, None,
+                                 None, None, None, ctypes.byref(sn)), "ftk_plan_tables_ctf")
+    H = H.value
+    ell, sig, G, k, w = np.zeros(H, np.int32), np.zeros(H), np.zeros((H, K)), np.zeros(K), np.zeros(K)
+    N, Y, sh, df = 0, None, None, None
+    if shifts_px is not None:
+        sh = np.ascontiguousarray(shifts_px, dtype=np.float64).reshape(-1, 2)
+        df = np.ascontiguousarray(defocus_A, dtype=np.float64).reshape(-1)
+        N = sh.shape[0]
+        Y = np.zeros((N, H), np.complex128)
+    _check(L.ftk_plan_tables_ctf(n, K, W, eps, ctypes.byref(c), sh.ctypes.data if sh is not None else None,
+                                 df.ctypes.data if df is not None else None, N, ctypes.byref(ctypes.c_int(0)),
+                                 ell.ctypes.data, sig.ctypes.data, G.ctypes.data, k.ctypes.data, w.ctypes.data,
+                                 Y.ctypes.data if Y is not None else None, ctypes.byref(sn)), "ftk_plan_tables_ctf")
+    return dict(H=H, ell=ell, sigma=sig, G=G, k=k, w=w, Y=Y, sigma_next=sn.value)
+
+
 class Plan:
     """Owns an ftk_plan (ftk_plan_create / ftk_plan_destroy)."""
 
-    def __init__(self, n: int, K: int, Q: int, W: float, eps: float, precision="fp32", weight=None):
+    def __init__(self, n: int, K: int, Q: int, W: float, eps: float, precision="fp32", weight=None, ctf=None):
         """weight: None, or (alpha, beta) of the k-side weight of the operator
-        SVD (ftk_plan_create_weighted)."""
+        SVD (ftk_plan_create_weighted).  ctf: None, or the ftk_ctf_t fields
+        as a dict (ftk_plan_create_ctf; poses then come from set_poses)."""
         L = lib()
         prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
         h = ctypes.c_void_p()
-        a, b, nt = _weight_arrays(weight)
-        _check(L.ftk_plan_create_weighted(ctypes.byref(h), n, K, Q, W, eps, prec, a.ctypes.data if nt else None,
-                                          b.ctypes.data if nt else None, nt), "ftk_plan_create")
+        if ctf is not None:
+            c = _ctf(ctf)
+            _check(L.ftk_plan_create_ctf(ctypes.byref(h), n, K, Q, W, eps, prec, ctypes.byref(c)),
+                   "ftk_plan_create_ctf")
+        else:
+            a, b, nt = _weight_arrays(weight)
+            _check(L.ftk_plan_create_weighted(ctypes.byref(h), n, K, Q, W, eps, prec, a.ctypes.data if nt else None,
+                                              b.ctypes.data if nt else None, nt), "ftk_plan_create")
         self._h = h
         self.n, self.M, self.Qa = n, K, Q
         self.N = 0
@@ -292,6 +338,15 @@ class Plan:
         """ftk_plan_set_rotations: U * Qa rotations (rotation upsampling)."""
         _check(lib().ftk_plan_set_rotations(self._h, int(upsample)), "ftk_plan_set_rotations")
         self.up = int(upsample)
+
+    def set_poses(self, shifts_px, defocus_A):
+        """ftk_set_poses: pose i = (shift_i, defocus_i) of a plan with a CTF."""
+        sh = np.ascontiguousarray(shifts_px, dtype=np.float64).reshape(-1, 2)
+        df = np.ascontiguousarray(defocus_A, dtype=np.float64).reshape(-1)
+        if df.size != sh.shape[0]:
+            raise ValueError("one defocus per shift")
+        _check(lib().ftk_set_poses(self._h, sh.ctypes.data, df.ctypes.data, sh.shape[0]), "ftk_set_poses")
+        self.N = sh.shape[0]
 
     def set_shifts(self, shifts_px):
         sh = np.ascontiguousarray(shifts_px, dtype=np.float64).reshape(-1, 2)
