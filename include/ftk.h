@@ -265,6 +265,19 @@ int ftk_plan_create_ctf(ftk_plan** out, int n, int K, int Q, double W, double ep
  * call is ftk_set_shifts.  Errors as ftk_set_shifts. */
 int ftk_set_poses(ftk_plan* plan, const double* shifts_px, const double* defocus_A, int N);
 
+/* Shift windows for the learned proposal's restricted search: window b
+ * holds the plan's shifts whose radius |delta| lies within half_width_px of
+ * centers_px[b] (an annulus: rotation-invariant features fix the size of a
+ * shift, not its direction).  For each window the library keeps the
+ * shift-side panels of that subset.  ftk_align_proposed (ftk_mlp.h) with a
+ * network of n_shift = nw bins then aligns each confidently proposed image
+ * only over the window of its predicted bin; the poses still index the
+ * plan's full shift list.  nw = 0 removes the windows; ftk_set_shifts
+ * removes them too.  Errors: FTK_EINVAL (a window without shifts, bad
+ * arguments), FTK_ESTATE (no shifts), FTK_EUNSUPPORTED (plan with a CTF),
+ * FTK_ENOMEM. */
+int ftk_plan_set_shift_windows(ftk_plan* plan, const double* centers_px, int nw, double half_width_px);
+
 /* Rotation upsampling (the remark after eq. 1dfft: zero-padding the angular
  * sum samples more rotations at little cost).  With upsample = U > 1 the
  * alignments of this plan evaluate X on U Q rotations gamma_r = 2 pi r / (U Q),

@@ -157,7 +157,13 @@ int ftk_best_template(const ftk_pose* poses, const int32_t* lists, int nA, int K
  *   n_fallback  : host int, number of images searched in full, or NULL
  *   kind, n_r, n_q : the features (ftk_features); their count must equal
  *                 dims[0]
- * Waits for the proposal before launching the fallback (one host sync).
+ * With shift windows on the plan (ftk_plan_set_shift_windows, one per shift
+ * bin of the network), each image at or above tau is aligned against its
+ * list over the shifts of the window of its predicted bin only (the
+ * restricted search); images below tau get the full search over all shifts
+ * and templates as without windows.  The poses index the plan's shift list.
+ * Waits for the proposal before launching the fallback (one host sync; with
+ * windows one more per window).
  * Workspace (coefficients, features, proposal, per-pair poses) is held by
  * the plan and the network and grown on demand.
  * Errors: FTK_EINVAL, FTK_ESTATE, FTK_ENOMEM, FTK_EDEVICE. */

@@ -637,6 +637,44 @@ int ftk_set_shifts(ftk_plan* p, const double* shifts_px, int N) {
   return set_poses_impl(p, shifts_px, nullptr, N);
 }
 
+int ftk_plan_set_shift_windows(ftk_plan* p, const double* centers_px, int nw, double half_width_px) {
+  if (!p) return fail(FTK_EINVAL, "ftk_plan_set_shift_windows: NULL plan");
+  if (p->N <= 0 || p->shifts.empty()) return fail(FTK_ESTATE, "ftk_plan_set_shift_windows: call ftk_set_shifts first");
+  if (p->has_ctf) return fail(FTK_EUNSUPPORTED, "ftk_plan_set_shift_windows: plans with a CTF are not supported");
+  if (nw < 0 || nw > 1024 || (nw > 0 && !centers_px))
+    return fail(FTK_EINVAL, "ftk_plan_set_shift_windows: nw must be in [0, 1024] with centres given");
+  if (nw > 0 && !(half_width_px > 0.0 && std::isfinite(half_width_px)))
+    return fail(FTK_EINVAL, "ftk_plan_set_shift_windows: half_width must be positive");
+  for (auto& w : p->windows) w.release();
+  p->windows.clear();
+  std::vector<ShiftWindow> ws(nw);
+  auto undo = [&](int rc) {
+    for (auto& w : ws) w.release();
+    return rc;
+  };
+  for (int b = 0; b < nw; ++b) {
+    const double c = centers_px[b];
+    if (!std::isfinite(c) || c < 0.0) return undo(fail(FTK_EINVAL, "ftk_plan_set_shift_windows: bad centre"));
+    std::vector<double> sub;
+    for (int i = 0; i < p->N; ++i) {
+      const double r = std::hypot(p->shifts[2 * i], p->shifts[2 * i + 1]);
+      if (std::fabs(r - c) <= half_width_px * (1.0 + 1e-12)) {
+        ws[b].idx.push_back(i);
+        sub.push_back(p->shifts[2 * i]);
+        sub.push_back(p->shifts[2 * i + 1]);
+      }
+    }
+    if (ws[b].idx.empty())
+      return undo(fail(FTK_EINVAL, "ftk_plan_set_shift_windows: window " + std::to_string(b) + " holds no shift"));
+    int rc = build_panels(p, sub.data(), nullptr, static_cast<int>(ws[b].idx.size()), ws[b].pan);
+    if (rc != FTK_OK) return undo(rc);
+    hipError_t e = upload(ws[b].didx, ws[b].idx);
+    if (e != hipSuccess) return undo(hip_fail(e, "ftk_plan_set_shift_windows: upload"));
+  }
+  p->windows = std::move(ws);
+  return FTK_OK;
+}
+
 int ftk_set_poses(ftk_plan* p, const double* shifts_px, const double* defocus_A, int N) {
   if (!p || !shifts_px) return fail(FTK_EINVAL, "ftk_set_poses: NULL argument");
   if (p->has_ctf != (defocus_A != nullptr))
@@ -647,9 +685,11 @@ int ftk_set_poses(ftk_plan* p, const double* shifts_px, const double* defocus_A,
 
 }  // extern "C"
 
-namespace {
+namespace ftkint {
 
-int set_poses_impl(ftk_plan* p, const double* shifts_px, const double* defocus, int N) {
+// The shift-side device panels of a pose list (Y embedded for Step 3 in the
+// plan's precision form, the brute-force (k dx, k dy) table), into out.
+int build_panels(const ftk_plan* p, const double* shifts_px, const double* defocus, int N, ShiftPanels& out) {
   if (N < 1 || N > 65536) return fail(FTK_EINVAL, "ftk_set_shifts: N must be in [1, 65536]");
   std::vector<std::complex<double>> Y;
   try {
@@ -673,7 +713,7 @@ int set_poses_impl(ftk_plan* p, const double* shifts_px, const double* defocus, 
       yt[static_cast<size_t>(z) * rs + 2 * d + 1] = yi;
       yt[static_cast<size_t>(Hp + z) * rs + 2 * d + 1] = yr;
     }
-  hipError_t e = upload(p->yt, yt);
+  hipError_t e = upload(out.yt, yt);
   if (e != hipSuccess) return hip_fail(e, "ftk_set_shifts: upload");
   // reduced-precision copies in MFMA lane order: [row tile][K step][lane][8],
   // row tile = 32 embedded rows (16 shifts), K step = 16 embedded terms; lane
@@ -700,8 +740,8 @@ int set_poses_impl(ftk_plan* p, const double* shifts_px, const double* defocus, 
             hi[i] = bf16_rne(static_cast<float>(v));
             lo[i] = bf16_rne(static_cast<float>(v - bf16_value(hi[i])));
           }
-    if ((e = upload(p->yt_hi, hi)) != hipSuccess) return hip_fail(e, "ftk_set_shifts: upload");
-    if ((e = upload(p->yt_lo, lo)) != hipSuccess) return hip_fail(e, "ftk_set_shifts: upload");
+    if ((e = upload(out.yt_hi, hi)) != hipSuccess) return hip_fail(e, "ftk_set_shifts: upload");
+    if ((e = upload(out.yt_lo, lo)) != hipSuccess) return hip_fail(e, "ftk_set_shifts: upload");
   }
   if (p->precision == FTK_FP16 || p->precision == FTK_FP16X3) {
     // fp16 panel, column zeta multiplied by sg_zeta and the whole panel
@@ -731,9 +771,9 @@ int set_poses_impl(ftk_plan* p, const double* shifts_px, const double* defocus, 
             h16[i] = f16_rne(v);
             if (split) l16[i] = f16_rne(v - f16_value(h16[i]));
           }
-    if ((e = upload(p->yt_hi, h16)) != hipSuccess) return hip_fail(e, "ftk_set_shifts: upload");
-    if (split && (e = upload(p->yt_lo, l16)) != hipSuccess) return hip_fail(e, "ftk_set_shifts: upload");
-    p->y_scale = static_cast<float>(sy);
+    if ((e = upload(out.yt_hi, h16)) != hipSuccess) return hip_fail(e, "ftk_set_shifts: upload");
+    if (split && (e = upload(out.yt_lo, l16)) != hipSuccess) return hip_fail(e, "ftk_set_shifts: upload");
+    out.y_scale = static_cast<float>(sy);
   }
   {
     // brute-force translations: (k_m dx, k_m dy), the shift in image units
@@ -745,10 +785,40 @@ int set_poses_impl(ftk_plan* p, const double* shifts_px, const double* defocus, 
         kd[2 * (static_cast<size_t>(d) * M + m) + 0] = static_cast<float>(p->t.k[m] * shifts_px[2 * d] * px);
         kd[2 * (static_cast<size_t>(d) * M + m) + 1] = static_cast<float>(p->t.k[m] * shifts_px[2 * d + 1] * px);
       }
-    if ((e = upload(p->bft_kd, kd)) != hipSuccess) return hip_fail(e, "ftk_set_shifts: upload");
+    if ((e = upload(out.kd, kd)) != hipSuccess) return hip_fail(e, "ftk_set_shifts: upload");
   }
-  p->N = N;
-  p->N_pad = Np;
+  out.N = N;
+  out.N_pad = Np;
+  return FTK_OK;
+}
+
+// swap the plan's shift-side panels with a set
+void swap_panels(ftk_plan* p, ShiftPanels& w) {
+  std::swap(p->yt, w.yt);
+  std::swap(p->yt_hi, w.yt_hi);
+  std::swap(p->yt_lo, w.yt_lo);
+  std::swap(p->bft_kd, w.kd);
+  std::swap(p->N, w.N);
+  std::swap(p->N_pad, w.N_pad);
+  std::swap(p->y_scale, w.y_scale);
+}
+
+}  // namespace ftkint
+
+namespace {
+
+int set_poses_impl(ftk_plan* p, const double* shifts_px, const double* defocus, int N) {
+  ShiftPanels sp;
+  int rc = build_panels(p, shifts_px, defocus, N, sp);
+  if (rc != FTK_OK) {
+    sp.release();
+    return rc;
+  }
+  swap_panels(p, sp);
+  sp.release();  // the previous panels
+  p->shifts.assign(shifts_px, shifts_px + 2 * static_cast<size_t>(N));
+  for (auto& w : p->windows) w.release();  // windows refer to the previous shift list
+  p->windows.clear();
   return FTK_OK;
 }
 

@@ -29,13 +29,15 @@ struct ftk_mlp {
   DevBuf row_loss;
   // proposal search workspace (grown on demand)
   DevBuf feat, top, mass, sbin, pair_poses, flist, fcount, fcoef, fposes, fbt, fbp, coef;
+  DevBuf wlist, wcoef, wtop, wposes;  // shift-window search
   size_t esize() const { return prec == FTK_MLP_BF16 ? 2 : 4; }
   size_t device_bytes() const {
     size_t s = mu.bytes + is.bytes + X0.bytes + row_loss.bytes;
     for (const auto* v : {&W, &b, &Wc, &mW, &vW, &mb, &vb, &dW, &db, &Z, &H})
       for (const auto& x : *v) s += x.bytes;
     for (int i = 0; i < 2; ++i) s += dZf[i].bytes + dZb[i].bytes;
-    for (const DevBuf* x : {&feat, &top, &mass, &sbin, &pair_poses, &flist, &fcount, &fcoef, &fposes, &fbt, &fbp, &coef})
+    for (const DevBuf* x : {&feat, &top, &mass, &sbin, &pair_poses, &flist, &fcount, &fcoef, &fposes, &fbt, &fbp, &coef,
+                            &wlist, &wcoef, &wtop, &wposes})
       s += x->bytes;
     return s;
   }
@@ -43,7 +45,7 @@ struct ftk_mlp {
     for (auto* v : {&W, &b, &Wc, &mW, &vW, &mb, &vb, &dW, &db, &Z, &H})
       for (auto& x : *v) x.release();
     for (DevBuf* x : {&mu, &is, &X0, &row_loss, &dZf[0], &dZf[1], &dZb[0], &dZb[1], &feat, &top, &mass, &sbin,
-                      &pair_poses, &flist, &fcount, &fcoef, &fposes, &fbt, &fbp, &coef})
+                      &pair_poses, &flist, &fcount, &fcoef, &fposes, &fbt, &fbp, &coef, &wlist, &wcoef, &wtop, &wposes})
       x->release();
   }
 };
@@ -87,6 +89,56 @@ int forward_rows(ftk_mlp* m, int B, float* logits, hipStream_t s) {
 
 int check_rows(const ftk_mlp* m, int B, const char* who) {
   if (B < 1 || B > m->maxB) return fail(FTK_EINVAL, std::string(who) + ": B must be in [1, max_batch]");
+  return FTK_OK;
+}
+
+// The proposed images grouped by the window of their predicted shift bin:
+// per window, the images' coefficients and template lists gathered, the
+// list alignment run with the window's shift panels in place of the plan's,
+// and the poses (window shift index mapped to the plan's) scattered back.
+// Images below tau are left to the full search.  One host sync (the
+// proposal's mass and bins).
+int align_windows(ftk_plan* p, ftk_mlp* m, int nA, const void* tmpl_coeffs, int nB, int topk, float tau,
+                  hipStream_t s) {
+  std::vector<float> mass(nA);
+  std::vector<int32_t> bin(nA);
+  hipError_t e;
+  if ((e = hipMemcpyAsync(mass.data(), m->mass.ptr, 4ull * nA, hipMemcpyDeviceToHost, s)) != hipSuccess ||
+      (e = hipMemcpyAsync(bin.data(), m->sbin.ptr, 4ull * nA, hipMemcpyDeviceToHost, s)) != hipSuccess ||
+      (e = hipStreamSynchronize(s)) != hipSuccess)
+    return hip_fail(e, "ftk_align_proposed: proposal to host");
+  const int nw = static_cast<int>(p->windows.size());
+  std::vector<std::vector<int32_t>> groups(nw);
+  for (int i = 0; i < nA; ++i)
+    if (!(mass[i] < tau)) groups[std::min(std::max(bin[i], 0), nw - 1)].push_back(i);
+  size_t most = 0;
+  for (const auto& g : groups) most = std::max(most, g.size());
+  if (most == 0) return FTK_OK;
+  const size_t cb = static_cast<size_t>(8) * p->M * p->Qa;
+  if (m->wlist.ensure(4 * most) != hipSuccess || m->wcoef.ensure(cb * most) != hipSuccess ||
+      m->wtop.ensure(4 * most * topk) != hipSuccess || m->wposes.ensure(12 * most * topk) != hipSuccess)
+    return fail(FTK_ENOMEM, "ftk_align_proposed: window workspace");
+  for (int b = 0; b < nw; ++b) {
+    const int cnt = static_cast<int>(groups[b].size());
+    if (cnt == 0) continue;
+    // the list stays alive until the stream has used it (synchronous copy)
+    if ((e = hipMemcpy(m->wlist.ptr, groups[b].data(), 4ull * cnt, hipMemcpyHostToDevice)) != hipSuccess)
+      return hip_fail(e, "ftk_align_proposed: window list");
+    if ((e = launch_gather_words(m->coef.ptr, m->wlist.as<int32_t>(), cnt, cb / 4, m->wcoef.ptr, s)) != hipSuccess ||
+        (e = launch_gather_words(m->top.ptr, m->wlist.as<int32_t>(), cnt, topk, m->wtop.ptr, s)) != hipSuccess)
+      return hip_fail(e, "ftk_align_proposed: window gather");
+    ShiftWindow& w = p->windows[b];
+    swap_panels(p, w.pan);
+    int rc = ftk_align_lists(p, m->wcoef.ptr, cnt, tmpl_coeffs, nB, m->wtop.as<int32_t>(), topk,
+                             m->wposes.as<ftk_pose>(), s);
+    swap_panels(p, w.pan);
+    if (rc != FTK_OK) return rc;
+    if ((e = launch_scatter_poses(m->wposes.ptr, m->wlist.as<int32_t>(), cnt, topk, w.didx.as<int32_t>(),
+                                  m->pair_poses.ptr, s)) != hipSuccess)
+      return hip_fail(e, "ftk_align_proposed: window scatter");
+    // the next window's list overwrites wlist: wait for this one's kernels
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e, "ftk_align_proposed: window sync");
+  }
   return FTK_OK;
 }
 
@@ -397,14 +449,18 @@ int ftk_align_proposed(ftk_plan* p, ftk_mlp* m, const float* images, int nA, con
       m->sbin.ensure(nA * 4ull) != hipSuccess || m->pair_poses.ensure(static_cast<size_t>(nA) * topk * 12) != hipSuccess ||
       m->flist.ensure(nA * 4ull) != hipSuccess || m->fcount.ensure(16) != hipSuccess)
     return fail(FTK_ENOMEM, "ftk_align_proposed: workspace");
+  const bool win = !p->windows.empty();
+  if (win && static_cast<int>(p->windows.size()) != m->n_s)
+    return fail(FTK_EINVAL, "ftk_align_proposed: the plan's shift windows must match the network's shift bins");
   int rc = ftk_transform(p, images, nA, m->coef.ptr, stream);
   if (rc == FTK_OK) rc = ftk_features(p, m->coef.ptr, nA, kind, n_r, n_q, m->feat.as<float>(), stream);
   if (rc == FTK_OK)
     rc = ftk_propose(m, m->feat.as<float>(), nA, topk, m->top.as<int32_t>(), m->mass.as<float>(),
                      m->sbin.as<int32_t>(), stream);
-  if (rc == FTK_OK)
+  if (rc == FTK_OK && !win)
     rc = ftk_align_lists(p, m->coef.ptr, nA, tmpl_coeffs, nB, m->top.as<int32_t>(), topk,
                          m->pair_poses.as<ftk_pose>(), stream);
+  if (rc == FTK_OK && win) rc = align_windows(p, m, nA, tmpl_coeffs, nB, topk, tau, s);
   if (rc == FTK_OK)
     rc = ftk_best_template(m->pair_poses.as<ftk_pose>(), m->top.as<int32_t>(), nA, topk, best_t, best_pose, stream);
   if (rc != FTK_OK) return rc;

@@ -436,6 +436,30 @@ __global__ void gather_rows_kernel(const uint2* __restrict__ src, const int32_t*
   }
 }
 
+__global__ void gather_words_kernel(const uint32_t* __restrict__ src, const int32_t* __restrict__ list, int count,
+                                    size_t words, uint32_t* __restrict__ dst) {
+  const size_t total = static_cast<size_t>(count) * words;
+  for (size_t t = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x; t < total;
+       t += static_cast<size_t>(gridDim.x) * blockDim.x) {
+    const size_t r = t / words;
+    dst[t] = src[static_cast<size_t>(list[r]) * words + (t - r * words)];
+  }
+}
+
+// dst[list[r]][j] = src[r][j] with the shift index mapped through map
+// (window index -> plan index); poses without a result (shift < 0) kept
+__global__ void scatter_poses_kernel(const Pose* __restrict__ src, const int32_t* __restrict__ list, int count, int K,
+                                     const int32_t* __restrict__ map, Pose* __restrict__ dst) {
+  const size_t total = static_cast<size_t>(count) * K;
+  for (size_t t = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x; t < total;
+       t += static_cast<size_t>(gridDim.x) * blockDim.x) {
+    const size_t r = t / K;
+    Pose p = src[t];
+    if (map && p.shift >= 0) p.shift = map[p.shift];
+    dst[static_cast<size_t>(list[r]) * K + (t - r * K)] = p;
+  }
+}
+
 __global__ void scatter_results_kernel(const int32_t* __restrict__ bt, const Pose* __restrict__ bp,
                                        const int32_t* __restrict__ list, int count, int32_t* __restrict__ dt,
                                        Pose* __restrict__ dp) {
@@ -565,6 +589,22 @@ hipError_t launch_gather_rows(const void* src, const int32_t* list, int count, s
   const size_t words = row_bytes / 8;
   hipLaunchKernelGGL(gather_rows_kernel, dim3(grid_for(static_cast<size_t>(count) * words)), dim3(kThreads), 0, s,
                      static_cast<const uint2*>(src), list, count, words, static_cast<uint2*>(dst));
+  return hipGetLastError();
+}
+
+hipError_t launch_gather_words(const void* src, const int32_t* list, int count, size_t row_words, void* dst,
+                               hipStream_t s) {
+  if (count <= 0 || row_words == 0) return hipSuccess;
+  hipLaunchKernelGGL(gather_words_kernel, dim3(grid_for(static_cast<size_t>(count) * row_words)), dim3(kThreads), 0, s,
+                     static_cast<const uint32_t*>(src), list, count, row_words, static_cast<uint32_t*>(dst));
+  return hipGetLastError();
+}
+
+hipError_t launch_scatter_poses(const void* src, const int32_t* list, int count, int K, const int32_t* map, void* dst,
+                                hipStream_t s) {
+  if (count <= 0 || K <= 0) return hipSuccess;
+  hipLaunchKernelGGL(scatter_poses_kernel, dim3(grid_for(static_cast<size_t>(count) * K)), dim3(kThreads), 0, s,
+                     static_cast<const Pose*>(src), list, count, K, map, static_cast<Pose*>(dst));
   return hipGetLastError();
 }
 

@@ -65,6 +65,13 @@ hipError_t launch_select_below(const float* mass, int nA, float tau, int32_t* li
 // dst[i] = src[list[i]] for rows of `row_bytes` bytes (multiple of 8)
 hipError_t launch_gather_rows(const void* src, const int32_t* list, int count, size_t row_bytes, void* dst,
                               hipStream_t s);
+// dst[i] = src[list[i]] for rows of row_words 4-byte words
+hipError_t launch_gather_words(const void* src, const int32_t* list, int count, size_t row_words, void* dst,
+                               hipStream_t s);
+// dst[list[i]][j] = src[i][j] for pose rows of K poses, shift indices mapped
+// through map (or kept when map is null)
+hipError_t launch_scatter_poses(const void* src, const int32_t* list, int count, int K, const int32_t* map, void* dst,
+                                hipStream_t s);
 // dst[list[i]] = src[i] for int32 and 12-byte pose rows
 hipError_t launch_scatter_results(const int32_t* bt, const void* bp, const int32_t* list, int count, int32_t* dst_t,
                                   void* dst_p, hipStream_t s);

@@ -90,6 +90,32 @@ struct Needs {
   int transform_chunk = 0;  // images per transform launch
 };
 
+// Shift-side device panels of one pose list (see ftk_set_shifts): Y
+// embedded for Step 3, the brute-force table, the counts and the FP16
+// panel scale.
+struct ShiftPanels {
+  DevBuf yt, yt_hi, yt_lo, kd;
+  int N = 0, N_pad = 0;
+  float y_scale = 1.f;
+  void release() {
+    for (DevBuf* b : {&yt, &yt_hi, &yt_lo, &kd}) b->release();
+  }
+  size_t bytes() const { return yt.bytes + yt_hi.bytes + yt_lo.bytes + kd.bytes; }
+};
+
+// A shift window (ftk_plan_set_shift_windows): the shifts of the plan whose
+// radius lies within half_width of the window's centre, their panels, and
+// the map from window index to plan index (host and device int32).
+struct ShiftWindow {
+  ShiftPanels pan;
+  std::vector<int32_t> idx;
+  DevBuf didx;
+  void release() {
+    pan.release();
+    didx.release();
+  }
+};
+
 }  // namespace ftkint
 
 struct ftk_plan {
@@ -115,15 +141,28 @@ struct ftk_plan {
   ftkint::DevBuf bft_cz, bft_kd;
   ftkint::Workspace own_ws;
   ftkint::Workspace* ws = &own_ws;
+  std::vector<double> shifts;  // the current shift list (px), [N][2]
+  std::vector<ftkint::ShiftWindow> windows;
+  ~ftk_plan() {
+    for (auto& w : windows) w.release();
+  }
   size_t device_bytes() const {
     return cz.bytes + ell.bytes + yt.bytes + yt_hi.bytes + yt_lo.bytes + tw_nf.bytes + tw_qa.bytes +
-           deapod.bytes + ptbase.bytes + ptker.bytes + rot16.bytes + bft_cz.bytes + bft_kd.bytes + own_ws.bytes();
+           deapod.bytes + ptbase.bytes + ptker.bytes + rot16.bytes + bft_cz.bytes + bft_kd.bytes + own_ws.bytes() +
+           windows_bytes();
+  }
+  size_t windows_bytes() const {
+    size_t s = 0;
+    for (const auto& w : windows) s += w.pan.bytes() + w.didx.bytes;
+    return s;
   }
   void release_all() {
     for (ftkint::DevBuf* b :
          {&cz, &ell, &yt, &yt_hi, &yt_lo, &tw_nf, &tw_qa, &deapod, &ptbase, &ptker, &rot16, &bft_cz, &bft_kd})
       b->release();
     own_ws.release();
+    for (auto& w : windows) w.release();
+    windows.clear();
   }
 };
 
@@ -184,6 +223,8 @@ inline SplitF16Exps split_f16_exps(int M) {
   while ((1 << c) < 4 * M) ++c;
   return SplitF16Exps{kData, c - 2 * kData, -(kData + c)};
 }
+int build_panels(const ftk_plan* p, const double* shifts_px, const double* defocus, int N, ShiftPanels& out);
+void swap_panels(ftk_plan* p, ShiftPanels& w);
 // ftk_transform's body; polar (optional) receives the ring samples
 // [cnt][M][Qa] that the ring DFT transforms (TransformArgs::polar).
 int transform_run(ftk_plan* p, const float* imgs, int cnt, float2* coeffs, float2* polar, void* stream);

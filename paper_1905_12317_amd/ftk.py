@@ -74,7 +74,7 @@ POSE_DTYPE = np.dtype([("value", np.float32), ("shift", np.int32), ("rot", np.in
 #: every symbol include/ftk.h declares
 EXPORTS = ["ftk_plan_create", "ftk_plan_destroy", "ftk_plan_info", "ftk_set_shifts", "ftk_transform",
            "ftk_align_coeffs", "ftk_align_coeffs_noalloc", "ftk_align", "ftk_bft_align", "ftk_plan_set_rotations", "ftk_plan_create_ctf", "ftk_set_poses",
-           "ftk_plan_tables_ctf", "ftk_plan_tables", "ftk_plan_create_weighted",
+           "ftk_plan_tables_ctf", "ftk_plan_set_shift_windows", "ftk_plan_tables", "ftk_plan_create_weighted",
            "ftk_plan_tables_weighted", "ftk_plan_profile", "ftk_plan_stage_times",
            "ftk_plan_set_tuning", "ftk_plan_get_tuning", "ftk_batch_create", "ftk_batch_run", "ftk_batch_info",
            "ftk_batch_destroy", "ftk_strerror", "ftk_last_error_message",
@@ -134,6 +134,7 @@ def lib() -> ctypes.CDLL:
     L.ftk_plan_set_rotations.argtypes = [vp, i]
     L.ftk_plan_create_ctf.argtypes = [ctypes.POINTER(vp), i, i, i, d, d, i, ctypes.POINTER(Ctf)]
     L.ftk_set_poses.argtypes = [vp, vp, vp, i]
+    L.ftk_plan_set_shift_windows.argtypes = [vp, vp, i, d]
     L.ftk_plan_tables_ctf.argtypes = [i, i, d, d, ctypes.POINTER(Ctf), vp, vp, i, ctypes.POINTER(i), vp, vp, vp, vp,
                                       vp, vp, ctypes.POINTER(d)]
     L.ftk_plan_tables.argtypes = [i, i, d, d, vp, i, ctypes.POINTER(i), vp, vp, vp, vp, vp, vp,
@@ -333,6 +334,13 @@ class Plan:
     def set_tuning(self, step3_waves=0, step1_zblk=0, step1_wgs=0, stage_mib=0):
         t = Tuning(step3_waves, step1_zblk, step1_wgs, stage_mib)
         _check(lib().ftk_plan_set_tuning(self._h, ctypes.byref(t)), "ftk_plan_set_tuning")
+
+    def set_shift_windows(self, centers_px, half_width_px: float):
+        """ftk_plan_set_shift_windows: annuli of shifts for the proposal's
+        restricted search (empty centers removes them)."""
+        c = np.ascontiguousarray(centers_px, dtype=np.float64).reshape(-1)
+        _check(lib().ftk_plan_set_shift_windows(self._h, c.ctypes.data if c.size else None, c.size,
+                                                float(half_width_px)), "ftk_plan_set_shift_windows")
 
     def set_rotations(self, upsample: int):
         """ftk_plan_set_rotations: U * Qa rotations (rotation upsampling)."""
