@@ -238,8 +238,8 @@ def cpu_baseline(inputs, w, shifts, n_img=8, n_tmp=48, n_dir=(2, 4)):
 
 
 RAGGED = dict(name="ragged_c4", stacks=64, seed=4, scale=0.25, nblob=60, snr=0.05, eps=1e-3)
-PROPOSAL = dict(name="proposal_n128", n=128, M=64, Qa=256, R=4.0, n_templates=1024, n_clean=16384, n_val=1024,
-                n_test=2048, nblob=60, snr=0.05, eps=1e-3, epochs=20, n_r=16, n_q=8, topk=32, hidden=1024, seed=5)
+PROPOSAL = dict(name="proposal_c5", n=128, M=64, Qa=256, R=4.0, n_templates=8192, n_clean=16384, n_val=1024,
+                n_test=2048, nblob=60, snr=0.05, eps=1e-3, epochs=12, n_r=16, n_q=8, topk=32, hidden=1024, seed=5)
 
 
 def bench_ragged(args):
@@ -316,9 +316,11 @@ def bench_ragged(args):
 
 
 def bench_proposal(args):
-    """Learned proposal at n = 128: train on re-noised images labelled by the
-    full FTK each epoch, choose the threshold on a validation split, then time
-    the proposal search against the full search on a test split."""
+    """Learned proposal on the 8192-template workload at n = 128: train on
+    re-noised images labelled each epoch by the two-pass search (FP16 over
+    every template, split bf16 on each image's best 4), choose the threshold
+    on a validation split, then time the proposal search (with and without
+    shift windows) against the full split-bf16 search on a test split."""
     import torch
     import synth
     from paper_1905_12317_amd import ftk
@@ -329,11 +331,14 @@ def bench_proposal(args):
     s = synth.make_alignment_set(w["seed"], w["n"], w["n_templates"], n_all, w["nblob"], w["R"], w["snr"],
                                  keep_clean=True)
     gen_s = time.perf_counter() - t0
+    log(f"[proposal] data {gen_s:.1f} s: {w['n_templates']} templates, {n_all} images")
     shifts = synth.shift_lattice(w["R"])
     bins = PR.shift_bins(shifts)
     n_t, n_s, kind = w["n_templates"], int(bins.max()) + 1, "cross"
     P = ftk.Plan(w["n"], w["M"], w["Qa"], w["R"], w["eps"], "bf16x3")
     P.set_shifts(shifts)
+    P16 = ftk.Plan(w["n"], w["M"], w["Qa"], w["R"], w["eps"], "fp16")
+    P16.set_shifts(shifts)
     tmps = torch.as_tensor(s.templates, dtype=torch.float32, device="cuda")
     tc = P.transform(tmps)
     nc = w["n_clean"]
@@ -343,15 +348,19 @@ def bench_proposal(args):
     net = ftk.MLP(dims, n_t, n_s, "bf16", max_batch=1024)
     net.set_params(synth.mlp_init(w["seed"], dims))
     perms = [synth.permutation(100 + e, nc) for e in range(w["epochs"])]
+    labeler = PR.refined_labeler(P16, P, tc, 4)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     losses = PR.train_online(net, P, clean, tc, bins, lambda e: synth.gaussian_noise(7000 + e, sig, w["n"]), perms,
-                             kind, w["n_r"], w["n_q"], batch=256, lr=2e-3, wd=1e-2)
+                             kind, w["n_r"], w["n_q"], batch=256, lr=2e-3, wd=1e-2, labeler=labeler,
+                             log=lambda e, l: log(f"  epoch {e}: loss {l:.4f}"))
     torch.cuda.synchronize()
     train_s = time.perf_counter() - t0
-    # training-step throughput of the network kernels alone
-    feats = ftk.features(P, P.transform(clean[:8192].contiguous()), w["n_r"], w["n_q"], kind=kind)
-    lab = torch.zeros(8192, dtype=torch.int32, device="cuda")
+    labelled_pairs = w["epochs"] * nc * n_t
+    # the network's kernels alone: a training step's loss + gradients, and
+    # the forward pass, at batch 256
+    feats = ftk.features(P, P.transform(clean[:4096].contiguous()), w["n_r"], w["n_q"], kind=kind)
+    lab = torch.zeros(4096, dtype=torch.int32, device="cuda")
     idx = torch.arange(256, dtype=torch.int32, device="cuda")
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     net.gradients(feats, lab, lab, idx)
@@ -361,47 +370,68 @@ def bench_proposal(args):
     e1.record()
     torch.cuda.synchronize()
     ms_grad = e0.elapsed_time(e1) / 20
-    mlp_flop = 6.0 * 256 * sum(dims[i] * dims[i + 1] for i in range(len(dims) - 1))
+    e0.record()
+    for _ in range(20):
+        net.forward(feats[:256])
+    e1.record()
+    torch.cuda.synchronize()
+    ms_fwd = e0.elapsed_time(e1) / 20
+    params = sum(dims[i] * dims[i + 1] for i in range(len(dims) - 1))
+    mlp_flop = 6.0 * 256 * params
     # threshold on the validation split
     vi = torch.as_tensor(s.images[nc:nc + w["n_val"]], dtype=torch.float32, device="cuda")
-    vlab, _, _ = PR.ftk_labels(P, vi, tmps, bins)
+    vlab, _ = labeler(P.transform(vi))
     vf = ftk.features(P, P.transform(vi), w["n_r"], w["n_q"], kind=kind)
     top, mass, _ = net.propose(vf, w["topk"])
     hit = (top.cpu().numpy() == vlab.cpu().numpy()[:, None]).any(axis=1)
     tau = PR.choose_tau(mass.cpu().numpy(), hit, max_miss=0.003)
-    # test split: proposal search vs full search, timed
+    log(f"[proposal] trained {train_s:.1f} s; validation top-{w['topk']} hit {hit.mean():.3f}, tau {tau:.4f}")
+    # test split: the full split-bf16 search and the proposal search, with and
+    # without shift windows (annuli of +-0.5 px around each shift bin's radius)
     ti = torch.as_tensor(s.images[nc + w["n_val"]:], dtype=torch.float32, device="cuda")
     nA = ti.shape[0]
-    ftk.align_proposed(P, net, ti, tc, w["n_r"], w["n_q"], w["topk"], tau, kind=kind)
-    _, full = P.align_coeffs(P.transform(ti), tc)
+    tic = P.transform(ti)
+    _, full = P.align_coeffs(tic, tc)
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    bt, bp, fb, nfb = ftk.align_proposed(P, net, ti, tc, w["n_r"], w["n_q"], w["topk"], tau, kind=kind)
-    torch.cuda.synchronize()
-    t_prop = time.perf_counter() - t0
     t0 = time.perf_counter()
     _, full = P.align_coeffs(P.transform(ti), tc)
     fbt, fbp = ftk.best_template(full)
     torch.cuda.synchronize()
     t_full = time.perf_counter() - t0
-    same = (bt.cpu().numpy() == fbt.cpu().numpy()) & np.all(bp.cpu().numpy() == fbp.cpu().numpy(), axis=1)
-    eff = nA * n_t / t_prop
+    fbt, fbp = fbt.cpu().numpy(), fbp.cpu().numpy()
+    res = {}
+    for mode in ("no_window", "window"):
+        P.set_shift_windows(0.5 * np.arange(n_s) if mode == "window" else [], 0.5)
+        ftk.align_proposed(P, net, ti, tc, w["n_r"], w["n_q"], w["topk"], tau, kind=kind)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        bt, bp, fb, nfb = ftk.align_proposed(P, net, ti, tc, w["n_r"], w["n_q"], w["topk"], tau, kind=kind)
+        torch.cuda.synchronize()
+        t_prop = time.perf_counter() - t0
+        same = (bt.cpu().numpy() == fbt) & np.all(bp.cpu().numpy() == fbp, axis=1)
+        res[mode] = {"recall": float(same.mean()), "fallback": int(nfb), "ms": t_prop * 1e3,
+                     "effective_pairs_per_s": nA * n_t / t_prop, "speedup_vs_full_search": t_full / t_prop}
+        log(f"[proposal {mode}] recall {same.mean():.4f}, fallback {nfb}/{nA}, {t_prop * 1e3:.1f} ms "
+            f"(full search {t_full * 1e3:.1f} ms)")
+    r = res["window"]
     out = {
         "metric": "effective pairs/s of the proposal search (images x all templates / time), recall of the full "
-                  "search's best pose", "value": eff, "unit": "pairs/s", "n_gpus": 1, "steps": 1, "warmup": 1,
-        "ms_per_step": t_prop * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "bf16 MLP + bf16x3 FTK", "data": "synthetic",
+                  "search's best pose", "value": r["effective_pairs_per_s"], "unit": "pairs/s", "n_gpus": 1,
+        "steps": 1, "warmup": 1, "ms_per_step": r["ms"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "bf16 MLP + bf16x3 FTK", "data": "synthetic",
         "config": {"workload": f"{w['name']}: {n_t} 60-blob templates n=128, M=64, Qa=256, N=197 shifts, SNR "
-                               f"{w['snr']}; {nc} training images re-noised and relabelled by the full FTK each of "
-                               f"{w['epochs']} epochs; cross-ring features n_r={w['n_r']} n_q={w['n_q']} "
-                               f"({dims[0]} inputs), MLP {dims}; top-{w['topk']}; test {nA} images",
-                   "recall": float(same.mean()), "fallback": int(nfb), "tau": tau,
+                               f"{w['snr']}; {nc} training images re-noised and relabelled by the two-pass search "
+                               f"each of {w['epochs']} epochs ({labelled_pairs} labelled pairs); cross-ring features "
+                               f"n_r={w['n_r']} n_q={w['n_q']} ({dims[0]} inputs), MLP {dims}; top-{w['topk']}; "
+                               f"test {nA} images",
+                   "window": res["window"], "no_window": res["no_window"], "tau": tau,
                    "validation_topk_hit": float(hit.mean()), "full_search_pairs_per_s": nA * n_t / t_full,
-                   "speedup_vs_full_search": t_full / t_prop, "train_s": train_s, "generate_s": gen_s,
-                   "loss_first_last": [losses[0], losses[-1]]},
+                   "train_s": train_s, "labelled_pairs_per_s": labelled_pairs / train_s, "generate_s": gen_s,
+                   "loss_first_last": [losses[0], losses[-1]],
+                   "mlp_forward_ms_b256": ms_fwd, "mlp_forward_tflops": 2.0 * 256 * params / (ms_fwd / 1e3) / 1e12},
         "roofline": {"kernel": "MLP loss + gradients (bf16 MFMA GEMMs), batch 256", "bound": "mfma",
                      "achieved": mlp_flop / (ms_grad / 1e3) / 1e12, "peak": PEAK_BF16_MFMA / 1e12, "unit": "TFLOP/s",
-                     "frac": mlp_flop / (ms_grad / 1e3) / PEAK_BF16_MFMA, "traffic": None},
+                     "frac": mlp_flop / (ms_grad / 1e3) / PEAK_BF16_MFMA, "traffic": None, "ms_per_step": ms_grad},
     }
     print(json.dumps(out), flush=True)
 

@@ -27,12 +27,13 @@ struct ftk_mlp {
   std::vector<DevBuf> H;     // H[l] = input of layer l (l >= 1), operand type
   DevBuf dZf[2], dZb[2];     // gradients w.r.t. pre-activations, ping-pong
   DevBuf row_loss;
+  DevBuf part;               // K-split partial sums of the bf16 GEMMs (kGemmPartFloats)
   // proposal search workspace (grown on demand)
   DevBuf feat, top, mass, sbin, pair_poses, flist, fcount, fcoef, fposes, fbt, fbp, coef;
   DevBuf wlist, wcoef, wtop, wposes;  // shift-window search
   size_t esize() const { return prec == FTK_MLP_BF16 ? 2 : 4; }
   size_t device_bytes() const {
-    size_t s = mu.bytes + is.bytes + X0.bytes + row_loss.bytes;
+    size_t s = mu.bytes + is.bytes + X0.bytes + row_loss.bytes + part.bytes;
     for (const auto* v : {&W, &b, &Wc, &mW, &vW, &mb, &vb, &dW, &db, &Z, &H})
       for (const auto& x : *v) s += x.bytes;
     for (int i = 0; i < 2; ++i) s += dZf[i].bytes + dZb[i].bytes;
@@ -44,13 +45,17 @@ struct ftk_mlp {
   void release() {
     for (auto* v : {&W, &b, &Wc, &mW, &vW, &mb, &vb, &dW, &db, &Z, &H})
       for (auto& x : *v) x.release();
-    for (DevBuf* x : {&mu, &is, &X0, &row_loss, &dZf[0], &dZf[1], &dZb[0], &dZb[1], &feat, &top, &mass, &sbin,
+    for (DevBuf* x : {&mu, &is, &X0, &row_loss, &part, &dZf[0], &dZf[1], &dZb[0], &dZb[1], &feat, &top, &mass, &sbin,
                       &pair_poses, &flist, &fcount, &fcoef, &fposes, &fbt, &fbp, &coef, &wlist, &wcoef, &wtop, &wposes})
       x->release();
   }
 };
 
 namespace {
+
+// Bound of the K-split workspace: a bf16 GEMM splits only while its tiles
+// times parts stay within 512, so kparts M N <= 512 x 128 x 128 floats.
+constexpr size_t kGemmPartFloats = static_cast<size_t>(512) * 128 * 128;
 
 hipError_t zero_fill(DevBuf& d) { return hipMemset(d.ptr, 0, d.bytes); }
 
@@ -80,6 +85,8 @@ int forward_rows(ftk_mlp* m, int B, float* logits, hipStream_t s) {
     g.Cb = last ? nullptr : m->H[l + 1].ptr;
     g.ldcb = dout;
     g.bias = m->b[l].as<float>();
+    g.part = m->part.as<float>();
+    g.part_floats = m->part.bytes / sizeof(float);
     g.relu = last ? 0 : 1;
     hipError_t e = launch_gemm(g, m->prec, s);
     if (e != hipSuccess) return hip_fail(e, "ftk_mlp: forward GEMM");
@@ -195,11 +202,12 @@ int ftk_mlp_create(ftk_mlp** out, const int* dims, int nlayers, int n_template, 
     if (l >= 1) grab(m->H[l], static_cast<size_t>(max_batch) * dims[l] * es);
   }
   grab(m->X0, static_cast<size_t>(max_batch) * dims[0] * es);
-  for (int i = 0; i < 2; ++i) {
-    grab(m->dZf[i], static_cast<size_t>(max_batch) * maxd * 4);
-    grab(m->dZb[i], static_cast<size_t>(max_batch) * maxd * es);
+  for (int i = 0; i < 2; ++i) {  // rows of up to maxd columns, padded to 8
+    grab(m->dZf[i], static_cast<size_t>(max_batch) * ((maxd + 7) / 8 * 8) * 4);
+    grab(m->dZb[i], static_cast<size_t>(max_batch) * ((maxd + 7) / 8 * 8) * es);
   }
   grab(m->row_loss, static_cast<size_t>(max_batch) * 4);
+  if (m->prec == FTK_MLP_BF16) grab(m->part, kGemmPartFloats * 4);
   grab(m->mu, static_cast<size_t>(dims[0]) * 4);
   grab(m->is, static_cast<size_t>(dims[0]) * 4);
   if (e == hipSuccess) {
@@ -323,18 +331,22 @@ int ftk_mlp_gradients(ftk_mlp* m, const float* x_all, const int32_t* lab_t, cons
   if (e != hipSuccess) return hip_fail(e, "ftk_mlp_gradients: input");
   if ((rc = forward_rows(m, B, nullptr, s)) != FTK_OK) return rc;
   const int L = m->L, D = m->dims[L];
+  // the output gradient rows are padded to a multiple of 8 columns, so the
+  // GEMMs that read them as bf16 get 16-byte aligned rows
+  const int ldz = (D + 7) / 8 * 8;
   int cur = 0;
-  if ((e = launch_softmax_ce(m->Z[L - 1].as<float>(), B, D, m->n_t, m->n_s, lab_t, lab_s, idx, m->dZf[cur].as<float>(),
+  if ((e = launch_softmax_ce(m->Z[L - 1].as<float>(), B, D, ldz, m->n_t, m->n_s, lab_t, lab_s, idx, m->dZf[cur].as<float>(),
                              m->dZb[cur].ptr, m->prec, m->row_loss.as<float>(), s)) != hipSuccess)
     return hip_fail(e, "ftk_mlp_gradients: loss");
   if ((e = launch_mean(m->row_loss.as<float>(), B, loss, s)) != hipSuccess) return hip_fail(e, "ftk_mlp_gradients");
   for (int l = L - 1; l >= 0; --l) {
     const int din = m->dims[l], dout = m->dims[l + 1];
+    const int ld = l == L - 1 ? ldz : dout;  // row stride of this layer's dZ
     // dW[o][j] = sum_b dZ[b][o] H_l[b][j]
     GemmArgs g{};
     g.A = m->dZb[cur].ptr;
     g.sai = 1;
-    g.sak = dout;
+    g.sak = ld;
     g.B = l == 0 ? m->X0.ptr : m->H[l].ptr;
     g.sbk = din;
     g.sbj = 1;
@@ -343,14 +355,16 @@ int ftk_mlp_gradients(ftk_mlp* m, const float* x_all, const int32_t* lab_t, cons
     g.K = B;
     g.C = m->dW[l].as<float>();
     g.ldc = din;
+    g.part = m->part.as<float>();
+    g.part_floats = m->part.bytes / sizeof(float);
     if ((e = launch_gemm(g, m->prec, s)) != hipSuccess) return hip_fail(e, "ftk_mlp_gradients: dW");
-    if ((e = launch_colsum(m->dZf[cur].as<float>(), B, dout, m->db[l].as<float>(), s)) != hipSuccess)
+    if ((e = launch_colsum(m->dZf[cur].as<float>(), B, dout, ld, m->db[l].as<float>(), s)) != hipSuccess)
       return hip_fail(e, "ftk_mlp_gradients: db");
     if (l == 0) break;
     // dZ_{l-1}[b][j] = (sum_o dZ[b][o] W[o][j]) (Z_{l-1}[b][j] > 0)
     GemmArgs h{};
     h.A = m->dZb[cur].ptr;
-    h.sai = dout;
+    h.sai = ld;
     h.sak = 1;
     h.B = m->Wc[l].ptr;
     h.sbk = din;
@@ -364,6 +378,8 @@ int ftk_mlp_gradients(ftk_mlp* m, const float* x_all, const int32_t* lab_t, cons
     h.ldc = din;
     h.Cb = m->dZb[cur ^ 1].ptr;
     h.ldcb = din;
+    h.part = m->part.as<float>();
+    h.part_floats = m->part.bytes / sizeof(float);
     if ((e = launch_gemm(h, m->prec, s)) != hipSuccess) return hip_fail(e, "ftk_mlp_gradients: dX");
     cur ^= 1;
   }

@@ -141,6 +141,185 @@ __global__ void __launch_bounds__(kThreads) gemm_kernel(GemmArgs g) {
   }
 }
 
+// bf16 GEMM, tiled for the wide layers: a (64 MI) x (64 NI) output tile per
+// workgroup of 4 waves (2 x 2), each wave (32 MI) x (32 NI) in MI x NI
+// accumulators of v_mfma_f32_32x32x16_bf16.  K runs in chunks of KC through
+// two LDS buffers ([row][k], KC + 8 bf16 per row; KC = 32 for the large
+// tile, 64 for the small one): the next chunk is loaded into
+// registers (16-byte loads where the operand's rows are 16-byte aligned,
+// else element loads) while the current one feeds the MFMAs.  Split K
+// (kparts > 1): workgroup z of the grid sums its K range into
+// part[z][M][N] and gemm_reduce_kernel adds the parts and applies the
+// epilogue; otherwise the epilogue (bias, ReLU mask, FP32 and bf16 outputs)
+// is applied here, as in gemm_kernel.
+template <int R, int KC>
+struct TileLoad {
+  // R rows x KC k of bf16 as 16-byte vectors of 8: V per thread
+  static constexpr int V = R * KC / (8 * 256);
+  uint4 v[V];
+};
+
+// vector u of this thread: k-contiguous operands take 8 consecutive k of one
+// row, row-contiguous ones 8 consecutive rows at one k
+template <int R, int KC>
+__device__ __forceinline__ void tile_coords(int u, bool kc, int& row, int& k) {
+  const int vi = threadIdx.x + 256 * u;
+  if (kc) {
+    row = vi / (KC / 8);
+    k = (vi % (KC / 8)) * 8;
+  } else {
+    k = vi / (R / 8);
+    row = (vi % (R / 8)) * 8;
+  }
+}
+
+// rows r0.. of an operand with element (row, k) at P[row * sr + k * sk]; kc:
+// k-contiguous (sk == 1), else row-contiguous (sr == 1); vec: 16-byte loads
+template <int R, int KC>
+__device__ __forceinline__ void tile_load(TileLoad<R, KC>& t, const __bf16* __restrict__ P, long long sr,
+                                          long long sk, int r0, int nrows, int k0, int K, bool kc, bool vec) {
+#pragma unroll
+  for (int u = 0; u < TileLoad<R, KC>::V; ++u) {
+    int row, k;
+    tile_coords<R, KC>(u, kc, row, k);
+    const int gr = r0 + row, gk = k0 + k;
+    __bf16 e[8];
+    if (kc) {
+      if (vec && gr < nrows && gk + 8 <= K) {
+        t.v[u] = *reinterpret_cast<const uint4*>(P + gr * sr + gk);
+        continue;
+      }
+#pragma unroll
+      for (int q = 0; q < 8; ++q) e[q] = (gr < nrows && gk + q < K) ? P[gr * sr + gk + q] : static_cast<__bf16>(0.f);
+    } else {
+      if (vec && gk < K && gr + 8 <= nrows) {
+        t.v[u] = *reinterpret_cast<const uint4*>(P + gk * sk + gr);
+        continue;
+      }
+#pragma unroll
+      for (int q = 0; q < 8; ++q) e[q] = (gr + q < nrows && gk < K) ? P[(gr + q) + gk * sk] : static_cast<__bf16>(0.f);
+    }
+    t.v[u] = *reinterpret_cast<const uint4*>(e);
+  }
+}
+
+template <int R, int KC>
+__device__ __forceinline__ void tile_store(const TileLoad<R, KC>& t, __bf16* __restrict__ S, bool kc) {
+  constexpr int TS = KC + 8;  // LDS row stride (bf16)
+#pragma unroll
+  for (int u = 0; u < TileLoad<R, KC>::V; ++u) {
+    int row, k;
+    tile_coords<R, KC>(u, kc, row, k);
+    if (kc) {
+      *reinterpret_cast<uint4*>(S + row * TS + k) = t.v[u];
+    } else {
+      const __bf16* e = reinterpret_cast<const __bf16*>(&t.v[u]);
+#pragma unroll
+      for (int q = 0; q < 8; ++q) S[(row + q) * TS + k] = e[q];
+    }
+  }
+}
+
+template <int MI, int NI, int KC>
+__global__ void __launch_bounds__(kThreads) gemm_bf16_tiled(GemmArgs g, int kparts, float* __restrict__ part) {
+  constexpr int TM = 64 * MI, TN = 64 * NI, TS = KC + 8;
+  __shared__ __attribute__((aligned(16))) __bf16 As[2][TM * TS];
+  __shared__ __attribute__((aligned(16))) __bf16 Bs[2][TN * TS];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int i0 = blockIdx.y * TM, j0 = blockIdx.x * TN;
+  const int wm = wave >> 1, wn = wave & 1;
+  const __bf16* A = static_cast<const __bf16*>(g.A);
+  const __bf16* B = static_cast<const __bf16*>(g.B);
+  const bool akc = g.sak == 1, bkc = g.sbk == 1;
+  // A rows are i (stride sai, k stride sak); B "rows" are j (stride sbj, k stride sbk)
+  const bool avec = (akc ? g.sai : g.sak) % 8 == 0 && (reinterpret_cast<uintptr_t>(A) & 15) == 0;
+  const bool bvec = (bkc ? g.sbj : g.sbk) % 8 == 0 && (reinterpret_cast<uintptr_t>(B) & 15) == 0;
+  // K range of this workgroup
+  const int nch = (g.K + KC - 1) / KC;
+  const int per = (nch + kparts - 1) / kparts;
+  const int c0 = blockIdx.z * per, c1 = min(nch, c0 + per);
+  f32x16 acc[MI][NI];
+#pragma unroll
+  for (int a = 0; a < MI; ++a)
+#pragma unroll
+    for (int b = 0; b < NI; ++b)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) acc[a][b][v] = 0.f;
+  TileLoad<TM, KC> ta;
+  TileLoad<TN, KC> tb;
+  if (c0 < c1) {
+    tile_load<TM, KC>(ta, A, g.sai, g.sak, i0, g.M, c0 * KC, g.K, akc, avec);
+    tile_load<TN, KC>(tb, B, g.sbj, g.sbk, j0, g.N, c0 * KC, g.K, bkc, bvec);
+    tile_store<TM, KC>(ta, As[0], akc);
+    tile_store<TN, KC>(tb, Bs[0], bkc);
+  }
+  __syncthreads();
+  const int r = lane & 31, h = lane >> 5;
+  for (int c = c0; c < c1; ++c) {
+    const int cur = (c - c0) & 1;
+    const bool more = c + 1 < c1;
+    if (more) {
+      tile_load<TM, KC>(ta, A, g.sai, g.sak, i0, g.M, (c + 1) * KC, g.K, akc, avec);
+      tile_load<TN, KC>(tb, B, g.sbj, g.sbk, j0, g.N, (c + 1) * KC, g.K, bkc, bvec);
+    }
+#pragma unroll
+    for (int st = 0; st < KC / 16; ++st) {
+      bf16x8 av[MI], bv[NI];
+#pragma unroll
+      for (int a = 0; a < MI; ++a)
+        av[a] = *reinterpret_cast<const bf16x8*>(&As[cur][(wm * 32 * MI + 32 * a + r) * TS + 16 * st + 8 * h]);
+#pragma unroll
+      for (int b = 0; b < NI; ++b)
+        bv[b] = *reinterpret_cast<const bf16x8*>(&Bs[cur][(wn * 32 * NI + 32 * b + r) * TS + 16 * st + 8 * h]);
+#pragma unroll
+      for (int a = 0; a < MI; ++a)
+#pragma unroll
+        for (int b = 0; b < NI; ++b) acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[a], bv[b], acc[a][b], 0, 0, 0);
+    }
+    if (more) {
+      tile_store<TM, KC>(ta, As[cur ^ 1], akc);
+      tile_store<TN, KC>(tb, Bs[cur ^ 1], bkc);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int b = 0; b < NI; ++b) {
+    const int j = j0 + wn * 32 * NI + 32 * b + r;
+    if (j >= g.N) continue;
+    const float bj = (kparts == 1 && g.bias) ? g.bias[j] : 0.f;
+#pragma unroll
+    for (int a = 0; a < MI; ++a)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const long long i = i0 + wm * 32 * MI + 32 * a + 8 * (v >> 2) + 4 * h + (v & 3);
+        if (i >= g.M) continue;
+        if (kparts > 1) {
+          part[(static_cast<size_t>(blockIdx.z) * g.M + i) * g.N + j] = acc[a][b][v];
+          continue;
+        }
+        float z = acc[a][b][v] + bj;
+        if (g.mask && !(g.mask[i * g.ldm + j] > 0.f)) z = 0.f;
+        if (g.C) g.C[i * g.ldc + j] = z;
+        if (g.Cb) static_cast<__bf16*>(g.Cb)[i * g.ldcb + j] = static_cast<__bf16>(g.relu ? fmaxf(z, 0.f) : z);
+      }
+  }
+}
+
+// sum of the K parts in a fixed order, then the epilogue of gemm_kernel
+__global__ void gemm_reduce_kernel(GemmArgs g, int kparts, const float* __restrict__ part) {
+  const size_t total = static_cast<size_t>(g.M) * g.N;
+  for (size_t t = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x; t < total;
+       t += static_cast<size_t>(gridDim.x) * blockDim.x) {
+    const long long i = static_cast<long long>(t / g.N), j = static_cast<long long>(t - i * g.N);
+    float z = 0.f;
+    for (int p = 0; p < kparts; ++p) z += part[p * total + t];
+    if (g.bias) z += g.bias[j];
+    if (g.mask && !(g.mask[i * g.ldm + j] > 0.f)) z = 0.f;
+    if (g.C) g.C[i * g.ldc + j] = z;
+    if (g.Cb) static_cast<__bf16*>(g.Cb)[i * g.ldcb + j] = static_cast<__bf16>(g.relu ? fmaxf(z, 0.f) : z);
+  }
+}
+
 // ---------------------------------------------------------------- rows
 
 template <typename T>
@@ -157,8 +336,8 @@ __global__ void standardise_kernel(const float* __restrict__ x, const int32_t* _
 }
 
 template <typename T>
-__global__ void __launch_bounds__(kThreads) softmax_ce_kernel(const float* __restrict__ logits, int B, int D, int n_t,
-                                                              int n_s, const int32_t* __restrict__ lab_t,
+__global__ void __launch_bounds__(kThreads) softmax_ce_kernel(const float* __restrict__ logits, int B, int D, int ldz,
+                                                              int n_t, int n_s, const int32_t* __restrict__ lab_t,
                                                               const int32_t* __restrict__ lab_s,
                                                               const int32_t* __restrict__ idx, float* __restrict__ dZ,
                                                               T* __restrict__ dZb, float* __restrict__ row_loss) {
@@ -182,10 +361,15 @@ __global__ void __launch_bounds__(kThreads) softmax_ce_kernel(const float* __res
     const float inv = 1.f / se;
     for (int j = lo + threadIdx.x; j < lo + width; j += kThreads) {
       const float d = (__expf(z[j] - mx) * inv - (j == lab ? 1.f : 0.f)) * invB;
-      dZ[static_cast<size_t>(b) * D + j] = d;
-      if (dZb) dZb[static_cast<size_t>(b) * D + j] = from_float<T>(d);
+      dZ[static_cast<size_t>(b) * ldz + j] = d;
+      if (dZb) dZb[static_cast<size_t>(b) * ldz + j] = from_float<T>(d);
     }
     loss += __logf(se) + mx - z[lab];
+  }
+  // padding columns of the gradient rows
+  for (int j = D + threadIdx.x; j < ldz; j += kThreads) {
+    dZ[static_cast<size_t>(b) * ldz + j] = 0.f;
+    if (dZb) dZb[static_cast<size_t>(b) * ldz + j] = from_float<T>(0.f);
   }
   if (threadIdx.x == 0) row_loss[b] = loss;
 }
@@ -198,12 +382,22 @@ __global__ void __launch_bounds__(kThreads) mean_kernel(const float* __restrict_
   if (threadIdx.x == 0) out[0] = s / static_cast<float>(n);
 }
 
-__global__ void colsum_kernel(const float* __restrict__ dZ, int B, int N, float* __restrict__ db) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= N) return;
+// db[j] = sum_b dZ[b][j]: a workgroup per 64 columns, its 4 waves summing a
+// quarter of the rows each (coalesced across the columns), then the four
+// partial sums added in a fixed order.
+__global__ void colsum_kernel(const float* __restrict__ dZ, int B, int N, int ld, float* __restrict__ db) {
+  __shared__ float part[4][64];
+  const int c = threadIdx.x & 63, g = threadIdx.x >> 6;
+  const int j = blockIdx.x * 64 + c;
   float s = 0.f;
-  for (int b = 0; b < B; ++b) s += dZ[static_cast<size_t>(b) * N + j];
-  db[j] = s;
+  if (j < N) {
+    const int b0 = g * ((B + 3) / 4), b1 = min(B, b0 + (B + 3) / 4);
+#pragma unroll 8
+    for (int b = b0; b < b1; ++b) s += dZ[static_cast<size_t>(b) * ld + j];
+  }
+  part[g][c] = s;
+  __syncthreads();
+  if (g == 0 && j < N) db[j] = (part[0][c] + part[1][c]) + (part[2][c] + part[3][c]);
 }
 
 template <typename T>
@@ -479,15 +673,43 @@ unsigned grid_for(size_t n) {
 
 }  // namespace
 
+GemmPlan gemm_plan(int M, int N, int K) {
+  GemmPlan p;
+  const long long t128 = static_cast<long long>((M + 127) / 128) * ((N + 127) / 128);
+  p.big = t128 >= 256;
+  const long long tiles = p.big ? t128 : static_cast<long long>((M + 63) / 64) * ((N + 63) / 64);
+  // split K until about 256 workgroups, keeping >= 8 chunks of 32 per part
+  p.kparts = 1;
+  while (tiles * p.kparts * 2 <= 512 && K / (p.kparts * 2) >= 256 && p.kparts < 16) p.kparts *= 2;
+  return p;
+}
+
+size_t gemm_part_floats(int M, int N, int K) {
+  const GemmPlan p = gemm_plan(M, N, K);
+  return p.kparts > 1 ? static_cast<size_t>(p.kparts) * M * N : 0;
+}
+
 hipError_t launch_gemm(const GemmArgs& g, int bf16, hipStream_t s) {
   if (g.M <= 0 || g.N <= 0) return hipSuccess;
   if (!((g.sak == 1) || (g.sai == 1)) || !((g.sbk == 1) || (g.sbj == 1))) return hipErrorInvalidValue;
-  dim3 grid((g.N + 63) / 64, (g.M + 63) / 64);
-  if (grid.y > 65535) return hipErrorInvalidValue;
-  if (bf16)
-    hipLaunchKernelGGL(gemm_kernel<__bf16>, grid, dim3(kThreads), 0, s, g);
-  else
+  if (!bf16) {
+    dim3 grid((g.N + 63) / 64, (g.M + 63) / 64);
+    if (grid.y > 65535) return hipErrorInvalidValue;
     hipLaunchKernelGGL(gemm_kernel<float>, grid, dim3(kThreads), 0, s, g);
+    return hipGetLastError();
+  }
+  GemmPlan pl = gemm_plan(g.M, g.N, g.K);
+  if (pl.kparts > 1 && (!g.part || g.part_floats < static_cast<size_t>(pl.kparts) * g.M * g.N)) pl.kparts = 1;
+  const int T = pl.big ? 128 : 64;
+  dim3 grid((g.N + T - 1) / T, (g.M + T - 1) / T, pl.kparts);
+  if (grid.y > 65535) return hipErrorInvalidValue;
+  if (pl.big)
+    hipLaunchKernelGGL((gemm_bf16_tiled<2, 2, 32>), grid, dim3(kThreads), 0, s, g, pl.kparts, g.part);
+  else
+    hipLaunchKernelGGL((gemm_bf16_tiled<1, 1, 64>), grid, dim3(kThreads), 0, s, g, pl.kparts, g.part);
+  if (pl.kparts > 1)
+    hipLaunchKernelGGL(gemm_reduce_kernel, dim3(grid_for(static_cast<size_t>(g.M) * g.N)), dim3(kThreads), 0, s, g,
+                       pl.kparts, static_cast<const float*>(g.part));
   return hipGetLastError();
 }
 
@@ -504,15 +726,15 @@ hipError_t launch_standardise(const float* x, const int32_t* idx, int B, int D, 
   return hipGetLastError();
 }
 
-hipError_t launch_softmax_ce(const float* logits, int B, int D, int n_t, int n_s, const int32_t* lab_t,
+hipError_t launch_softmax_ce(const float* logits, int B, int D, int ldz, int n_t, int n_s, const int32_t* lab_t,
                              const int32_t* lab_s, const int32_t* idx, float* dZ, void* dZb, int bf16,
                              float* row_loss, hipStream_t s) {
   if (B <= 0) return hipSuccess;
   if (bf16)
-    hipLaunchKernelGGL(softmax_ce_kernel<__bf16>, dim3(B), dim3(kThreads), 0, s, logits, B, D, n_t, n_s, lab_t,
+    hipLaunchKernelGGL(softmax_ce_kernel<__bf16>, dim3(B), dim3(kThreads), 0, s, logits, B, D, ldz, n_t, n_s, lab_t,
                        lab_s, idx, dZ, static_cast<__bf16*>(dZb), row_loss);
   else
-    hipLaunchKernelGGL(softmax_ce_kernel<float>, dim3(B), dim3(kThreads), 0, s, logits, B, D, n_t, n_s, lab_t, lab_s,
+    hipLaunchKernelGGL(softmax_ce_kernel<float>, dim3(B), dim3(kThreads), 0, s, logits, B, D, ldz, n_t, n_s, lab_t, lab_s,
                        idx, dZ, static_cast<float*>(dZb), row_loss);
   return hipGetLastError();
 }
@@ -523,9 +745,9 @@ hipError_t launch_mean(const float* row_loss, int B, float* loss, hipStream_t s)
   return hipGetLastError();
 }
 
-hipError_t launch_colsum(const float* dZ, int B, int N, float* db, hipStream_t s) {
+hipError_t launch_colsum(const float* dZ, int B, int N, int ld, float* db, hipStream_t s) {
   if (N <= 0) return hipSuccess;
-  hipLaunchKernelGGL(colsum_kernel, dim3((N + kThreads - 1) / kThreads), dim3(kThreads), 0, s, dZ, B, N, db);
+  hipLaunchKernelGGL(colsum_kernel, dim3((N + 63) / 64), dim3(kThreads), 0, s, dZ, B, N, ld, db);
   return hipGetLastError();
 }
 

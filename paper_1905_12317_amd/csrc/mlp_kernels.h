@@ -22,7 +22,19 @@ struct GemmArgs {
   const float* mask;
   long long ldm;
   int relu;
+  float* part;         // bf16 GEMMs split over K: FP32 partial sums (gemm_part_floats), or null
+  size_t part_floats;
 };
+
+// Launch shape of a bf16 GEMM: 128 x 128 tiles when there are at least 256
+// of them, else 64 x 64; K split into kparts when the grid is small.
+struct GemmPlan {
+  bool big = false;
+  int kparts = 1;
+};
+GemmPlan gemm_plan(int M, int N, int K);
+// FP32 workspace a bf16 GEMM of this shape needs for its K parts (0: none)
+size_t gemm_part_floats(int M, int N, int K);
 
 // bf16 = 1: operands are bf16 (v_mfma_f32_32x32x16_bf16); 0: FP32 operands
 // (v_mfma_f32_32x32x2_f32).
@@ -36,13 +48,13 @@ hipError_t launch_standardise(const float* x, const int32_t* idx, int B, int D, 
 // Two-head softmax cross-entropy, one row per workgroup: labels of row b are
 // lab_t[r], lab_s[r] with r = idx ? idx[b] : b.  dZ = (softmax - onehot) / B
 // (FP32 and operand-type copies), row_loss[b] = CE_t + CE_s.
-hipError_t launch_softmax_ce(const float* logits, int B, int D, int n_t, int n_s, const int32_t* lab_t,
+hipError_t launch_softmax_ce(const float* logits, int B, int D, int ldz, int n_t, int n_s, const int32_t* lab_t,
                              const int32_t* lab_s, const int32_t* idx, float* dZ, void* dZb, int bf16,
                              float* row_loss, hipStream_t s);
 // loss = sum(row_loss[0..B)) / B, one workgroup, fixed order.
 hipError_t launch_mean(const float* row_loss, int B, float* loss, hipStream_t s);
 // db[j] = sum_b dZ[b][j]
-hipError_t launch_colsum(const float* dZ, int B, int N, float* db, hipStream_t s);
+hipError_t launch_colsum(const float* dZ, int B, int N, int ld, float* db, hipStream_t s);
 // AdamW on n parameters; refreshes the operand-type copy wc if non-null.
 hipError_t launch_adamw(float* w, const float* g, float* m, float* v, size_t n, float lr, float beta1, float beta2,
                         float eps, float wd, float bc1, float bc2, void* wc, int bf16, hipStream_t s);

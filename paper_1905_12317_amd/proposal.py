@@ -76,16 +76,36 @@ def train(net: F.MLP, feats, lab_t, lab_s, perms, batch: int, lr: float, wd: flo
     return losses
 
 
+def full_search_labeler(plan: F.Plan, tmpl_coeffs, stream=None):
+    """Labels by the plan's full search: coefficients -> (best template,
+    best pose) device tensors."""
+    def label(ic):
+        _, best = plan.align_coeffs(ic, tmpl_coeffs, stream=stream)
+        return F.best_template(best, stream=stream)
+    return label
+
+
+def refined_labeler(coarse: F.Plan, fine: F.Plan, tmpl_coeffs, k: int = 4, stream=None):
+    """Labels by the two-pass search (ftk_align_refined: the coarse form over
+    every template, the fine form on each image's k best)."""
+    def label(ic):
+        _, bt, bp = F.align_refined(coarse, fine, ic, tmpl_coeffs, k, stream=stream)
+        return bt, bp
+    return label
+
+
 def train_online(net: F.MLP, plan: F.Plan, clean, tmpl_coeffs, shift_bin: np.ndarray, noise_fn, perms,
                  kind: str, n_r: int, n_q: int, batch: int, lr: float, wd: float = 1e-2, lr_final=None,
-                 label_chunk: int = 4096, stream=None):
+                 label_chunk: int = 4096, stream=None, labeler=None, log=None):
     """Training with fresh noise every epoch: epoch e re-noises the clean
     device images [nI][n][n] with noise_fn(e) (a device tensor of the same
     shape, drawn by the caller), labels them with the full FTK search
     against the template coefficients, takes their features and runs one
     epoch of minibatch AdamW in the order perms[e].  The input
-    standardisation is set from the first epoch's features.  Returns the
-    mean loss per epoch."""
+    standardisation is set from the first epoch's features.  labeler:
+    coefficients -> (best template, best pose), default the plan's full
+    search; log(e, loss) is called after each epoch.  Returns the mean loss
+    per epoch."""
     import torch
     nI = clean.shape[0]
     sb = torch.as_tensor(shift_bin, dtype=torch.int32, device=clean.device)
@@ -99,12 +119,12 @@ def train_online(net: F.MLP, plan: F.Plan, clean, tmpl_coeffs, shift_bin: np.nda
     feats = torch.empty((nI, F.feature_count(kind, n_r, n_q)), dtype=torch.float32, device=clean.device)
     losses = []
     step = 0
+    labeler = labeler or full_search_labeler(plan, tmpl_coeffs, stream)
     for e, order in enumerate(perms):
         imgs = clean + noise_fn(e)
         for i0 in range(0, nI, label_chunk):
             ic = plan.transform(imgs[i0:i0 + label_chunk].contiguous(), stream=stream)
-            _, best = plan.align_coeffs(ic, tmpl_coeffs, stream=stream)
-            bt, bp = F.best_template(best, stream=stream)
+            bt, bp = labeler(ic)
             lab_t[i0:i0 + label_chunk] = bt
             lab_s[i0:i0 + label_chunk] = sb[bp[:, 1].long()]
             F.features(plan, ic, n_r, n_q, kind=kind, out=feats[i0:i0 + label_chunk], stream=stream)
@@ -120,6 +140,8 @@ def train_online(net: F.MLP, plan: F.Plan, clean, tmpl_coeffs, shift_bin: np.nda
             acc += loss
             step += 1
         losses.append(float(acc.item()) / steps)
+        if log:
+            log(e, losses[-1])
     return losses
 
 

@@ -57,7 +57,7 @@ def test_proposal_recall_and_gain(lib):
     dims = [F.feature_count(kind, n_r, n_q), 1024, 1024, n_t + n_s]
     net = F.MLP(dims, n_t, n_s, "bf16", max_batch=1024)
     net.set_params(synth.mlp_init(4, dims))
-    perms = [synth.permutation(100 + e, n_clean) for e in range(30)]
+    perms = [synth.permutation(100 + e, n_clean) for e in range(60)]
     t0 = time.perf_counter()
     losses = PR.train_online(net, plan, clean, tc, bins, lambda e: synth.gaussian_noise(1000 + e, sig, n), perms,
                              kind, n_r, n_q, batch=256, lr=2e-3, wd=1e-2)
