@@ -237,14 +237,14 @@ def cpu_baseline(inputs, w, shifts, n_img=8, n_tmp=48, n_dir=(2, 4)):
             "direct_X_pairs_per_s": n_d / dt_dir}
 
 
-RAGGED = dict(name="ragged_c4", stacks=64, seed=4, scale=0.25, nblob=60, snr=0.05, eps=1e-3)
+RAGGED = dict(name="ragged_c4", stacks=64, seed=4, nblob=60, snr=0.05, eps=1e-3)
 PROPOSAL = dict(name="proposal_c5", n=128, M=64, Qa=256, R=4.0, n_templates=8192, n_clean=16384, n_val=1024,
                 n_test=2048, nblob=60, snr=0.05, eps=1e-3, epochs=12, n_r=16, n_q=8, topk=32, hidden=1024, seed=5)
 
 
 def bench_ragged(args):
     """64 stacks of uneven n, template and image counts and shift radii (the
-    ragged workload, image and template counts scaled by RAGGED['scale']),
+    ragged workload, image and template counts scaled by --ragged-scale),
     split-bf16 form: one ftk_batch run (--lanes lanes, one hipGraph, autotuned
     launch shapes) against the same stacks aligned one ftk_align at a time."""
     import torch
@@ -252,7 +252,7 @@ def bench_ragged(args):
     from paper_1905_12317_amd import ftk
     w = RAGGED
     t0 = time.perf_counter()
-    specs = synth.ragged_stack_specs(w["seed"], count=w["stacks"], scale=w["scale"])
+    specs = synth.ragged_stack_specs(w["seed"], count=w["stacks"], scale=args.ragged_scale)
     stacks, flop = [], 0.0
     for i, sp in enumerate(specs):
         s = synth.make_alignment_set(1000 * w["seed"] + i, sp["n"], sp["n_templates"], sp["n_images"], w["nblob"],
@@ -284,17 +284,17 @@ def bench_ragged(args):
     ev1.record(stream)
     stream.synchronize()
     ms_batch = ev0.elapsed_time(ev1) / args.steps
-    # the same stacks one call at a time, default launch shapes
-    with torch.cuda.stream(stream):
-        for st in stacks:
-            st["plan"].align(st["images"], st["templates"], best=st["best"], stream=stream)
-        stream.synchronize()
-        ev0.record(stream)
-        for _ in range(args.steps):
-            for st in stacks:
-                st["plan"].align(st["images"], st["templates"], best=st["best"], stream=stream)
-        ev1.record(stream)
-        stream.synchronize()
+    # the same stacks one after another on one lane, no graph, default launch
+    # shapes: the single-stack ftk_align path, sharing one workspace (64
+    # plans holding a staging buffer each would not fit at full size)
+    S = ftk.Batch(stacks, lanes=1, graph=False, autotune=False, stream=stream)
+    S.run(stream)
+    stream.synchronize()
+    ev0.record(stream)
+    for _ in range(args.steps):
+        S.run(stream)
+    ev1.record(stream)
+    stream.synchronize()
     ms_seq = ev0.elapsed_time(ev1) / args.steps
     info = B.info()
     achieved = flop / (ms_batch / 1e3)
@@ -304,7 +304,7 @@ def bench_ragged(args):
         "warmup": args.warmup, "ms_per_step": ms_batch, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "bf16x3->f32", "data": "synthetic",
         "config": {"workload": f"{w['name']}: 64 stacks, n in {{64,96,128,192}}, M=n/2, Qa=2n, templates "
-                               f"log-uniform 100-4000 and images 16-256 scaled by {w['scale']}, shift radius "
+                               f"log-uniform 100-4000 and images 16-256 scaled by {args.ragged_scale}, shift radius "
                                f"2-8 px (0.5 px lattice), 60-blob templates, SNR {w['snr']}, eps={w['eps']}",
                    "pairs": pairs, "lanes": info["lanes"], "graph_nodes": info["graph_nodes"],
                    "autotune_s": tune_s, "sequential_ms_per_step": ms_seq, "batch_speedup": ms_seq / ms_batch},
@@ -444,7 +444,10 @@ def main():
                          "learned-proposal measurements, each printing its own JSON line")
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--form", default="all", choices=["fp32", "bf16x3", "fp16x3", "fp16", "fp16+bf16x3", "all"])
+    ap.add_argument("--form", default="all", choices=["fp32", "bf16x3", "fp16x3", "fp16", "fp16+bf16x3", "bft", "all"],
+                    help="the forms to run (bft: brute-force translations alone, its own JSON line)")
+    ap.add_argument("--ragged-scale", type=float, default=1.0,
+                    help="ragged workload: image and template counts scaled by this (1.0: the full workload)")
     ap.add_argument("--lanes", type=int, default=4, help="ragged workload: concurrent lanes of the batch (1-4)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-weighted", action="store_true", help="skip the weighted-SVD measurement")
@@ -485,6 +488,17 @@ def main():
     shifts = synth.shift_lattice(w["R"])
     log(f"inputs generated in {time.perf_counter() - t:.1f} s: {w['n_images']} x {w['n_templates']} "
         f"n={w['n']} N={len(shifts)}")
+    if args.form == "bft":
+        rb = run_form("bft", inputs, w, args.steps, args.warmup, shifts)
+        log(f"[bft] {rb['ms_per_step']:.2f} ms/step, {rb['pairs_per_s']:.4g} pairs/s, stages {rb['stages']}")
+        print(json.dumps({"metric": "pairs/s of brute-force translations (the paper's comparison method)",
+                          "value": rb["pairs_per_s"], "unit": "pairs/s", "n_gpus": 1, "steps": args.steps,
+                          "warmup": args.warmup, "ms_per_step": rb["ms_per_step"], "higher_is_better": True,
+                          "dtype": "f32", "data": "synthetic",
+                          "config": {"workload": w["name"],
+                                     "stage_ms_per_step": {k: v[0] / args.steps for k, v in rb["stages"].items()}}}),
+              flush=True)
+        return
     forms = ["fp32", "bf16x3", "fp16x3", "fp16", "fp16+bf16x3"] if args.form == "all" else [args.form]
     results = {}
     for f in forms:
