@@ -316,6 +316,33 @@ int ftk_plan_set_rotations(ftk_plan* plan, int upsample);
 int ftk_bft_align(ftk_plan* plan, const float* images, int nA, const float* templates, int nB, float* X,
                   ftk_pose* best, void* stream);
 
+/* Brute-force rotations (Section 6.1, eq. 2dconv), the paper's other
+ * comparison method: for every rotation gamma_r = 2 pi r / R (R = Q times
+ * the plan's rotation upsampling factor, 1 unless ftk_plan_set_rotations)
+ * the correlation of the image with the rotated template through the 2D
+ * convolution theorem on the Cartesian Fourier grid of the pixel DFT,
+ *   X(delta, r) = pi^2 sum_k exp(-i k . delta) Ahat(k) conj(Bhat(R_gamma k)),
+ * k = pi (u, v) over the integer points of the disk u^2 + v^2 <= (n/2)^2,
+ * Ahat and Bhat the type-2 NUFFT of the pixels at those points (rotated for
+ * the template).  It approximates the same inner product as ftk_align on a
+ * Cartesian instead of a polar quadrature (the two agree to rounding for
+ * images whose spectra vanish at Kmax; they differ by the quadratures'
+ * error otherwise).  The shifts are those of ftk_set_shifts, evaluated on
+ * the product grid of their distinct x and y offsets (any list is allowed;
+ * lattices cost least).  FP32 whatever the plan's precision form; the SVD
+ * tables are not used.  Arguments, ownership and results as ftk_bft_align:
+ * pixels in, X [nA][nB][N][R] optional, best [nA][nB] (rotation index in
+ * [0, R)); asynchronous on the stream after a short host wait for the
+ * call's tables.  The plan's workspace grows by the image spectra
+ * ((n/2 + 1) x (n + 4) complex per image) and the spectra of one chunk of
+ * templates at all R rotations (R times that per template), templates
+ * chunked to the staging size of ftk_plan_set_tuning.  Stage timing: the
+ * fine grids stage 0, the spectra stage 6, the correlation stage 7.
+ * Errors: FTK_EINVAL, FTK_ESTATE (no shifts), FTK_ENOMEM, FTK_EUNSUPPORTED
+ * (a plan with a CTF, R not a multiple of 64), FTK_EDEVICE. */
+int ftk_bfr_align(ftk_plan* plan, const float* images, int nA, const float* templates, int nB, float* X,
+                  ftk_pose* best, void* stream);
+
 /* FP64 planning tables, host only (no device work, usable without a GPU):
  * the same truncation and factor tables a plan with these arguments uses.
  * Pass NULL for any output not wanted; sizes come from *H_out (call once
@@ -352,6 +379,8 @@ int ftk_plan_tables_ctf(int n, int K, double W, double eps, const ftk_ctf_t* ctf
  *   4 operand preparation (templates embedded, and split for bf16x3,
  *     into Step 1's lane order, once per call)
  *   5 translated coefficients of ftk_bft_align
+ *   6 Cartesian spectra of ftk_bfr_align (fine grid interpolated)
+ *   7 correlation of ftk_bfr_align
  * ftk_plan_profile(plan, 1) enables (and clears), 0 disables.
  * ftk_plan_stage_times waits for the recorded events, writes per-stage sums
  * of elapsed milliseconds and launch counts into ms[nstages] and

@@ -27,7 +27,7 @@ DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-I", os.path.join(ROOT, "include"),
           "-Wall", "-Wno-unused-result"]
 
-SOURCES = ["planner.cpp", "kern_transform.hip", "kern_align.hip", "kern_align_bf16.hip", "kern_align_fp16.hip", "kern_step1.hip", "ftk_api.hip", "ftk_batch.hip", "kern_mlp.hip", "ftk_mlp.hip", "ftk_refine.hip", "ftk_noalloc.hip", "kern_bft.hip", "ftk_bft.hip"]
+SOURCES = ["planner.cpp", "kern_transform.hip", "kern_align.hip", "kern_align_bf16.hip", "kern_align_fp16.hip", "kern_step1.hip", "ftk_api.hip", "ftk_batch.hip", "kern_mlp.hip", "ftk_mlp.hip", "ftk_refine.hip", "ftk_noalloc.hip", "kern_bft.hip", "ftk_bft.hip", "kern_bfr.hip", "ftk_bfr.hip"]
 
 
 def _compile(src: str) -> str:

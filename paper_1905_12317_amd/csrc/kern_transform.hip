@@ -184,6 +184,7 @@ __global__ void __launch_bounds__(1024) transform_kernel(TransformArgs p) {
     }
     __syncthreads();
   }
+  if (!p.coeffs) return;  // the fine grid only (uniform over the launch)
   // ---- 2+3. per ring: interpolate half the angles, fill by symmetry, ring DFT
   const int half = Qa / 2;
   float2* ring = lds + wave * 2 * Qa;

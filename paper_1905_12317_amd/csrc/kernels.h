@@ -7,7 +7,7 @@
 
 struct TransformArgs {
   const float* imgs;     // [cnt][n][n]
-  float2* coeffs;        // [cnt][Qa][M]
+  float2* coeffs;        // [cnt][Qa][M], or null: stop after the fine grid (scratchG)
   float2* polar;         // [cnt][M][Qa] ring samples Ahat(k_m, psi_p) / Qa, or null
   float2* scratchH;      // [cnt][n][nf]
   float2* scratchG;      // [cnt][nf][nf] (transposed: [l2][l1])
@@ -156,3 +156,39 @@ hipError_t launch_step1_bft(const Step1Args& args, hipStream_t stream);
 // rotation), as U passes of the Qa-point transform on phase-shifted Xhat.
 size_t xhat_rotate_lds_bytes(int Qa, int nwaves, int up);
 hipError_t launch_xhat_rotate(const Step3Args& args, hipStream_t stream);
+
+// Brute-force rotations (Section 6.1, eq. 2dconv).  Spectra on the
+// Cartesian disk grid k = pi (u, v), u^2 + v^2 <= V^2 (V = n / 2), stored as
+// half-disk rows v = 0..V of Up complex values at j = u + V (zero outside
+// the disk and for j > 2V), per image and rotation: out[img][R][V + 1][Up].
+struct BfrSpectraArgs {
+  const float2* grid;   // [cnt][nf][nf] fine grids of the transform's first stage ([l2][l1])
+  float2* out;          // [cnt][R or 1][V + 1][Up]
+  const double* cs;     // [R / 4] (cos, sin) of gamma_r = 2 pi r / R (quarter form only)
+  int cnt, nf, w, V, Up, R;
+  int quarter;          // 1: rotations r < R / 4 over the full disk, scattered to all R by quarter turns
+  double s_per_u;       // fine-grid units per unit of u: pi dx / h
+  float beta;           // spreading kernel shape
+  float scale;          // the grid holds Ahat / Qa
+};
+hipError_t launch_bfr_spectra(const BfrSpectraArgs& args, hipStream_t stream);
+
+// The correlation over the product grid of the requested shifts' x and y
+// offsets: rows are images (64 per workgroup), columns (template, rotation,
+// x offset) (32 per workgroup); per Fourier row v an MFMA sum over u, then
+// the y offsets of the pass accumulated in registers; argmax keys and X.
+constexpr int kBfrDy = 17;  // y offsets per pass
+struct BfrCorrArgs {
+  const float2* sa;     // image spectra [nA][V + 1][Up]
+  const float2* sb;     // template spectra of the chunk [nBc][R][V + 1][Up]
+  const float2* ex;     // [Dx][Up] exp(-2 pi i (j - V) x_ix / n)
+  const float2* ey;     // [Dy_pad][V + 1] pi^2 c_v exp(-2 pi i v y_iy / n), c_0 = 1, c_v = 2
+  const int4* chunks;   // [nch] (v, first j, K-steps of 4, last chunk of its row)
+  const int* head;      // [Dx * Dy] lowest shift index at (x_ix, y_iy), -1 for none
+  const int* nxt;       // [N] next shift index at the same point, -1 for none
+  unsigned long long* keys;  // [nA][nB] pose keys (index shift * R + rotation)
+  float* X;             // [nA][nB][N][R] or null
+  int nA, nB, B0, nBc, R, Dx, Dy, iy0, N, V, Up, nch;
+};
+size_t bfr_corr_lds_bytes(int V);
+hipError_t launch_bfr_corr(const BfrCorrArgs& args, hipStream_t stream);

@@ -71,12 +71,15 @@ struct Workspace {
   DevBuf refine;     // lists and poses of the two-pass alignment
   DevBuf polar, ta;  // brute-force translations: ring samples, translated coefficients
   DevBuf xhat;       // rotation upsampling: Xhat of a chunk of pairs
+  DevBuf bfr_a, bfr_b, bfr_tab;  // brute-force rotations: Cartesian spectra of images, of templates, tables
   size_t bytes() const {
     return tr_h.bytes + tr_g.bytes + coef_a.bytes + coef_b.bytes + stage.bytes + keys.bytes + tmpl.bytes +
-           scales.bytes + refine.bytes + polar.bytes + ta.bytes + xhat.bytes;
+           scales.bytes + refine.bytes + polar.bytes + ta.bytes + xhat.bytes + bfr_a.bytes + bfr_b.bytes +
+           bfr_tab.bytes;
   }
   void release() {
-    for (DevBuf* b : {&tr_h, &tr_g, &coef_a, &coef_b, &stage, &keys, &tmpl, &scales, &refine, &polar, &ta, &xhat})
+    for (DevBuf* b : {&tr_h, &tr_g, &coef_a, &coef_b, &stage, &keys, &tmpl, &scales, &refine, &polar, &ta, &xhat,
+                      &bfr_a, &bfr_b, &bfr_tab})
       b->release();
   }
 };

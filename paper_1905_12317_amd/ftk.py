@@ -73,7 +73,7 @@ POSE_DTYPE = np.dtype([("value", np.float32), ("shift", np.int32), ("rot", np.in
 
 #: every symbol include/ftk.h declares
 EXPORTS = ["ftk_plan_create", "ftk_plan_destroy", "ftk_plan_info", "ftk_set_shifts", "ftk_transform",
-           "ftk_align_coeffs", "ftk_align_coeffs_noalloc", "ftk_align", "ftk_bft_align", "ftk_plan_set_rotations", "ftk_plan_create_ctf", "ftk_set_poses",
+           "ftk_align_coeffs", "ftk_align_coeffs_noalloc", "ftk_align", "ftk_bft_align", "ftk_bfr_align", "ftk_plan_set_rotations", "ftk_plan_create_ctf", "ftk_set_poses",
            "ftk_plan_tables_ctf", "ftk_plan_set_shift_windows", "ftk_plan_tables", "ftk_plan_create_weighted",
            "ftk_plan_tables_weighted", "ftk_plan_profile", "ftk_plan_stage_times",
            "ftk_plan_set_tuning", "ftk_plan_get_tuning", "ftk_batch_create", "ftk_batch_run", "ftk_batch_info",
@@ -131,6 +131,7 @@ def lib() -> ctypes.CDLL:
     L.ftk_align_coeffs_noalloc.argtypes = [vp, vp, i, vp, i, vp, vp, vp]
     L.ftk_align.argtypes = [vp, vp, i, vp, i, vp, vp, vp]
     L.ftk_bft_align.argtypes = [vp, vp, i, vp, i, vp, vp, vp]
+    L.ftk_bfr_align.argtypes = [vp, vp, i, vp, i, vp, vp, vp]
     L.ftk_plan_set_rotations.argtypes = [vp, i]
     L.ftk_plan_create_ctf.argtypes = [ctypes.POINTER(vp), i, i, i, d, d, i, ctypes.POINTER(Ctf)]
     L.ftk_set_poses.argtypes = [vp, vp, vp, i]
@@ -313,7 +314,8 @@ class Plan:
         _check(lib().ftk_plan_info(self._h, ctypes.byref(inf)), "ftk_plan_info")
         return inf.as_dict()
 
-    STAGES = ("transform", "step1", "step3", "bookkeeping", "operand_prep", "bft_translate")
+    STAGES = ("transform", "step1", "step3", "bookkeeping", "operand_prep", "bft_translate", "bfr_spectra",
+              "bfr_correlation")
 
     def profile(self, enable: bool = True):
         _check(lib().ftk_plan_profile(self._h, 1 if enable else 0), "ftk_plan_profile")
@@ -416,6 +418,17 @@ class Plan:
         X, best = self._outputs(images.shape[0], templates.shape[0], want_X, images.device, X, best)
         _check(lib().ftk_bft_align(self._h, _ptr(images), images.shape[0], _ptr(templates), templates.shape[0],
                                    _ptr(X), _ptr(best), _stream(stream)), "ftk_bft_align")
+        return X, best
+
+    def bfr_align(self, images, templates, want_X=False, X=None, best=None, stream=None):
+        """ftk_bfr_align: brute-force rotations (the paper's other comparison
+        method, FP32) on this plan's shifts and rotations; outputs as align()."""
+        import torch
+        _require_cuda(images, torch.float32, "images")
+        _require_cuda(templates, torch.float32, "templates")
+        X, best = self._outputs(images.shape[0], templates.shape[0], want_X, images.device, X, best)
+        _check(lib().ftk_bfr_align(self._h, _ptr(images), images.shape[0], _ptr(templates), templates.shape[0],
+                                   _ptr(X), _ptr(best), _stream(stream)), "ftk_bfr_align")
         return X, best
 
 
