@@ -94,22 +94,27 @@ REFINE_K = 4  # templates per image re-aligned by the split form in the two-pass
 CTF_PARAMS = dict(wavelength_A=0.019687, cs_mm=2.7, amplitude_contrast=0.07, pixel_A=2.0,
                   defocus_min_A=14000.0, defocus_max_A=16000.0)
 CTF_DEFOCI = [14000.0, 14500.0, 15000.0, 15500.0, 16000.0]
+BFR_TEMPLATES = 256  # templates of the brute-force-rotation sample (all images)
 UPSAMPLE = 5  # rotation upsampling factor of the upsampled measurement (5 x 256 = 1280 rotations)
 WEIGHTED_EPS = 5e-3  # eps of the weighted-SVD plan: the paper plan's accuracy at eps = 1e-3 (see main)
 
 
-def run_form(form, inputs, w, steps, warmup, shifts, eps=None, weight=None, up=1, ctf=None, defoci=None):
+def run_form(form, inputs, w, steps, warmup, shifts, eps=None, weight=None, up=1, ctf=None, defoci=None,
+             n_images=None, n_templates=None):
     """One form over the workload.  "fp16+bf16x3" is the two-pass form: the
     FP16 form over every pair, then the split form on each image's REFINE_K
     best FP16 templates (ftk_align_refined).  "bft": brute-force
-    translations (ftk_bft_align, FP32), the paper's comparison method.  eps / weight: a plan other than
-    the workload's (the k-side weighted operator SVD)."""
+    translations (ftk_bft_align, FP32), "bfr": brute-force rotations
+    (ftk_bfr_align, FP32), the paper's comparison methods.  eps / weight: a
+    plan other than the workload's (the k-side weighted operator SVD).
+    n_images / n_templates: the first ones only (a sample of the workload)."""
     import torch
     from paper_1905_12317_amd import ftk
     dev = torch.device("cuda:0")
     two = form == "fp16+bf16x3"
     bft = form == "bft"
-    prec = "fp16" if two else ("fp32" if bft else form)
+    bfr = form == "bfr"
+    prec = "fp16" if two else ("fp32" if (bft or bfr) else form)
     P = ftk.Plan(w["n"], w["M"], w["Qa"], w["R"], eps or w["eps"], precision=prec, weight=weight, ctf=ctf)
     if ctf is not None:
         # poses: every shift at every defocus value
@@ -123,8 +128,8 @@ def run_form(form, inputs, w, steps, warmup, shifts, eps=None, weight=None, up=1
         Pf = ftk.Plan(w["n"], w["M"], w["Qa"], w["R"], w["eps"], precision="bf16x3")
         Pf.set_shifts(shifts)
     info = P.info()
-    images = torch.as_tensor(inputs.images, dtype=torch.float32, device=dev).contiguous()
-    templates = torch.as_tensor(inputs.templates, dtype=torch.float32, device=dev).contiguous()
+    images = torch.as_tensor(inputs.images[:n_images], dtype=torch.float32, device=dev).contiguous()
+    templates = torch.as_tensor(inputs.templates[:n_templates], dtype=torch.float32, device=dev).contiguous()
     nA, nB = images.shape[0], templates.shape[0]
     best = torch.empty((nA, nB, 3), dtype=torch.int32, device=dev)
     stream = torch.cuda.current_stream()
@@ -142,6 +147,8 @@ def run_form(form, inputs, w, steps, warmup, shifts, eps=None, weight=None, up=1
                                                                       stream=stream)
         elif bft:
             P.bft_align(images, templates, best=best, stream=stream)
+        elif bfr:
+            P.bfr_align(images, templates, best=best, stream=stream)
         else:
             P.align(images, templates, best=best, stream=stream)
 
@@ -179,6 +186,18 @@ def run_form(form, inputs, w, steps, warmup, shifts, eps=None, weight=None, up=1
     ms_step = ms_total / steps
     return dict(form=form, info=info, ms_per_step=ms_step, wall_s=wall, pairs_per_s=nA * nB / (ms_step / 1e3),
                 stages=stages, poses=poses, img_best=img_best)
+
+
+def bfr_flop_per_pair(n, R, shifts):
+    """Algorithmic flop of brute-force rotations per pair: per rotation the
+    product Ahat conj(Bhat_r) on the half-disk rows (6 per point), the sums
+    over u for every x offset (8 per point and offset) and the real parts
+    over v for every (x, y) offset (4 per row and offset pair)."""
+    V = n // 2
+    pts = sum(2 * math.isqrt(V * V - v * v) + 1 for v in range(V + 1))
+    dx = len(np.unique(np.asarray(shifts)[:, 0]))
+    dy = len(np.unique(np.asarray(shifts)[:, 1]))
+    return R * (6 * pts + 8 * dx * pts + 4 * dx * dy * (V + 1))
 
 
 def image_best(poses):
@@ -444,7 +463,8 @@ def main():
                          "learned-proposal measurements, each printing its own JSON line")
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--form", default="all", choices=["fp32", "bf16x3", "fp16x3", "fp16", "fp16+bf16x3", "bft", "all"],
+    ap.add_argument("--form", default="all",
+                    choices=["fp32", "bf16x3", "fp16x3", "fp16", "fp16+bf16x3", "bft", "bfr", "all"],
                     help="the forms to run (bft: brute-force translations alone, its own JSON line)")
     ap.add_argument("--ragged-scale", type=float, default=1.0,
                     help="ragged workload: image and template counts scaled by this (1.0: the full workload)")
@@ -452,6 +472,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-weighted", action="store_true", help="skip the weighted-SVD measurement")
     ap.add_argument("--no-bft", action="store_true", help="skip the brute-force-translation measurement")
+    ap.add_argument("--no-bfr", action="store_true", help="skip the brute-force-rotation measurement")
     ap.add_argument("--no-upsample", action="store_true", help="skip the rotation-upsampling measurement")
     ap.add_argument("--no-ctf", action="store_true", help="skip the joint translation-CTF measurement")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
@@ -497,6 +518,27 @@ def main():
                           "dtype": "f32", "data": "synthetic",
                           "config": {"workload": w["name"],
                                      "stage_ms_per_step": {k: v[0] / args.steps for k, v in rb["stages"].items()}}}),
+              flush=True)
+        return
+    if args.form == "bfr":
+        # brute-force rotations over the whole workload (a few seconds per step)
+        steps, warm = min(args.steps, 3), min(args.warmup, 1)
+        rb = run_form("bfr", inputs, w, steps, warm, shifts)
+        log(f"[bfr] {rb['ms_per_step']:.2f} ms/step, {rb['pairs_per_s']:.4g} pairs/s, stages {rb['stages']}")
+        pairs = w["n_images"] * w["n_templates"]
+        fl = bfr_flop_per_pair(w["n"], w["Qa"], shifts)
+        corr_ms = rb["stages"]["bfr_correlation"][0] / steps
+        achieved = fl * pairs / (corr_ms / 1e3) / 1e12
+        print(json.dumps({"metric": "pairs/s of brute-force rotations (the paper's comparison method)",
+                          "value": rb["pairs_per_s"], "unit": "pairs/s", "n_gpus": 1, "steps": steps,
+                          "warmup": warm, "ms_per_step": rb["ms_per_step"], "higher_is_better": True,
+                          "dtype": "f32", "data": "synthetic",
+                          "config": {"workload": w["name"], "rotations": w["Qa"],
+                                     "algorithmic_gflop_per_pair": fl / 1e9,
+                                     "stage_ms_per_step": {k: v[0] / steps for k, v in rb["stages"].items()}},
+                          "roofline": {"kernel": "bfr_corr (FP32 MFMA u sums + y-offset accumulation, argmax)",
+                                       "bound": "mfma", "achieved": achieved, "peak": PEAK_FP32_MFMA / 1e12,
+                                       "unit": "TFLOP/s", "frac": achieved / (PEAK_FP32_MFMA / 1e12), "traffic": None}}),
               flush=True)
         return
     forms = ["fp32", "bf16x3", "fp16x3", "fp16", "fp16+bf16x3"] if args.form == "all" else [args.form]
@@ -610,6 +652,29 @@ def main():
             "best_pose_agreement_vs_ftk_fp32": agreement(rb["img_best"], results["fp32"]["img_best"])
             if "fp32" in results else None,
             "recall_true_template": recall(rb["img_best"], inputs)}
+    if not args.no_bfr:
+        # brute-force rotations (Section 6.1) on a sample of the workload (all
+        # images against the first BFR_TEMPLATES templates, so that the
+        # template-side spectra keep their share): the paper's FTK-versus-BFR
+        # axis on this GPU
+        bs = min(args.steps, 2)
+        rr = run_form("bfr", inputs, w, bs, 1, shifts, n_templates=BFR_TEMPLATES)
+        log(f"[bfr] {rr['ms_per_step']:.2f} ms/step, {rr['pairs_per_s']:.4g} pairs/s, stages {rr['stages']}")
+        fl = bfr_flop_per_pair(w["n"], Qa, shifts)
+        nbp = w["n_images"] * BFR_TEMPLATES
+        corr_s = rr["stages"]["bfr_correlation"][0] / bs / 1e3
+        same = None
+        if "fp32" in results:
+            fp = results["fp32"]["poses"][:, :BFR_TEMPLATES]
+            same = float(np.mean((fp["shift"] == rr["poses"]["shift"]) & (fp["rot"] == rr["poses"]["rot"])))
+        out["config"]["bfr"] = {
+            "sample": f"{w['n_images']} images x {BFR_TEMPLATES} templates",
+            "pairs_per_s": rr["pairs_per_s"], "ms_per_step": rr["ms_per_step"],
+            "stage_ms_per_step": {k: v[0] / bs for k, v in rr["stages"].items()},
+            "algorithmic_gflop_per_pair": fl / 1e9,
+            "correlation_tflops": fl * nbp / corr_s / 1e12,
+            "ftk_speedup_over_bfr": {k: v["pairs_per_s"] / rr["pairs_per_s"] for k, v in results.items()},
+            "pair_pose_agreement_vs_ftk_fp32": same}
     if not args.no_upsample:
         # rotation upsampling (remark after eq. 1dfft) to 5 Qa = 1280 rotations,
         # about the paper's n pi^2 rotation grid, for the split-fp16 form and BFT
