@@ -200,6 +200,55 @@ def bfr_flop_per_pair(n, R, shifts):
     return R * (6 * pts + 8 * dx * pts + 4 * dx * dy * (V + 1))
 
 
+def oracle_best_pose(inputs, w, shifts, results, chosen, n_img=16, seed=17):
+    """Part of the CPU-oracle leg: the FP64 oracle's per-image best
+    (template, shift, rotation) on a seeded sample of images against the
+    chosen form's and the FP32 form's.  Candidates per image: every template
+    whose FP32 best value lies within twice the FP32 error bound (1e-5 of the
+    pair scale, bounded through sqrt(X_BB(0, 0)) <= 4 pi for unit-L2
+    templates) of the image's FP32 best, plus the chosen form's pick; the
+    oracle's answer counts as decided where its margin over every other
+    candidate pose and over the bound of the other templates exceeds twice
+    the chosen form's bar (1e-3 of the pair scale; 1e-5 for FP32)."""
+    from oracle import ftk as O
+    plan = O.set_shifts(O.make_plan(w["n"], w["M"], w["Qa"], w["R"], w["eps"]), shifts)
+    v32 = results["fp32"]["poses"]
+    ct, cs, cr = results[chosen]["img_best"]
+    bar = 1e-5 if chosen == "fp32" else 1e-3
+    rng = np.random.default_rng(seed)
+    sample = np.sort(rng.choice(len(inputs.images), n_img, replace=False))
+    sb = 4.0 * math.pi
+    decided = same_chosen = same32 = 0
+    t0 = time.perf_counter()
+    for i in sample:
+        a = O.fb_coefficients(inputs.images[i], plan)
+        e32 = 1e-5 * math.sqrt(O.pair_scale(a, a, plan)) * sb
+        vals = v32["value"][i].astype(np.float64)
+        cand = sorted(set(np.nonzero(vals >= vals.max() - 2 * e32)[0].tolist()) | {int(ct[i])})
+        outside = np.delete(vals, cand)
+        others = [outside.max() + e32] if outside.size else []
+        best = None
+        for j in cand:
+            b = O.fb_coefficients(inputs.templates[j], plan)
+            X = np.real(O.ftk_X(a, b, plan))
+            v, si, ri, margin = O.best_pose(X)
+            if best is None or v > best[0]:
+                if best is not None:
+                    others.append(best[0])
+                best = (v, j, si, ri, margin, O.pair_scale(a, b, plan))
+            else:
+                others.append(v)
+        v, j, si, ri, margin, sc = best
+        margin = min([margin] + [v - o for o in others])
+        if margin > 2 * bar * sc:
+            decided += 1
+            same_chosen += int((int(ct[i]), int(cs[i]), int(cr[i])) == (j, si, ri))
+            j32 = int(np.argmax(vals))
+            same32 += int((j32, int(v32["shift"][i, j32]), int(v32["rot"][i, j32])) == (j, si, ri))
+    return {"images": n_img, "decided": decided, "chosen_form_equal": same_chosen, "fp32_equal": same32,
+            "seconds": time.perf_counter() - t0}
+
+
 def image_best(poses):
     """Per image: the template with the largest best value (the lower
     template number on ties) and its pose's shift and rotation."""
@@ -701,6 +750,9 @@ def main():
             "stage_ms_per_step": {k: v[0] / args.steps for k, v in rc["stages"].items()}}
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(inputs, w, shifts)
+        if "fp32" in results:
+            out["config"]["oracle_best_pose"] = oracle_best_pose(inputs, w, shifts, results, chosen)
+            log(f"[oracle check] {out['config']['oracle_best_pose']}")
     print(json.dumps(out), flush=True)
 
 
