@@ -206,10 +206,12 @@ def oracle_best_pose(inputs, w, shifts, results, chosen, n_img=16, seed=17):
     chosen form's and the FP32 form's.  Candidates per image: every template
     whose FP32 best value lies within twice the FP32 error bound (1e-5 of the
     pair scale, bounded through sqrt(X_BB(0, 0)) <= 4 pi for unit-L2
-    templates) of the image's FP32 best, plus the chosen form's pick; the
-    oracle's answer counts as decided where its margin over every other
-    candidate pose and over the bound of the other templates exceeds twice
-    the chosen form's bar (1e-3 of the pair scale; 1e-5 for FP32)."""
+    templates) of the image's FP32 best, plus the chosen form's pick.  The
+    oracle's answer counts as decided for a form where its margin over every
+    other candidate pose and over the bound of the other templates exceeds
+    twice that form's bar (FP32 1e-5 of the pair scale; the reduced forms
+    1e-3); both forms are compared on the images decided at the FP32 bar,
+    and the chosen form also on those decided at its own bar."""
     from oracle import ftk as O
     plan = O.set_shifts(O.make_plan(w["n"], w["M"], w["Qa"], w["R"], w["eps"]), shifts)
     v32 = results["fp32"]["poses"]
@@ -218,7 +220,8 @@ def oracle_best_pose(inputs, w, shifts, results, chosen, n_img=16, seed=17):
     rng = np.random.default_rng(seed)
     sample = np.sort(rng.choice(len(inputs.images), n_img, replace=False))
     sb = 4.0 * math.pi
-    decided = same_chosen = same32 = 0
+    decided = same_chosen = 0
+    d32 = same32 = same_c32 = 0
     t0 = time.perf_counter()
     for i in sample:
         a = O.fb_coefficients(inputs.images[i], plan)
@@ -240,12 +243,18 @@ def oracle_best_pose(inputs, w, shifts, results, chosen, n_img=16, seed=17):
                 others.append(v)
         v, j, si, ri, margin, sc = best
         margin = min([margin] + [v - o for o in others])
+        ch_eq = (int(ct[i]), int(cs[i]), int(cr[i])) == (j, si, ri)
+        j32 = int(np.argmax(vals))
+        f32_eq = (j32, int(v32["shift"][i, j32]), int(v32["rot"][i, j32])) == (j, si, ri)
+        if margin > 2e-5 * sc:
+            d32 += 1
+            same32 += int(f32_eq)
+            same_c32 += int(ch_eq)
         if margin > 2 * bar * sc:
             decided += 1
-            same_chosen += int((int(ct[i]), int(cs[i]), int(cr[i])) == (j, si, ri))
-            j32 = int(np.argmax(vals))
-            same32 += int((j32, int(v32["shift"][i, j32]), int(v32["rot"][i, j32])) == (j, si, ri))
-    return {"images": n_img, "decided": decided, "chosen_form_equal": same_chosen, "fp32_equal": same32,
+            same_chosen += int(ch_eq)
+    return {"images": n_img, "decided_at_fp32_bar": d32, "fp32_equal": same32, "chosen_form_equal": same_c32,
+            "decided_at_chosen_bar": decided, "chosen_form_equal_there": same_chosen,
             "seconds": time.perf_counter() - t0}
 
 
