@@ -742,6 +742,14 @@ def main():
             log(f"[{f} x{UPSAMPLE} rotations] {ru['ms_per_step']:.2f} ms/step, {ru['pairs_per_s']:.4g} pairs/s")
             ups[f] = {"pairs_per_s": ru["pairs_per_s"], "ms_per_step": ru["ms_per_step"],
                       "stage_ms_per_step": {k: v[0] / args.steps for k, v in ru["stages"].items()}}
+        if not args.no_bfr:
+            # brute-force rotations at the same rotation count, on the sample
+            ru = run_form("bfr", inputs, w, min(args.steps, 2), 1, shifts, up=UPSAMPLE, n_templates=BFR_TEMPLATES)
+            log(f"[bfr x{UPSAMPLE} rotations] {ru['ms_per_step']:.2f} ms/step, {ru['pairs_per_s']:.4g} pairs/s")
+            ups["bfr"] = {"pairs_per_s": ru["pairs_per_s"], "ms_per_step": ru["ms_per_step"],
+                          "sample": f"{w['n_images']} images x {BFR_TEMPLATES} templates",
+                          "stage_ms_per_step": {k: v[0] / min(args.steps, 2) for k, v in ru["stages"].items()}}
+            ups["ftk_fp16x3_speedup_over_bfr"] = ups["fp16x3"]["pairs_per_s"] / ups["bfr"]["pairs_per_s"]
         ups["rotations"] = UPSAMPLE * Qa
         ups["ftk_fp16x3_speedup_over_bft"] = ups["fp16x3"]["pairs_per_s"] / ups["bft"]["pairs_per_s"]
         out["config"]["upsampled_rotations"] = ups

@@ -154,8 +154,10 @@ __global__ void __launch_bounds__(256) bfr_corr_kernel(BfrCorrArgs p) {
     const int iy = p.iy0 + i / V1;
     Es[i] = iy < p.Dy ? p.ey[static_cast<size_t>(iy) * V1 + i % V1] : make_float2(0.f, 0.f);
   }
-  // staging roles: image rows (row, 8 u from jp), columns (col, 4 u from 4 jq)
-  const int lrow = tid >> 2, jp = (tid & 3) * 8;
+  // staging roles: image rows (row = lane: a wave stores 64 consecutive rows of
+  // one u into the transposed tile, free of bank conflicts; 8 u from jp),
+  // columns (col, 4 u from 4 jq)
+  const int lrow = tid & 63, jp = (tid >> 6) * 8;
   const bool lvalid = A0 + lrow < p.nA;
   const float2* lsrc = p.sa + static_cast<size_t>(lvalid ? A0 + lrow : 0) * V1 * Up;
   const int scol = tid & 31, jq = tid >> 5;

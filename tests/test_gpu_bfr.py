@@ -4,7 +4,7 @@ eq. 2dconv) with the oracle's BFR (oracle/bfr.py), element by element over
 wherever the margin exceeds twice the pair's error, and equal to the argmax
 of the X the call wrote.
 
-Shapes: n = 32 / Qa = 64 over the 2 px lattice; n = 64 / Qa = 128 with 70
+Shapes: n = 32 / Qa = 64 over the 2 px lattice; n = 96 / Qa = 192; n = 64 / Qa = 128 with 70
 images (two row tiles, ragged), off-lattice and repeated shifts (two passes
 of y offsets, a shift listed twice); the benchmark shape n = 128 / Qa = 256
 / 197 shifts on sampled rotations; upsampled rotations (R = 2 Qa); template
@@ -97,6 +97,16 @@ def test_bfr_small(ftk):
     assert X.shape == (len(s.images), len(s.templates), len(shifts), Qa)
     pairs = [(i, j) for i in range(len(s.images)) for j in range(len(s.templates))]
     assert _check_pairs(X, poses, s.images, s.templates, shifts, Qa, pairs, tag="n=32") <= 1e-5
+
+
+def test_bfr_n96(ftk):
+    # n = 96 (fine grid 192, rows of 100 values), Qa = 192 rotations
+    n, Qa, R = 96, 192, 2.5
+    s = synth.make_alignment_set(8, n, 3, 5, 30, R, 0.1)
+    shifts = synth.shift_lattice(R)
+    X, poses = _run(ftk, n, Qa, R, s.images, s.templates, shifts)
+    pairs = [(0, 0), (3, 2), (4, 1)]
+    assert _check_pairs(X, poses, s.images, s.templates, shifts, Qa, pairs, rots=[0, 7, 48, 150], tag="n=96") <= 1e-5
 
 
 def test_bfr_template_chunks(ftk):
