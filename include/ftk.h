@@ -333,7 +333,7 @@ int ftk_bft_align(ftk_plan* plan, const float* images, int nA, const float* temp
  * tables are not used.  Arguments, ownership and results as ftk_bft_align:
  * pixels in, X [nA][nB][N][R] optional, best [nA][nB] (rotation index in
  * [0, R)); asynchronous on the stream after a short host wait for the
- * call's tables.  The plan's workspace grows by the image spectra
+ * call's tables (so not for use under stream capture).  The plan's workspace grows by the image spectra
  * ((n/2 + 1) x (n + 4) complex per image) and the spectra of one chunk of
  * templates at all R rotations (R times that per template), templates
  * chunked to the staging size of ftk_plan_set_tuning.  Stage timing: the
