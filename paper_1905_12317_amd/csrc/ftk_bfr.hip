@@ -180,6 +180,8 @@ int ftk_bfr_align(ftk_plan* p, const float* images, int nA, const float* templat
   sp.s_per_u = kPiD * (2.0 / n) / p->sk.h;
   sp.beta = static_cast<float>(p->sk.beta);
   sp.scale = static_cast<float>(p->Qa);
+  sp.patch = bfr_spectra_patch(sp.s_per_u);
+  if (sizeof(float2) * sp.patch * sp.patch > 64 * 1024) return fail(FTK_EUNSUPPORTED, "ftk_bfr_align: spectra patch");
   // spectra of cnt images from imgs into out (quarter: all R rotations)
   auto spectra = [&](const float* imgs, int cnt, float2* out, int quarter) -> int {
     const size_t per = static_cast<size_t>(quarter ? R : 1) * V1 * Up;

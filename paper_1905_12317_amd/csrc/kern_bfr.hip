@@ -33,78 +33,98 @@ using f32x4 = float __attribute__((ext_vector_type(4)));
 
 // ---- spectra: the transform's fine grid interpolated at (rotated) grid points
 //
-// One thread per source point (a, b) of the disk for rotation r.  With
+// One workgroup per tile of 16 x 16 source points (a, b) of rotation r and
+// one image; the tile's rotated points span a patch of the fine grid at most
+// 15 s (|cos| + |sin|) + 8 taps wide (s = fine-grid units per unit of u),
+// which is staged in LDS once and read by every point's 8 x 8 taps.  With
 // quarter set, the rotations r < R / 4 are interpolated over the full disk
 // and each value is written for the four quarter turns: the disk maps onto
 // itself, Bhat_{r + R/4}(u, v) = Bhat_r(-v, u), so the value at (a, b) of
 // rotation r is the value at (b, -a) of rotation r + R / 4.  Only rows
-// v >= 0 are stored.  The spreading-kernel weights are evaluated per tap
-// from the fine-grid coordinate taken in double precision (a float
-// coordinate near nf / 2 would move the point by 1e-5 grid units).
+// v >= 0 are stored.  The points' fine-grid coordinates are formed in double
+// precision (a float coordinate near nf / 2 would move the point by 1e-5 grid
+// units); the tap weights then need only its fractional part, in float, and
+// are evaluated as exp(-beta z^2 / (1 + sqrt(1 - z^2))), which equals
+// exp(beta (sqrt(1 - z^2) - 1)) without its cancellation at small z.
 constexpr int kW = 8;
+constexpr int kTile = 16;
 
 __global__ void __launch_bounds__(256) bfr_spectra_kernel(BfrSpectraArgs p) {
+  extern __shared__ float2 patch[];  // [ps][ps]
   const int img = blockIdx.y;
-  const int V = p.V, side = 2 * V + 1;
-  const long long per_rot = static_cast<long long>(side) * side;
-  const long long npts = p.quarter ? static_cast<long long>(p.R / 4) * per_rot : static_cast<long long>(V + 1) * side;
-  const long long id = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (id >= npts) return;
-  int r = 0, a, b;
+  const int V = p.V, ps = p.patch, nf = p.nf;
+  const int bmin = p.quarter ? -V : 0;
+  const int TA = (2 * V + kTile) / kTile, TB = (V - bmin + kTile) / kTile;
+  int t = static_cast<int>(blockIdx.x);
+  const int r = t / (TA * TB);
+  t -= r * TA * TB;
+  const int tb = t / TA, ta = t - tb * TA;
+  const int a0 = -V + kTile * ta, b0 = bmin + kTile * tb;
+  const int a = a0 + (threadIdx.x & (kTile - 1)), b = b0 + static_cast<int>(threadIdx.x / kTile);
+  double c = 1.0, sn = 0.0;
   if (p.quarter) {
-    r = static_cast<int>(id / per_rot);
-    const int rem = static_cast<int>(id - r * per_rot);
-    b = rem / side - V;
-    a = rem - (b + V) * side - V;
-  } else {
-    b = static_cast<int>(id / side);
-    a = static_cast<int>(id - static_cast<long long>(b) * side) - V;
+    c = p.cs[2 * r];
+    sn = p.cs[2 * r + 1];
+  }
+  // patch origin: the tile's smallest rotated coordinates (a corner) minus
+  // the taps below a point
+  double mx = 1e300, my = 1e300;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const double ca = a0 + (k & 1) * (kTile - 1), cb = b0 + (k >> 1) * (kTile - 1);
+    mx = fmin(mx, (c * ca - sn * cb) * p.s_per_u);
+    my = fmin(my, (sn * ca + c * cb) * p.s_per_u);
+  }
+  const int ox = static_cast<int>(floor(mx)) - kW / 2 + 1, oy = static_cast<int>(floor(my)) - kW / 2 + 1;
+  // the tile's point nearest the origin decides whether any point is in the disk
+  const int na = a0 > 0 ? a0 : (a0 + kTile - 1 < 0 ? a0 + kTile - 1 : 0);
+  const int nb = b0 > 0 ? b0 : (b0 + kTile - 1 < 0 ? b0 + kTile - 1 : 0);
+  const bool any = na * na + nb * nb <= V * V;  // uniform over the workgroup
+  if (any) {
+    const float2* G = p.grid + static_cast<size_t>(img) * nf * nf;
+    for (int i = threadIdx.x; i < ps * ps; i += blockDim.x) {
+      const int ly = i / ps, lx = i - ly * ps;
+      int gy = (oy + ly) % nf, gx = (ox + lx) % nf;
+      gy += gy < 0 ? nf : 0;
+      gx += gx < 0 ? nf : 0;
+      patch[i] = G[static_cast<size_t>(gy) * nf + gx];
+    }
+    __syncthreads();
   }
   float2 val = make_float2(0.f, 0.f);
-  if (a * a + b * b <= V * V) {
-    double c = 1.0, sn = 0.0;
-    if (p.quarter) {
-      c = p.cs[2 * r];
-      sn = p.cs[2 * r + 1];
-    }
+  if (any && a <= V && b <= V && a * a + b * b <= V * V) {
     const double sx = (c * a - sn * b) * p.s_per_u;  // fine-grid coordinates of R_gamma k
     const double sy = (sn * a + c * b) * p.s_per_u;
-    const int nf = p.nf;
     const double fx = floor(sx), fy = floor(sy);
-    const int bx = static_cast<int>(fx) - kW / 2 + 1;
-    const int by = static_cast<int>(fy) - kW / 2 + 1;
+    const float rx = static_cast<float>(sx - fx), ry = static_cast<float>(sy - fy);
+    const int bx = static_cast<int>(fx) - kW / 2 + 1 - ox, by = static_cast<int>(fy) - kW / 2 + 1 - oy;
     float wx[kW], wy[kW];
 #pragma unroll
-    for (int t = 0; t < kW; ++t) {
-      const double zx = (sx - static_cast<double>(bx + t)) * (2.0 / kW);
-      const double zy = (sy - static_cast<double>(by + t)) * (2.0 / kW);
-      wx[t] = fabs(zx) < 1.0 ? __expf(static_cast<float>(p.beta * (sqrt(1.0 - zx * zx) - 1.0))) : 0.f;
-      wy[t] = fabs(zy) < 1.0 ? __expf(static_cast<float>(p.beta * (sqrt(1.0 - zy * zy) - 1.0))) : 0.f;
+    for (int k = 0; k < kW; ++k) {
+      // z = (s - (floor(s) - kW/2 + 1 + k)) / (kW / 2)
+      const float zx = (rx + static_cast<float>(kW / 2 - 1 - k)) * (2.f / kW);
+      const float zy = (ry + static_cast<float>(kW / 2 - 1 - k)) * (2.f / kW);
+      const float qx = zx * zx, qy = zy * zy;
+      wx[k] = qx < 1.f ? __expf(-p.beta * qx / (1.f + sqrtf(1.f - qx))) : 0.f;
+      wy[k] = qy < 1.f ? __expf(-p.beta * qy / (1.f + sqrtf(1.f - qy))) : 0.f;
     }
-    const float2* G = p.grid + static_cast<size_t>(img) * nf * nf;
-    int l1s = bx % nf;
-    l1s += l1s < 0 ? nf : 0;
-    int l2 = by % nf;
-    l2 += l2 < 0 ? nf : 0;
     float2 acc = make_float2(0.f, 0.f);
 #pragma unroll
     for (int bi = 0; bi < kW; ++bi) {
-      const float2* col = G + static_cast<size_t>(l2) * nf;
-      float2 s = make_float2(0.f, 0.f);
-      int l1 = l1s;
+      const float2* row = patch + (by + bi) * ps + bx;
+      float2 s2 = make_float2(0.f, 0.f);
 #pragma unroll
       for (int ai = 0; ai < kW; ++ai) {
-        const float2 g = col[l1];
-        s.x += wx[ai] * g.x;
-        s.y += wx[ai] * g.y;
-        l1 = (l1 + 1 == nf) ? 0 : l1 + 1;
+        const float2 g = row[ai];
+        s2.x += wx[ai] * g.x;
+        s2.y += wx[ai] * g.y;
       }
-      acc.x += wy[bi] * s.x;
-      acc.y += wy[bi] * s.y;
-      l2 = (l2 + 1 == nf) ? 0 : l2 + 1;
+      acc.x += wy[bi] * s2.x;
+      acc.y += wy[bi] * s2.y;
     }
     val = make_float2(acc.x * p.scale, acc.y * p.scale);
   }
+  if (a > V || b > V) return;
   const size_t V1 = static_cast<size_t>(V + 1);
   if (!p.quarter) {
     p.out[(static_cast<size_t>(img) * V1 + b) * p.Up + a + V] = val;
@@ -117,9 +137,9 @@ __global__ void __launch_bounds__(256) bfr_spectra_kernel(BfrSpectraArgs p) {
       const size_t rr = static_cast<size_t>(img) * p.R + r + j * (p.R / 4);
       p.out[(rr * V1 + v) * p.Up + u + V] = val;
     }
-    const int t = u;  // (u, v) -> (v, -u): the same value one quarter turn on
+    const int tmp = u;  // (u, v) -> (v, -u): the same value one quarter turn on
     u = v;
-    v = -t;
+    v = -tmp;
   }
 }
 
@@ -293,12 +313,22 @@ __global__ void __launch_bounds__(256) bfr_corr_kernel(BfrCorrArgs p) {
 
 }  // namespace
 
+int bfr_spectra_patch(double s_per_u) {
+  // the rotated tile's extent (at most (kTile - 1) s sqrt 2) plus the taps and rounding
+  return static_cast<int>(std::ceil((kTile - 1) * s_per_u * 1.4142135623730951)) + kW + 2;
+}
+
 hipError_t launch_bfr_spectra(const BfrSpectraArgs& a, hipStream_t s) {
   if (a.cnt <= 0) return hipSuccess;
-  const long long side = 2LL * a.V + 1;
-  const long long npts = a.quarter ? static_cast<long long>(a.R / 4) * side * side : (a.V + 1LL) * side;
-  const unsigned gx = static_cast<unsigned>((npts + 255) / 256);
-  hipLaunchKernelGGL(bfr_spectra_kernel, dim3(gx, a.cnt), dim3(256), 0, s, a);
+  if (a.w != kW || a.patch < bfr_spectra_patch(a.s_per_u)) return hipErrorInvalidValue;
+  const long long TA = (2LL * a.V + kTile) / kTile, TB = ((a.quarter ? 2LL * a.V : a.V) + kTile) / kTile;
+  const long long nblk = TA * TB * (a.quarter ? a.R / 4 : 1);
+  if (nblk > 0x7fffffffLL) return hipErrorInvalidConfiguration;
+  const size_t lds = sizeof(float2) * a.patch * a.patch;
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(bfr_spectra_kernel),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(bfr_spectra_kernel, dim3(static_cast<unsigned>(nblk), a.cnt), dim3(kTile * kTile), lds, s, a);
   return hipGetLastError();
 }
 

@@ -170,7 +170,9 @@ struct BfrSpectraArgs {
   double s_per_u;       // fine-grid units per unit of u: pi dx / h
   float beta;           // spreading kernel shape
   float scale;          // the grid holds Ahat / Qa
+  int patch;            // side of the LDS patch of fine grid per tile, >= bfr_spectra_patch(s_per_u)
 };
+int bfr_spectra_patch(double s_per_u);
 hipError_t launch_bfr_spectra(const BfrSpectraArgs& args, hipStream_t stream);
 
 // The correlation over the product grid of the requested shifts' x and y
