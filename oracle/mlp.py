@@ -27,6 +27,8 @@ definition (8 exponent bits, 7 stored mantissa bits).
 """
 from __future__ import annotations
 
+import math
+
 import numpy as np
 
 
@@ -72,6 +74,27 @@ def cross_features(coeffs_rings_modes: np.ndarray, n_r: int, n_q: int) -> np.nda
         out.extend(im)
     v = np.asarray(out, dtype=np.float64)
     return np.sign(v) * np.sqrt(np.abs(v))
+
+
+def invariant_features(coeffs_rings_modes: np.ndarray, n_r: int, n_q: int) -> np.ndarray:
+    """Features invariant to both the rotation and the shift of the image.
+    A shift multiplies Ahat(k) by a phase (eq. Fdk), so the power |Ahat(k_m,
+    psi)|^2 on ring m does not change; a rotation turns it in psi, so the
+    moduli of its angular Fourier coefficients do not change.  With the ring
+    samples Ahat(k_m, psi_p) = sum_q a(k_m; q) exp(i q psi_p) (eq. aqkcalc
+    inverted) the coefficient of exp(i s psi) in the power is the cyclic
+    autocorrelation P(k_m; s) = sum_q a(k_m; q) conj a(k_m; q - s) (indices
+    mod Qa); for real images the power is pi-periodic in psi, so only even s
+    carry information.  F[m * n_q + j] = sqrt|P(k_m; 2 j)| (homogeneous of
+    degree one in the image), m < n_r, j < n_q."""
+    a = np.asarray(coeffs_rings_modes, dtype=np.complex128)
+    Qa = a.shape[1]
+    out = np.zeros((n_r, n_q))
+    for m in range(n_r):
+        for j in range(n_q):
+            s = 2 * j
+            out[m, j] = math.sqrt(abs(np.sum(a[m] * np.conj(a[m, (np.arange(Qa) - s) % Qa]))))
+    return out.reshape(-1)
 
 
 def standardise(F: np.ndarray, mu: np.ndarray, inv_sigma: np.ndarray) -> np.ndarray:

@@ -199,6 +199,69 @@ def test_cross_features_rotation_invariant_and_laid_out():
     assert f0[72 + 0] == pytest.approx(math.sqrt(abs(a0[0, 2]) ** 2), rel=1e-12)
 
 
+def _bordered_blob_image(n, seed):
+    # blobs well inside the frame, the outer 4 pixels exactly zero: a cyclic
+    # roll by up to 4 pixels is then an exact shift of the image
+    img = synth.render(synth.random_blobs(np.random.default_rng(seed), 10, disk_px=4.0, sigma_px=(1.0, 2.0)), n)
+    img[:4, :] = 0.0
+    img[-4:, :] = 0.0
+    img[:, :4] = 0.0
+    img[:, -4:] = 0.0
+    img[0, :] = 0.0
+    img[:, 0] = 0.0
+    return img
+
+
+def test_invariant_features_definition():
+    """sqrt|P(k; 2j)| computed from the ring samples (the inverse ring DFT of
+    the coefficients, then the DFT of their power) equals the cyclic
+    autocorrelation of the coefficients; the odd harmonics of the power of a
+    real image vanish."""
+    n, M, Qa = 32, 16, 64
+    img = synth.white_noise_images(4, 1, n)[0]
+    a = O.fb_coefficients(img, O.make_plan(n, M, Qa, 2.0, 1e-3))
+    f = ML.invariant_features(a, M, 20)
+    samples = Qa * np.fft.ifft(a, axis=1)  # Ahat(k_m, psi_p) = sum_q a(k_m; q) e^{i q psi_p}
+    P = np.fft.fft(np.abs(samples) ** 2, axis=1) / Qa
+    ref = np.abs(P[:, 0:40:2]).reshape(-1)
+    # compare |P| itself (the square root magnifies rounding near zero)
+    assert np.max(np.abs(f ** 2 - ref)) <= 1e-12 * np.max(ref)
+    assert np.max(np.abs(P[:, 1::2])) <= 1e-12 * np.max(np.abs(P))
+
+
+def test_invariant_features_shift_and_rotation_invariant(monkeypatch):
+    n, M, Qa = 32, 16, 64
+    plan = O.make_plan(n, M, Qa, 2.0, 1e-3)
+    img = _bordered_blob_image(n, 12)
+    f0 = ML.invariant_features(O.fb_coefficients(img, plan), M, 16)
+    # exact pixel shifts (the frame's zero border absorbs the roll)
+    for d in [(3, -2), (-4, 1), (1, 4)]:
+        f1 = ML.invariant_features(O.fb_coefficients(np.roll(img, d, axis=(0, 1)), plan), M, 16)
+        # |P| = F^2 (the square root magnifies rounding near zero)
+        assert np.max(np.abs(f1 ** 2 - f0 ** 2)) <= 1e-12 * np.max(f0 ** 2), d
+    # an exact quarter turn about pixel (n/2, n/2)
+    rot = np.roll(np.rot90(img), 1, axis=0)
+    f2 = ML.invariant_features(O.fb_coefficients(rot, plan), M, 16)
+    assert np.max(np.abs(f2 ** 2 - f0 ** 2)) <= 1e-12 * np.max(f0 ** 2)
+    # both at once, with the shift off the pixel grid: the image is rendered
+    # with its blobs moved, so agreement is to the sampling of the blobs
+    rng = np.random.default_rng(12)
+    blobs = synth.random_blobs(rng, 10, disk_px=4.0, sigma_px=(2.0, 3.0))
+    g0 = ML.invariant_features(O.fb_coefficients(synth.render(blobs, n), plan), M, 16)
+    moved = synth.render(blobs.moved(0.7, (1.3, -0.6)), n)
+    g1 = ML.invariant_features(O.fb_coefficients(moved, plan), M, 16)
+    assert np.max(np.abs(g1 ** 2 - g0 ** 2)) <= 1e-5 * np.max(g0 ** 2)  # measured 6e-7
+    # planted: without the conjugate the product is not shift invariant
+    def bad(c, n_r, n_q):
+        a = np.asarray(c)
+        return np.array([math.sqrt(abs(np.sum(a[m] * a[m, (np.arange(Qa) - 2 * j) % Qa])))
+                         for m in range(n_r) for j in range(n_q)])
+    monkeypatch.setattr(ML, "invariant_features", bad)
+    b0 = ML.invariant_features(O.fb_coefficients(img, plan), M, 16)
+    b1 = ML.invariant_features(O.fb_coefficients(np.roll(img, (3, -2), axis=(0, 1)), plan), M, 16)
+    assert np.max(np.abs(b1 ** 2 - b0 ** 2)) > 1e-2 * np.max(b0 ** 2)
+
+
 def test_features_of_real_image_are_symmetric_in_q():
     n, M, Qa = 32, 16, 64
     img = synth.white_noise_images(2, 1, n)[0]
