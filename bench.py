@@ -316,7 +316,9 @@ def cpu_baseline(inputs, w, shifts, n_img=8, n_tmp=48, n_dir=(2, 4)):
 
 RAGGED = dict(name="ragged_c4", stacks=64, seed=4, nblob=60, snr=0.05, eps=1e-3)
 PROPOSAL = dict(name="proposal_c5", n=128, M=64, Qa=256, R=4.0, n_templates=8192, n_clean=16384, n_val=1024,
-                n_test=2048, nblob=60, snr=0.05, eps=1e-3, epochs=12, n_r=16, n_q=8, topk=32, hidden=1024, seed=5)
+                n_test=2048, nblob=60, snr=0.05, eps=1e-3, epochs=12, topk=32, hidden=1024, seed=5)
+# rings and modes of each feature kind (2048 inputs either way)
+PROPOSAL_FEATURES = {"cross": (16, 8), "invariant": (64, 32)}
 
 
 def bench_ragged(args):
@@ -411,7 +413,9 @@ def bench_proposal(args):
     log(f"[proposal] data {gen_s:.1f} s: {w['n_templates']} templates, {n_all} images")
     shifts = synth.shift_lattice(w["R"])
     bins = PR.shift_bins(shifts)
-    n_t, n_s, kind = w["n_templates"], int(bins.max()) + 1, "cross"
+    kind = args.proposal_features
+    n_r, n_q = PROPOSAL_FEATURES[kind]
+    n_t, n_s = w["n_templates"], int(bins.max()) + 1
     P = ftk.Plan(w["n"], w["M"], w["Qa"], w["R"], w["eps"], "bf16x3")
     P.set_shifts(shifts)
     P16 = ftk.Plan(w["n"], w["M"], w["Qa"], w["R"], w["eps"], "fp16")
@@ -421,7 +425,7 @@ def bench_proposal(args):
     nc = w["n_clean"]
     clean = torch.as_tensor(s.clean[:nc], dtype=torch.float32, device="cuda")
     sig = s.noise_sigma[:nc]
-    dims = [ftk.feature_count(kind, w["n_r"], w["n_q"]), w["hidden"], w["hidden"], w["hidden"], n_t + n_s]
+    dims = [ftk.feature_count(kind, n_r, n_q), w["hidden"], w["hidden"], w["hidden"], n_t + n_s]
     net = ftk.MLP(dims, n_t, n_s, "bf16", max_batch=1024)
     net.set_params(synth.mlp_init(w["seed"], dims))
     perms = [synth.permutation(100 + e, nc) for e in range(w["epochs"])]
@@ -429,14 +433,14 @@ def bench_proposal(args):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     losses = PR.train_online(net, P, clean, tc, bins, lambda e: synth.gaussian_noise(7000 + e, sig, w["n"]), perms,
-                             kind, w["n_r"], w["n_q"], batch=256, lr=2e-3, wd=1e-2, labeler=labeler,
+                             kind, n_r, n_q, batch=256, lr=2e-3, wd=1e-2, labeler=labeler,
                              log=lambda e, l: log(f"  epoch {e}: loss {l:.4f}"))
     torch.cuda.synchronize()
     train_s = time.perf_counter() - t0
     labelled_pairs = w["epochs"] * nc * n_t
     # the network's kernels alone: a training step's loss + gradients, and
     # the forward pass, at batch 256
-    feats = ftk.features(P, P.transform(clean[:4096].contiguous()), w["n_r"], w["n_q"], kind=kind)
+    feats = ftk.features(P, P.transform(clean[:4096].contiguous()), n_r, n_q, kind=kind)
     lab = torch.zeros(4096, dtype=torch.int32, device="cuda")
     idx = torch.arange(256, dtype=torch.int32, device="cuda")
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -458,7 +462,7 @@ def bench_proposal(args):
     # threshold on the validation split
     vi = torch.as_tensor(s.images[nc:nc + w["n_val"]], dtype=torch.float32, device="cuda")
     vlab, _ = labeler(P.transform(vi))
-    vf = ftk.features(P, P.transform(vi), w["n_r"], w["n_q"], kind=kind)
+    vf = ftk.features(P, P.transform(vi), n_r, n_q, kind=kind)
     top, mass, _ = net.propose(vf, w["topk"])
     hit = (top.cpu().numpy() == vlab.cpu().numpy()[:, None]).any(axis=1)
     tau = PR.choose_tau(mass.cpu().numpy(), hit, max_miss=0.003)
@@ -479,10 +483,10 @@ def bench_proposal(args):
     res = {}
     for mode in ("no_window", "window"):
         P.set_shift_windows(0.5 * np.arange(n_s) if mode == "window" else [], 0.5)
-        ftk.align_proposed(P, net, ti, tc, w["n_r"], w["n_q"], w["topk"], tau, kind=kind)
+        ftk.align_proposed(P, net, ti, tc, n_r, n_q, w["topk"], tau, kind=kind)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        bt, bp, fb, nfb = ftk.align_proposed(P, net, ti, tc, w["n_r"], w["n_q"], w["topk"], tau, kind=kind)
+        bt, bp, fb, nfb = ftk.align_proposed(P, net, ti, tc, n_r, n_q, w["topk"], tau, kind=kind)
         torch.cuda.synchronize()
         t_prop = time.perf_counter() - t0
         same = (bt.cpu().numpy() == fbt) & np.all(bp.cpu().numpy() == fbp, axis=1)
@@ -498,8 +502,8 @@ def bench_proposal(args):
         "vs_baseline": None, "dtype": "bf16 MLP + bf16x3 FTK", "data": "synthetic",
         "config": {"workload": f"{w['name']}: {n_t} 60-blob templates n=128, M=64, Qa=256, N=197 shifts, SNR "
                                f"{w['snr']}; {nc} training images re-noised and relabelled by the two-pass search "
-                               f"each of {w['epochs']} epochs ({labelled_pairs} labelled pairs); cross-ring features "
-                               f"n_r={w['n_r']} n_q={w['n_q']} ({dims[0]} inputs), MLP {dims}; top-{w['topk']}; "
+                               f"each of {w['epochs']} epochs ({labelled_pairs} labelled pairs); {kind} features "
+                               f"n_r={n_r} n_q={n_q} ({dims[0]} inputs), MLP {dims}; top-{w['topk']}; "
                                f"test {nA} images",
                    "window": res["window"], "no_window": res["no_window"], "tau": tau,
                    "validation_topk_hit": float(hit.mean()), "full_search_pairs_per_s": nA * n_t / t_full,
@@ -527,6 +531,9 @@ def main():
     ap.add_argument("--ragged-scale", type=float, default=1.0,
                     help="ragged workload: image and template counts scaled by this (1.0: the full workload)")
     ap.add_argument("--lanes", type=int, default=4, help="ragged workload: concurrent lanes of the batch (1-4)")
+    ap.add_argument("--proposal-features", default="cross", choices=sorted(PROPOSAL_FEATURES),
+                    help="proposal workload: the network's input features (invariant: shift- and rotation-invariant "
+                         "ring-power harmonics; cross: rotation-invariant cross-ring products)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-weighted", action="store_true", help="skip the weighted-SVD measurement")
     ap.add_argument("--no-bft", action="store_true", help="skip the brute-force-translation measurement")

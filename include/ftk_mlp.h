@@ -75,7 +75,8 @@ int ftk_mlp_get_layer(const ftk_mlp* mlp, int layer, float* W, float* b);
 /* Feature standardisation, host arrays [dims[0]].  Synchronous. */
 int ftk_mlp_set_input_norm(ftk_mlp* mlp, const float* mu, const float* inv_sigma);
 
-/* Rotation-invariant features of nA images from their coefficients
+/* Rotation-invariant (and for FTK_FEATURES_INVARIANT shift-invariant)
+ * features of nA images from their coefficients
  * (device [nA][Qa][M] complex64, the layout of ftk_transform) into device
  * float [nA][D], over the first n_r rings (n_r <= M) and modes
  * 0 <= q < n_q (n_q <= Qa/2):
@@ -85,9 +86,15 @@ int ftk_mlp_set_input_norm(ftk_mlp* mlp, const float* mu, const float* inv_sigma
  *     factors by the same phase, which cancels; unlike the power features
  *     they keep the phase between rings): s(Re c) for k1 <= k2, then
  *     s(Im c) for k1 < k2, pairs in row-major (k1, k2) order, with
- *     s(x) = sign(x) sqrt|x|.
+ *     s(x) = sign(x) sqrt|x|;
+ *   FTK_FEATURES_INVARIANT: D = n_r n_q, F[m n_q + j] = sqrt|P(k_m; 2 j)|,
+ *     P(k; s) = sum_q a(k; q) conj a(k; q - s) (indices mod Qa): the
+ *     angular Fourier coefficients of the ring power |Ahat(k, psi)|^2, which
+ *     a shift of the image leaves unchanged (eq. Fdk is a phase) and a
+ *     rotation only turns (so their moduli are invariant to both); odd s
+ *     vanish for real images.
  * Errors: FTK_EINVAL, FTK_EDEVICE. */
-enum { FTK_FEATURES_POWER = 0, FTK_FEATURES_CROSS = 1 };
+enum { FTK_FEATURES_POWER = 0, FTK_FEATURES_CROSS = 1, FTK_FEATURES_INVARIANT = 2 };
 int ftk_features(const ftk_plan* plan, const void* coeffs, int nA, int kind, int n_r, int n_q, float* F,
                  void* stream);
 

@@ -297,7 +297,8 @@ int ftk_mlp_set_input_norm(ftk_mlp* m, const float* mu, const float* inv_sigma) 
 
 int ftk_features(const ftk_plan* p, const void* coeffs, int nA, int kind, int n_r, int n_q, float* F, void* stream) {
   if (!p) return fail(FTK_EINVAL, "ftk_features: NULL plan");
-  if (kind != FTK_FEATURES_POWER && kind != FTK_FEATURES_CROSS) return fail(FTK_EINVAL, "ftk_features: unknown kind");
+  if (kind != FTK_FEATURES_POWER && kind != FTK_FEATURES_CROSS && kind != FTK_FEATURES_INVARIANT)
+    return fail(FTK_EINVAL, "ftk_features: unknown kind");
   if (nA < 0 || n_r < 1 || n_r > p->M || n_q < 1 || n_q > p->Qa / 2)
     return fail(FTK_EINVAL, "ftk_features: sizes out of range");
   if (nA == 0) return FTK_OK;
@@ -451,7 +452,7 @@ int ftk_align_proposed(ftk_plan* p, ftk_mlp* m, const float* images, int nA, con
   if (n_fallback) *n_fallback = 0;
   if (nA < 0) return fail(FTK_EINVAL, "ftk_align_proposed: nA < 0");
   if (nB != m->n_t) return fail(FTK_EINVAL, "ftk_align_proposed: nB must equal the network's n_template");
-  const long long nfeat = kind == FTK_FEATURES_POWER ? 1LL * n_r * n_q : 1LL * n_r * n_r * n_q;
+  const long long nfeat = kind == FTK_FEATURES_CROSS ? 1LL * n_r * n_r * n_q : 1LL * n_r * n_q;
   if (nfeat != m->dims[0]) return fail(FTK_EINVAL, "ftk_align_proposed: the feature count must equal dims[0]");
   if (topk < 1 || topk > 64 || topk > nB) return fail(FTK_EINVAL, "ftk_align_proposed: topk out of range");
   if (p->N <= 0) return fail(FTK_ESTATE, "ftk_align_proposed: call ftk_set_shifts first");

@@ -433,7 +433,7 @@ __global__ void convert_kernel(const float* __restrict__ w, size_t n, T* __restr
 // s(x) = sign(x) sqrt|x|.
 __global__ void features_kernel(const float2* __restrict__ c, int nA, int Qa, int M, int kind, int n_r, int n_q,
                                 float* __restrict__ F) {
-  const size_t D = kind == 0 ? static_cast<size_t>(n_r) * n_q : static_cast<size_t>(n_r) * n_r * n_q;
+  const size_t D = kind == 1 ? static_cast<size_t>(n_r) * n_r * n_q : static_cast<size_t>(n_r) * n_q;
   const size_t total = static_cast<size_t>(nA) * D;
   for (size_t t = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x; t < total;
        t += static_cast<size_t>(gridDim.x) * blockDim.x) {
@@ -444,6 +444,24 @@ __global__ void features_kernel(const float2* __restrict__ c, int nA, int Qa, in
       const int q = f - m * n_q;
       const float2 v = c[(a * Qa + q) * M + m];
       F[t] = v.x * v.x + v.y * v.y;
+      continue;
+    }
+    if (kind == 2) {
+      // sqrt|P(k_m; 2 j)|, P(k; s) = sum_q a(k; q) conj a(k; q - s) (indices
+      // mod Qa): the ring power's angular Fourier coefficient, unchanged by
+      // shifts (a phase on Ahat) and, in modulus, by rotations
+      const int m = f / n_q;
+      const int s2 = 2 * (f - m * n_q);
+      const float2* col = c + a * Qa * M + m;
+      float re = 0.f, im = 0.f;
+      for (int q = 0; q < Qa; ++q) {
+        int q2 = q - s2;
+        q2 += q2 < 0 ? Qa : 0;
+        const float2 u = col[static_cast<size_t>(q) * M], w = col[static_cast<size_t>(q2) * M];
+        re += u.x * w.x + u.y * w.y;
+        im += u.y * w.x - u.x * w.y;
+      }
+      F[t] = sqrtf(hypotf(re, im));
       continue;
     }
     const int blk = n_r * n_r;
@@ -776,7 +794,7 @@ hipError_t launch_convert(const float* w, size_t n, void* wc, int bf16, hipStrea
 hipError_t launch_features(const float2* coeffs, int nA, int Qa, int M, int kind, int n_r, int n_q, float* F,
                            hipStream_t s) {
   if (nA <= 0) return hipSuccess;
-  const size_t D = kind == 0 ? static_cast<size_t>(n_r) * n_q : static_cast<size_t>(n_r) * n_r * n_q;
+  const size_t D = kind == 1 ? static_cast<size_t>(n_r) * n_r * n_q : static_cast<size_t>(n_r) * n_q;
   hipLaunchKernelGGL(features_kernel, dim3(grid_for(static_cast<size_t>(nA) * D)), dim3(kThreads), 0, s, coeffs, nA,
                      Qa, M, kind, n_r, n_q, F);
   return hipGetLastError();

@@ -590,12 +590,13 @@ class MLP:
 
 FTK_FEATURES_POWER = 0
 FTK_FEATURES_CROSS = 1
-FEATURE_KINDS = {"power": FTK_FEATURES_POWER, "cross": FTK_FEATURES_CROSS}
+FTK_FEATURES_INVARIANT = 2
+FEATURE_KINDS = {"power": FTK_FEATURES_POWER, "cross": FTK_FEATURES_CROSS, "invariant": FTK_FEATURES_INVARIANT}
 
 
 def feature_count(kind, n_r: int, n_q: int) -> int:
     k = FEATURE_KINDS[kind] if isinstance(kind, str) else int(kind)
-    return n_r * n_q if k == FTK_FEATURES_POWER else n_r * n_r * n_q
+    return n_r * n_r * n_q if k == FTK_FEATURES_CROSS else n_r * n_q
 
 
 def features(plan: "Plan", coeffs, n_r: int, n_q: int, kind="power", out=None, stream=None):

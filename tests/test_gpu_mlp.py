@@ -144,8 +144,13 @@ def test_features_and_proposal_match_oracle(ftk):
     F = ftk.features(P, coeffs, 32, 32).cpu().numpy()
     Fx = ftk.features(P, coeffs, 13, 7, kind="cross").cpu().numpy()
     assert Fx.shape == (10, 7 * 13 * 13)
+    Fi = ftk.features(P, coeffs, 32, 24, kind="invariant").cpu().numpy()
+    assert Fi.shape == (10, 32 * 24)
     c = coeffs.cpu().numpy()
     for a in range(c.shape[0]):
+        # shift- and rotation-invariant features: compare |P| = F^2
+        refi = ML.invariant_features(c[a].T.astype(np.complex128), 32, 24)
+        assert _rel(Fi[a].astype(np.float64) ** 2, refi ** 2) <= 1e-5
         ref = ML.features(c[a].T.astype(np.complex128), 32, 32)
         assert _rel(F[a], ref) <= 1e-6
         # cross features: compare the products (the square root magnifies
