@@ -164,6 +164,32 @@ def test_bfr_upsampled_rotations(ftk):
     assert np.max(np.abs(X[..., ::2] - Xp)) <= 1e-6 * np.max(np.abs(Xp))
 
 
+def test_bfr_degenerate_inputs(ftk):
+    import ctypes
+    n, Qa, R = 32, 64, 2.0
+    P = ftk.Plan(n, n // 2, Qa, R, 1e-3)
+    P.set_shifts(np.array([[0.5, -1.0]]))  # one shift: one x and one y offset
+    s = synth.workload_set("plain_n32", 1)
+    X, poses = P.bfr_align(_dev(s.images[:3]), _dev(s.templates[:2]), want_X=True)
+    torch.cuda.synchronize()
+    X, poses = X.cpu().numpy(), ftk.poses_numpy(poses)
+    u, v = BR.cartesian_grid(n)
+    for i, j in [(0, 0), (2, 1)]:
+        a = BR.ft_at(s.images[i], math.pi * u, math.pi * v)
+        Xr = np.real(BR.bfr_X_spectra(a, BR.rotated_spectra(s.templates[j], Qa), n, [[0.5, -1.0]]))
+        assert np.max(np.abs(X[i, j] - Xr)) <= 1e-5 * _scale(s.images[i], s.templates[j], n)
+        assert poses[i, j]["shift"] == 0 and poses[i, j]["rot"] == int(np.argmax(X[i, j, 0]))
+    # empty calls do nothing and succeed; both outputs NULL is an error
+    L = ftk.lib()
+    x = _dev(s.images[:1])
+    assert L.ftk_bfr_align(P._h, ctypes.c_void_p(x.data_ptr()), 0, ctypes.c_void_p(x.data_ptr()), 1, None, None,
+                           None) == 0
+    assert L.ftk_bfr_align(P._h, ctypes.c_void_p(x.data_ptr()), 1, ctypes.c_void_p(x.data_ptr()), 0, None, None,
+                           None) == 0
+    assert L.ftk_bfr_align(P._h, ctypes.c_void_p(x.data_ptr()), 1, ctypes.c_void_p(x.data_ptr()), 1, None, None,
+                           None) != 0
+
+
 def test_bfr_refusals(ftk):
     P = ftk.Plan(32, 16, 64, 2.0, 1e-3)
     x = torch.zeros((1, 32, 32), dtype=torch.float32, device="cuda")
