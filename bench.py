@@ -48,11 +48,11 @@ PEAK_HBM = 8.0e12
 # Source: profiles/step3_<form>_cryoem_n128.md.
 TRAFFIC = {
     "bf16x3": {"bytes_per_launch": 8.791e+09, "sources": ["kern_align_bf16.hip", "step3_epilogue.h", "device_common.h", "kernels.h"],
-        "sha1": "28142398d69c700b10909147d9d854a7250c1732"},
+        "sha1": "5687834082d6ed5b4696aa9481364c1488e58666"},
     "fp32": {"bytes_per_launch": 9.627e+09, "sources": ["kern_align.hip", "step3_epilogue.h", "device_common.h", "kernels.h"],
-        "sha1": "cac4666a8467ffe15f3937eddd568e3a788875d2"},
+        "sha1": "700029d305407183e020a799f8ad560623527315"},
     "fp16": {"bytes_per_launch": 8.626e+09, "sources": ["kern_align_fp16.hip", "step3_epilogue.h", "device_common.h", "kernels.h"],
-        "sha1": "5ea6efe16ab3e0e128dc5668b2ac307bcb627fcd"},
+        "sha1": "bc8dd0db4f7f6d9ca6f6774c316990c02bc71b72"},
 }
 
 
