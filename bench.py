@@ -323,9 +323,10 @@ PROPOSAL_FEATURES = {"cross": (16, 8), "invariant": (64, 32)}
 
 def bench_ragged(args):
     """64 stacks of uneven n, template and image counts and shift radii (the
-    ragged workload, image and template counts scaled by --ragged-scale),
-    split-bf16 form: one ftk_batch run (--lanes lanes, one hipGraph, autotuned
-    launch shapes) against the same stacks aligned one ftk_align at a time."""
+    ragged workload, image and template counts scaled by --ragged-scale), in
+    the --ragged-form precision form: one ftk_batch run (--lanes lanes, one
+    hipGraph, autotuned launch shapes) against the same stacks aligned one
+    ftk_align at a time."""
     import torch
     import synth
     from paper_1905_12317_amd import ftk
@@ -337,7 +338,7 @@ def bench_ragged(args):
         s = synth.make_alignment_set(1000 * w["seed"] + i, sp["n"], sp["n_templates"], sp["n_images"], w["nblob"],
                                      sp["R"], w["snr"])
         shifts = synth.shift_lattice(sp["R"])
-        P = ftk.Plan(sp["n"], sp["M"], sp["Qa"], sp["R"], w["eps"], "bf16x3")
+        P = ftk.Plan(sp["n"], sp["M"], sp["Qa"], sp["R"], w["eps"], args.ragged_form)
         P.set_shifts(shifts)
         inf = P.info()
         imgs = torch.as_tensor(s.images, dtype=torch.float32, device="cuda")
@@ -381,11 +382,11 @@ def bench_ragged(args):
         "metric": "pairs/s over a ragged batch of 64 stacks (uneven n, templates, images, shift radius)",
         "value": pairs / (ms_batch / 1e3), "unit": "pairs/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms_batch, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "bf16x3->f32", "data": "synthetic",
+        "vs_baseline": None, "dtype": f"{args.ragged_form}->f32", "data": "synthetic",
         "config": {"workload": f"{w['name']}: 64 stacks, n in {{64,96,128,192}}, M=n/2, Qa=2n, templates "
                                f"log-uniform 100-4000 and images 16-256 scaled by {args.ragged_scale}, shift radius "
                                f"2-8 px (0.5 px lattice), 60-blob templates, SNR {w['snr']}, eps={w['eps']}",
-                   "pairs": pairs, "lanes": info["lanes"], "graph_nodes": info["graph_nodes"],
+                   "form": args.ragged_form, "pairs": pairs, "lanes": info["lanes"], "graph_nodes": info["graph_nodes"],
                    "autotune_s": tune_s, "sequential_ms_per_step": ms_seq, "batch_speedup": ms_seq / ms_batch},
         "roofline": {"kernel": "whole batch (Step 1 + Step 3 algorithmic flop)", "bound": "mfma",
                      "achieved": achieved / 1e12, "peak": PEAK_BF16_MFMA / 1e12, "unit": "TFLOP/s",
@@ -531,6 +532,8 @@ def main():
     ap.add_argument("--ragged-scale", type=float, default=1.0,
                     help="ragged workload: image and template counts scaled by this (1.0: the full workload)")
     ap.add_argument("--lanes", type=int, default=4, help="ragged workload: concurrent lanes of the batch (1-4)")
+    ap.add_argument("--ragged-form", default="fp16x3", choices=["fp32", "bf16x3", "fp16x3", "fp16"],
+                    help="ragged workload: the precision form of every stack")
     ap.add_argument("--proposal-features", default="cross", choices=sorted(PROPOSAL_FEATURES),
                     help="proposal workload: the network's input features (invariant: shift- and rotation-invariant "
                          "ring-power harmonics; cross: rotation-invariant cross-ring products)")

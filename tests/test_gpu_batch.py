@@ -46,11 +46,11 @@ def _bits(t):
 def _stack_specs():
     """Scaled-down ragged workload: shapes drawn like the 64-stack batch
     (n in {64, 96, 128, 192}, M = n/2, Qa = 2n, W in 2..8 px) plus the
-    largest shape forced in; precisions alternate."""
+    largest shape forced in; the four precision forms alternate."""
     specs = synth.ragged_stack_specs(11, count=6, scale=0.03)
     specs.append(dict(n=192, M=96, Qa=384, R=8.0, n_templates=3, n_images=2))
     for i, sp in enumerate(specs):
-        sp["precision"] = ("fp32", "bf16x3", "fp16")[i % 3]
+        sp["precision"] = ("fp32", "bf16x3", "fp16", "fp16x3")[i % 4]
         sp["want_X"] = i % 2 == 0
     return specs
 
@@ -100,7 +100,7 @@ def test_tuning_does_not_change_results(ftk):
     n, M, Qa, R = 128, 64, 256, 4.0
     s = synth.make_alignment_set(7, n, 40, 5, 30, R, 0.05)
     shifts = synth.shift_lattice(R)
-    for prec in ("fp32", "bf16x3", "fp16"):
+    for prec in ("fp32", "bf16x3", "fp16", "fp16x3"):
         P = ftk.Plan(n, M, Qa, R, 1e-3, prec)
         P.set_shifts(shifts)
         d = P.tuning()
@@ -199,11 +199,11 @@ def test_batch_eager_one_lane(ftk, stacks):
     B.close()
 
 
-@pytest.mark.parametrize("prec,tol", [("fp32", 1e-5), ("bf16x3", 1e-3), ("fp16", 1e-3)])
+@pytest.mark.parametrize("prec,tol", [("fp32", 1e-5), ("bf16x3", 1e-3), ("fp16", 1e-3), ("fp16x3", 1e-5)])
 def test_largest_stack_shape_against_oracle(ftk, prec, tol):
     """n = 192, M = 96, Qa = 384, W = 8 px (797 shifts) through a batch,
-    against the FP64 oracle element by element (FP32: 1e-5, split bf16 and
-    FP16: eps = 1e-3, of the pair scale)."""
+    against the FP64 oracle element by element (FP32 and split fp16: 1e-5,
+    split bf16 and FP16: eps = 1e-3, of the pair scale)."""
     n, M, Qa, R = 192, 96, 384, 8.0
     s = synth.make_alignment_set(41, n, 2, 1, 30, 4.0, 0.1)
     shifts = synth.shift_lattice(R)
