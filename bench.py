@@ -317,8 +317,9 @@ def cpu_baseline(inputs, w, shifts, n_img=8, n_tmp=48, n_dir=(2, 4)):
 RAGGED = dict(name="ragged_c4", stacks=64, seed=4, nblob=60, snr=0.05, eps=1e-3)
 PROPOSAL = dict(name="proposal_c5", n=128, M=64, Qa=256, R=4.0, n_templates=8192, n_clean=16384, n_val=1024,
                 n_test=2048, nblob=60, snr=0.05, eps=1e-3, epochs=12, topk=32, hidden=1024, seed=5)
-# rings and modes of each feature kind (2048 inputs either way)
-PROPOSAL_FEATURES = {"cross": (16, 8), "invariant": (64, 32)}
+# rings and modes of each feature kind (2048 inputs each); "power" is the
+# workload's own: |a(k; q)|^2 over 64 radii x the 32 lowest modes
+PROPOSAL_FEATURES = {"power": (64, 32), "cross": (16, 8), "invariant": (64, 32)}
 
 
 def bench_ragged(args):
@@ -534,9 +535,10 @@ def main():
     ap.add_argument("--lanes", type=int, default=4, help="ragged workload: concurrent lanes of the batch (1-4)")
     ap.add_argument("--ragged-form", default="fp16x3", choices=["fp32", "bf16x3", "fp16x3", "fp16"],
                     help="ragged workload: the precision form of every stack")
-    ap.add_argument("--proposal-features", default="cross", choices=sorted(PROPOSAL_FEATURES),
-                    help="proposal workload: the network's input features (invariant: shift- and rotation-invariant "
-                         "ring-power harmonics; cross: rotation-invariant cross-ring products)")
+    ap.add_argument("--proposal-features", default="power", choices=sorted(PROPOSAL_FEATURES),
+                    help="proposal workload: the network's input features (power: |a(k; q)|^2, 64 radii x 32 modes; "
+                         "cross: rotation-invariant cross-ring products; invariant: shift- and rotation-invariant "
+                         "ring-power harmonics)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-weighted", action="store_true", help="skip the weighted-SVD measurement")
     ap.add_argument("--no-bft", action="store_true", help="skip the brute-force-translation measurement")
