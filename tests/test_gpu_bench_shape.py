@@ -31,7 +31,7 @@ def setup():
     return ftk, s, shifts, plan
 
 
-@pytest.mark.parametrize("form,tol", [("fp32", 1e-5), ("bf16x3", 1e-3), ("fp16", 1e-3)])
+@pytest.mark.parametrize("form,tol", [("fp32", 1e-5), ("bf16x3", 1e-3), ("fp16", 1e-3), ("fp16x3", 1e-5)])
 def test_full_size_sampled_pairs(setup, form, tol):
     ftk, s, shifts, plan = setup
     print(f"[bench shape] form={form} 512x2048 n=128 N=197", flush=True)
