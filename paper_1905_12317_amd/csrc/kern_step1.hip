@@ -568,7 +568,67 @@ __global__ void __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(NW
 __host__ __device__ constexpr int fp16_store_row_words(int zb) { return zb / 2 + 4; }
 __host__ __device__ constexpr int fp16_store_words(int zb) { return 32 * fp16_store_row_words(zb); }
 
-template <int RT, int CT, bool FOLD>
+// Plain slots of the FP16 form: each (template, part) holds ZB consecutive
+// k' = c H_pad + z0 + zeta, whole 128-byte staging rows.  The wave's RT
+// template tiles from rt0 go through its LDS rows so that 8 lanes store one
+// row with 16-byte stores.  zw: the image's staging at mode q.
+template <int RT, int CT>
+__device__ __forceinline__ void fp16_store_plain(const Step1Args& p, float* smem, const f32x16 (&acc)[RT][CT],
+                                                 int rt0, int z0, uint32_t* zw) {
+  constexpr int ZB = 32 * CT;
+  constexpr int SRW = fp16_store_row_words(ZB);
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int r = lane >> 5;
+  const int c32 = lane & 31;
+  const int odd = c32 & 1;
+  const int nRT = (p.nB + 15) / 16;
+  const int QH = p.Qa / 2;
+  const size_t pair_words = static_cast<size_t>(QH) * p.H_pad;
+  // after the image operand (the larger of a plain and a fold slot)
+  const int opw = max(p.zblk * (p.M + 4), 32 * (2 * p.M + 4));
+  uint32_t* st = reinterpret_cast<uint32_t*>(smem + opw) + wave * fp16_store_words(ZB);
+#pragma unroll
+  for (int i = 0; i < RT; ++i) {
+    const int rt = rt0 + i;
+    if (rt >= nRT) break;
+#pragma unroll
+    for (int j = 0; j < CT; ++j)
+#pragma unroll
+      for (int v = 0; v < 16; v += 2) {
+        const float xr = acc[i][j][v], xi = acc[i][j][v + 1];
+        // even lane: (re of zeta, re of zeta + 1); odd lane: (im of zeta - 1, im of zeta)
+        const float got = __builtin_bit_cast(
+            float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, odd ? xr : xi), 0xB1, 0xF, 0xF, false));
+        f16x2 w;
+        w[0] = static_cast<_Float16>(odd ? got : xr);
+        w[1] = static_cast<_Float16>(odd ? xi : got);
+        const int t = 4 * (v >> 2) + 2 * r + ((v & 3) >> 1);
+        st[(2 * t + odd) * SRW + 16 * j + (c32 >> 1)] = __builtin_bit_cast(uint32_t, w);
+      }
+    wave_sync();
+    // 16-byte units u: row (t, c) = u / (ZB / 8), segment u % (ZB / 8)
+    constexpr int SEGS = ZB / 8;
+#pragma unroll
+    for (int k = 0; k < (32 * SEGS) / 64; ++k) {
+      const int u = lane + 64 * k;
+      const int row = u / SEGS, seg = u - row * SEGS;
+      const int t = row >> 1, c = row & 1;
+      const int B = rt * 16 + t;
+      if (B < p.nB) {
+        const int kp = c * p.H_pad + z0 + 8 * seg;
+        const float4 val = *reinterpret_cast<const float4*>(st + row * SRW + 4 * seg);
+        typedef float v4f __attribute__((ext_vector_type(4)));
+        __builtin_nontemporal_store(v4f{val.x, val.y, val.z, val.w},
+                                    reinterpret_cast<v4f*>(zw + static_cast<size_t>(B) * pair_words +
+                                                           static_cast<size_t>(kp >> 6) * QH * 32 + ((kp & 63) >> 1)));
+      }
+    }
+    wave_sync();
+  }
+}
+
+template <int RT, int CT, bool FOLD, int NKS>
 __device__ __forceinline__ void step1_fp16_tile(const Step1Args& p, float* smem, int A, int q, int z0, int part) {
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -604,6 +664,66 @@ __device__ __forceinline__ void step1_fp16_tile(const Step1Args& p, float* smem,
   uint32_t* zw = static_cast<uint32_t*>(p.zs) + static_cast<size_t>(A) * p.nB * pair_words + static_cast<size_t>(q) * 32;
   const size_t img_off = static_cast<size_t>(A) * p.img_tiles;
   const int nw = static_cast<int>(blockDim.x) >> 6;
+  if constexpr (!FOLD && NKS > 0) {
+    // Plain slots with nks = NKS: the template operand of the wave's next
+    // tiles is loaded during the K loop of the current ones (each K step's
+    // registers refilled once its MFMAs have read them) and has landed
+    // before the current tiles' stores are issued.  Loads and stores share
+    // one completion count per wave, so a load issued after a tile's stores
+    // can only be waited for together with them: loading the next operand at
+    // the head of its K loop, as the general loop does, holds the matrix
+    // cores until the previous stores have reached memory, whereas here the
+    // next K loop runs while they drain (n = 128, 64 images x 2048
+    // templates: 2.0 -> 1.6 ms per launch).  Past the last tile the loads
+    // repeat the last tile (unused).
+    const f16x8* rq = reinterpret_cast<const f16x8*>(p.r16) +
+                      (static_cast<size_t>(q) * p.tiles_per_q + img_off) * NKS * 64 + lane;
+    const int stride = nw * RT * p.tparts;
+    int rt0 = (part * nw + wave) * RT;
+    if (rt0 >= nRT) return;
+    f16x8 ah[RT][NKS];
+#pragma unroll
+    for (int i = 0; i < RT; ++i) {
+      const f16x8* ra = rq + static_cast<size_t>(min(rt0 + i, nRT - 1)) * NKS * 64;
+#pragma unroll
+      for (int ks = 0; ks < NKS; ++ks) ah[i][ks] = ra[ks * 64];
+    }
+    // landed before the loop as well: the loop head then has no operand load
+    // in flight on either path into it, and waits for none of the stores
+#pragma unroll
+    for (int i = 0; i < RT; ++i)
+#pragma unroll
+      for (int ks = 0; ks < NKS; ++ks) asm volatile("" ::"v"(ah[i][ks]));
+    for (; rt0 < nRT; rt0 += stride) {
+      const f16x8* rb[RT];
+#pragma unroll
+      for (int i = 0; i < RT; ++i) rb[i] = rq + static_cast<size_t>(min(rt0 + stride + i, nRT - 1)) * NKS * 64;
+      f32x16 acc[RT][CT];
+#pragma unroll
+      for (int i = 0; i < RT; ++i)
+#pragma unroll
+        for (int j = 0; j < CT; ++j) acc[i][j] = zero16();
+#pragma unroll
+      for (int ks = 0; ks < NKS; ++ks) {
+#pragma unroll
+        for (int j = 0; j < CT; ++j) {
+          const f16x8 bv = *reinterpret_cast<const f16x8*>(Pb + j * 32 * RW + 8 * ks);
+#pragma unroll
+          for (int i = 0; i < RT; ++i)
+            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah[i][ks], bv, acc[i][j], 0, 0, 0);
+        }
+#pragma unroll
+        for (int i = 0; i < RT; ++i) ah[i][ks] = rb[i][ks * 64];
+      }
+      // the next tiles' operands have landed before this tile's stores
+#pragma unroll
+      for (int i = 0; i < RT; ++i)
+#pragma unroll
+        for (int ks = 0; ks < NKS; ++ks) asm volatile("" ::"v"(ah[i][ks]));
+      fp16_store_plain<RT, CT>(p, smem, acc, rt0, z0, zw);
+    }
+    return;
+  }
   for (int rt0 = (part * nw + wave) * RT; rt0 < nRT; rt0 += nw * RT * p.tparts) {
     f32x16 acc[RT][CT];
 #pragma unroll
@@ -641,51 +761,7 @@ __device__ __forceinline__ void step1_fp16_tile(const Step1Args& p, float* smem,
     // Accumulator row 8 (v / 4) + 4 r + v % 4 is template rt 16 + 4 (v / 4)
     // + 2 r + (v % 4) / 2 (re|im in adjacent rows).
     if constexpr (!FOLD) {
-      // Plain slots: each (template, part) holds ZB consecutive k' = c H_pad +
-      // z0 + zeta, whole 128-byte staging rows.  The tile goes through this
-      // wave's LDS rows so that 8 lanes store one row with 16-byte stores.
-      constexpr int SRW = fp16_store_row_words(ZB);
-      // after the image operand (the larger of a plain and a fold slot)
-      const int opw = max(p.zblk * (p.M + 4), 32 * (2 * p.M + 4));
-      uint32_t* st = reinterpret_cast<uint32_t*>(smem + opw) + wave * fp16_store_words(ZB);
-#pragma unroll
-      for (int i = 0; i < RT; ++i) {
-        const int rt = rt0 + i;
-        if (rt >= nRT) break;
-#pragma unroll
-        for (int j = 0; j < CT; ++j)
-#pragma unroll
-          for (int v = 0; v < 16; v += 2) {
-            const float xr = acc[i][j][v], xi = acc[i][j][v + 1];
-            // even lane: (re of zeta, re of zeta + 1); odd lane: (im of zeta - 1, im of zeta)
-            const float got = __builtin_bit_cast(
-                float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, odd ? xr : xi), 0xB1, 0xF, 0xF, false));
-            f16x2 w;
-            w[0] = static_cast<_Float16>(odd ? got : xr);
-            w[1] = static_cast<_Float16>(odd ? xi : got);
-            const int t = 4 * (v >> 2) + 2 * r + ((v & 3) >> 1);
-            st[(2 * t + odd) * SRW + 16 * j + (c32 >> 1)] = __builtin_bit_cast(uint32_t, w);
-          }
-        wave_sync();
-        // 16-byte units u: row (t, c) = u / (ZB / 8), segment u % (ZB / 8)
-        constexpr int SEGS = ZB / 8;
-#pragma unroll
-        for (int k = 0; k < (32 * SEGS) / 64; ++k) {
-          const int u = lane + 64 * k;
-          const int row = u / SEGS, seg = u - row * SEGS;
-          const int t = row >> 1, c = row & 1;
-          const int B = rt * 16 + t;
-          if (B < p.nB) {
-            const int kp = c * p.H_pad + z0 + 8 * seg;
-            const float4 val = *reinterpret_cast<const float4*>(st + row * SRW + 4 * seg);
-            typedef float v4f __attribute__((ext_vector_type(4)));
-            __builtin_nontemporal_store(v4f{val.x, val.y, val.z, val.w},
-                                        reinterpret_cast<v4f*>(zw + static_cast<size_t>(B) * pair_words +
-                                                               static_cast<size_t>(kp >> 6) * QH * 32 + ((kp & 63) >> 1)));
-          }
-        }
-        wave_sync();
-      }
+      fp16_store_plain<RT, CT>(p, smem, acc, rt0, z0, zw);
       continue;
     }
 #pragma unroll
@@ -723,7 +799,8 @@ __device__ __forceinline__ void step1_fp16_tile(const Step1Args& p, float* smem,
   }
 }
 
-template <int RT, int CT>
+// NKS > 0: the plain slots of plans with M = 8 NKS take the prefetching loop.
+template <int RT, int CT, int NKS>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) step1_fp16_v2(Step1Args p) {
   extern __shared__ float smem[];
   int A, y, zp;
@@ -731,9 +808,9 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) s
   const int zb = (zp / p.tparts) * (32 * CT);
   const int part = zp % p.tparts;
   if (y < CT)
-    step1_fp16_tile<RT, 1, true>(p, smem, A, 0, zb + 32 * y, part);
+    step1_fp16_tile<RT, 1, true, 0>(p, smem, A, 0, zb + 32 * y, part);
   else
-    step1_fp16_tile<RT, CT, false>(p, smem, A, y - CT + 1, zb, part);
+    step1_fp16_tile<RT, CT, false, NKS>(p, smem, A, y - CT + 1, zb, part);
 }
 
 template <class K>
@@ -836,7 +913,7 @@ hipError_t launch_step1_v2(const Step1Args& a, int precision, hipStream_t s) {
     if (!a.dscale) return hipErrorInvalidValue;
 #define FTK_S1(ct)                                              \
   case ct: {                                                     \
-    auto k = step1_fp16_v2<2, ct>;                              \
+    auto k = a.M == 64 ? step1_fp16_v2<2, ct, 8> : step1_fp16_v2<2, ct, 0>; \
     if ((e = set_lds(k, lds)) != hipSuccess) return e;          \
     hipLaunchKernelGGL(k, grid, dim3(256), lds, s, a);          \
     break;                                                       \
