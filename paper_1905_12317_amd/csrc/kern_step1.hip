@@ -799,7 +799,9 @@ __device__ __forceinline__ void step1_fp16_tile(const Step1Args& p, float* smem,
   }
 }
 
-// NKS > 0: the plain slots of plans with M = 8 NKS take the prefetching loop.
+// NKS > 0: the plain slots of plans with M = 8 NKS take the prefetching loop
+// (M = 48, 64, 96; at M = 32 it measured no faster, and NKS = 12 needs one
+// column tile per workgroup to fit the registers).
 template <int RT, int CT, int NKS>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) step1_fp16_v2(Step1Args p) {
   extern __shared__ float smem[];
@@ -913,7 +915,10 @@ hipError_t launch_step1_v2(const Step1Args& a, int precision, hipStream_t s) {
     if (!a.dscale) return hipErrorInvalidValue;
 #define FTK_S1(ct)                                              \
   case ct: {                                                     \
-    auto k = a.M == 64 ? step1_fp16_v2<2, ct, 8> : step1_fp16_v2<2, ct, 0>; \
+    auto k = a.M == 64   ? step1_fp16_v2<2, ct, 8>                                      \
+             : a.M == 48 ? step1_fp16_v2<2, ct, 6>                                      \
+             : a.M == 96 ? step1_fp16_v2<2, ct, (ct == 2 ? 12 : 0)>                     \
+                         : step1_fp16_v2<2, ct, 0>;                                     \
     if ((e = set_lds(k, lds)) != hipSuccess) return e;          \
     hipLaunchKernelGGL(k, grid, dim3(256), lds, s, a);          \
     break;                                                       \

@@ -14,6 +14,11 @@ current pair.  Whole X arrays [197][256] of pairs taken by the first and by
 the second pass of that loop are compared with the oracle.  A second run with
 a 16 MiB staging buffer (the images in several chunks, hence several Step 1 /
 Step 3 launches) must give the same X and poses bitwise.
+
+One image against 150 templates (FP16): ten 16-template tiles, so the Step 1
+wave that takes tiles 0 and 1 also takes tiles 8 and 9 (the last one partial,
+6 templates), with the next-tile operand loads clamped past the end; sampled
+templates from every such tile against the oracle.
 """
 import sys
 
@@ -104,3 +109,25 @@ def test_benchmark_instances_elementwise(case, form):
     assert np.array_equal(X.view(np.uint32), X2.view(np.uint32))
     for k in ("value", "shift", "rot"):
         assert np.array_equal(poses[k], poses2[k])
+
+
+def test_fp16_step1_second_tile_pass(case):
+    ftk = case[0]
+    nB = 150
+    s = synth.make_alignment_set(21, 128, nB, 1, 60, 4.0, 0.05)
+    shifts = synth.shift_lattice(4.0)
+    plan = O.set_shifts(O.make_plan(128, 64, 256, 4.0, 1e-3), shifts)
+    _say(f"[qa256] fp16, 1 image x {nB} templates (10 template tiles)")
+    X, poses = _align(ftk, s, shifts, "fp16")
+    assert X.shape == (1, nB, 197, 256) and np.all(np.isfinite(X))
+    a = O.fb_coefficients(s.images[0], plan)
+    worst = 0.0
+    for j in (0, 17, 40, 127, 128, 135, 143, 144, 149):
+        b = O.fb_coefficients(s.templates[j], plan)
+        Xr, sc = np.real(O.ftk_X(a, b, plan)), O.pair_scale(a, b, plan)
+        err = float(np.max(np.abs(X[0, j] - Xr))) / sc
+        worst = max(worst, err)
+        assert err <= BARS["fp16"], (j, err)
+        v, si, ri, _ = O.best_pose(X[0, j])
+        assert (poses[0, j]["shift"], poses[0, j]["rot"]) == (si, ri), j
+    _say(f"  worst rel err {worst:.3e} over 9 templates in tiles 0, 1, 2, 7, 8, 9")
