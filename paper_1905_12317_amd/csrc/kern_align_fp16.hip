@@ -317,14 +317,14 @@ __device__ __forceinline__ void mt_stager(const Step3Args& p, float* region, int
 }
 
 // One chunk of the transposed contraction for a compute wave: K steps
-// 4 c .. 4 c + 3 from LDS buffer `buf`, both tiles; the shift panel operands
+// 4 c .. 4 c + 3 from LDS buffer `buf`, both tiles (only the first if !two); the shift panel operands
 // come from a ring of four register slots, each refilled after use with the
 // K step four ahead (wrapping into the next unit's tiles at the end of the
 // pair: yn0, yn1).
 template <int CTQ>
 __device__ __forceinline__ void mt_chunk(const float* region, int buf, int c, int nks, f32x16 (&acc)[kMtTiles][CTQ],
                                          f16x8 (&y0)[4], f16x8 (&y1)[4], const f16x8* y0p, const f16x8* y1p,
-                                         const f16x8* yn0, const f16x8* yn1, int lane) {
+                                         const f16x8* yn0, const f16x8* yn1, bool two, int lane) {
   using S = MtStage<CTQ>;
   const float* Zb = region + buf * S::BUF + (lane & 31) * S::ROWW + 4 * (lane >> 5);
 #pragma unroll
@@ -335,11 +335,13 @@ __device__ __forceinline__ void mt_chunk(const float* region, int buf, int c, in
 #pragma unroll
     for (int ct = 0; ct < CTQ; ++ct)
       acc[0][ct] = __builtin_amdgcn_mfma_f32_32x32x16_f16(a[ct], y0[s], acc[0][ct], 0, 0, 0);
-    // a missing second tile multiplies the first one's panel (its results
-    // are never used): no branch in the loop
+    // a slot with one tile skips the second (wave-uniform branch; its panel
+    // registers still cycle, loaded from the last tile)
+    if (two) {
 #pragma unroll
-    for (int ct = 0; ct < CTQ; ++ct)
-      acc[1][ct] = __builtin_amdgcn_mfma_f32_32x32x16_f16(a[ct], y1[s], acc[1][ct], 0, 0, 0);
+      for (int ct = 0; ct < CTQ; ++ct)
+        acc[1][ct] = __builtin_amdgcn_mfma_f32_32x32x16_f16(a[ct], y1[s], acc[1][ct], 0, 0, 0);
+    }
     const int kn = 4 * c + s + 4;
     const bool wrap = kn >= nks;
     const int ko = (wrap ? kn - nks : kn) * 64;
@@ -423,6 +425,9 @@ __device__ __forceinline__ void mt_epilogue(const Step3Args& p, f32x16 (&acc)[kM
       dE[slot][st] = f32x4{0.f, 0.f, 0.f, 0.f};
       dO[slot][st] = f32x4{0.f, 0.f, 0.f, 0.f};
     }
+    // a missing second tile's products are formed too (its shifts take no
+    // part: valid[1] is false); a branch here costs more registers than the
+    // kernel has
 #pragma unroll
     for (int s = 0; s < CTQ; ++s)
 #pragma unroll
@@ -554,16 +559,21 @@ __global__ void __launch_bounds__(64 * kMtWaves) step3_fp16_mt(Step3Args p) {
   const int ntiles = (p.N + 15) / 16;
   const int ntile_pad = p.N_pad / 16;
   // shift panel fragments [tile][K step][lane][8] fp16 (column j = 16 c + dl)
-  // of the wave's two tiles in shift block yb (a missing tile reads the last)
-  auto panel = [&](int yb, int st) {
-    const int t = min((yb * kMtCompute + wave) * kMtTiles + st, ntile_pad - 1);
+  // of the two tiles of slot ws in shift block yb (a missing tile reads the
+  // last).  A shift block is kMtCompute slots of two tiles; the wave takes
+  // slot (wave + k) mod kMtCompute in the k-th unit of its workgroup, so a
+  // short last slot (N = 197: 13 tiles in 7 slots) falls on each wave, hence
+  // each SIMD, in turn instead of always on the same one.
+  auto panel = [&](int yb, int ws, int st) {
+    const int t = min((yb * kMtCompute + ws) * kMtTiles + st, ntile_pad - 1);
     return reinterpret_cast<const f16x8*>(p.yt_hi) + static_cast<size_t>(t) * nks * 64 + lane;
   };
   int b = blockIdx.x;
   int pair, yb;
   step3_block(b, p.nblk, p.pairs, pair, yb);
-  const f16x8* y0p = panel(yb, 0);
-  const f16x8* y1p = panel(yb, 1);
+  int ws = wave;
+  const f16x8* y0p = panel(yb, ws, 0);
+  const f16x8* y1p = panel(yb, ws, 1);
   f16x8 y0[4], y1[4];
 #pragma unroll
   for (int s = 0; s < 4; ++s) {
@@ -572,13 +582,14 @@ __global__ void __launch_bounds__(64 * kMtWaves) step3_fp16_mt(Step3Args p) {
   }
   int g = 0;  // stream position
   for (;;) {
-    const int t0 = (yb * kMtCompute + wave) * kMtTiles;
+    const int t0 = (yb * kMtCompute + ws) * kMtTiles;
     const int nt = max(0, min(kMtTiles, ntiles - t0));
     const int bn = b + gridDim.x;
     int pn = pair, ybn = yb;
     if (bn < total) step3_block(bn, p.nblk, p.pairs, pn, ybn);
-    const f16x8* yn0 = panel(ybn, 0);
-    const f16x8* yn1 = panel(ybn, 1);
+    const int wsn = ws + 1 == kMtCompute ? 0 : ws + 1;
+    const f16x8* yn0 = panel(ybn, wsn, 0);
+    const f16x8* yn1 = panel(ybn, wsn, 1);
     f32x16 acc[kMtTiles][CTQ];
 #pragma unroll
     for (int st = 0; st < kMtTiles; ++st)
@@ -587,14 +598,25 @@ __global__ void __launch_bounds__(64 * kMtWaves) step3_fp16_mt(Step3Args p) {
     for (int c = 0; c < nch; ++c, ++g) {
       const int buf = g % kMtRing;
       mt_wait_ge(ready + buf, g + 1, abort);  // chunk g is in buffer g % kMtRing
-      if (nt > 0) mt_chunk<CTQ>(region, buf, c, nks, acc, y0, y1, y0p, y1p, yn0, yn1, lane);
+      if (nt > 0) mt_chunk<CTQ>(region, buf, c, nks, acc, y0, y1, y0p, y1p, yn0, yn1, nt > 1, lane);
       mt_publish(prog + wave, g + 1);  // done reading chunk g
     }
-    if (nt > 0) mt_epilogue<CTQ, WX>(p, acc, pair, t0, tbl, lane);
+    if (nt > 0) {
+      mt_epilogue<CTQ, WX>(p, acc, pair, t0, tbl, lane);
+    } else {
+      // an idle unit did not run the K loop, whose last chunk loads the next
+      // unit's first four K steps into the panel ring: load them here
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        y0[s] = yn0[s * 64];
+        y1[s] = yn1[s * 64];
+      }
+    }
     if (bn >= total) break;
     b = bn;
     pair = pn;
     yb = ybn;
+    ws = wsn;
     y0p = yn0;
     y1p = yn1;
   }

@@ -147,6 +147,25 @@ def test_align_fp16_input_scale(ftk):
     assert rel.max() <= eps
 
 
+@pytest.mark.parametrize("nshift,nA,nB", [(49, 20, 20), (460, 12, 10)])
+def test_persistent_loop_with_idle_slots(ftk, nshift, nA, nB):
+    """More (pair, shift block) units than compute units, so the persistent
+    Step 3 loops over units, and shift slots without tiles: 49 lattice shifts
+    give 4 tiles for 7 compute waves; 460 shifts give three shift blocks, the
+    last with one tile, and a workgroup's units change shift block.  A wave
+    idle in one unit and busy in the next must multiply the next unit's shift
+    panel.  Every pair against the oracle."""
+    n, M, Qa, R, eps = 32, 16, 64, 2.0, 1e-3
+    rng = np.random.default_rng(11)
+    shifts = (synth.shift_lattice(R) if nshift == 49
+              else np.array([synth.area_uniform_disk(rng, R) for _ in range(nshift)]))
+    assert len(shifts) == nshift
+    st = synth.make_alignment_set(17, n, nB, nA, 20, R, 0.1)
+    X, poses, Xref, errs, S = _run(ftk, n, M, Qa, R, eps, st.images, st.templates, shifts, f"loop N={nshift}")
+    assert errs.max() <= eps
+    _check_poses(poses, Xref, errs * S)
+
+
 @pytest.mark.parametrize("n,M,Qa,R,nshift", [(32, 16, 64, 2.0, 49), (64, 32, 128, 3.0, 0), (128, 64, 256, 4.0, 0),
                                              (128, 64, 256, 8.0, 0), (32, 16, 128, 2.5, 30)])
 def test_poses_without_X_equal_poses_with_X(ftk, n, M, Qa, R, nshift):
