@@ -52,7 +52,7 @@ TRAFFIC = {
     "fp32": {"bytes_per_launch": 9.627e+09, "sources": ["kern_align.hip", "step3_epilogue.h", "device_common.h", "kernels.h"],
         "sha1": "700029d305407183e020a799f8ad560623527315"},
     "fp16": {"bytes_per_launch": 8.626e+09, "sources": ["kern_align_fp16.hip", "step3_epilogue.h", "device_common.h", "kernels.h"],
-        "sha1": "bc8dd0db4f7f6d9ca6f6774c316990c02bc71b72"},
+        "sha1": "99159a6944325a17b0b8e56991ccb2be5214b9bf"},
 }
 
 
