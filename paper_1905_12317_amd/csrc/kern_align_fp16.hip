@@ -327,11 +327,19 @@ __device__ __forceinline__ void mt_chunk(const float* region, int buf, int c, in
                                          const f16x8* yn0, const f16x8* yn1, bool two, int lane) {
   using S = MtStage<CTQ>;
   const float* Zb = region + buf * S::BUF + (lane & 31) * S::ROWW + 4 * (lane >> 5);
+  // Zhat fragments double-buffered: those of K step s + 1 are read while the
+  // MFMAs of step s issue
+  f16x8 a2[2][CTQ];
+#pragma unroll
+  for (int ct = 0; ct < CTQ; ++ct) a2[0][ct] = *reinterpret_cast<const f16x8*>(Zb + ct * 32 * S::ROWW);
 #pragma unroll
   for (int s = 0; s < 4; ++s) {
-    f16x8 a[CTQ];
+    if (s + 1 < 4) {
 #pragma unroll
-    for (int ct = 0; ct < CTQ; ++ct) a[ct] = *reinterpret_cast<const f16x8*>(Zb + ct * 32 * S::ROWW + 8 * s);
+      for (int ct = 0; ct < CTQ; ++ct)
+        a2[(s + 1) & 1][ct] = *reinterpret_cast<const f16x8*>(Zb + ct * 32 * S::ROWW + 8 * (s + 1));
+    }
+    const f16x8 (&a)[CTQ] = a2[s & 1];
 #pragma unroll
     for (int ct = 0; ct < CTQ; ++ct)
       acc[0][ct] = __builtin_amdgcn_mfma_f32_32x32x16_f16(a[ct], y0[s], acc[0][ct], 0, 0, 0);
