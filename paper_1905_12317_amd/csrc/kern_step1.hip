@@ -193,12 +193,19 @@ __device__ __forceinline__ FillData fill_load(const Step1Args& p, const float2* 
 }
 // the 4 values (times scale), multiplied by i in the Nyquist half:
 // i (x + i y) = -y + i x
+// The products are rounded to FP32 here, in every kernel that inlines this:
+// left visible, a conversion of a product to fp16 may be selected as one
+// mixed-precision fused instruction (a single rounding of the exact product)
+// in one kernel and as a multiply and a conversion (two roundings) in
+// another, and the fp16 forms' Step 1 would then depend on the launch shape.
 __device__ __forceinline__ void fill_value(const FillData& d, bool ny, float scale, float (&x)[4]) {
   const float c0 = d.cm.x * scale, c1 = d.cm.y * scale;
   x[0] = c0 * d.av.x;
   x[1] = c0 * d.av.y;
   x[2] = c1 * d.av.z;
   x[3] = c1 * d.av.w;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) asm volatile("" : "+v"(x[e]));
   if (ny) {
     const float t0 = x[0], t2 = x[2];
     x[0] = -x[1];

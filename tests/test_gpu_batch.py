@@ -131,6 +131,29 @@ def test_tuning_does_not_change_results(ftk):
             P.set_tuning(stage_mib=8)
 
 
+@pytest.mark.parametrize("n,M,Qa,R,nA,nB", [(64, 32, 128, 6.0, 8, 99), (192, 96, 384, 4.0, 2, 6)])
+def test_svd_block_does_not_change_fp16_forms(ftk, n, M, Qa, R, nA, nB):
+    """The fp16 forms' Step 1 with 64 and 128 SVD terms per workgroup: bitwise
+    the same X.  At these shapes the image operand's conversions to fp16 once
+    differed between the two kernels (a fused product-and-round in one, a
+    product rounded to FP32 and then converted in the other), which an
+    autotuned batch then showed as a few pairs differing from ftk_align."""
+    s = synth.make_alignment_set(103, n, nB, nA, 20, min(R, 4.0), 0.1)
+    shifts = synth.shift_lattice(R)
+    for prec in ("fp16", "fp16x3"):
+        P = ftk.Plan(n, M, Qa, R, 1e-3, prec)
+        P.set_shifts(shifts)
+        out = []
+        for z in (128, 64):
+            P.set_tuning(step1_zblk=z)
+            X, b = P.align(_dev(s.images), _dev(s.templates), want_X=True)
+            torch.cuda.synchronize()
+            out.append((_bits(X), _bits(b)))
+        nd = int(np.sum(out[0][0] != out[1][0]))
+        _say(f"[svd block n={n} {prec}] N={len(shifts)} H={P.info()['H']}: X elements differing {nd}")
+        assert nd == 0 and np.array_equal(out[0][1], out[1][1])
+
+
 def test_batch_graph_two_lanes_autotuned(ftk, stacks, tmp_path):
     refs = [_reference(st) for st in stacks]
     os.environ["FTK_TUNE_CACHE"] = str(tmp_path / "tune.txt")
