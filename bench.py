@@ -52,7 +52,7 @@ TRAFFIC = {
     "fp32": {"bytes_per_launch": 9.627e+09, "sources": ["kern_align.hip", "step3_epilogue.h", "device_common.h", "kernels.h"],
         "sha1": "700029d305407183e020a799f8ad560623527315"},
     "fp16": {"bytes_per_launch": 8.627e+09, "sources": ["kern_align_fp16.hip", "step3_epilogue.h", "device_common.h", "kernels.h"],
-        "sha1": "bd7c6f6ced3abdf1cbbf68ec6ff690ed69d6fc12"},
+        "sha1": "256126cff62d64aa3273599c0e60be1a69efba83"},
 }
 
 

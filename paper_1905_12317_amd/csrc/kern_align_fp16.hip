@@ -317,10 +317,10 @@ __device__ __forceinline__ void mt_stager(const Step3Args& p, float* region, int
 }
 
 // One chunk of the transposed contraction for a compute wave: K steps
-// 4 c .. 4 c + 3 from LDS buffer `buf`, both tiles (only the first if !two); the shift panel operands
-// come from a ring of four register slots, each refilled after use with the
-// K step four ahead (wrapping into the next unit's tiles at the end of the
-// pair: yn0, yn1).
+// 4 c .. 4 c + 3 from LDS buffer `buf`, both tiles (only the first if !two);
+// the shift panel operands come from a ring of four register slots, each
+// refilled after use with the K step four ahead (wrapping into the next
+// unit's tiles at the end of the pair: yn0, yn1).
 template <int CTQ>
 __device__ __forceinline__ void mt_chunk(const float* region, int buf, int c, int nks, f32x16 (&acc)[kMtTiles][CTQ],
                                          f16x8 (&y0)[4], f16x8 (&y1)[4], const f16x8* y0p, const f16x8* y1p,
