@@ -147,6 +147,34 @@ def test_align_fp16_input_scale(ftk):
     assert rel.max() <= eps
 
 
+def test_data_scales_unaligned_coefficients(ftk):
+    """The per-call data scales (max |a|, max |b| over the coefficients) are
+    read with 16-byte loads where the coefficients are 16-byte aligned and
+    one by one otherwise: coefficients 8 bytes off that alignment give bitwise
+    the same X and poses in both fp16 forms."""
+    n, M, Qa, R = 32, 16, 64, 2.0
+    st = synth.make_alignment_set(5, n, 7, 3, 20, R, 0.1)
+    shifts = synth.shift_lattice(R)
+
+    def offset_copy(t):
+        buf = torch.empty(t.numel() + 1, dtype=t.dtype, device=t.device)
+        v = buf[1:].view(t.shape)
+        v.copy_(t)
+        return v
+
+    for prec in ("fp16", "fp16x3"):
+        P = ftk.Plan(n, M, Qa, R, 1e-3, precision=prec)
+        P.set_shifts(shifts)
+        a, b = P.transform(_dev(st.images)), P.transform(_dev(st.templates))
+        X0, b0 = P.align_coeffs(a, b, want_X=True)
+        a1, b1 = offset_copy(a), offset_copy(b)
+        assert a.data_ptr() % 16 == 0 and a1.data_ptr() % 16 == 8 and b1.data_ptr() % 16 == 8
+        X1, bb1 = P.align_coeffs(a1, b1, want_X=True)
+        torch.cuda.synchronize()
+        assert torch.equal(X0.view(torch.int32), X1.view(torch.int32)), prec
+        assert torch.equal(b0, bb1), prec
+
+
 @pytest.mark.parametrize("nshift,nA,nB", [(49, 20, 20), (460, 12, 10)])
 def test_persistent_loop_with_idle_slots(ftk, nshift, nA, nB):
     """More (pair, shift block) units than compute units, so the persistent
