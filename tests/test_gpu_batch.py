@@ -132,15 +132,16 @@ def test_tuning_does_not_change_results(ftk):
 
 
 @pytest.mark.parametrize("n,M,Qa,R,nA,nB", [(64, 32, 128, 6.0, 8, 99), (192, 96, 384, 4.0, 2, 6)])
-def test_svd_block_does_not_change_fp16_forms(ftk, n, M, Qa, R, nA, nB):
-    """The fp16 forms' Step 1 with 64 and 128 SVD terms per workgroup: bitwise
-    the same X.  At these shapes the image operand's conversions to fp16 once
-    differed between the two kernels (a fused product-and-round in one, a
-    product rounded to FP32 and then converted in the other), which an
-    autotuned batch then showed as a few pairs differing from ftk_align."""
+def test_svd_block_does_not_change_results(ftk, n, M, Qa, R, nA, nB):
+    """Step 1 with 64 and 128 SVD terms per workgroup, every precision form:
+    bitwise the same X.  At these shapes the fp16 forms' image operand
+    conversions once differed between the two kernels (a fused
+    product-and-round in one, a product rounded to FP32 and then converted in
+    the other), which an autotuned batch then showed as a few pairs differing
+    from ftk_align."""
     s = synth.make_alignment_set(103, n, nB, nA, 20, min(R, 4.0), 0.1)
     shifts = synth.shift_lattice(R)
-    for prec in ("fp16", "fp16x3"):
+    for prec in ("fp32", "bf16x3", "fp16", "fp16x3"):
         P = ftk.Plan(n, M, Qa, R, 1e-3, prec)
         P.set_shifts(shifts)
         out = []
