@@ -192,6 +192,14 @@ def test_persistent_loop_with_idle_slots(ftk, nshift, nA, nB):
     X, poses, Xref, errs, S = _run(ftk, n, M, Qa, R, eps, st.images, st.templates, shifts, f"loop N={nshift}")
     assert errs.max() <= eps
     _check_poses(poses, Xref, errs * S)
+    # the best-pose-only kernel (no X written) on the same inputs: bitwise the same poses
+    P = ftk.Plan(n, M, Qa, R, eps, precision="fp16")
+    P.set_shifts(shifts)
+    _, b2 = P.align(_dev(st.images), _dev(st.templates))
+    torch.cuda.synchronize()
+    p2 = ftk.poses_numpy(b2)
+    for k in ("value", "shift", "rot"):
+        assert np.array_equal(poses[k], p2[k]), k
 
 
 @pytest.mark.parametrize("n,M,Qa,R,nshift", [(32, 16, 64, 2.0, 49), (64, 32, 128, 3.0, 0), (128, 64, 256, 4.0, 0),
