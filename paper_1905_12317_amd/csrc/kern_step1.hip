@@ -889,7 +889,8 @@ size_t step1_v2_lds_bytes(int M, int zb, int precision) {
   return plain > fold ? plain : fold;
 }
 
-// split form: template row tiles per wave and waves per workgroup
+// split form: template row tiles per wave and waves per workgroup (per-image
+// lists of at most 16 templates have one tile per image: one per wave)
 constexpr int kBf16RT = 2, kBf16NW = 4;
 
 hipError_t launch_step1_v2(const Step1Args& a, int precision, hipStream_t s) {
@@ -940,7 +941,8 @@ hipError_t launch_step1_v2(const Step1Args& a, int precision, hipStream_t s) {
     if (!a.dscale) return hipErrorInvalidValue;
 #define FTK_S1(ct)                                                        \
   case ct: {                                                               \
-    auto k = step1_split_v2<_Float16, kBf16RT, ct, kBf16NW>;              \
+    auto k = a.img_tiles == 1 ? step1_split_v2<_Float16, 1, ct, kBf16NW>                 \
+                              : step1_split_v2<_Float16, kBf16RT, ct, kBf16NW>;          \
     if ((e = set_lds(k, lds)) != hipSuccess) return e;                    \
     hipLaunchKernelGGL(k, grid, dim3(64 * kBf16NW), lds, s, a);           \
     break;                                                                 \
@@ -954,7 +956,8 @@ hipError_t launch_step1_v2(const Step1Args& a, int precision, hipStream_t s) {
   } else {
 #define FTK_S1(ct)                                                        \
   case ct: {                                                               \
-    auto k = step1_split_v2<__bf16, kBf16RT, ct, kBf16NW>;                \
+    auto k = a.img_tiles == 1 ? step1_split_v2<__bf16, 1, ct, kBf16NW>                 \
+                              : step1_split_v2<__bf16, kBf16RT, ct, kBf16NW>;          \
     if ((e = set_lds(k, lds)) != hipSuccess) return e;                    \
     hipLaunchKernelGGL(k, grid, dim3(64 * kBf16NW), lds, s, a);           \
     break;                                                                 \
